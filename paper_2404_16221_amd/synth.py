@@ -1,0 +1,315 @@
+"""Seeded synthetic ray samples packed by spatial region.
+
+This module is the input generator shared by the tests, the benchmark and the
+oracle checks.  It holds none of the rendering arithmetic: it draws samples
+and lays them out, nothing else.
+
+Shape of the data (the paper's setting, Sec. 4.2 "Non-overlapped NeRFs"): the
+scene cube [-1, 1]^3 is split into a grid of disjoint axis-aligned boxes, one
+NeRF (in the paper, one GPU) per box.  Every ray carries sorted, non-overlapping
+sample intervals; the samples of one ray that fall in one box form one
+contiguous run, a *segment* (boxes are convex, so a straight ray meets each box
+in one interval).  Samples are stored region-major: all segments of box 0 (in
+ray order), then box 1, and so on, which is how each GPU in the paper holds the
+samples of its own box.  The per-ray order of segments (Alg. 1/2's index list
+I) is given by ``ray_offsets``/``seg_ids``.
+
+Random numbers are counter based, so any ray can be regenerated alone: value
+``s`` of ray ``r`` is ``mix64(key(r) + (s + 1) * GAMMA)``, where ``mix64`` is
+the SplitMix64 output function (Steele, Lea & Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014) and ``key(r) = mix64(mix64(seed)
++ r * GAMMA)``.
+
+Per ray (slots 0..255):
+  * origin o ~ U[-1, 1)^3                                   (slots 0, 1, 2)
+  * sample count N ~ U{n_min..n_max} (multiply-shift range)  (slot 3)
+  * start offset u                                          (slot 4)
+  * direction: uniform on the sphere by rejection from the cube (tries j, slots
+    16 + 3j .. 16 + 3j + 2, at most 64 tries)
+Per sample i (slots 256 + 8 i + k):
+  * width   delta = -width_mean * log(u), u in (0, 1]       (k = 0)
+  * density sigma = exp(mu + s * z), z by Box-Muller         (k = 1, 2)
+            zeroed when u < zero_frac                        (k = 3)
+  * colour  rgb ~ U[0, 1)^3                                  (k = 4, 5, 6)
+Widths are rescaled to sum to t_far when they exceed it; the intervals are
+contiguous from a start drawn uniformly in [0, t_far - sum].
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_S30, _S27, _S31 = np.uint64(30), np.uint64(27), np.uint64(31)
+_S11, _S32 = np.uint64(11), np.uint64(32)
+_INV53 = 1.0 / 9007199254740992.0  # 2^-53
+
+SEED_BASE = 2404_16221
+RAY_SLOTS = 256
+SAMPLE_STRIDE = 8
+DIR_TRIES = 64
+
+
+def mix64(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function on uint64 arrays (wrapping arithmetic)."""
+    z = np.asarray(z, dtype=np.uint64).copy()
+    z ^= z >> _S30
+    z *= _M1
+    z ^= z >> _S27
+    z *= _M2
+    z ^= z >> _S31
+    return z
+
+
+def ray_keys(seed: int, rays: np.ndarray) -> np.ndarray:
+    s = mix64(np.array([seed], dtype=np.uint64))[0]
+    with np.errstate(over="ignore"):
+        return mix64(s + np.asarray(rays, dtype=np.uint64) * GAMMA)
+
+
+def draw(keys: np.ndarray, slots) -> np.ndarray:
+    with np.errstate(over="ignore"):
+        return mix64(keys + (np.asarray(slots, dtype=np.uint64) + np.uint64(1)) * GAMMA)
+
+
+def u01(v: np.ndarray) -> np.ndarray:
+    """Uniform double in [0, 1)."""
+    return (v >> _S11).astype(np.float64) * _INV53
+
+
+def u01_open0(v: np.ndarray) -> np.ndarray:
+    """Uniform double in (0, 1]."""
+    return ((v >> _S11) + np.uint64(1)).astype(np.float64) * _INV53
+
+
+@dataclass(frozen=True)
+class Workload:
+    """Generator parameters for one synthetic workload."""
+    name: str
+    n_rays: int
+    n_min: int
+    n_max: int
+    sigma_mu: float
+    sigma_s: float
+    zero_frac: float
+    grid: Tuple[int, int, int]
+    seed: int
+    width_mean: float = 0.02
+    t_far: float = 3.0
+
+    @property
+    def k(self) -> int:
+        return self.grid[0] * self.grid[1] * self.grid[2]
+
+    def plain(self) -> "Workload":
+        """The same samples as one K=1 region (one segment per ray)."""
+        return replace(self, name=self.name + "-plain", grid=(1, 1, 1))
+
+
+# The five workloads: 0 parity (K=1), 1 merge check (K=8), 2 training batch
+# (K=16), 3 serving scene (K=32, rays per request set by the image size),
+# 4 large partition (K=64, processed in chunks of 262,144 rays).
+WORKLOADS: Dict[int, Workload] = {
+    0: Workload("k1-4096r", 4096, 1, 128, 0.0, 1.5, 0.0, (1, 1, 1), SEED_BASE + 0),
+    1: Workload("k8-65536r", 65536, 1, 256, 0.0, 1.5, 0.0, (2, 2, 2), SEED_BASE + 1),
+    2: Workload("k16-262144r", 262144, 8, 1024, 0.0, 2.0, 0.3, (4, 2, 2), SEED_BASE + 2),
+    3: Workload("k32-serve", 256 * 256, 16, 512, 0.0, 1.5, 0.0, (4, 4, 2), SEED_BASE + 3),
+    4: Workload("k64-4194304r", 4194304, 32, 512, 0.0, 1.5, 0.0, (4, 4, 4), SEED_BASE + 4),
+}
+CHUNK_RAYS_K64 = 262144
+SERVE_SIZES = ((256, 256), (512, 512), (1280, 720), (1920, 1080))
+
+
+@dataclass
+class Batch:
+    """Packed samples of a set of rays (host arrays).
+
+    sigma[n] f32, rgb[n,3] f32, t_start[n] f32, t_end[n] f32: samples,
+    region-major.  seg_offsets[n_seg+1] i64: CSR over samples.  ray_offsets[R+1]
+    i64 and seg_ids[n_seg] i64: segment ids of each ray, front to back.
+    seg_box[n_seg] i32, seg_ray[n_seg] i64: bookkeeping for tests.
+    """
+    sigma: np.ndarray
+    rgb: np.ndarray
+    t_start: np.ndarray
+    t_end: np.ndarray
+    seg_offsets: np.ndarray
+    ray_offsets: np.ndarray
+    seg_ids: np.ndarray
+    seg_box: np.ndarray
+    seg_ray: np.ndarray
+    rays: np.ndarray
+    workload: Optional[Workload] = None
+
+    @property
+    def n(self) -> int:
+        return int(self.sigma.shape[0])
+
+    @property
+    def n_seg(self) -> int:
+        return int(self.seg_offsets.shape[0] - 1)
+
+    @property
+    def n_rays(self) -> int:
+        return int(self.ray_offsets.shape[0] - 1)
+
+    def ray_sample_index(self, r: int) -> np.ndarray:
+        """Indices of ray r's samples in t order (its segments front to back)."""
+        parts = [np.arange(self.seg_offsets[s], self.seg_offsets[s + 1])
+                 for s in self.seg_ids[self.ray_offsets[r]:self.ray_offsets[r + 1]]]
+        if not parts:
+            return np.zeros(0, dtype=np.int64)
+        return np.concatenate(parts)
+
+    def ray_segments(self, r: int) -> np.ndarray:
+        return self.seg_ids[self.ray_offsets[r]:self.ray_offsets[r + 1]]
+
+
+def _directions(keys: np.ndarray) -> np.ndarray:
+    n = keys.shape[0]
+    d = np.zeros((n, 3), dtype=np.float64)
+    d[:, 2] = 1.0
+    todo = np.arange(n)
+    for j in range(DIR_TRIES):
+        if todo.size == 0:
+            break
+        k = keys[todo]
+        v = np.stack([2.0 * u01(draw(k, 16 + 3 * j + c)) - 1.0 for c in range(3)], axis=1)
+        r2 = (v * v).sum(axis=1)
+        ok = (r2 > 1e-12) & (r2 <= 1.0)
+        sel = todo[ok]
+        d[sel] = v[ok] / np.sqrt(r2[ok])[:, None]
+        todo = todo[~ok]
+    return d
+
+
+def _gen_ray_major(w: Workload, rays: np.ndarray):
+    """Samples of `rays` in ray-major order plus per-sample box tags."""
+    rays = np.asarray(rays, dtype=np.int64)
+    keys = ray_keys(w.seed, rays)
+    R = rays.shape[0]
+    o = np.stack([2.0 * u01(draw(keys, c)) - 1.0 for c in range(3)], axis=1)
+    span = np.uint64(w.n_max - w.n_min + 1)
+    cnt = (np.int64(w.n_min) + (((draw(keys, 3) >> _S32) * span) >> _S32).astype(np.int64))
+    u_start = u01(draw(keys, 4))
+    d = _directions(keys)
+
+    off = np.zeros(R + 1, dtype=np.int64)
+    np.cumsum(cnt, out=off[1:])
+    n = int(off[-1])
+    ray_of = np.repeat(np.arange(R, dtype=np.int64), cnt)
+    idx = np.arange(n, dtype=np.int64) - off[ray_of]
+    sk = keys[ray_of]
+    base = np.uint64(RAY_SLOTS) + idx.astype(np.uint64) * np.uint64(SAMPLE_STRIDE)
+
+    width = -w.width_mean * np.log(u01_open0(draw(sk, base + np.uint64(0))))
+    u1 = u01_open0(draw(sk, base + np.uint64(1)))
+    u2 = u01(draw(sk, base + np.uint64(2)))
+    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    sigma = np.exp(w.sigma_mu + w.sigma_s * z)
+    if w.zero_frac > 0.0:
+        sigma[u01(draw(sk, base + np.uint64(3))) < w.zero_frac] = 0.0
+    rgb = np.stack([u01(draw(sk, base + np.uint64(4 + c))) for c in range(3)], axis=1)
+    del sk, base, u1, u2, z
+
+    # Per-ray width sums and starts; positions by a sequential per-ray sum.
+    nmax = int(cnt.max()) if R else 0
+    pad = np.zeros((R, nmax), dtype=np.float64)
+    pad[ray_of, idx] = width
+    tot = np.cumsum(pad, axis=1)[:, -1] if nmax else np.zeros(R)
+    scale = np.where(tot > w.t_far, w.t_far / np.where(tot > 0, tot, 1.0), 1.0)
+    pad *= scale[:, None]
+    tot = np.cumsum(pad, axis=1)[:, -1] if nmax else np.zeros(R)
+    s0 = u_start * np.maximum(w.t_far - tot, 0.0)
+    # Sample i ends at s0 + (delta_0 + ... + delta_i), summed left to right, and
+    # starts where sample i-1 ends, so consecutive intervals share an end point.
+    pad[:, 0] += s0
+    edges = np.cumsum(pad, axis=1)
+    del pad
+    t_end64 = edges[ray_of, idx]
+    t_start64 = s0[ray_of].copy()
+    inner = idx > 0
+    t_start64[inner] = edges[ray_of[inner], idx[inner] - 1]
+    del edges
+    t_start = t_start64.astype(np.float32)
+    t_end = t_end64.astype(np.float32)
+
+    # Box tag of each sample from its midpoint (computed from the stored f32 ends).
+    mid = 0.5 * (t_start.astype(np.float64) + t_end.astype(np.float64))
+    p = o[ray_of] + mid[:, None] * d[ray_of]
+    g = np.array(w.grid, dtype=np.int64)
+    cell = np.clip(np.floor((p + 1.0) * 0.5 * g).astype(np.int64), 0, g - 1)
+    box = (cell[:, 0] + g[0] * (cell[:, 1] + g[1] * cell[:, 2])).astype(np.int32)
+    return dict(sigma=sigma.astype(np.float32), rgb=rgb.astype(np.float32),
+                t_start=t_start, t_end=t_end, box=box, off=off, ray_of=ray_of)
+
+
+def generate(w: Workload, rays: Optional[Sequence[int]] = None,
+             chunk: int = 32768) -> Batch:
+    """Generate the rays `rays` (default: all of w) and pack them region-major."""
+    if rays is None:
+        rays = np.arange(w.n_rays, dtype=np.int64)
+    rays = np.asarray(rays, dtype=np.int64)
+    parts = []
+    for c0 in range(0, max(rays.shape[0], 1), chunk):
+        sub = rays[c0:c0 + chunk]
+        if sub.size:
+            parts.append(_gen_ray_major(w, sub))
+    if not parts:
+        z32 = np.zeros(0, np.float32)
+        return Batch(z32, np.zeros((0, 3), np.float32), z32, z32,
+                     np.zeros(1, np.int64), np.zeros(1, np.int64),
+                     np.zeros(0, np.int64), np.zeros(0, np.int32),
+                     np.zeros(0, np.int64), rays, w)
+    sigma = np.concatenate([q["sigma"] for q in parts])
+    rgb = np.concatenate([q["rgb"] for q in parts])
+    t_start = np.concatenate([q["t_start"] for q in parts])
+    t_end = np.concatenate([q["t_end"] for q in parts])
+    box = np.concatenate([q["box"] for q in parts])
+    ray_of, base = [], 0
+    for q in parts:
+        ray_of.append(q["ray_of"] + base)
+        base += q["off"].shape[0] - 1
+    ray_of = np.concatenate(ray_of)
+    del parts
+    return pack(sigma, rgb, t_start, t_end, box, ray_of, rays.shape[0], rays, w)
+
+
+def pack(sigma, rgb, t_start, t_end, box, ray_of, n_rays, rays=None, w=None) -> Batch:
+    """Cut ray-major samples into segments (runs of one box) and pack region-major."""
+    n = sigma.shape[0]
+    head = np.ones(n, dtype=bool)
+    if n > 1:
+        head[1:] = (box[1:] != box[:-1]) | (ray_of[1:] != ray_of[:-1])
+    seg_start = np.flatnonzero(head)
+    n_seg = seg_start.shape[0]
+    seg_len = np.diff(np.append(seg_start, n))
+    seg_box = box[seg_start]
+    seg_ray = ray_of[seg_start]
+    # Region-major: stable order by box keeps ray order (and t order) inside a box.
+    order = np.argsort(seg_box.astype(np.uint8 if seg_box.size == 0 or seg_box.max() < 256
+                                      else np.int32), kind="stable")
+    new_len = seg_len[order]
+    seg_offsets = np.zeros(n_seg + 1, dtype=np.int64)
+    np.cumsum(new_len, out=seg_offsets[1:])
+    gather = np.repeat(seg_start[order] - seg_offsets[:-1], new_len) + np.arange(n, dtype=np.int64)
+    new_of_old = np.empty(n_seg, dtype=np.int64)
+    new_of_old[order] = np.arange(n_seg, dtype=np.int64)
+    segs_per_ray = np.bincount(seg_ray, minlength=n_rays).astype(np.int64)
+    ray_offsets = np.zeros(n_rays + 1, dtype=np.int64)
+    np.cumsum(segs_per_ray, out=ray_offsets[1:])
+    return Batch(sigma=sigma[gather], rgb=rgb[gather], t_start=t_start[gather],
+                 t_end=t_end[gather], seg_offsets=seg_offsets, ray_offsets=ray_offsets,
+                 seg_ids=new_of_old, seg_box=seg_box[order].astype(np.int32),
+                 seg_ray=seg_ray[order].astype(np.int64),
+                 rays=np.arange(n_rays) if rays is None else np.asarray(rays), workload=w)
+
+
+def serve_workload(width: int, height: int, seed: int) -> Workload:
+    """The serving scene (K=32) at one image size: one ray per pixel."""
+    return replace(WORKLOADS[3], name=f"k32-serve-{width}x{height}", n_rays=width * height,
+                   seed=seed)

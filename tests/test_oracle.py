@@ -1,0 +1,325 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every check compares the oracle with something other than itself: hand-derived
+worked examples (tests/golden), closed forms of the continuous integrals,
+brute-force integration, the paper's sequential Alg. 1/2 loops, algebraic
+identities and finite differences.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import render as O
+from paper_2404_16221_amd import synth
+from tests.conftest import read_golden
+
+LN2 = math.log(2.0)
+
+
+def _split_tuples(sig, rgb, t0, t1, cuts):
+    """Segment tuples of a ray cut at the sample indices `cuts`."""
+    edges = [0] + list(cuts) + [len(sig)]
+    return [O.composite(sig[a:b], rgb[a:b], t0[a:b], t1[a:b]) for a, b in zip(edges[:-1], edges[1:])]
+
+
+def _random_ray(rng, n, zero_frac=0.0, s=1.5):
+    w = rng.exponential(0.02, size=n)
+    if w.sum() > 3.0:
+        w *= 3.0 / w.sum()
+    t0 = np.concatenate([[0.0], np.cumsum(w)[:-1]]) + rng.uniform(0, 3.0 - w.sum())
+    t1 = t0 + w
+    sig = np.exp(rng.normal(0.0, s, size=n))
+    sig[rng.uniform(size=n) < zero_frac] = 0.0
+    rgb = rng.uniform(size=(n, 3))
+    return sig, rgb, t0, t1
+
+
+# ---------------------------------------------------------------- golden
+def test_golden_three_samples():
+    g = read_golden("three_samples_ln2.txt")
+    rgb = np.tile(g["rgb"], (3, 1))
+    ray = O.to_ray_tuple(O.composite(g["sigma"], rgb, g["t_start"], g["t_end"]))
+    np.testing.assert_allclose(ray, g["ray"], rtol=1e-14, atol=1e-15)
+    parts = _split_tuples(g["sigma"], rgb, g["t_start"], g["t_end"], [1])
+    np.testing.assert_allclose(parts[0], g["seg1"], rtol=1e-14, atol=1e-15)
+    np.testing.assert_allclose(parts[1], g["seg2"], rtol=1e-14, atol=1e-15)
+    np.testing.assert_allclose(O.merge(parts), g["ray"], rtol=1e-14, atol=1e-15)
+    ga = np.zeros(7); ga[4] = 1.0
+    gd = np.zeros(7); gd[5] = 1.0
+    ds_a, _ = O.grad_single(g["sigma"], rgb, g["t_start"], g["t_end"], ga)
+    ds_d, _ = O.grad_single(g["sigma"], rgb, g["t_start"], g["t_end"], gd)
+    np.testing.assert_allclose(ds_a, g["dA_dsigma"], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(ds_d, g["dD_dsigma"], rtol=1e-13, atol=1e-15)
+
+
+def test_golden_one_sample():
+    g = read_golden("one_sample.txt")
+    ray = O.to_ray_tuple(O.composite(g["sigma"], g["rgb"].reshape(1, 3), g["t_start"], g["t_end"]))
+    np.testing.assert_allclose(ray, g["ray"], rtol=1e-14, atol=1e-16)
+
+
+# ---------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("sigma", [0.1, 1.0, 7.5])
+def test_constant_density_closed_form(sigma):
+    rng = np.random.default_rng(1)
+    w = rng.uniform(0.001, 0.05, size=97)
+    t0 = 0.3 + np.concatenate([[0.0], np.cumsum(w)[:-1]])
+    t1 = 0.3 + np.cumsum(w)
+    Ltot = t1[-1] - t0[0]
+    c = np.array([0.25, 0.5, 0.75])
+    out = O.composite(np.full(97, sigma), np.tile(c, (97, 1)), t0, t1)
+    assert math.exp(-out[0]) == pytest.approx(math.exp(-sigma * Ltot), rel=1e-13)
+    assert out[4] == pytest.approx(-math.expm1(-sigma * Ltot), rel=1e-13)
+    np.testing.assert_allclose(out[1:4], c * (-math.expm1(-sigma * Ltot)), rtol=1e-13)
+
+
+@pytest.mark.parametrize("sigma,delta,N", [(0.5, 0.03, 100), (3.0, 0.01, 300), (20.0, 0.02, 150)])
+def test_equal_width_depth_series(sigma, delta, N):
+    """Depth with equal widths is an arithmetico-geometric series in r = exp(-sigma delta)."""
+    r = math.exp(-sigma * delta)
+    S1 = r * (1 - N * r ** (N - 1) + (N - 1) * r ** N) / (1 - r) ** 2   # sum i r^i
+    S0 = (1 - r ** N) / (1 - r)                                        # sum r^i
+    D_closed = delta * (1 - r) * (S1 + 0.5 * S0)
+    t0 = np.arange(N) * delta
+    out = O.composite(np.full(N, sigma), np.ones((N, 3)), t0, t0 + delta)
+    assert out[5] == pytest.approx(D_closed, rel=1e-11)
+
+
+def test_quadrature_converges_to_continuous_integrals():
+    """Constant density on [0, Lmax]: depth and distortion tend to their integrals."""
+    sigma, Lmax = 2.0, 1.5
+    e = math.exp(-sigma * Lmax)
+    D_int = (1 - e * (1 + sigma * Lmax)) / sigma
+    L_int = 2 * ((1 - e * (1 + sigma * Lmax)) / sigma - (1 - e) / sigma
+                 + (1 - math.exp(-2 * sigma * Lmax)) / (2 * sigma))
+    errs = []
+    for N in (50, 100, 200, 400):
+        t0 = np.linspace(0, Lmax, N + 1)[:-1]
+        t1 = np.linspace(0, Lmax, N + 1)[1:]
+        out = O.composite(np.full(N, sigma), np.ones((N, 3)), t0, t1)
+        errs.append((abs(out[5] - D_int), abs(out[6] - L_int)))
+    errs = np.array(errs)
+    # second order in the step for depth (midpoint rule), at least first order for L
+    assert np.all(errs[:-1, 0] / errs[1:, 0] > 3.5)
+    assert np.all(errs[:-1, 1] / errs[1:, 1] > 1.9)
+    assert errs[-1, 0] < 1e-5 and errs[-1, 1] < 1e-3
+
+
+def test_distortion_is_double_integral_of_step_weights():
+    """Pairwise form = prefix form = brute-force double integral of piecewise-constant weights."""
+    rng = np.random.default_rng(2)
+    sig, rgb, t0, t1 = _random_ray(rng, 9)
+    t0 = t0.copy(); t1 = t1.copy()
+    t1[3] = t0[3] + 0.5 * (t1[3] - t0[3])  # a gap: intervals need not touch
+    delta, m, tau, alpha, T, w = O.quadrature(sig, t0, t1)
+    Lp = O.distortion_pairwise(w, m, delta)
+    Lq = O.distortion_prefix(w, m, delta)
+    sub = 400
+    us, ws = [], []
+    for i in range(len(w)):
+        edges = np.linspace(t0[i], t1[i], sub + 1)
+        us.append(0.5 * (edges[1:] + edges[:-1]))
+        ws.append(np.full(sub, w[i] / sub))
+    u = np.concatenate(us); wt = np.concatenate(ws)
+    brute = float(wt @ np.abs(u[:, None] - u[None, :]) @ wt)
+    assert Lp == pytest.approx(Lq, rel=1e-13)
+    assert Lp == pytest.approx(brute, rel=1e-4)
+
+
+# ---------------------------------------------------------------- equivalence and algebra
+def test_any_split_merges_to_single_pass():
+    rng = np.random.default_rng(3)
+    for trial in range(40):
+        n = int(rng.integers(1, 60))
+        sig, rgb, t0, t1 = _random_ray(rng, n, zero_frac=0.2, s=2.0)
+        single = O.to_ray_tuple(O.composite(sig, rgb, t0, t1))
+        k = int(rng.integers(0, n))
+        cuts = sorted(rng.choice(np.arange(1, n), size=min(k, n - 1), replace=False)) if n > 1 else []
+        np.testing.assert_allclose(O.merge(_split_tuples(sig, rgb, t0, t1, cuts)), single,
+                                   rtol=1e-12, atol=1e-14)
+        per_sample = _split_tuples(sig, rgb, t0, t1, list(range(1, n)))
+        np.testing.assert_allclose(O.merge(per_sample), single, rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(O.merge(_split_tuples(sig, rgb, t0, t1, [])), single,
+                                   rtol=1e-14, atol=1e-16)
+
+
+def _as_seg(ray_tuple):
+    out = np.array(ray_tuple, copy=True)
+    out[0] = -math.log(out[0])
+    return out
+
+
+def test_merge_associative_with_identity():
+    rng = np.random.default_rng(4)
+    sig, rgb, t0, t1 = _random_ray(rng, 30)
+    x1, x2, x3 = _split_tuples(sig, rgb, t0, t1, [8, 19])
+    left = O.merge([_as_seg(O.merge([x1, x2])), x3])
+    right = O.merge([x1, _as_seg(O.merge([x2, x3]))])
+    flat = O.merge([x1, x2, x3])
+    np.testing.assert_allclose(left, flat, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(right, flat, rtol=1e-12, atol=1e-14)
+    e = np.zeros(7)
+    np.testing.assert_allclose(O.merge([e, x1, e, x2, e, x3, e]), flat, rtol=1e-14, atol=1e-16)
+
+
+def test_opacity_plus_transmittance_and_shift_invariance():
+    rng = np.random.default_rng(5)
+    sig, rgb, t0, t1 = _random_ray(rng, 50)
+    a = O.to_ray_tuple(O.composite(sig, rgb, t0, t1))
+    assert a[4] + a[0] == pytest.approx(1.0, abs=1e-14)
+    c = 0.37
+    b = O.to_ray_tuple(O.composite(sig, rgb, t0 + c, t1 + c))
+    np.testing.assert_allclose(b[:5], a[:5], rtol=1e-12)
+    assert b[5] == pytest.approx(a[5] + c * a[4], rel=1e-12)
+    assert b[6] == pytest.approx(a[6], rel=1e-10)
+
+
+def _alg1_alg2(parts):
+    """The paper's per-GPU loops (App. A.2, Alg. 1 and 2) over the ray's segments
+    in the order I, with Eq. 7/8's factor 2 and the s-th segment's own A, D."""
+    T, C, A, D, L = 1.0, np.zeros(3), 0.0, 0.0, 0.0
+    for x in parts:
+        Ti, Ci, Ai, Di, Li = math.exp(-x[0]), x[1:4], x[4], x[5], x[6]
+        S = Di * A - Ai * D
+        L += T * T * Li + 2.0 * T * S
+        C = C + T * Ci
+        A += T * Ai
+        D += T * Di
+        T *= Ti
+    return np.array([T, *C, A, D, L])
+
+
+def test_sequential_algorithm_loops_match_merge():
+    rng = np.random.default_rng(6)
+    for trial in range(20):
+        n = int(rng.integers(2, 80))
+        sig, rgb, t0, t1 = _random_ray(rng, n, s=2.0)
+        cuts = sorted(rng.choice(np.arange(1, n), size=min(5, n - 1), replace=False))
+        parts = _split_tuples(sig, rgb, t0, t1, cuts)
+        np.testing.assert_allclose(_alg1_alg2(parts), O.merge(parts), rtol=1e-12, atol=1e-14)
+
+
+def test_printed_alg2_without_factor_two_differs():
+    """Alg. 2 as printed accumulates T*S, not 2*T*S; only Eq. 7's form matches one pass."""
+    rng = np.random.default_rng(7)
+    sig, rgb, t0, t1 = _random_ray(rng, 40)
+    parts = _split_tuples(sig, rgb, t0, t1, [13, 27])
+    single = O.to_ray_tuple(O.composite(sig, rgb, t0, t1))
+    T, A, D, L = 1.0, 0.0, 0.0, 0.0
+    for x in parts:
+        S = x[5] * A - x[4] * D
+        L += T * T * x[6] + T * S
+        A += T * x[4]; D += T * x[5]; T *= math.exp(-x[0])
+    assert abs(L - single[6]) > 1e-3
+    assert O.merge(parts)[6] == pytest.approx(single[6], rel=1e-12)
+
+
+# ---------------------------------------------------------------- edge cases
+def test_edge_cases():
+    e = O.merge([])
+    np.testing.assert_array_equal(e, [1, 0, 0, 0, 0, 0, 0])
+    np.testing.assert_array_equal(O.composite([], np.zeros((0, 3)), [], []), np.zeros(7))
+    rng = np.random.default_rng(8)
+    sig, rgb, t0, t1 = _random_ray(rng, 20)
+    z = O.to_ray_tuple(O.composite(np.zeros(20), rgb, t0, t1))
+    np.testing.assert_array_equal(z, [1, 0, 0, 0, 0, 0, 0])
+    one = O.composite([2.0], [[0.1, 0.2, 0.3]], [0.5], [0.75])
+    a = -math.expm1(-0.5)
+    assert one[6] == pytest.approx(a * a * 0.25 / 3.0, rel=1e-14)
+    s2 = sig.copy(); s2[0] = 1e6
+    big = O.to_ray_tuple(O.composite(s2, rgb, t0, t1))
+    np.testing.assert_allclose(big[1:4], rgb[0], rtol=1e-12)
+    assert big[5] == pytest.approx(big[4] * 0.5 * (t0[0] + t1[0]), rel=1e-12)
+    # zero-width intervals contribute nothing
+    t1z = t1.copy(); t1z[5] = t0[5]
+    t0z = t0.copy()
+    keep = np.ones(20, bool); keep[5] = False
+    np.testing.assert_allclose(O.composite(sig, rgb, t0z, t1z)[[0, 1, 2, 3, 4, 5]],
+                               O.composite(sig[keep], rgb[keep], t0z[keep], t1z[keep])[[0, 1, 2, 3, 4, 5]],
+                               rtol=1e-13)
+    # large optical depth: T underflows double only past ~745
+    deep = O.composite(np.full(10, 200.0), rgb[:10], np.arange(10) * 0.1, np.arange(10) * 0.1 + 0.1)
+    assert deep[0] == pytest.approx(200.0, rel=1e-14) and deep[4] == pytest.approx(1.0)
+
+
+# ---------------------------------------------------------------- gradients
+def _central_fd(f, x, h_rel=1e-6):
+    g = np.zeros_like(x)
+    for i in range(x.size):
+        h = h_rel * max(1.0, abs(x.flat[i]))
+        xp = x.copy(); xp.flat[i] += h
+        xm = x.copy(); xm.flat[i] -= h
+        g.flat[i] = (f(xp) - f(xm)) / (2 * h)
+    return g
+
+
+def test_gradients_match_finite_differences():
+    rng = np.random.default_rng(9)
+    sig, rgb, t0, t1 = _random_ray(rng, 12)
+    g_ray = rng.normal(size=7)
+    ds, dc = O.grad_single(sig, rgb, t0, t1, g_ray)
+    f_s = lambda s: float(O.to_ray_tuple(O.composite(s, rgb, t0, t1)) @ g_ray)
+    f_c = lambda c: float(O.to_ray_tuple(O.composite(sig, c.reshape(-1, 3), t0, t1)) @ g_ray)
+    np.testing.assert_allclose(ds, _central_fd(f_s, sig), rtol=1e-6, atol=1e-8)
+    np.testing.assert_allclose(dc, _central_fd(f_c, rgb), rtol=1e-6, atol=1e-8)
+    parts = _split_tuples(sig, rgb, t0, t1, [4, 9])
+    gk = O.merge_bwd(parts, g_ray)
+    for k in range(3):
+        def f_k(xk, k=k):
+            q = [p.copy() for p in parts]; q[k] = xk
+            return float(O.merge(q) @ g_ray)
+        np.testing.assert_allclose(gk[k], _central_fd(f_k, parts[k].copy()), rtol=1e-6, atol=1e-8)
+
+
+def test_gradient_formulas_match_autodiff():
+    rng = np.random.default_rng(10)
+    for trial in range(10):
+        n = int(rng.integers(1, 50))
+        sig, rgb, t0, t1 = _random_ray(rng, n, zero_frac=0.2, s=2.0)
+        g = rng.normal(size=7)
+        a = O.grad_composite(sig, rgb, t0, t1, g)
+        b = O.grad_composite_formula(sig, rgb, t0, t1, g)
+        scale = max(1e-300, np.abs(a[0]).max())
+        np.testing.assert_allclose(a[0], b[0], rtol=1e-10, atol=1e-12 * scale)
+        np.testing.assert_allclose(a[1], b[1], rtol=1e-12, atol=1e-15)
+        cuts = sorted(rng.choice(np.arange(1, n), size=min(4, n - 1), replace=False)) if n > 1 else []
+        parts = _split_tuples(sig, rgb, t0, t1, cuts)
+        np.testing.assert_allclose(O.merge_bwd(parts, g), O.merge_bwd_formula(parts, g),
+                                   rtol=1e-10, atol=1e-12)
+
+
+def test_torch_gradcheck_of_definitions():
+    rng = np.random.default_rng(11)
+    sig, rgb, t0, t1 = _random_ray(rng, 8)
+    s = torch.tensor(sig, dtype=torch.float64, requires_grad=True)
+    c = torch.tensor(rgb, dtype=torch.float64, requires_grad=True)
+    a, b = torch.tensor(t0), torch.tensor(t1)
+    assert torch.autograd.gradcheck(lambda s_, c_: O._composite_t(s_, c_, a, b), (s, c))
+    x = torch.tensor(np.array(_split_tuples(sig, rgb, t0, t1, [3, 5])), requires_grad=True)
+    assert torch.autograd.gradcheck(O._merge_t, (x,))
+
+
+def test_partitioned_backward_equals_single_pass_backward():
+    b = synth.generate(synth.WORKLOADS[1], rays=np.arange(60))
+    g = np.random.default_rng(12).normal(size=(7, b.n_rays))
+    _, _, idx, ds, dc = O.backward_partitioned(b.sigma, b.rgb, b.t_start, b.t_end, b.seg_offsets,
+                                               b.ray_offsets, b.seg_ids, g)
+    pos = np.empty(b.n, np.int64); pos[idx] = np.arange(idx.size)
+    for r in range(b.n_rays):
+        ii = b.ray_sample_index(r)
+        s1, c1 = O.grad_single(b.sigma[ii], b.rgb[ii], b.t_start[ii], b.t_end[ii], g[:, r])
+        np.testing.assert_allclose(ds[pos[ii]], s1, rtol=1e-10, atol=1e-13)
+        np.testing.assert_allclose(dc[pos[ii]], c1, rtol=1e-10, atol=1e-13)
+
+
+# ---------------------------------------------------------------- generated batches
+def test_batch_partitioned_equals_single_on_generated_rays():
+    for cfg in (0, 1, 2):
+        b = synth.generate(synth.WORKLOADS[cfg], rays=np.arange(40))
+        _, part = O.render_rays_partitioned(b.sigma, b.rgb, b.t_start, b.t_end, b.seg_offsets,
+                                            b.ray_offsets, b.seg_ids)
+        single = O.render_rays_single(b.sigma, b.rgb, b.t_start, b.t_end, b.seg_offsets,
+                                      b.ray_offsets, b.seg_ids)
+        np.testing.assert_allclose(part, single, rtol=1e-11, atol=1e-14)

@@ -1,0 +1,63 @@
+"""Host input generator: determinism, regeneration of single rays, packing invariants."""
+import numpy as np
+
+from paper_2404_16221_amd import synth
+
+
+def _check_packing(b):
+    so, ro, ids = b.seg_offsets, b.ray_offsets, b.seg_ids
+    assert so[0] == 0 and so[-1] == b.n and np.all(np.diff(so) >= 1)
+    assert ro[0] == 0 and ro[-1] == b.n_seg and np.all(np.diff(ro) >= 1)
+    assert np.array_equal(np.sort(ids), np.arange(b.n_seg))
+    # region-major: box ids non-decreasing over the packed segments
+    assert np.all(np.diff(b.seg_box) >= 0)
+    for r in range(0, b.n_rays, max(1, b.n_rays // 50)):
+        segs = b.ray_segments(r)
+        assert np.all(b.seg_ray[segs] == r)
+        assert len(set(b.seg_box[segs].tolist())) == len(segs)  # one run per box
+        idx = b.ray_sample_index(r)
+        assert np.all(b.t_end[idx] >= b.t_start[idx])
+        assert np.all(b.t_start[idx][1:] >= b.t_end[idx][:-1])
+        assert np.all(b.t_start[idx][1:] == b.t_end[idx][:-1])  # contiguous intervals
+
+
+def test_generator_deterministic_and_regenerable():
+    w = synth.WORKLOADS[1]
+    a = synth.generate(w, rays=np.arange(300))
+    b = synth.generate(w, rays=np.arange(300), chunk=77)
+    for f in ("sigma", "rgb", "t_start", "t_end", "seg_offsets", "ray_offsets", "seg_ids"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+    one = synth.generate(w, rays=[123])
+    idx = a.ray_sample_index(123)
+    assert np.array_equal(one.sigma, a.sigma[idx])
+    assert np.array_equal(one.t_start, a.t_start[idx])
+    assert np.array_equal(one.rgb, a.rgb[idx])
+
+
+def test_packing_invariants_all_workloads():
+    for cfg in (0, 1, 2, 3, 4):
+        b = synth.generate(synth.WORKLOADS[cfg], rays=np.arange(400))
+        _check_packing(b)
+        w = synth.WORKLOADS[cfg]
+        counts = np.array([b.ray_sample_index(r).size for r in range(b.n_rays)])
+        assert counts.min() >= w.n_min and counts.max() <= w.n_max
+        assert b.seg_box.max() < w.k
+        assert np.all(b.t_end <= np.float32(3.0) * (1 + 1e-6))
+        if w.zero_frac:
+            assert abs((b.sigma == 0).mean() - w.zero_frac) < 0.02
+
+
+def test_plain_form_has_one_segment_per_ray():
+    w = synth.WORKLOADS[2]
+    p = synth.generate(w.plain(), rays=np.arange(100))
+    k = synth.generate(w, rays=np.arange(100))
+    assert p.n_seg == 100 and np.array_equal(p.seg_ids, np.arange(100))
+    for r in range(100):
+        assert np.array_equal(p.sigma[p.ray_sample_index(r)], k.sigma[k.ray_sample_index(r)])
+
+
+def test_segment_statistics_match_workload_shape():
+    b = synth.generate(synth.WORKLOADS[2], rays=np.arange(4000))
+    segs_per_ray = b.n_seg / b.n_rays
+    assert 2.6 < segs_per_ray < 3.3
+    assert np.diff(b.ray_offsets).max() <= 6
