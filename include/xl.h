@@ -1,0 +1,159 @@
+/*
+ * xl.h -- C ABI of the partitioned volume renderer (NeRF-XL, arXiv 2404.16221)
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The method (Sec. 4.3): each of K disjoint axis-aligned regions composites
+ * the samples it owns along every ray into a per-segment partial tuple; the
+ * tuples of one ray are then merged front to back with an exclusive product of
+ * the segment transmittances (Eq. 3-8).  The merge equals single-pass
+ * rendering exactly (App. B.1).  Here the K regions are K shares of one GPU.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked "device" are HIP device memory owned by the caller; the
+ *     library never frees or retains them.  Sample arrays must be 16-byte
+ *     aligned.  `stream` is a hipStream_t passed as void* (NULL = null stream).
+ *   - Compute calls are asynchronous on `stream`, allocate nothing, and never
+ *     synchronise the device.  Argument errors are detected on the host before
+ *     anything is launched.
+ *   - Return value: XL_OK (0) or a negative error code; xl_last_error() gives
+ *     a message for the calling thread.
+ *   - Sample layout (the paper's "distribute ray samples among GPUs based on
+ *     the bounding box of the tiles", Sec. 4.2): samples of all regions packed
+ *     region-major; segment s owns samples [seg_offsets[s], seg_offsets[s+1]),
+ *     which belong to one ray and one region, sorted by t, with
+ *     non-overlapping intervals [t_start, t_end].  Density sigma >= 0 and
+ *     finite; colour in any finite range.
+ *   - Segment tuple (the per-region "locally integrated data", App. A.2):
+ *     seg_out is structure-of-arrays float32 [7][n_seg]:
+ *       0 tau = sum sigma_i delta_i  (segment transmittance is exp(-tau))
+ *       1-3 C = sum w_i c_i, 4 A = sum w_i, 5 D = sum w_i m_i (unnormalised),
+ *       6 L = sum_ij w_i w_j |m_i - m_j| + 1/3 sum_i w_i^2 delta_i,
+ *     with delta_i = t_end - t_start, m_i the interval midpoint, alpha_i =
+ *     1 - exp(-sigma_i delta_i), w_i = alpha_i prod_{j<i} (1 - alpha_j) taken
+ *     inside the segment (transmittance starts at 1).  An empty segment has
+ *     the identity tuple (all zeros).
+ *   - Ray tuple: ray_out is float32 [7][n_rays] = (T, r, g, b, A, D, L) of the
+ *     whole ray (Eq. 3-7); a ray with no segments gives (1, 0, ..., 0).
+ */
+#ifndef XL_H
+#define XL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define XL_OK 0
+#define XL_PENDING 1
+#define XL_EINVAL (-1)
+#define XL_ENOMEM (-2)
+#define XL_EHIP (-3)
+#define XL_EAGAIN (-4)
+#define XL_EFAULT (-5)
+
+/* Storage type of sigma and rgb (and of their gradients).  t_start/t_end are
+ * always float32; accumulation is always float32 or wider. */
+#define XL_F32 0
+#define XL_BF16 1
+#define XL_F16 2
+
+/* xl_merge_* flags. */
+#define XL_MERGE_FP64 1 /* cross-segment prefix sums and products in float64 */
+
+typedef struct xl_samples {
+  int32_t dtype;        /* XL_F32, XL_BF16 or XL_F16 */
+  const void* sigma;    /* device [n] densities */
+  const void* rgb;      /* device [n][3] colours */
+  const float* t_start; /* device [n] interval starts */
+  const float* t_end;   /* device [n] interval ends */
+  int64_t n;            /* number of samples (>= 0) */
+} xl_samples;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int xl_version(void);
+
+/* Message describing the last error on this thread ("" if none). */
+const char* xl_last_error(void);
+
+/* Bytes of device workspace that xl_render_segments_fwd fills and
+ * xl_render_segments_bwd reads for n samples (per-tile partial tuples and
+ * carries; about 0.4 byte per sample). */
+size_t xl_segments_workspace_bytes(int64_t n);
+
+/*
+ * Per-segment composite, forward (Sec. 4.3: "reduce the per-sample data into
+ * per-tile data in parallel within each GPU"; Eq. 1-2 evaluated per segment).
+ *   s            samples (device arrays, see conventions)
+ *   seg_offsets  device int64 [n_seg + 1], non-decreasing, seg_offsets[0] = 0,
+ *                seg_offsets[n_seg] = s->n
+ *   seg_out      device float32 [7][n_seg], written (every segment)
+ *   workspace    device, >= xl_segments_workspace_bytes(s->n) bytes, written;
+ *                keep it unchanged for the matching backward call
+ * Errors: XL_EINVAL for null pointers, bad dtype, negative sizes, misaligned
+ * sample arrays or a workspace that is too small; XL_EHIP if a launch fails.
+ */
+int xl_render_segments_fwd(const xl_samples* s, const int64_t* seg_offsets, int64_t n_seg,
+                           float* seg_out, void* workspace, size_t workspace_bytes,
+                           void* stream);
+
+/*
+ * Per-segment composite, backward.  Given grad_seg = dl/d(seg tuple) (device
+ * float32 [7][n_seg], component 0 is dl/dtau), writes dl/dsigma (device [n])
+ * and dl/drgb (device [n][3]) in the storage dtype of `s`, overwriting them.
+ * Transmittance is recomputed (forward and reverse wave scans); nothing per
+ * sample is kept from the forward.  `workspace` must hold what the forward
+ * call on the same inputs wrote.  Errors as for the forward.
+ */
+int xl_render_segments_bwd(const xl_samples* s, const int64_t* seg_offsets, int64_t n_seg,
+                           const void* workspace, size_t workspace_bytes,
+                           const float* grad_seg, void* grad_sigma, void* grad_rgb,
+                           void* stream);
+
+/*
+ * Merge of segment tuples in ray order (Eq. 3-8; Alg. 1 and 2 of App. A.2
+ * with Eq. 7's factor 2 and each segment's own A, D in the cross term).
+ *   seg_out      device float32 [7][n_seg] from xl_render_segments_fwd
+ *   ray_offsets  device int64 [n_rays + 1]; ray r's segments are
+ *                seg_ids[ray_offsets[r] .. ray_offsets[r+1]) front to back
+ *                (the paper's ordered index list I)
+ *   seg_ids      device int64, values in [0, n_seg)
+ *   ray_out      device float32 [7][n_rays], written
+ *   flags        0 or XL_MERGE_FP64
+ */
+int xl_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
+                 const int64_t* seg_ids, int64_t n_rays, float* ray_out, int32_t flags,
+                 void* stream);
+
+/*
+ * Merge, backward: grad_ray = dl/d(T, r, g, b, A, D, L) (device float32
+ * [7][n_rays]) -> grad_seg = dl/d(tau, r, g, b, A, D, L) of every segment
+ * listed in seg_ids (device float32 [7][n_seg], overwritten there; entries of
+ * segments that no ray lists are left untouched).  Each segment is listed by
+ * at most one ray.  Exclusive prefix and suffix folds per ray; the paper's
+ * rule that each region differentiates only through its own tuple (Sec. 4.2,
+ * App. A.2) is exactly this per-segment Jacobian.
+ */
+int xl_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
+                 const int64_t* seg_ids, int64_t n_rays, const float* grad_ray,
+                 float* grad_seg, int32_t flags, void* stream);
+
+/*
+ * Input validation (synchronous; for debugging and tests).  Checks on the
+ * device that seg_offsets is non-decreasing from 0 to n, every interval has
+ * t_end >= t_start, intervals inside a segment are sorted and disjoint,
+ * ray_offsets is non-decreasing from 0 to n_seg and seg_ids are in range.
+ * Returns XL_OK or XL_EINVAL with a message naming the first failed check.
+ * ray_offsets/seg_ids may be NULL (then n_rays is ignored).
+ */
+int xl_check_inputs(const xl_samples* s, const int64_t* seg_offsets, int64_t n_seg,
+                    const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                    void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XL_H */

@@ -1,0 +1,192 @@
+"""ctypes binding of libxl.so (include/xl.h).  Argument marshalling only.
+
+Every function has the name of the C entry point it calls.  Tensors must live
+on the GPU, be contiguous and have the documented dtype; the call is enqueued
+on torch's current stream.  There is no fallback: if libxl.so is missing or a
+call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxl.so")
+
+XL_OK, XL_PENDING = 0, 1
+XL_EINVAL, XL_ENOMEM, XL_EHIP, XL_EAGAIN, XL_EFAULT = -1, -2, -3, -4, -5
+XL_F32, XL_BF16, XL_F16 = 0, 1, 2
+XL_MERGE_FP64 = 1
+DTYPES = {torch.float32: XL_F32, torch.bfloat16: XL_BF16, torch.float16: XL_F16}
+TORCH_DTYPES = {v: k for k, v in DTYPES.items()}
+TUPLE = 7
+
+_c = ctypes
+_vp, _i64, _i32, _sz = _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_size_t
+
+
+class XLSamples(_c.Structure):
+    _fields_ = [("dtype", _i32), ("sigma", _vp), ("rgb", _vp), ("t_start", _vp),
+                ("t_end", _vp), ("n", _i64)]
+
+
+class XLError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libxl error {code}: {msg}")
+        self.code = code
+
+
+_LIB: Optional[ctypes.CDLL] = None
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "xl_version": (_c.c_int, []),
+    "xl_last_error": (_c.c_char_p, []),
+    "xl_segments_workspace_bytes": (_sz, [_i64]),
+    "xl_render_segments_fwd": (_c.c_int, [_c.POINTER(XLSamples), _vp, _i64, _vp, _vp, _sz, _vp]),
+    "xl_render_segments_bwd": (_c.c_int, [_c.POINTER(XLSamples), _vp, _i64, _vp, _sz, _vp, _vp,
+                                          _vp, _vp]),
+    "xl_merge_fwd": (_c.c_int, [_vp, _i64, _vp, _vp, _i64, _vp, _i32, _vp]),
+    "xl_merge_bwd": (_c.c_int, [_vp, _i64, _vp, _vp, _i64, _vp, _vp, _i32, _vp]),
+    "xl_check_inputs": (_c.c_int, [_c.POINTER(XLSamples), _vp, _i64, _vp, _vp, _i64, _vp]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libxl.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2404_16221_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(rc: int) -> None:
+    if rc != XL_OK:
+        raise XLError(rc, lib().xl_last_error().decode())
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    return t.data_ptr() if t.numel() else 0
+
+
+def samples(sigma, rgb, t_start, t_end) -> XLSamples:
+    if sigma.dtype not in DTYPES:
+        raise ValueError(f"unsupported storage dtype {sigma.dtype}")
+    if rgb.dtype != sigma.dtype:
+        raise ValueError("sigma and rgb must share the storage dtype")
+    n = sigma.shape[0]
+    if rgb.shape != (n, 3) or t_start.shape != (n,) or t_end.shape != (n,):
+        raise ValueError("shapes must be sigma[n], rgb[n,3], t_start[n], t_end[n]")
+    return XLSamples(DTYPES[sigma.dtype], _dev(sigma, "sigma"), _dev(rgb, "rgb"),
+                     _dev(t_start, "t_start", torch.float32), _dev(t_end, "t_end", torch.float32), n)
+
+
+def xl_version() -> int:
+    return lib().xl_version()
+
+
+def xl_segments_workspace_bytes(n: int) -> int:
+    return lib().xl_segments_workspace_bytes(n)
+
+
+def xl_render_segments_fwd(sigma, rgb, t_start, t_end, seg_offsets, seg_out=None,
+                           workspace=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """seg_out[7, n_seg] and the workspace the backward needs."""
+    s = samples(sigma, rgb, t_start, t_end)
+    n_seg = seg_offsets.shape[0] - 1
+    dev = sigma.device
+    if seg_out is None:
+        seg_out = torch.empty((TUPLE, n_seg), dtype=torch.float32, device=dev)
+    wsb = xl_segments_workspace_bytes(s.n)
+    if workspace is None:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    _check(lib().xl_render_segments_fwd(ctypes.byref(s), _dev(seg_offsets, "seg_offsets", torch.int64),
+                                        n_seg, _dev(seg_out, "seg_out", torch.float32),
+                                        _dev(workspace, "workspace"), workspace.numel(), _stream()))
+    return seg_out, workspace
+
+
+def xl_render_segments_bwd(sigma, rgb, t_start, t_end, seg_offsets, workspace, grad_seg,
+                           grad_sigma=None, grad_rgb=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """(dl/dsigma [n], dl/drgb [n, 3]) in the storage dtype."""
+    s = samples(sigma, rgb, t_start, t_end)
+    n_seg = seg_offsets.shape[0] - 1
+    if grad_sigma is None:
+        grad_sigma = torch.empty_like(sigma)
+    if grad_rgb is None:
+        grad_rgb = torch.empty_like(rgb)
+    _check(lib().xl_render_segments_bwd(ctypes.byref(s), _dev(seg_offsets, "seg_offsets", torch.int64),
+                                        n_seg, _dev(workspace, "workspace"), workspace.numel(),
+                                        _dev(grad_seg, "grad_seg", torch.float32),
+                                        _dev(grad_sigma, "grad_sigma", sigma.dtype),
+                                        _dev(grad_rgb, "grad_rgb", sigma.dtype), _stream()))
+    return grad_sigma, grad_rgb
+
+
+def _check_ids(seg_out, seg_ids):
+    if seg_ids.shape != (seg_out.shape[1],):
+        raise ValueError("seg_ids must list every segment once: shape (n_seg,)")
+
+
+def xl_merge_fwd(seg_out, ray_offsets, seg_ids, ray_out=None, fp64: bool = False) -> torch.Tensor:
+    """ray_out[7, n_rays] = (T, r, g, b, A, D, L)."""
+    _check_ids(seg_out, seg_ids)
+    n_seg = seg_out.shape[1]
+    n_rays = ray_offsets.shape[0] - 1
+    if ray_out is None:
+        ray_out = torch.empty((TUPLE, n_rays), dtype=torch.float32, device=seg_out.device)
+    _check(lib().xl_merge_fwd(_dev(seg_out, "seg_out", torch.float32), n_seg,
+                              _dev(ray_offsets, "ray_offsets", torch.int64),
+                              _dev(seg_ids, "seg_ids", torch.int64), n_rays,
+                              _dev(ray_out, "ray_out", torch.float32),
+                              XL_MERGE_FP64 if fp64 else 0, _stream()))
+    return ray_out
+
+
+def xl_merge_bwd(seg_out, ray_offsets, seg_ids, grad_ray, grad_seg=None,
+                 fp64: bool = False) -> torch.Tensor:
+    """grad_seg[7, n_seg] = dl/d(tau, r, g, b, A, D, L) of each listed segment."""
+    _check_ids(seg_out, seg_ids)
+    n_seg = seg_out.shape[1]
+    n_rays = ray_offsets.shape[0] - 1
+    if grad_seg is None:
+        grad_seg = torch.zeros((TUPLE, n_seg), dtype=torch.float32, device=seg_out.device)
+    _check(lib().xl_merge_bwd(_dev(seg_out, "seg_out", torch.float32), n_seg,
+                              _dev(ray_offsets, "ray_offsets", torch.int64),
+                              _dev(seg_ids, "seg_ids", torch.int64), n_rays,
+                              _dev(grad_ray, "grad_ray", torch.float32),
+                              _dev(grad_seg, "grad_seg", torch.float32),
+                              XL_MERGE_FP64 if fp64 else 0, _stream()))
+    return grad_seg
+
+
+def xl_check_inputs(sigma, rgb, t_start, t_end, seg_offsets, ray_offsets=None,
+                    seg_ids=None) -> None:
+    s = samples(sigma, rgb, t_start, t_end)
+    n_seg = seg_offsets.shape[0] - 1
+    n_rays = 0 if ray_offsets is None else ray_offsets.shape[0] - 1
+    _check(lib().xl_check_inputs(ctypes.byref(s), _dev(seg_offsets, "seg_offsets", torch.int64),
+                                 n_seg, None if ray_offsets is None else _dev(ray_offsets, "ray_offsets"),
+                                 None if seg_ids is None else _dev(seg_ids, "seg_ids"), n_rays,
+                                 _stream()))

@@ -1,0 +1,188 @@
+// C ABI of libxl: argument validation, error reporting and dispatch to the
+// HIP launchers.  Nothing here allocates on the compute path.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/xl.h"
+#include "internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int ok() {
+  g_err[0] = '\0';
+  return XL_OK;
+}
+
+int hip_status(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(XL_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return ok();
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int check_samples(const xl_samples* s, xl::SamplesDev* out) {
+  if (s == nullptr) return fail(XL_EINVAL, "samples descriptor is NULL");
+  if (s->dtype != XL_F32 && s->dtype != XL_BF16 && s->dtype != XL_F16)
+    return fail(XL_EINVAL, "unknown sample dtype %d", s->dtype);
+  if (s->n < 0) return fail(XL_EINVAL, "negative sample count %lld", (long long)s->n);
+  if (s->n > 0) {
+    if (!s->sigma || !s->rgb || !s->t_start || !s->t_end)
+      return fail(XL_EINVAL, "NULL sample array with n = %lld", (long long)s->n);
+    if (!aligned16(s->sigma) || !aligned16(s->rgb) || !aligned16(s->t_start) ||
+        !aligned16(s->t_end))
+      return fail(XL_EINVAL, "sample arrays must be 16-byte aligned");
+  }
+  out->dtype = s->dtype;
+  out->sigma = s->sigma;
+  out->rgb = s->rgb;
+  out->t0 = s->t_start;
+  out->t1 = s->t_end;
+  out->n = s->n;
+  return XL_OK;
+}
+
+int check_segments(const xl::SamplesDev& s, const int64_t* seg_offsets, int64_t n_seg) {
+  if (n_seg < 0) return fail(XL_EINVAL, "negative segment count %lld", (long long)n_seg);
+  if (seg_offsets == nullptr) return fail(XL_EINVAL, "seg_offsets is NULL");
+  if (n_seg == 0 && s.n > 0) return fail(XL_EINVAL, "%lld samples but no segments", (long long)s.n);
+  return XL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int xl_version(void) { return 100; }
+
+const char* xl_last_error(void) { return g_err; }
+
+size_t xl_segments_workspace_bytes(int64_t n) {
+  const int64_t nt = n > 0 ? xl::num_tiles(n) : 1;
+  return static_cast<size_t>(nt) * xl::tile_rec_bytes();
+}
+
+int xl_render_segments_fwd(const xl_samples* s, const int64_t* seg_offsets, int64_t n_seg,
+                           float* seg_out, void* workspace, size_t workspace_bytes,
+                           void* stream) {
+  xl::SamplesDev d;
+  int rc = check_samples(s, &d);
+  if (rc) return rc;
+  if ((rc = check_segments(d, seg_offsets, n_seg))) return rc;
+  if (n_seg > 0 && seg_out == nullptr) return fail(XL_EINVAL, "seg_out is NULL");
+  if (d.n > 0) {
+    if (workspace == nullptr) return fail(XL_EINVAL, "workspace is NULL");
+    if (!aligned16(workspace)) return fail(XL_EINVAL, "workspace must be 16-byte aligned");
+    if (workspace_bytes < xl_segments_workspace_bytes(d.n))
+      return fail(XL_EINVAL, "workspace too small: %zu < %zu bytes", workspace_bytes,
+                  xl_segments_workspace_bytes(d.n));
+  }
+  return hip_status(xl::launch_segments_fwd(d, seg_offsets, n_seg, seg_out,
+                                            static_cast<xl::TileRec*>(workspace),
+                                            static_cast<hipStream_t>(stream)),
+                    "xl_render_segments_fwd launch");
+}
+
+int xl_render_segments_bwd(const xl_samples* s, const int64_t* seg_offsets, int64_t n_seg,
+                           const void* workspace, size_t workspace_bytes, const float* grad_seg,
+                           void* grad_sigma, void* grad_rgb, void* stream) {
+  xl::SamplesDev d;
+  int rc = check_samples(s, &d);
+  if (rc) return rc;
+  if ((rc = check_segments(d, seg_offsets, n_seg))) return rc;
+  if (d.n > 0) {
+    if (workspace == nullptr || grad_seg == nullptr || grad_sigma == nullptr || grad_rgb == nullptr)
+      return fail(XL_EINVAL, "NULL workspace or gradient array");
+    if (!aligned16(workspace) || !aligned16(grad_sigma) || !aligned16(grad_rgb))
+      return fail(XL_EINVAL, "workspace and gradient arrays must be 16-byte aligned");
+    if (workspace_bytes < xl_segments_workspace_bytes(d.n))
+      return fail(XL_EINVAL, "workspace too small: %zu < %zu bytes", workspace_bytes,
+                  xl_segments_workspace_bytes(d.n));
+  }
+  return hip_status(xl::launch_segments_bwd(d, seg_offsets, n_seg,
+                                            static_cast<const xl::TileRec*>(workspace), grad_seg,
+                                            grad_sigma, grad_rgb, static_cast<hipStream_t>(stream)),
+                    "xl_render_segments_bwd launch");
+}
+
+static int check_merge_args(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
+                            const int64_t* seg_ids, int64_t n_rays, int32_t flags) {
+  if (n_seg < 0 || n_rays < 0) return fail(XL_EINVAL, "negative count");
+  if (flags & ~XL_MERGE_FP64) return fail(XL_EINVAL, "unknown merge flags 0x%x", flags);
+  if (n_rays > 0 && ray_offsets == nullptr) return fail(XL_EINVAL, "ray_offsets is NULL");
+  if (n_seg > 0 && (seg_out == nullptr || seg_ids == nullptr))
+    return fail(XL_EINVAL, "seg_out or seg_ids is NULL");
+  return XL_OK;
+}
+
+int xl_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
+                 const int64_t* seg_ids, int64_t n_rays, float* ray_out, int32_t flags,
+                 void* stream) {
+  int rc = check_merge_args(seg_out, n_seg, ray_offsets, seg_ids, n_rays, flags);
+  if (rc) return rc;
+  if (n_rays > 0 && ray_out == nullptr) return fail(XL_EINVAL, "ray_out is NULL");
+  return hip_status(xl::launch_merge_fwd(seg_out, n_seg, ray_offsets, seg_ids, n_rays, ray_out,
+                                         (flags & XL_MERGE_FP64) != 0,
+                                         static_cast<hipStream_t>(stream)),
+                    "xl_merge_fwd launch");
+}
+
+int xl_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
+                 const int64_t* seg_ids, int64_t n_rays, const float* grad_ray, float* grad_seg,
+                 int32_t flags, void* stream) {
+  int rc = check_merge_args(seg_out, n_seg, ray_offsets, seg_ids, n_rays, flags);
+  if (rc) return rc;
+  if (n_rays > 0 && (grad_ray == nullptr || (n_seg > 0 && grad_seg == nullptr)))
+    return fail(XL_EINVAL, "grad_ray or grad_seg is NULL");
+  return hip_status(xl::launch_merge_bwd(seg_out, n_seg, ray_offsets, seg_ids, n_rays, grad_ray,
+                                         grad_seg, (flags & XL_MERGE_FP64) != 0,
+                                         static_cast<hipStream_t>(stream)),
+                    "xl_merge_bwd launch");
+}
+
+int xl_check_inputs(const xl_samples* s, const int64_t* seg_offsets, int64_t n_seg,
+                    const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                    void* stream) {
+  xl::SamplesDev d;
+  int rc = check_samples(s, &d);
+  if (rc) return rc;
+  if ((rc = check_segments(d, seg_offsets, n_seg))) return rc;
+  if (n_rays < 0) return fail(XL_EINVAL, "negative ray count");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int* code = nullptr;
+  hipError_t e = hipMalloc(&code, sizeof(int));
+  if (e != hipSuccess) return fail(XL_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
+  const int big = 1 << 30;
+  e = hipMemcpyAsync(code, &big, sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = xl::launch_check(d, seg_offsets, n_seg, ray_offsets, seg_ids, n_rays, code, st);
+  int host = big;
+  if (e == hipSuccess) e = hipMemcpyAsync(&host, code, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(code);
+  if (e != hipSuccess) return fail(XL_EHIP, "xl_check_inputs: %s", hipGetErrorString(e));
+  static const char* what[] = {"",
+                               "seg_offsets[0] != 0",
+                               "seg_offsets[n_seg] != n",
+                               "seg_offsets decreasing",
+                               "t_end < t_start",
+                               "intervals unsorted or overlapping inside a segment",
+                               "ray_offsets must run from 0 to n_seg",
+                               "ray_offsets decreasing",
+                               "seg_ids out of range"};
+  if (host != big && host >= 1 && host <= 8) return fail(XL_EINVAL, "invalid input: %s", what[host]);
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,40 @@
+// Internal launcher interface between the C ABI (api.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xl {
+
+struct SamplesDev {
+  int dtype;
+  const void* sigma;
+  const void* rgb;
+  const float* t0;
+  const float* t1;
+  int64_t n;
+};
+
+struct TileRec;
+
+int64_t num_tiles(int64_t n);
+size_t tile_rec_bytes();
+
+hipError_t launch_segments_fwd(const SamplesDev& s, const int64_t* seg_offsets, int64_t n_seg,
+                               float* seg_out, TileRec* recs, hipStream_t stream);
+hipError_t launch_segments_bwd(const SamplesDev& s, const int64_t* seg_offsets, int64_t n_seg,
+                               const TileRec* recs, const float* grad_seg, void* grad_sigma,
+                               void* grad_rgb, hipStream_t stream);
+hipError_t launch_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
+                            const int64_t* seg_ids, int64_t n_rays, float* ray_out, bool fp64,
+                            hipStream_t stream);
+hipError_t launch_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
+                            const int64_t* seg_ids, int64_t n_rays, const float* grad_ray,
+                            float* grad_seg, bool fp64, hipStream_t stream);
+// Device-side input checks; writes the number of the first failed check (0 =
+// none) to *code_dev.
+hipError_t launch_check(const SamplesDev& s, const int64_t* seg_offsets, int64_t n_seg,
+                        const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                        int* code_dev, hipStream_t stream);
+
+}  // namespace xl

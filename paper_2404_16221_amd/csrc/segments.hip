@@ -1,0 +1,510 @@
+// Per-segment composite, forward and backward (Sec. 4.3: each region reduces
+// its own samples to per-ray partial tuples before anything is exchanged).
+//
+// Work decomposition: the packed sample array is cut into fixed tiles of
+// kTile = 512 samples, one wavefront per tile and kRun = 8 consecutive samples
+// per lane, independent of where segments begin and end.  That keeps every
+// load a full, aligned 16-byte vector access and balances ragged segments
+// (1..1000+ samples) perfectly.  Inside a tile:
+//   1. the segment boundaries that fall in the tile are staged in LDS (one
+//      entry per sample: local id of the segment ending there, or -1);
+//   2. each lane folds its 8 samples serially into ranges (positive form of
+//      the merge operator, see xl_device.hpp);
+//   3. a segmented wave scan carries the open range across lanes;
+//   4. segments that cross a tile boundary are completed by a small fixup
+//      kernel from per-tile head/tail ranges, which also leaves the carries
+//      the backward pass needs (prefix into and suffix out of each tile).
+// The backward recomputes transmittance with the same forward scan, takes the
+// suffix with a reverse scan, and applies the exact per-sample Jacobian of the
+// merge operator, so nothing per sample is stored between the passes.
+#include "internal.h"
+#include "xl_device.hpp"
+
+namespace xl {
+
+int64_t num_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
+size_t tile_rec_bytes() { return sizeof(TileRec); }
+
+// First segment of each tile's window: the segment containing the tile's
+// first sample if it starts before the tile, else the first segment (empty
+// ones included) starting at the tile's first sample.
+__global__ void plan_kernel(const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
+                            TileRec* __restrict__ recs) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const int64_t base = t * kTile;
+  int64_t lo = 0, hi = n_seg;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (off[mid] < base) lo = mid + 1; else hi = mid;
+  }
+  int64_t w = lo;
+  if (w == n_seg || off[w] > base) w -= 1;
+  recs[t].first_seg = w < 0 ? 0 : w;
+}
+
+__global__ void fill_zero_kernel(float* __restrict__ p, int64_t count) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0.f;
+}
+
+__device__ __forceinline__ void write_tuple(float* __restrict__ out, int64_t n_seg, int64_t s,
+                                            const Range& r) {
+  out[s] = r.tau;
+  out[n_seg + s] = r.cr;
+  out[2 * n_seg + s] = r.cg;
+  out[3 * n_seg + s] = r.cb;
+  out[4 * n_seg + s] = r.A;
+  out[5 * n_seg + s] = fmaf(r.A, r.m0, r.F);  // D = sum w m
+  out[6 * n_seg + s] = r.L;
+}
+
+// Stage the segment ends of tile t in LDS.  endloc[p] = local id (segment -
+// s_lo) of the segment whose last sample is base + p, or -1.  Empty segments
+// owned by this tile get the identity tuple when WRITE_EMPTY.
+template <bool WRITE_EMPTY>
+__device__ __forceinline__ void stage_ends(const int64_t* __restrict__ off, int64_t n_seg,
+                                           int64_t n, int64_t t, int64_t n_tiles, int64_t s_lo,
+                                           int lane, int* __restrict__ endloc,
+                                           int64_t* __restrict__ tailseg,
+                                           float* __restrict__ seg_out) {
+  const int64_t base = t * kTile;
+  const int64_t tile_end = base + kTile < n ? base + kTile : n;
+  const int64_t last = tile_end - 1;
+  const bool last_tile = (t == n_tiles - 1);
+  for (int64_t j0 = 0;; j0 += kWave) {
+    const int64_t sg = s_lo + j0 + lane;
+    bool in = false;
+    if (sg < n_seg) {
+      const int64_t a = off[sg], e1 = off[sg + 1];
+      in = last_tile || a < base + kTile;
+      if (in) {
+        if (a >= e1) {
+          if (WRITE_EMPTY && a >= base) {
+            write_tuple(seg_out, n_seg, sg, range_identity());
+          }
+        } else {
+          const int64_t e = e1 - 1;
+          if (e >= base && e < tile_end) endloc[e - base] = static_cast<int>(sg - s_lo);
+          if (a <= last && last <= e) *tailseg = sg;
+        }
+      }
+    }
+    if (!__any(in)) break;
+  }
+}
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
+                                                         const int64_t* __restrict__ off,
+                                                         int64_t n_seg, int64_t n_tiles,
+                                                         float* __restrict__ seg_out,
+                                                         TileRec* __restrict__ recs) {
+  __shared__ int endloc_all[kWavesPerBlock][kTile];
+  __shared__ int64_t tailseg_all[kWavesPerBlock];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
+  const bool active = t < n_tiles;
+  int* endloc = endloc_all[wave];
+#pragma unroll
+  for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
+  if (lane == 0) tailseg_all[wave] = -1;
+  __syncthreads();
+  const int64_t n = s.n;
+  const int64_t base = t * kTile;
+  int64_t s_lo = 0;
+  bool start_head = false;
+  if (active) {
+    s_lo = recs[t].first_seg;
+    stage_ends<true>(off, n_seg, n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], seg_out);
+    start_head = (off[s_lo] == base);
+  }
+  __syncthreads();
+  if (!active) return;
+
+  int ends[kRun];
+#pragma unroll
+  for (int j = 0; j < kRun; ++j) ends[j] = endloc[lane * kRun + j];
+  const bool h0 = lane == 0 ? start_head : (endloc[lane * kRun - 1] >= 0);
+
+  const int64_t i0 = base + static_cast<int64_t>(lane) * kRun;
+  const int64_t rem = n - i0;
+  const int cnt = rem <= 0 ? 0 : (rem >= kRun ? kRun : static_cast<int>(rem));
+  float sg[kRun], c[3 * kRun], a[kRun], b[kRun];
+  if (cnt > 0) load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, i0, cnt, sg, c, a, b);
+
+  Range cur = range_identity(), pend = range_identity();
+  bool have = false, cur_head = false, has_pend = false, any_end = false, any_head = false;
+  int pend_seg = -1;
+#pragma unroll
+  for (int j = 0; j < kRun; ++j) {
+    if (j < cnt) {
+      const Smp x = make_sample(sg[j], c[3 * j], c[3 * j + 1], c[3 * j + 2], a[j], b[j]);
+      const bool head = j == 0 ? h0 : (ends[j - 1] >= 0);
+      any_head |= head;
+      if (!have || head) {
+        cur = range_of(x);
+        cur_head = head;
+        have = true;
+      } else {
+        append(cur, x);
+      }
+      if (ends[j] >= 0) {
+        any_end = true;
+        if (cur_head) {
+          write_tuple(seg_out, n_seg, s_lo + ends[j], cur);
+        } else {
+          pend = cur;
+          pend_seg = ends[j];
+          has_pend = true;
+        }
+        have = false;
+      }
+    }
+  }
+
+  // Carry the open range across lanes.
+  Range inc = have ? cur : range_identity();
+  bool fin = have ? cur_head : true;
+  scan_up(inc, fin, lane);
+  const Range ex = shfl_up_range(inc, 1);
+  const int exf = __shfl_up(static_cast<int>(fin), 1);
+  if (has_pend) {
+    if (lane > 0 && exf) {
+      write_tuple(seg_out, n_seg, s_lo + pend_seg, combine(ex, pend));
+    } else {
+      // The tile's first segment end closes a segment that began in an
+      // earlier tile: keep the part inside this tile for the fixup.
+      recs[t].head = lane > 0 ? combine(ex, pend) : pend;
+    }
+  }
+  const unsigned long long end_mask = __ballot(any_end);
+  const unsigned long long head_mask = __ballot(any_head);
+  if (lane == kWave - 1) {
+    const int flags = (start_head ? kStartHead : 0) | (end_mask ? kHasEnd : 0) |
+                      (head_mask ? kHasHead : 0) | (have ? kTailOpen : 0);
+    recs[t].flags = flags;
+    recs[t].tail_seg = tailseg_all[wave];
+    if (have) recs[t].tail = inc;
+    if (!start_head && !end_mask) recs[t].head = inc;
+  }
+}
+
+// Completes segments that cross tile boundaries and leaves, in every tile
+// such a segment passes through, the carries the backward needs.  One thread
+// per tile where a segment starts and continues past the tile end.
+__global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restrict__ seg_out,
+                                 TileRec* __restrict__ recs) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const int fl = recs[t].flags;
+  if (!((fl & kHasHead) && (fl & kTailOpen))) return;
+  Range acc = recs[t].tail;
+  int64_t u = t + 1;
+  bool closed = false;
+  while (u < n_tiles) {
+    recs[u].pre = acc;
+    const int fu = recs[u].flags;
+    acc = combine(acc, recs[u].head);
+    if (fu & kHasEnd) {
+      closed = true;
+      break;
+    }
+    ++u;
+  }
+  if (!closed) return;  // malformed offsets: the last segment must end at n
+  const int64_t sgi = recs[t].tail_seg;
+  if (sgi >= 0 && sgi < n_seg) write_tuple(seg_out, n_seg, sgi, acc);
+  Range suf = recs[u].head;
+  for (int64_t v = u - 1; v >= t; --v) {
+    recs[v].suf = suf;
+    if (v > t) suf = combine(recs[v].head, suf);
+  }
+}
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
+    SamplesDev s, const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
+    const TileRec* __restrict__ recs, const float* __restrict__ gseg, void* __restrict__ gsig_p,
+    void* __restrict__ grgb_p) {
+  __shared__ int endloc_all[kWavesPerBlock][kTile];
+  __shared__ int64_t tailseg_all[kWavesPerBlock];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
+  const bool active = t < n_tiles;
+  int* endloc = endloc_all[wave];
+#pragma unroll
+  for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
+  if (lane == 0) tailseg_all[wave] = -1;
+  __syncthreads();
+  const int64_t n = s.n;
+  const int64_t base = t * kTile;
+  int64_t s_lo = 0;
+  if (active) {
+    s_lo = recs[t].first_seg;
+    stage_ends<false>(off, n_seg, n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], nullptr);
+  }
+  __syncthreads();
+  if (!active) return;
+
+  const int flags = recs[t].flags;
+  const bool start_head = (flags & kStartHead) != 0;
+  const bool tail_open = (flags & kTailOpen) != 0;
+  int ends[kRun];
+#pragma unroll
+  for (int j = 0; j < kRun; ++j) ends[j] = endloc[lane * kRun + j];
+  const bool h0 = lane == 0 ? start_head : (endloc[lane * kRun - 1] >= 0);
+
+  const int64_t i0 = base + static_cast<int64_t>(lane) * kRun;
+  const int64_t rem = n - i0;
+  const int cnt = rem <= 0 ? 0 : (rem >= kRun ? kRun : static_cast<int>(rem));
+  float sg[kRun], c[3 * kRun], a[kRun], b[kRun];
+  if (cnt > 0) load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, i0, cnt, sg, c, a, b);
+  Smp x[kRun];
+#pragma unroll
+  for (int j = 0; j < kRun; ++j) x[j] = make_sample(sg[j], c[3 * j], c[3 * j + 1], c[3 * j + 2], a[j], b[j]);
+
+  // Pass 1: lane ranges for both scans.
+  Range cur = range_identity(), first = range_identity();
+  bool have = false, cur_head = false, has_end = false;
+  int first_end = -1;
+#pragma unroll
+  for (int j = 0; j < kRun; ++j) {
+    if (j < cnt) {
+      const bool head = j == 0 ? h0 : (ends[j - 1] >= 0);
+      if (!have || head) {
+        cur = range_of(x[j]);
+        cur_head = head;
+        have = true;
+      } else {
+        append(cur, x[j]);
+      }
+      if (ends[j] >= 0) {
+        if (!has_end) {
+          first = cur;
+          first_end = ends[j];
+          has_end = true;
+        }
+        have = false;
+      }
+    }
+  }
+  Range inc = have ? cur : range_identity();
+  bool fin = have ? cur_head : true;
+  Range rinc = has_end ? first : (cnt > 0 ? cur : range_identity());
+  bool rfl = has_end || cnt == 0;
+  int rseg = has_end ? first_end : -1;
+  scan_up(inc, fin, lane);
+  scan_down(rinc, rfl, rseg, lane);
+  const Range ex = shfl_up_range(inc, 1);
+  const int exf = __shfl_up(static_cast<int>(fin), 1);
+  const Range sx = shfl_down_range(rinc, 1);
+  const int sxf = __shfl_down(static_cast<int>(rfl), 1);
+  const int sxseg = __shfl_down(rseg, 1);
+
+  // Prefix carried into this lane's first sample (used unless it is a head).
+  Range pc = range_identity();
+  if (lane > 0 && exf) {
+    pc = ex;
+  } else if (!start_head) {
+    pc = lane > 0 ? combine(recs[t].pre, ex) : recs[t].pre;
+  }
+  // Suffix carried out of this lane's last sample (used unless it is an end),
+  // as a range in its own frame (transmittance 1 at its first sample).
+  Range sc = range_identity();
+  int64_t cseg = -1;
+  if (lane < kWave - 1 && sxf) {
+    sc = sx;
+    cseg = s_lo + sxseg;
+  } else if (tail_open) {
+    sc = lane < kWave - 1 ? combine(sx, recs[t].suf) : recs[t].suf;
+    cseg = recs[t].tail_seg;
+  }
+
+  // Pass 2: exclusive prefix state of every sample inside its segment:
+  // optical depth, opacity and sum_{k<j} w_k (m_j - m_k).
+  float Pt[kRun], PA[kRun], PZ[kRun];
+  Range P = pc;
+#pragma unroll
+  for (int j = 0; j < kRun; ++j) {
+    const bool head = j == 0 ? h0 : (ends[j - 1] >= 0);
+    if (head) {
+      Pt[j] = 0.f; PA[j] = 0.f; PZ[j] = 0.f;
+      P = range_of(x[j]);
+    } else {
+      Pt[j] = P.tau; PA[j] = P.A; PZ[j] = fmaf(P.A, x[j].m - P.m1, P.B);
+      append(P, x[j]);
+    }
+  }
+
+  // Pass 3: reverse sweep.  The suffix sums are weighted with each sample's
+  // transmittance from the start of its segment:
+  //   SC = sum_{k>j} w_k c_k, SA = sum_{k>j} w_k, SF = sum_{k>j} w_k (m_k - mf),
+  //   SL = distortion of the samples after j,
+  // and dl/dtau_j = g_tau + g_C.(T_{j+1} c_j - SC) + g_A T_N + g_D (m_j T_N - Zs)
+  //   + g_L [2 T_N Zp_j - 2 A_{<j} Zs + 2/3 T_{j+1} w_j delta_j - 2 SL + 2 (T_{j+1} - w_j) Zs]
+  // with Zs = sum_{k>j} w_k (m_k - m_j) and T_N the segment's transmittance:
+  // the derivative of the segment tuple with every difference of positions
+  // taken before it is multiplied.
+  float g[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float SCr = 0.f, SCg = 0.f, SCb = 0.f, SA = 0.f, SF = 0.f, SL = 0.f, mf = 0.f, TN = 1.f;
+  if (cnt > 0 && ends[cnt - 1] < 0) {
+    const float tq = Pt[cnt - 1] + x[cnt - 1].tau;
+    const float Tq = exp_neg(tq);
+    SCr = Tq * sc.cr; SCg = Tq * sc.cg; SCb = Tq * sc.cb;
+    SA = Tq * sc.A; SF = Tq * sc.F; SL = Tq * Tq * sc.L; mf = sc.m0;
+    TN = exp_neg(tq + sc.tau);
+    if (cseg >= 0 && cseg < n_seg) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) g[k] = gseg[k * n_seg + cseg];
+    }
+  }
+  float dsg[kRun], dc[3 * kRun];
+#pragma unroll
+  for (int j = kRun - 1; j >= 0; --j) {
+    dsg[j] = 0.f; dc[3 * j] = dc[3 * j + 1] = dc[3 * j + 2] = 0.f;
+    if (j < cnt) {
+      const Smp& q = x[j];
+      if (ends[j] >= 0) {
+        SCr = SCg = SCb = 0.f; SA = 0.f; SF = 0.f; SL = 0.f; mf = q.m;
+        TN = exp_neg(Pt[j] + q.tau);
+        const int64_t sgi = s_lo + ends[j];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) g[k] = gseg[k * n_seg + sgi];
+      }
+      const float Ti = exp_neg(Pt[j]);
+      const float Ti1 = exp_neg(Pt[j] + q.tau);
+      const float w = Ti * q.alpha;
+      const float Zs = fmaf(SA, mf - q.m, SF);
+      const float wd3 = w * q.delta * (1.f / 3.f);
+      const float cdot = g[1] * fmaf(Ti1, q.c0, -SCr) + g[2] * fmaf(Ti1, q.c1, -SCg) +
+                         g[3] * fmaf(Ti1, q.c2, -SCb);
+      const float dL = 2.f * (TN * PZ[j] - PA[j] * Zs - SL + (Ti1 - w) * Zs) + 2.f * Ti1 * wd3;
+      const float dtau = g[0] + cdot + g[4] * TN + g[5] * fmaf(q.m, TN, -Zs) + g[6] * dL;
+      dsg[j] = q.delta * dtau;
+      dc[3 * j] = w * g[1];
+      dc[3 * j + 1] = w * g[2];
+      dc[3 * j + 2] = w * g[3];
+      // sample j joins the suffix
+      SCr = fmaf(w, q.c0, SCr);
+      SCg = fmaf(w, q.c1, SCg);
+      SCb = fmaf(w, q.c2, SCb);
+      SL = fmaf(2.f * w, Zs, SL + w * wd3);
+      SF = Zs;
+      SA += w;
+      mf = q.m;
+    }
+  }
+
+  if (cnt == kRun) {
+    if (DT == kF32) {
+      float4* GS = reinterpret_cast<float4*>(static_cast<float*>(gsig_p) + i0);
+      float4* GC = reinterpret_cast<float4*>(static_cast<float*>(grgb_p) + 3 * i0);
+#pragma unroll
+      for (int q = 0; q < kRun / 4; ++q)
+        GS[q] = make_float4(dsg[4 * q], dsg[4 * q + 1], dsg[4 * q + 2], dsg[4 * q + 3]);
+#pragma unroll
+      for (int q = 0; q < 3 * kRun / 4; ++q)
+        GC[q] = make_float4(dc[4 * q], dc[4 * q + 1], dc[4 * q + 2], dc[4 * q + 3]);
+    } else {
+      uint4* GS = reinterpret_cast<uint4*>(static_cast<uint16_t*>(gsig_p) + i0);
+      uint4* GC = reinterpret_cast<uint4*>(static_cast<uint16_t*>(grgb_p) + 3 * i0);
+#pragma unroll
+      for (int q = 0; q < kRun / 8; ++q) {
+        uint32_t w[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+          w[h] = static_cast<uint32_t>(from_f32<DT>(dsg[8 * q + 2 * h])) |
+                 (static_cast<uint32_t>(from_f32<DT>(dsg[8 * q + 2 * h + 1])) << 16);
+        GS[q] = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+#pragma unroll
+      for (int q = 0; q < 3 * kRun / 8; ++q) {
+        uint32_t w[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+          w[h] = static_cast<uint32_t>(from_f32<DT>(dc[8 * q + 2 * h])) |
+                 (static_cast<uint32_t>(from_f32<DT>(dc[8 * q + 2 * h + 1])) << 16);
+        GC[q] = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+      if (j < cnt) {
+        const int64_t i = i0 + j;
+        if (DT == kF32) {
+          static_cast<float*>(gsig_p)[i] = dsg[j];
+          float* GC = static_cast<float*>(grgb_p);
+          GC[3 * i] = dc[3 * j]; GC[3 * i + 1] = dc[3 * j + 1]; GC[3 * i + 2] = dc[3 * j + 2];
+        } else {
+          static_cast<uint16_t*>(gsig_p)[i] = from_f32<DT>(dsg[j]);
+          uint16_t* GC = static_cast<uint16_t*>(grgb_p);
+          GC[3 * i] = from_f32<DT>(dc[3 * j]);
+          GC[3 * i + 1] = from_f32<DT>(dc[3 * j + 1]);
+          GC[3 * i + 2] = from_f32<DT>(dc[3 * j + 2]);
+        }
+      }
+    }
+  }
+}
+
+static inline unsigned grid_for(int64_t count, int block) {
+  return static_cast<unsigned>((count + block - 1) / block);
+}
+
+hipError_t launch_segments_fwd(const SamplesDev& s, const int64_t* off, int64_t n_seg,
+                               float* seg_out, TileRec* recs, hipStream_t stream) {
+  if (n_seg == 0) return hipSuccess;
+  if (s.n == 0) {
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(7 * n_seg, 256)), dim3(256), 0, stream,
+                       seg_out, 7 * n_seg);
+    return hipGetLastError();
+  }
+  const int64_t nt = num_tiles(s.n);
+  hipLaunchKernelGGL(plan_kernel, dim3(grid_for(nt, 256)), dim3(256), 0, stream, off, n_seg, nt,
+                     recs);
+  const dim3 grid(grid_for(nt, kWavesPerBlock));
+  switch (s.dtype) {
+    case kF32:
+      hipLaunchKernelGGL(seg_fwd_kernel<kF32>, grid, dim3(kBlock), 0, stream, s, off, n_seg, nt,
+                         seg_out, recs);
+      break;
+    case kBF16:
+      hipLaunchKernelGGL(seg_fwd_kernel<kBF16>, grid, dim3(kBlock), 0, stream, s, off, n_seg, nt,
+                         seg_out, recs);
+      break;
+    default:
+      hipLaunchKernelGGL(seg_fwd_kernel<kF16>, grid, dim3(kBlock), 0, stream, s, off, n_seg, nt,
+                         seg_out, recs);
+      break;
+  }
+  hipLaunchKernelGGL(seg_fixup_kernel, dim3(grid_for(nt, 256)), dim3(256), 0, stream, nt, n_seg,
+                     seg_out, recs);
+  return hipGetLastError();
+}
+
+hipError_t launch_segments_bwd(const SamplesDev& s, const int64_t* off, int64_t n_seg,
+                               const TileRec* recs, const float* grad_seg, void* grad_sigma,
+                               void* grad_rgb, hipStream_t stream) {
+  if (s.n == 0 || n_seg == 0) return hipSuccess;
+  const int64_t nt = num_tiles(s.n);
+  const dim3 grid(grid_for(nt, kWavesPerBlock));
+  switch (s.dtype) {
+    case kF32:
+      hipLaunchKernelGGL(seg_bwd_kernel<kF32>, grid, dim3(kBlock), 0, stream, s, off, n_seg, nt,
+                         recs, grad_seg, grad_sigma, grad_rgb);
+      break;
+    case kBF16:
+      hipLaunchKernelGGL(seg_bwd_kernel<kBF16>, grid, dim3(kBlock), 0, stream, s, off, n_seg, nt,
+                         recs, grad_seg, grad_sigma, grad_rgb);
+      break;
+    default:
+      hipLaunchKernelGGL(seg_bwd_kernel<kF16>, grid, dim3(kBlock), 0, stream, s, off, n_seg, nt,
+                         recs, grad_seg, grad_sigma, grad_rgb);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace xl

@@ -1,0 +1,295 @@
+// Device-side building blocks of the partitioned renderer (gfx950, wave64).
+//
+// A "range" is the partial tuple of a contiguous run of one segment's
+// samples.  Ranges combine front to back with the associative operator of
+// Eq. 3-8 (Sec. 4.3): colour, opacity and depth of the later range are
+// weighted by the earlier range's transmittance, and the distortion loss gains
+// the cross term of Eq. 7/8.  The cross term is evaluated in a form where every
+// added quantity is non-negative: with F = sum w (m - m0) (depth measured from
+// the range's first midpoint m0) and B = sum w (m1 - m) (measured back from its
+// last midpoint m1),
+//   sum_{i in y, j in x} w_i w_j (m_i - m_j) = A_x F_y + A_x A_y (m0_y - m1_x) + A_y B_x,
+// which equals D_y A_x - A_y D_x of Eq. 8 without its cancellation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xl {
+
+constexpr int kWave = 64;                 // CDNA wavefront
+constexpr int kRun = 8;                   // consecutive samples per lane
+constexpr int kTile = kWave * kRun;       // samples per wave tile
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+
+enum Dtype : int { kF32 = 0, kBF16 = 1, kF16 = 2 };
+
+struct Range {
+  float tau;        // sum of optical depths sigma * delta; transmittance is exp(-tau)
+  float cr, cg, cb; // colour
+  float A;          // opacity (sum of weights)
+  float F;          // sum w (m - m0)
+  float B;          // sum w (m1 - m)
+  float L;          // distortion loss inside the range
+  float m0, m1;     // first and last sample midpoints
+};
+
+// Per-tile record kept in the workspace between forward and backward.
+struct alignas(16) TileRec {
+  int64_t first_seg;  // segment containing the tile's first sample (or the
+                      // first segment starting at it, empty ones included)
+  int64_t tail_seg;   // segment containing the tile's last sample
+  int32_t flags;
+  int32_t pad[3];
+  Range head;  // first sample .. first segment end (whole tile if none)
+  Range tail;  // last segment head .. last sample
+  Range pre;   // carry-in: the first sample's segment before this tile
+  Range suf;   // carry-in: the last sample's segment after this tile
+};
+constexpr int kStartHead = 1;  // first sample starts a segment
+constexpr int kHasEnd = 2;     // some segment ends inside the tile
+constexpr int kHasHead = 4;    // some segment starts inside the tile
+constexpr int kTailOpen = 8;   // the last sample's segment continues past the tile
+
+__device__ __forceinline__ Range range_identity() {
+  Range r;
+  r.tau = 0.f; r.cr = r.cg = r.cb = 0.f; r.A = 0.f;
+  r.F = 0.f; r.B = 0.f; r.L = 0.f; r.m0 = 0.f; r.m1 = 0.f;
+  return r;
+}
+
+__device__ __forceinline__ float exp_neg(float tau) {
+  return __builtin_amdgcn_exp2f(-1.4426950408889634f * tau);
+}
+
+// x then y (x in front).  Transmittance is always taken as exp(-sum tau), one
+// rounding, never as a running product of per-sample factors (whose roundings
+// would add up over long segments).
+__device__ __forceinline__ Range combine(const Range& x, const Range& y) {
+  Range r;
+  const float T1 = exp_neg(x.tau);
+  r.tau = x.tau + y.tau;
+  r.cr = fmaf(T1, y.cr, x.cr);
+  r.cg = fmaf(T1, y.cg, x.cg);
+  r.cb = fmaf(T1, y.cb, x.cb);
+  r.A = fmaf(T1, y.A, x.A);
+  r.F = fmaf(T1, fmaf(y.A, y.m0 - x.m0, y.F), x.F);
+  r.B = fmaf(T1, y.B, fmaf(x.A, y.m1 - x.m1, x.B));
+  const float cross = fmaf(x.A, fmaf(y.A, y.m0 - x.m1, y.F), y.A * x.B);
+  r.L = fmaf(T1 * T1, y.L, fmaf(2.f * T1, cross, x.L));
+  r.m0 = x.m0;
+  r.m1 = y.m1;
+  return r;
+}
+
+// One sample, reduced to what the composite needs.
+struct Smp {
+  float tau, alpha, m, delta, c0, c1, c2;
+};
+
+// 1 - exp(-tau) without cancellation: Taylor series (Horner form, error below
+// tau^6/5040 relative) for tau < 1/4, else 1 - exp(-tau).
+__device__ __forceinline__ float one_minus_exp_neg(float tau, float e) {
+  const float p = tau * (1.f - tau * (1.f / 2.f) * (1.f - tau * (1.f / 3.f) * (1.f - tau * (1.f / 4.f) *
+                  (1.f - tau * (1.f / 5.f) * (1.f - tau * (1.f / 6.f))))));
+  return tau < 0.25f ? p : 1.f - e;
+}
+
+__device__ __forceinline__ Smp make_sample(float sigma, float c0, float c1, float c2, float t0,
+                                           float t1) {
+  Smp s;
+  s.delta = t1 - t0;
+  s.m = 0.5f * (t0 + t1);
+  s.tau = sigma * s.delta;
+  s.alpha = one_minus_exp_neg(s.tau, exp_neg(s.tau));
+  s.c0 = c0; s.c1 = c1; s.c2 = c2;
+  return s;
+}
+
+__device__ __forceinline__ Range range_of(const Smp& s) {
+  Range r;
+  r.tau = s.tau;
+  r.cr = s.alpha * s.c0; r.cg = s.alpha * s.c1; r.cb = s.alpha * s.c2;
+  r.A = s.alpha; r.F = 0.f; r.B = 0.f;
+  r.L = s.alpha * s.alpha * s.delta * (1.f / 3.f);
+  r.m0 = s.m; r.m1 = s.m;
+  return r;
+}
+
+// Append one sample behind range r.
+__device__ __forceinline__ void append(Range& r, const Smp& s) {
+  const float w = exp_neg(r.tau) * s.alpha;
+  const float Z = fmaf(r.A, s.m - r.m1, r.B);  // sum_{j<i} w_j (m_i - m_j)
+  r.L = fmaf(w, fmaf(2.f, Z, w * s.delta * (1.f / 3.f)), r.L);
+  r.F = fmaf(w, s.m - r.m0, r.F);
+  r.B = Z;
+  r.cr = fmaf(w, s.c0, r.cr);
+  r.cg = fmaf(w, s.c1, r.cg);
+  r.cb = fmaf(w, s.c2, r.cb);
+  r.A += w;
+  r.tau += s.tau;
+  r.m1 = s.m;
+}
+
+// ---------------------------------------------------------------- storage
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16(float x) {  // round to nearest even
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float f16_to_f32(uint16_t h) {
+  return static_cast<float>(__builtin_bit_cast(_Float16, h));
+}
+__device__ __forceinline__ uint16_t f32_to_f16(float x) {
+  return __builtin_bit_cast(uint16_t, static_cast<_Float16>(x));
+}
+
+template <int DT>
+__device__ __forceinline__ float to_f32(uint16_t h) {
+  return DT == kBF16 ? bf16_to_f32(h) : f16_to_f32(h);
+}
+template <int DT>
+__device__ __forceinline__ uint16_t from_f32(float x) {
+  return DT == kBF16 ? f32_to_bf16(x) : f32_to_f16(x);
+}
+
+// Load kRun consecutive samples starting at index i (i % kRun == 0) into
+// registers.  `full` means all kRun samples exist; otherwise only `cnt` are
+// loaded and the rest are zero.
+template <int DT>
+__device__ __forceinline__ void load_run(const void* __restrict__ sigma_p,
+                                         const void* __restrict__ rgb_p,
+                                         const float* __restrict__ t0_p,
+                                         const float* __restrict__ t1_p, int64_t i, int cnt,
+                                         float (&sg)[kRun], float (&c)[3 * kRun],
+                                         float (&a)[kRun], float (&b)[kRun]) {
+  if (cnt == kRun) {
+    const float4* T0 = reinterpret_cast<const float4*>(t0_p + i);
+    const float4* T1 = reinterpret_cast<const float4*>(t1_p + i);
+#pragma unroll
+    for (int q = 0; q < kRun / 4; ++q) {
+      const float4 u = T0[q], v = T1[q];
+      a[4 * q] = u.x; a[4 * q + 1] = u.y; a[4 * q + 2] = u.z; a[4 * q + 3] = u.w;
+      b[4 * q] = v.x; b[4 * q + 1] = v.y; b[4 * q + 2] = v.z; b[4 * q + 3] = v.w;
+    }
+    if (DT == kF32) {
+      const float4* S = reinterpret_cast<const float4*>(static_cast<const float*>(sigma_p) + i);
+      const float4* C = reinterpret_cast<const float4*>(static_cast<const float*>(rgb_p) + 3 * i);
+#pragma unroll
+      for (int q = 0; q < kRun / 4; ++q) {
+        const float4 u = S[q];
+        sg[4 * q] = u.x; sg[4 * q + 1] = u.y; sg[4 * q + 2] = u.z; sg[4 * q + 3] = u.w;
+      }
+#pragma unroll
+      for (int q = 0; q < 3 * kRun / 4; ++q) {
+        const float4 u = C[q];
+        c[4 * q] = u.x; c[4 * q + 1] = u.y; c[4 * q + 2] = u.z; c[4 * q + 3] = u.w;
+      }
+    } else {
+      const uint4* S = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(sigma_p) + i);
+      const uint4* C = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(rgb_p) + 3 * i);
+#pragma unroll
+      for (int q = 0; q < kRun / 8; ++q) {
+        const uint4 u = S[q];
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          sg[8 * q + 2 * h] = to_f32<DT>(static_cast<uint16_t>(w[h] & 0xffffu));
+          sg[8 * q + 2 * h + 1] = to_f32<DT>(static_cast<uint16_t>(w[h] >> 16));
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 3 * kRun / 8; ++q) {
+        const uint4 u = C[q];
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          c[8 * q + 2 * h] = to_f32<DT>(static_cast<uint16_t>(w[h] & 0xffffu));
+          c[8 * q + 2 * h + 1] = to_f32<DT>(static_cast<uint16_t>(w[h] >> 16));
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+      const bool ok = j < cnt;
+      a[j] = ok ? t0_p[i + j] : 0.f;
+      b[j] = ok ? t1_p[i + j] : 0.f;
+      if (DT == kF32) {
+        const float* S = static_cast<const float*>(sigma_p);
+        const float* C = static_cast<const float*>(rgb_p);
+        sg[j] = ok ? S[i + j] : 0.f;
+        c[3 * j] = ok ? C[3 * (i + j)] : 0.f;
+        c[3 * j + 1] = ok ? C[3 * (i + j) + 1] : 0.f;
+        c[3 * j + 2] = ok ? C[3 * (i + j) + 2] : 0.f;
+      } else {
+        const uint16_t* S = static_cast<const uint16_t*>(sigma_p);
+        const uint16_t* C = static_cast<const uint16_t*>(rgb_p);
+        sg[j] = ok ? to_f32<DT>(S[i + j]) : 0.f;
+        c[3 * j] = ok ? to_f32<DT>(C[3 * (i + j)]) : 0.f;
+        c[3 * j + 1] = ok ? to_f32<DT>(C[3 * (i + j) + 1]) : 0.f;
+        c[3 * j + 2] = ok ? to_f32<DT>(C[3 * (i + j) + 2]) : 0.f;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- wave scans
+__device__ __forceinline__ Range shfl_up_range(const Range& x, int d) {
+  Range y;
+  y.tau = __shfl_up(x.tau, d);
+  y.cr = __shfl_up(x.cr, d); y.cg = __shfl_up(x.cg, d); y.cb = __shfl_up(x.cb, d);
+  y.A = __shfl_up(x.A, d); y.F = __shfl_up(x.F, d); y.B = __shfl_up(x.B, d);
+  y.L = __shfl_up(x.L, d); y.m0 = __shfl_up(x.m0, d); y.m1 = __shfl_up(x.m1, d);
+  return y;
+}
+__device__ __forceinline__ Range shfl_down_range(const Range& x, int d) {
+  Range y;
+  y.tau = __shfl_down(x.tau, d);
+  y.cr = __shfl_down(x.cr, d); y.cg = __shfl_down(x.cg, d); y.cb = __shfl_down(x.cb, d);
+  y.A = __shfl_down(x.A, d); y.F = __shfl_down(x.F, d); y.B = __shfl_down(x.B, d);
+  y.L = __shfl_down(x.L, d); y.m0 = __shfl_down(x.m0, d); y.m1 = __shfl_down(x.m1, d);
+  return y;
+}
+
+// Inclusive segmented scan in lane order.  A lane whose flag is set starts a
+// new segment: nothing from lower lanes is combined into it.
+__device__ __forceinline__ void scan_up(Range& x, bool& f, int lane) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const Range y = shfl_up_range(x, d);
+    const int fy = __shfl_up(static_cast<int>(f), d);
+    if (lane >= d) {
+      if (!f) x = combine(y, x);
+      f = f || (fy != 0);
+    }
+  }
+}
+
+// Inclusive segmented scan against lane order (suffix).  A lane whose flag is
+// set ends its segment: nothing from higher lanes is combined into it.  `seg`
+// travels with the range (the segment whose end closes it).
+__device__ __forceinline__ void scan_down(Range& x, bool& f, int& seg, int lane) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const Range y = shfl_down_range(x, d);
+    const int fy = __shfl_down(static_cast<int>(f), d);
+    const int sy = __shfl_down(seg, d);
+    if (lane + d < kWave) {
+      if (!f) {
+        x = combine(x, y);
+        seg = sy;
+      }
+      f = f || (fy != 0);
+    }
+  }
+}
+
+__device__ __forceinline__ void store_range(Range* dst, const Range& r) { *dst = r; }
+
+}  // namespace xl

@@ -248,17 +248,26 @@ def _gen_ray_major(w: Workload, rays: np.ndarray):
                 t_start=t_start, t_end=t_end, box=box, off=off, ray_of=ray_of)
 
 
+def _gen_chunk(args):
+    w, sub = args
+    return _gen_ray_major(w, sub)
+
+
 def generate(w: Workload, rays: Optional[Sequence[int]] = None,
-             chunk: int = 32768) -> Batch:
-    """Generate the rays `rays` (default: all of w) and pack them region-major."""
+             chunk: int = 32768, processes: int = 1) -> Batch:
+    """Generate the rays `rays` (default: all of w) and pack them region-major.
+
+    `processes` > 1 generates ray chunks in worker processes (same result)."""
     if rays is None:
         rays = np.arange(w.n_rays, dtype=np.int64)
     rays = np.asarray(rays, dtype=np.int64)
-    parts = []
-    for c0 in range(0, max(rays.shape[0], 1), chunk):
-        sub = rays[c0:c0 + chunk]
-        if sub.size:
-            parts.append(_gen_ray_major(w, sub))
+    subs = [rays[c0:c0 + chunk] for c0 in range(0, rays.shape[0], chunk)]
+    if processes > 1 and len(subs) > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(processes, len(subs))) as pool:
+            parts = pool.map(_gen_chunk, [(w, sub) for sub in subs])
+    else:
+        parts = [_gen_ray_major(w, sub) for sub in subs]
     if not parts:
         z32 = np.zeros(0, np.float32)
         return Batch(z32, np.zeros((0, 3), np.float32), z32, z32,

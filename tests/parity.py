@@ -1,0 +1,121 @@
+"""Helpers for GPU-vs-oracle parity tests: device upload and tolerance checks.
+
+Tolerances (FP32 path, the 1e-5 relative bar with explicit floors):
+  * colour and opacity (values in [0, 1]):  |x - x64| <= 1e-5 |x64| + 1e-8
+  * depth and distortion (t <= 3):          |x - x64| <= 1e-5 |x64| + 3e-8
+  * transmittance is judged through tau = -log T:
+        |tau - tau64| <= 1e-5 tau64 + 1e-7  (1e-7 ~ one FP32 ulp of T near 1);
+    where tau64 > 80 (T below FP32's normal range) T must be < 1e-34
+  * gradients: |g - g64| <= 1e-5 |g64| + 1e-6 max|g64| per element and
+    ||g - g64|| <= 1e-5 ||g64||.  The 1e-6 floor (about 16 FP32 ulps of the
+    largest gradient) covers elements that are differences of terms of the
+    size of the largest gradient (moving weight between samples), whose FP32
+    rounding is absolute, not relative.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+RTOL = 1e-5
+ATOL = np.array([0.0, 1e-8, 1e-8, 1e-8, 1e-8, 3e-8, 3e-8])
+TAU_ATOL = 1e-7
+
+
+@dataclass
+class Dev:
+    sigma: torch.Tensor
+    rgb: torch.Tensor
+    t0: torch.Tensor
+    t1: torch.Tensor
+    seg_offsets: torch.Tensor
+    ray_offsets: torch.Tensor
+    seg_ids: torch.Tensor
+
+
+def to_dev(b, dtype=torch.float32, device="cuda") -> Dev:
+    def T(a, dt=None):
+        t = torch.from_numpy(np.ascontiguousarray(a))
+        return t.to(device=device, dtype=dt) if dt is not None else t.to(device)
+    return Dev(T(b.sigma, dtype), T(b.rgb, dtype), T(b.t_start), T(b.t_end), T(b.seg_offsets),
+               T(b.ray_offsets), T(b.seg_ids))
+
+
+def quantize(b, dtype):
+    """Host copies of sigma, rgb rounded to `dtype` (round to nearest even) and back."""
+    s = torch.from_numpy(b.sigma).to(dtype).to(torch.float32).numpy()
+    c = torch.from_numpy(b.rgb).to(dtype).to(torch.float32).numpy()
+    return s, c
+
+
+def tuple_report(got, ref, kind: str, rtol=RTOL, atol=ATOL):
+    """Per-component worst normalised error (<= 1 passes) for [7, N] tuples.
+
+    kind = "seg": component 0 is tau; kind = "ray": component 0 is T.
+    """
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    rep = {"norm": np.zeros(7), "rel": np.zeros(7), "floored": np.zeros(7, int), "n": ref.shape[1]}
+    if ref.shape[1] == 0:
+        return rep
+    if kind == "ray":
+        with np.errstate(divide="ignore"):
+            tau_ref = -np.log(ref[0])
+            tau_got = -np.log(np.maximum(got[0], 1e-300))
+        deep = tau_ref > 80.0
+        lim = rtol * tau_ref + TAU_ATOL
+        e = np.where(deep, 0.0, np.abs(tau_got - tau_ref) / np.where(deep, 1.0, lim))
+        e = np.where(deep & (got[0] >= 1e-34), np.inf, e)
+        rep["norm"][0] = e.max()
+        ok = ~deep & (tau_ref > 0)
+        rep["rel"][0] = (np.abs(tau_got - tau_ref)[ok] / tau_ref[ok]).max() if ok.any() else 0.0
+    else:
+        lim = rtol * np.abs(ref[0]) + TAU_ATOL
+        rep["norm"][0] = (np.abs(got[0] - ref[0]) / lim).max()
+        nz = ref[0] > 0
+        rep["rel"][0] = (np.abs(got[0] - ref[0])[nz] / ref[0][nz]).max() if nz.any() else 0.0
+    for k in range(1, 7):
+        err = np.abs(got[k] - ref[k])
+        lim = rtol * np.abs(ref[k]) + atol[k]
+        rep["norm"][k] = (err / lim).max()
+        nz = np.abs(ref[k]) > 0
+        rep["rel"][k] = (err[nz] / np.abs(ref[k][nz])).max() if nz.any() else err.max()
+        rep["floored"][k] = int((atol[k] > rtol * np.abs(ref[k])).sum())
+    return rep
+
+
+def assert_tuples(got, ref, kind, what="", **kw):
+    rep = tuple_report(got, ref, kind, **kw)
+    names = ["T" if kind == "ray" else "tau", "r", "g", "b", "A", "D", "L"]
+    msg = f"{what}: worst normalised error " + ", ".join(
+        f"{n}={v:.3g}" for n, v in zip(names, rep["norm"])) + "; max rel " + ", ".join(
+        f"{n}={v:.3g}" for n, v in zip(names, rep["rel"]))
+    assert np.all(rep["norm"] <= 1.0), msg
+    return rep
+
+
+def grad_report(got, ref, rtol=RTOL, floor=1e-6):
+    got = np.asarray(got, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    if ref.size == 0:
+        return 0.0, 0.0
+    s = np.abs(ref).max()
+    lim = rtol * np.abs(ref) + floor * s
+    norm = float((np.abs(got - ref) / np.where(lim > 0, lim, 1.0)).max()) if s > 0 else float(np.abs(got).max())
+    nrm = float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+    return norm, nrm
+
+
+def assert_grads(got, ref, what="", rtol=RTOL, floor=1e-6, norm_tol=1e-5):
+    norm, nrm = grad_report(got, ref, rtol, floor)
+    assert norm <= 1.0 and nrm <= norm_tol, f"{what}: worst normalised {norm:.3g}, norm-wise rel {nrm:.3g}"
+    return norm, nrm
+
+
+def sample_rays(n_rays, k, seed):
+    rng = np.random.default_rng(seed)
+    k = min(k, n_rays)
+    return np.sort(rng.choice(n_rays, size=k, replace=False))
