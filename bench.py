@@ -69,6 +69,11 @@ class Form:
         self.gs = torch.empty_like(sigma)
         self.gc = torch.empty_like(rgb)
 
+    def release(self):
+        for k in list(vars(self)):
+            if isinstance(getattr(self, k), torch.Tensor):
+                setattr(self, k, None)
+
     def step(self, ev=None):
         xl = self.xl
         xl.xl_render_segments_fwd(self.sigma, self.rgb, self.t0, self.t1, self.seg_offsets,
@@ -136,11 +141,74 @@ def cpu_baseline(w, budget_s=15.0):
         return time.perf_counter() - t, b.n
 
     dt, n = run(4)
-    k = int(max(4, min(2048, 4 * budget_s / max(dt, 1e-3))))
+    k = int(max(4, min(16384, 4 * budget_s / max(dt, 1e-3))))
     dt, n = run(k)
     return {"value": n / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
             "sample": f"{k} random rays of the {w.name} workload ({n} samples), FP64 oracle, "
                       f"segment composite + merge + merge backward + segment backward, {dt:.1f} s"}
+
+
+def serve_stream(n_req, warmup, rate, dtype, slots, seed=2404_16221 + 103):
+    """Poisson arrivals of view requests (sizes uniform over the four image sizes,
+    K=32 scene) against the render server; latency per request."""
+    import threading
+    from paper_2404_16221_amd import synth
+    from paper_2404_16221_amd.serve import Server, request
+    w3 = synth.WORKLOADS[3]
+    scene = dict(grid=w3.grid, n_min=w3.n_min, n_max=w3.n_max, sigma_mu=w3.sigma_mu,
+                 sigma_s=w3.sigma_s, zero_frac=w3.zero_frac)
+    rng = np.random.default_rng(seed)
+    total = n_req + warmup
+    gaps = rng.exponential(1.0 / rate, size=total)
+    sizes = rng.integers(0, len(synth.SERVE_SIZES), size=total)
+    tickets = [None] * total
+    submitted = [0.0] * total
+    srv = Server(hbm_budget_bytes=64 << 30, max_slots=slots, max_queue=4096, dtype=dtype)
+    t_start = time.perf_counter()
+
+    def producer():
+        t = t_start
+        for i in range(total):
+            t += gaps[i]
+            d = t - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            wdt, hgt = synth.SERVE_SIZES[sizes[i]]
+            submitted[i] = time.perf_counter()
+            tickets[i] = srv.submit(request(wdt, hgt, seed=seed + 1000 + i, **scene))
+
+    th = threading.Thread(target=producer)
+    th.start()
+    res = []
+    for i in range(total):
+        while tickets[i] is None:
+            time.sleep(0.0005)
+        r = srv.poll(tickets[i], timeout_us=-1)
+        if r["rc"] != 0:
+            raise RuntimeError(f"request {i} failed: {r}")
+        srv.release(tickets[i])
+        res.append(r)
+    th.join()
+    srv.close()
+    m = res[warmup:]
+    lat = np.array([r["latency_us"] for r in m]) / 1e3
+    sub = np.array(submitted[warmup:])
+    span = float((sub + lat / 1e3).max() - sub.min())
+    samples = sum(r["n_samples"] for r in m)
+    return {"requests": n_req, "warmup": warmup, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "device_ms_mean": float(np.mean([r["device_us"] for r in m]) / 1e3),
+            "requests_per_s": n_req / span, "samples_per_s": samples / span}
+
+
+def serving(n_req, warmup, rate):
+    """Continuous batching (FP16, 4 slots) and the FIFO single-request FP32 baseline."""
+    cb = serve_stream(n_req, warmup, rate, torch.float16, slots=4)
+    log("serving fp16 x4 slots:", json.dumps(cb))
+    fifo = serve_stream(max(n_req // 3, 20), max(warmup // 3, 5), rate, torch.float32, slots=1)
+    log("serving fifo fp32:", json.dumps(fifo))
+    return {"workload": "k32 scene, Poisson %.0f/s, sizes 256^2/512^2/1280x720/1920x1080" % rate,
+            "continuous_batching_fp16": cb, "fifo_fp32_baseline": fifo}
 
 
 def main():
@@ -150,37 +218,51 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="bf16,fp32,plain")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="measured serving requests (0 skips the serving run)")
+    ap.add_argument("--serve-warmup", type=int, default=30)
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals per second")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 1 GiB device to device (scales HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read": x.numel() * 4,
+                          "bytes_written": y.numel() * 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU exchange "
               "of segment tuples is a design in DESIGN.md, not part of this build.", file=sys.stderr)
         sys.exit(2)
     import paper_2404_16221_amd  # noqa: F401  (fails loudly without libxl.so)
+    from paper_2404_16221_amd import _lib as xl
     from paper_2404_16221_amd import synth
     dev = torch.device("cuda:0")
     w = synth.WORKLOADS[2]
-    t = time.perf_counter()
-    b = synth.generate(w, processes=min(16, os.cpu_count() or 1))
-    log(f"generated {w.name}: {b.n} samples, {b.n_seg} segments in {time.perf_counter() - t:.1f} s")
-    grad_ray = torch.from_numpy(np.random.default_rng(3).normal(size=(7, b.n_rays)).astype(np.float32)).to(dev)
-    T = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype=dt)
-    t0, t1 = T(b.t_start), T(b.t_end)
-    so, ro, ids = T(b.seg_offsets), T(b.ray_offsets), T(b.seg_ids)
-    forms = {}
     want = args.forms.split(",")
-    results = {}
+    forms, results = {}, {}
+    grad_ray = torch.from_numpy(
+        np.random.default_rng(3).normal(size=(7, w.n_rays)).astype(np.float32)).to(dev)
+
+    def make(name, workload, dtype, regions):
+        t = time.perf_counter()
+        g = xl.xl_gen(workload, dtype)
+        torch.cuda.synchronize()
+        log(f"generated {name} on the device: {g['sigma'].shape[0]} samples, "
+            f"{g['seg_ids'].shape[0]} segments in {time.perf_counter() - t:.2f} s")
+        return Form(name, g["sigma"], g["rgb"], g["t_start"], g["t_end"], g["seg_offsets"],
+                    g["ray_offsets"], g["seg_ids"], grad_ray, regions)
+
     if "bf16" in want:
-        forms["bf16"] = Form("k16-bf16", T(b.sigma, torch.bfloat16), T(b.rgb, torch.bfloat16), t0, t1,
-                             so, ro, ids, grad_ray, 16)
+        forms["bf16"] = make("k16-bf16", w, torch.bfloat16, 16)
     if "fp32" in want:
-        forms["fp32"] = Form("k16-fp32", T(b.sigma), T(b.rgb), t0, t1, so, ro, ids, grad_ray, 16)
+        forms["fp32"] = make("k16-fp32", w, torch.float32, 16)
     if "plain" in want:
-        gather, pso = plain_arrays(b)
-        forms["plain"] = Form("k1-plain-fp32", T(b.sigma[gather]), T(b.rgb[gather]),
-                              T(b.t_start[gather]), T(b.t_end[gather]), T(pso),
-                              T(np.arange(b.n_rays + 1, dtype=np.int64)),
-                              T(np.arange(b.n_rays, dtype=np.int64)), grad_ray, 1)
-    del b
+        forms["plain"] = make("k1-plain-fp32", w.plain(), torch.float32, 1)
     for key, f in forms.items():
         ms, kms, wall = time_form(f, args.steps, args.warmup)
         results[key] = dict(name=f.name, ms_per_step=ms, samples_per_s=f.n / (ms * 1e-3),
@@ -205,6 +287,12 @@ def main():
                      "kernel": "seg_bwd_kernel", "step_achieved": hr["step_gbs"],
                      "step_frac": hr["step_gbs"] / HBM_PEAK_GBS},
     }
+    if args.serve_requests > 0:
+        for f in forms.values():
+            f.release()
+        forms.clear()
+        torch.cuda.empty_cache()
+        out["serving"] = serving(args.serve_requests, args.serve_warmup, args.serve_rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

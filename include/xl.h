@@ -152,6 +152,111 @@ int xl_check_inputs(const xl_samples* s, const int64_t* seg_offsets, int64_t n_s
                     const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
                     void* stream);
 
+/*
+ * Synthetic workload generator on the device (the stand-in for per-region
+ * NeRF evaluation): rays [ray0, ray0 + n_rays) of a seeded workload, packed
+ * region-major exactly as the input contract above requires.  Bit-identical
+ * to the host generator (synth.py) in t_start, t_end and the layout; densities
+ * agree to about 1e-6 relative.  grid[0]*grid[1]*grid[2] <= 256 regions,
+ * grid[0]+grid[1]+grid[2] <= 18.
+ */
+typedef struct xl_gen_params {
+  int64_t n_rays;    /* rays to generate */
+  int64_t ray0;      /* index of the first ray in the workload */
+  int32_t n_min;     /* samples per ray, uniform in [n_min, n_max] */
+  int32_t n_max;
+  int32_t grid[3];   /* regions: a gx x gy x gz grid over [-1, 1]^3 */
+  int32_t reserved;
+  double sigma_mu;   /* density lognormal(mu, s) */
+  double sigma_s;
+  double zero_frac;  /* fraction of densities set to 0 */
+  double width_mean; /* mean interval width (exponential) */
+  double t_far;      /* rays span [0, t_far] */
+  uint64_t seed;
+} xl_gen_params;
+
+/* Device workspace bytes for xl_gen_plan / xl_gen_fill. */
+size_t xl_gen_workspace_bytes(const xl_gen_params* p);
+
+/* Phase 1 (synchronises `stream`): ray structure and layout into the
+ * workspace; returns the number of samples and segments to allocate. */
+int xl_gen_plan(const xl_gen_params* p, void* workspace, size_t workspace_bytes,
+                int64_t* n_samples, int64_t* n_seg, void* stream);
+
+/* Phase 2 (asynchronous): samples in storage type `dtype` and the CSR arrays
+ * (seg_offsets [n_seg+1], ray_offsets [n_rays+1], seg_ids [n_seg]; any of the
+ * three may be NULL) from the workspace filled by xl_gen_plan with the same
+ * parameters. */
+int xl_gen_fill(const xl_gen_params* p, int32_t dtype, void* workspace, size_t workspace_bytes,
+                int64_t n_seg, void* sigma, void* rgb, float* t_start, float* t_end,
+                int64_t* seg_offsets, int64_t* ray_offsets, int64_t* seg_ids, void* stream);
+
+/*
+ * Render server: continuous batching of novel-view requests (the inference
+ * path of App. A.2: per-region composite, then the merge on one device).
+ * Requests are generated on the device (stand-in for per-region NeRF
+ * evaluation), rendered with xl_render_segments_fwd + xl_merge_fwd and kept
+ * until released.  Up to max_slots requests run at once, each on its own HIP
+ * stream; a request is admitted when a slot is free and its exact HBM
+ * footprint (known after generation planning) fits in hbm_budget_bytes next to
+ * the requests in flight.  A request's result does not depend on the others.
+ * All functions are thread-safe.
+ */
+typedef struct xl_server xl_server;
+
+typedef struct xl_serve_config {
+  uint64_t hbm_budget_bytes; /* device memory in-flight requests may hold */
+  int32_t max_slots;         /* requests processed concurrently (>= 1) */
+  int32_t max_queue;         /* requests waiting for a slot; XL_EAGAIN beyond */
+  int32_t device;            /* HIP device ordinal */
+  int32_t dtype;             /* sample storage: XL_F32, XL_BF16, XL_F16 */
+  int32_t merge_fp64;        /* 1: merge with XL_MERGE_FP64 */
+  int32_t reserved;
+} xl_serve_config;
+
+typedef struct xl_request {
+  int32_t width, height;     /* one ray per pixel */
+  int32_t grid[3];           /* regions of the scene */
+  int32_t n_min, n_max;      /* samples per ray */
+  int32_t inject_fault;      /* tests: fail this request with XL_EFAULT */
+  double sigma_mu, sigma_s, zero_frac;
+  double width_mean, t_far;  /* 0 = defaults 0.02 and 3 */
+  uint64_t seed;             /* the view's generator seed */
+} xl_request;
+
+typedef struct xl_result {
+  int32_t status;            /* XL_OK, XL_PENDING or an error code */
+  int32_t reserved;
+  const float* ray_out;      /* device [7][n_rays], valid until xl_serve_release */
+  int64_t n_rays, n_samples, n_segments;
+  uint64_t footprint_bytes;  /* HBM the request held while rendering */
+  int64_t latency_us;        /* completion - arrival (host monotonic clock) */
+  int64_t queue_us;          /* admission to a slot - arrival */
+  int64_t device_us;         /* generation + composite + merge on the device */
+} xl_result;
+
+typedef struct xl_serve_stats {
+  int64_t completed, failed, queued, samples;
+  uint64_t budget_used_bytes;
+  int64_t p50_latency_us, p99_latency_us, max_latency_us;
+  int64_t span_us;           /* first arrival to last completion */
+} xl_serve_stats;
+
+int xl_serve_create(const xl_serve_config* cfg, xl_server** out);
+/* Non-blocking; XL_EAGAIN when max_queue requests are already waiting. */
+int xl_serve_submit(xl_server* s, const xl_request* req, uint64_t* ticket);
+/* Waits up to timeout_us (0: no wait, < 0: forever).  Returns XL_PENDING, or
+ * the request's final status (XL_OK or its error) with *out filled in. */
+int xl_serve_poll(xl_server* s, uint64_t ticket, xl_result* out, int64_t timeout_us);
+/* Copies a finished request's ray tuple [7][n_rays] to dst (device), async on
+ * `stream`. */
+int xl_serve_copy_result(xl_server* s, uint64_t ticket, float* dst, void* stream);
+/* Frees a finished request's result (ray_out becomes invalid). */
+int xl_serve_release(xl_server* s, uint64_t ticket);
+int xl_serve_stats_get(xl_server* s, xl_serve_stats* out);
+/* Finishes queued requests, then frees everything. */
+int xl_serve_destroy(xl_server* s);
+
 #ifdef __cplusplus
 }
 #endif

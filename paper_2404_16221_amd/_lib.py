@@ -33,6 +33,13 @@ class XLSamples(_c.Structure):
                 ("t_end", _vp), ("n", _i64)]
 
 
+class XLGenParams(_c.Structure):
+    _fields_ = [("n_rays", _i64), ("ray0", _i64), ("n_min", _i32), ("n_max", _i32),
+                ("grid", _i32 * 3), ("reserved", _i32), ("sigma_mu", _c.c_double),
+                ("sigma_s", _c.c_double), ("zero_frac", _c.c_double), ("width_mean", _c.c_double),
+                ("t_far", _c.c_double), ("seed", _c.c_uint64)]
+
+
 class XLError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libxl error {code}: {msg}")
@@ -52,6 +59,11 @@ SIGNATURES = {
     "xl_merge_fwd": (_c.c_int, [_vp, _i64, _vp, _vp, _i64, _vp, _i32, _vp]),
     "xl_merge_bwd": (_c.c_int, [_vp, _i64, _vp, _vp, _i64, _vp, _vp, _i32, _vp]),
     "xl_check_inputs": (_c.c_int, [_c.POINTER(XLSamples), _vp, _i64, _vp, _vp, _i64, _vp]),
+    "xl_gen_workspace_bytes": (_sz, [_c.POINTER(XLGenParams)]),
+    "xl_gen_plan": (_c.c_int, [_c.POINTER(XLGenParams), _vp, _sz, _c.POINTER(_i64),
+                               _c.POINTER(_i64), _vp]),
+    "xl_gen_fill": (_c.c_int, [_c.POINTER(XLGenParams), _i32, _vp, _sz, _i64, _vp, _vp, _vp, _vp,
+                               _vp, _vp, _vp, _vp]),
 }
 
 
@@ -190,3 +202,40 @@ def xl_check_inputs(sigma, rgb, t_start, t_end, seg_offsets, ray_offsets=None,
                                  n_seg, None if ray_offsets is None else _dev(ray_offsets, "ray_offsets"),
                                  None if seg_ids is None else _dev(seg_ids, "seg_ids"), n_rays,
                                  _stream()))
+
+
+def gen_params(w, ray0: int = 0, n_rays: Optional[int] = None) -> XLGenParams:
+    """Device generator parameters for rays [ray0, ray0 + n_rays) of workload `w`
+    (a synth.Workload)."""
+    n = w.n_rays - ray0 if n_rays is None else n_rays
+    return XLGenParams(n, ray0, w.n_min, w.n_max, (_i32 * 3)(*w.grid), 0, w.sigma_mu, w.sigma_s,
+                       w.zero_frac, w.width_mean, w.t_far, w.seed)
+
+
+def xl_gen(w, dtype=torch.float32, ray0: int = 0, n_rays: Optional[int] = None,
+           device="cuda") -> dict:
+    """Generate rays of workload `w` on the device, packed region-major.
+
+    Returns device tensors sigma, rgb (storage dtype), t_start, t_end,
+    seg_offsets, ray_offsets, seg_ids."""
+    p = gen_params(w, ray0, n_rays)
+    L = lib()
+    wsb = L.xl_gen_workspace_bytes(ctypes.byref(p))
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=device)
+    ns, nseg = _i64(0), _i64(0)
+    _check(L.xl_gen_plan(ctypes.byref(p), ws.data_ptr(), wsb, ctypes.byref(ns), ctypes.byref(nseg),
+                         _stream()))
+    n, n_seg = ns.value, nseg.value
+    out = dict(sigma=torch.empty(n, dtype=dtype, device=device),
+               rgb=torch.empty((n, 3), dtype=dtype, device=device),
+               t_start=torch.empty(n, dtype=torch.float32, device=device),
+               t_end=torch.empty(n, dtype=torch.float32, device=device),
+               seg_offsets=torch.empty(n_seg + 1, dtype=torch.int64, device=device),
+               ray_offsets=torch.empty(p.n_rays + 1, dtype=torch.int64, device=device),
+               seg_ids=torch.empty(n_seg, dtype=torch.int64, device=device))
+    _check(L.xl_gen_fill(ctypes.byref(p), DTYPES[dtype], ws.data_ptr(), wsb, n_seg,
+                         _dev(out["sigma"], "sigma"), _dev(out["rgb"], "rgb"),
+                         _dev(out["t_start"], "t_start"), _dev(out["t_end"], "t_end"),
+                         _dev(out["seg_offsets"], "seg_offsets"), _dev(out["ray_offsets"], "ray_offsets"),
+                         _dev(out["seg_ids"], "seg_ids"), _stream()))
+    return out

@@ -6,7 +6,6 @@
 #include <cstdio>
 #include <cstring>
 
-#include "../../include/xl.h"
 #include "internal.h"
 
 namespace {
@@ -62,6 +61,17 @@ int check_segments(const xl::SamplesDev& s, const int64_t* seg_offsets, int64_t 
 }
 
 }  // namespace
+
+namespace xl {
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+int clear_error() { return ok(); }
+}  // namespace xl
 
 extern "C" {
 
@@ -183,6 +193,55 @@ int xl_check_inputs(const xl_samples* s, const int64_t* seg_offsets, int64_t n_s
                                "seg_ids out of range"};
   if (host != big && host >= 1 && host <= 8) return fail(XL_EINVAL, "invalid input: %s", what[host]);
   return ok();
+}
+
+static int check_gen(const xl_gen_params* p) {
+  if (p == nullptr) return fail(XL_EINVAL, "generator parameters are NULL");
+  if (p->n_rays < 0 || p->ray0 < 0) return fail(XL_EINVAL, "negative ray count or offset");
+  if (p->n_min < 0 || p->n_max < p->n_min) return fail(XL_EINVAL, "bad samples-per-ray range");
+  for (int c = 0; c < 3; ++c)
+    if (p->grid[c] < 1) return fail(XL_EINVAL, "grid dimensions must be >= 1");
+  if (static_cast<int64_t>(p->grid[0]) * p->grid[1] * p->grid[2] > 256 ||
+      p->grid[0] + p->grid[1] + p->grid[2] > 18)
+    return fail(XL_EINVAL, "grid too large (at most 256 regions, gx + gy + gz <= 18)");
+  if (!(p->width_mean > 0) || !(p->t_far > 0)) return fail(XL_EINVAL, "bad width_mean or t_far");
+  return XL_OK;
+}
+
+size_t xl_gen_workspace_bytes(const xl_gen_params* p) {
+  return check_gen(p) == XL_OK ? xl::gen_workspace_bytes(p) : 0;
+}
+
+int xl_gen_plan(const xl_gen_params* p, void* workspace, size_t workspace_bytes,
+                int64_t* n_samples, int64_t* n_seg, void* stream) {
+  int rc = check_gen(p);
+  if (rc) return rc;
+  if (!workspace || workspace_bytes < xl::gen_workspace_bytes(p) || !n_samples || !n_seg)
+    return fail(XL_EINVAL, "workspace missing or too small, or NULL outputs");
+  int overflow = 0;
+  rc = hip_status(xl::gen_plan(p, workspace, static_cast<hipStream_t>(stream), n_samples, n_seg,
+                               &overflow),
+                  "xl_gen_plan");
+  if (rc) return rc;
+  if (overflow) return fail(XL_EINVAL, "a ray crossed more regions than the grid allows");
+  return ok();
+}
+
+int xl_gen_fill(const xl_gen_params* p, int32_t dtype, void* workspace, size_t workspace_bytes,
+                int64_t n_seg, void* sigma, void* rgb, float* t_start, float* t_end,
+                int64_t* seg_offsets, int64_t* ray_offsets, int64_t* seg_ids, void* stream) {
+  int rc = check_gen(p);
+  if (rc) return rc;
+  if (dtype != XL_F32 && dtype != XL_BF16 && dtype != XL_F16)
+    return fail(XL_EINVAL, "unknown sample dtype %d", dtype);
+  if (!workspace || workspace_bytes < xl::gen_workspace_bytes(p))
+    return fail(XL_EINVAL, "workspace missing or too small");
+  if (n_seg < 0) return fail(XL_EINVAL, "negative segment count");
+  if (p->n_rays > 0 && (!sigma || !rgb || !t_start || !t_end))
+    return fail(XL_EINVAL, "NULL sample array");
+  return hip_status(xl::gen_fill(p, dtype, workspace, n_seg, sigma, rgb, t_start, t_end, seg_offsets,
+                                 ray_offsets, seg_ids, static_cast<hipStream_t>(stream)),
+                    "xl_gen_fill");
 }
 
 }  // extern "C"

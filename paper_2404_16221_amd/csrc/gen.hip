@@ -1,0 +1,527 @@
+// Synthetic sample generator on the device: the stand-in for per-region NeRF
+// evaluation in the serving loop, and the fast path for large benchmark
+// inputs.  It is the device twin of the host generator in synth.py: the same
+// counter-based draws (SplitMix64 output function, Steele, Lea & Flood 2014),
+// the same float32 logarithm for interval widths (atanh series in a fixed
+// operation order), the same sequential float64 position sums and box tags,
+// so t_start, t_end, the segment structure and the region-major layout are
+// bit-identical to the host's; densities use float32 library functions and
+// agree to about 1e-6 relative.
+//
+// Pipeline for a batch of rays (all asynchronous on one stream):
+//   gen_struct   one lane per ray: widths, positions and box tags -> the ray's
+//                segments (runs of one box) and its position scale/start
+//   block_hist   per block of 256 rays, segments per box
+//   scan         exclusive scans (segments per ray -> ray_offsets; per-box
+//                block counts -> stable region-major slots)
+//   gen_rank     packed index of every segment (stable counting sort by box)
+//   scan         packed segment lengths -> seg_offsets
+//   gen_fill     one lane per ray: regenerate samples into their packed slots
+#include <cstdio>
+
+#include "../../include/xl.h"
+#include "internal.h"
+#include "xl_device.hpp"
+
+namespace xl {
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+constexpr int kRayBlock = 256;
+constexpr int kDirTries = 64;
+constexpr int kRaySlots = 256;
+constexpr int kSampleStride = 2;
+
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return z;
+}
+__device__ __forceinline__ uint64_t draw(uint64_t key, uint64_t slot) {
+  return mix64(key + (slot + 1ull) * kGamma);
+}
+__device__ __forceinline__ double u53(uint64_t v) {
+  return static_cast<double>(v >> 11) * 0x1p-53;
+}
+// Bits [shift, shift + bits) of v as k / 2^bits.
+__device__ __forceinline__ double field(uint64_t v, int shift, int bits) {
+  return static_cast<double>((v >> shift) & ((1ull << bits) - 1ull)) * ldexp(1.0, -bits);
+}
+__device__ __forceinline__ float u24_open0(uint64_t v) {
+  return __fmul_rn(static_cast<float>((v >> 40) + 1ull), 0x1p-24f);
+}
+
+// float32 natural log from IEEE operations only: u = 2^e x, x in
+// [sqrt(1/2), sqrt(2)), log x = 2 atanh(s) with s = (x - 1)/(x + 1), summed to
+// s^9.  Operation order and constants match the host twin exactly.
+__device__ __forceinline__ float log_f32(float u) {
+  const int bits = __float_as_int(u);
+  int e = ((bits >> 23) & 0xff) - 127;
+  float x = __int_as_float((bits & 0x7fffff) | 0x3f800000);
+  if (x > __int_as_float(0x3FB504F3)) {
+    x = __fmul_rn(x, 0.5f);
+    e += 1;
+  }
+  const float s = __fdiv_rn(__fsub_rn(x, 1.f), __fadd_rn(x, 1.f));
+  const float s2 = __fmul_rn(s, s);
+  float p = __fadd_rn(__int_as_float(0x3E124925), __fmul_rn(s2, __int_as_float(0x3DE38E39)));
+  p = __fadd_rn(__int_as_float(0x3E4CCCCD), __fmul_rn(s2, p));
+  p = __fadd_rn(__int_as_float(0x3EAAAAAB), __fmul_rn(s2, p));
+  p = __fmul_rn(s2, p);
+  const float lx = __fmul_rn(2.f, __fadd_rn(s, __fmul_rn(s, p)));
+  return __fadd_rn(__fmul_rn(static_cast<float>(e), __int_as_float(0x3F317218)), lx);
+}
+
+struct GenDev {
+  int64_t n_rays, ray0;
+  int32_t n_min, n_max, gx, gy, gz, max_segs;
+  float wm, mu, sg;
+  double zero_frac, t_far;
+  uint64_t seedkey;  // mix64(seed)
+};
+
+struct RayState {
+  uint64_t key;
+  int32_t count;
+  double o[3], d[3];
+  double u_start;
+};
+
+__device__ __forceinline__ RayState ray_state(const GenDev& g, int64_t r) {
+  RayState s;
+  s.key = mix64(g.seedkey + static_cast<uint64_t>(g.ray0 + r) * kGamma);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) s.o[c] = __dsub_rn(__dmul_rn(2.0, u53(draw(s.key, c))), 1.0);
+  const uint64_t span = static_cast<uint64_t>(g.n_max - g.n_min + 1);
+  s.count = g.n_min + static_cast<int32_t>(((draw(s.key, 3) >> 32) * span) >> 32);
+  s.u_start = u53(draw(s.key, 4));
+  s.d[0] = 0.0; s.d[1] = 0.0; s.d[2] = 1.0;
+  for (int j = 0; j < kDirTries; ++j) {
+    double v[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      v[c] = __dsub_rn(__dmul_rn(2.0, u53(draw(s.key, 16 + 3 * j + c))), 1.0);
+    const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(v[0], v[0]), __dmul_rn(v[1], v[1])),
+                                __dmul_rn(v[2], v[2]));
+    if (r2 > 1e-12 && r2 <= 1.0) {
+      const double q = __dsqrt_rn(r2);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s.d[c] = __ddiv_rn(v[c], q);
+      break;
+    }
+  }
+  return s;
+}
+
+__device__ __forceinline__ double width_of(const GenDev& g, uint64_t key, int i) {
+  const uint64_t v = draw(key, kRaySlots + static_cast<uint64_t>(kSampleStride) * i);
+  return static_cast<double>(-__fmul_rn(g.wm, log_f32(u24_open0(v))));
+}
+
+__device__ __forceinline__ int box_of(const GenDev& g, const RayState& s, float t0, float t1) {
+  const double mid = __dmul_rn(0.5, __dadd_rn(static_cast<double>(t0), static_cast<double>(t1)));
+  const int gsz[3] = {g.gx, g.gy, g.gz};
+  int cell[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double p = __dadd_rn(s.o[c], __dmul_rn(mid, s.d[c]));
+    const double f = floor(__dmul_rn(__dmul_rn(__dadd_rn(p, 1.0), 0.5), static_cast<double>(gsz[c])));
+    int64_t k = static_cast<int64_t>(f);
+    k = k < 0 ? 0 : (k > gsz[c] - 1 ? gsz[c] - 1 : k);
+    cell[c] = static_cast<int>(k);
+  }
+  return cell[0] + g.gx * (cell[1] + g.gy * cell[2]);
+}
+
+// Workspace views (all per-ray arrays have n_rays entries; segment lists have
+// max_segs entries per ray).
+struct GenWs {
+  int32_t* nseg;      // [R]
+  int32_t* seg_box;   // [R * M]
+  int32_t* seg_len;   // [R * M]
+  int64_t* seg_pid;   // [R * M] packed index
+  double* scale;      // [R]
+  double* s0;         // [R]
+  int64_t* nseg64;    // [R]      scan input
+  int64_t* ray_off;   // [R + 1]  scan output (ray_offsets)
+  int64_t* blk_cnt;   // [K * nblk]
+  int64_t* blk_base;  // [K * nblk + 1]
+  int64_t* plen;      // [R * M]  packed segment lengths
+  int64_t* seg_off;   // [R * M + 1]
+  int64_t* seg_ids;   // [R * M]
+  int64_t* scan_tmp;  // scan scratch
+  int32_t* err;       // [1] 1 if some ray had more segments than max_segs
+};
+
+__global__ void gen_struct_kernel(GenDev g, GenWs w) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= g.n_rays) return;
+  const RayState s = ray_state(g, r);
+  double tot = 0.0;
+  for (int i = 0; i < s.count; ++i) tot = __dadd_rn(tot, width_of(g, s.key, i));
+  const double scale = tot > g.t_far ? __ddiv_rn(g.t_far, tot) : 1.0;
+  const double rest = __dsub_rn(g.t_far, __dmul_rn(tot, scale));
+  const double s0 = __dmul_rn(s.u_start, rest > 0.0 ? rest : 0.0);
+  w.scale[r] = scale;
+  w.s0[r] = s0;
+  const int M = g.max_segs;
+  int k = -1, cur = -1;
+  double run = s0;
+  for (int i = 0; i < s.count; ++i) {
+    const double t0 = run;
+    run = __dadd_rn(run, __dmul_rn(width_of(g, s.key, i), scale));
+    const int b = box_of(g, s, static_cast<float>(t0), static_cast<float>(run));
+    if (b != cur) {
+      if (k + 1 < M) {
+        ++k;
+        w.seg_box[r * M + k] = b;
+        w.seg_len[r * M + k] = 0;
+      } else {
+        w.err[0] = 1;
+      }
+      cur = b;
+    }
+    w.seg_len[r * M + k] += 1;
+  }
+  w.nseg[r] = k + 1;
+  w.nseg64[r] = k + 1;
+}
+
+// Segments per box in each block of kRayBlock rays (box-major layout).
+__global__ void block_hist_kernel(GenDev g, GenWs w, int64_t nblk, int K) {
+  __shared__ int hist[256];
+  const int64_t blk = blockIdx.x;
+  for (int b = threadIdx.x; b < K; b += blockDim.x) hist[b] = 0;
+  __syncthreads();
+  const int64_t r = blk * kRayBlock + threadIdx.x;
+  if (r < g.n_rays) {
+    const int M = g.max_segs;
+    for (int k = 0; k < w.nseg[r]; ++k) atomicAdd(&hist[w.seg_box[r * M + k]], 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < K; b += blockDim.x) w.blk_cnt[b * nblk + blk] = hist[b];
+}
+
+// Stable region-major slot of every segment: all segments of box b in earlier
+// blocks and earlier boxes (blk_base), plus those of earlier rays in the block.
+__global__ void gen_rank_kernel(GenDev g, GenWs w, int64_t nblk, int K) {
+  __shared__ int wave_cnt[kRayBlock / kWave][256];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int64_t blk = blockIdx.x;
+  const int64_t r = blk * kRayBlock + threadIdx.x;
+  const bool valid = r < g.n_rays;
+  const int M = g.max_segs;
+  const int ns = valid ? w.nseg[r] : 0;
+  int boxes[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) boxes[k] = (k < ns && k < M) ? w.seg_box[r * M + k] : -1;
+  int rank_in_wave[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) rank_in_wave[k] = 0;
+  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (int b = 0; b < K; ++b) {
+    bool has = false;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) has |= boxes[k] == b;
+    const unsigned long long m = __ballot(has);
+    if (lane == 0) wave_cnt[wave][b] = __popcll(m);
+    const int rk = __popcll(m & lt);
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (boxes[k] == b) rank_in_wave[k] = rk;
+  }
+  __syncthreads();
+  if (!valid) return;
+  for (int k = 0; k < ns && k < 16; ++k) {
+    const int b = boxes[k];
+    int before = 0;
+    for (int v = 0; v < wave; ++v) before += wave_cnt[v][b];
+    const int64_t p = w.blk_base[b * nblk + blk] + before + rank_in_wave[k];
+    w.seg_pid[r * M + k] = p;
+    w.plen[p] = w.seg_len[r * M + k];
+    w.seg_ids[w.ray_off[r] + k] = p;
+  }
+}
+
+template <int DT>
+__device__ __forceinline__ void put_sample(void* sigma, void* rgb, int64_t i, float sg, float c0,
+                                           float c1, float c2) {
+  if (DT == kF32) {
+    static_cast<float*>(sigma)[i] = sg;
+    float* C = static_cast<float*>(rgb) + 3 * i;
+    C[0] = c0; C[1] = c1; C[2] = c2;
+  } else {
+    static_cast<uint16_t*>(sigma)[i] = from_f32<DT>(sg);
+    uint16_t* C = static_cast<uint16_t*>(rgb) + 3 * i;
+    C[0] = from_f32<DT>(c0); C[1] = from_f32<DT>(c1); C[2] = from_f32<DT>(c2);
+  }
+}
+
+template <int DT>
+__global__ void gen_fill_kernel(GenDev g, GenWs w, void* __restrict__ sigma, void* __restrict__ rgb,
+                                float* __restrict__ t_start, float* __restrict__ t_end) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= g.n_rays) return;
+  const uint64_t key = mix64(g.seedkey + static_cast<uint64_t>(g.ray0 + r) * kGamma);
+  const uint64_t span = static_cast<uint64_t>(g.n_max - g.n_min + 1);
+  const int count = g.n_min + static_cast<int32_t>(((draw(key, 3) >> 32) * span) >> 32);
+  const double scale = w.scale[r];
+  double run = w.s0[r];
+  const int M = g.max_segs;
+  const int ns = w.nseg[r];
+  int k = 0, left = ns > 0 ? w.seg_len[r * M] : 0;
+  int64_t dst = ns > 0 ? w.seg_off[w.seg_pid[r * M]] : 0;
+  const float two_pi = 6.283185307179586f;
+  for (int i = 0; i < count; ++i) {
+    if (left == 0 && k + 1 < ns) {
+      ++k;
+      left = w.seg_len[r * M + k];
+      dst = w.seg_off[w.seg_pid[r * M + k]];
+    }
+    const double t0 = run;
+    run = __dadd_rn(run, __dmul_rn(width_of(g, key, i), scale));
+    const uint64_t base = kRaySlots + static_cast<uint64_t>(kSampleStride) * i;
+    const uint64_t v1 = draw(key, base), v2 = draw(key, base + 1);
+    const float u1 = static_cast<float>(field(v1, 20, 20) + 0x1p-20);
+    const float u2 = static_cast<float>(field(v1, 0, 20));
+    const float z = sqrtf(-2.f * logf(u1)) * cosf(two_pi * u2);
+    float sg = expf(g.mu + g.sg * z);
+    if (field(v2, 48, 16) < g.zero_frac) sg = 0.f;
+    put_sample<DT>(sigma, rgb, dst, sg, static_cast<float>(field(v2, 32, 16)),
+                   static_cast<float>(field(v2, 16, 16)), static_cast<float>(field(v2, 0, 16)));
+    t_start[dst] = static_cast<float>(t0);
+    t_end[dst] = static_cast<float>(run);
+    ++dst;
+    --left;
+  }
+}
+
+// ---------------------------------------------------------------- scan
+// Exclusive scan of int64 with out[n] = total.  Blocks of 1024 elements, block
+// totals scanned recursively (scratch: ceil(n/1024) + ceil(n/1024^2) + ...).
+constexpr int kScanBlock = 1024;
+
+__global__ __launch_bounds__(kScanBlock) void scan_block_kernel(const int64_t* __restrict__ in,
+                                                                int64_t* __restrict__ out, int64_t n,
+                                                                int64_t* __restrict__ sums) {
+  __shared__ int64_t wsum[kScanBlock / kWave];
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kScanBlock + threadIdx.x;
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int64_t x = i < n ? in[i] : 0;
+  int64_t v = x;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t y = __shfl_up(v, d);
+    if (lane >= d) v += y;
+  }
+  if (lane == kWave - 1) wsum[wave] = v;
+  __syncthreads();
+  if (wave == 0) {
+    int64_t s = lane < kScanBlock / kWave ? wsum[lane] : 0;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int64_t y = __shfl_up(s, d);
+      if (lane >= d) s += y;
+    }
+    if (lane < kScanBlock / kWave) wsum[lane] = s;
+  }
+  __syncthreads();
+  const int64_t before = wave > 0 ? wsum[wave - 1] : 0;
+  if (i < n) out[i] = before + v - x;
+  if (threadIdx.x == kScanBlock - 1) sums[blockIdx.x] = wsum[kScanBlock / kWave - 1];
+}
+
+__global__ void scan_add_kernel(int64_t* __restrict__ out, int64_t n, const int64_t* __restrict__ offs) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kScanBlock + threadIdx.x;
+  if (i < n) out[i] += offs[blockIdx.x];
+}
+
+__global__ void scan_total_kernel(int64_t* __restrict__ out, int64_t n, const int64_t* __restrict__ in) {
+  out[n] = n > 0 ? out[n - 1] + in[n - 1] : 0;
+}
+
+size_t scan_tmp_elems(int64_t n) {
+  size_t total = 0;
+  int64_t m = n;
+  while (m > 1) {
+    m = (m + kScanBlock - 1) / kScanBlock;
+    total += static_cast<size_t>(m) + 1;
+  }
+  return total + 2;
+}
+
+// out has n + 1 entries; tmp has scan_tmp_elems(n) entries.
+hipError_t scan_exclusive(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t st) {
+  if (n <= 0) {
+    hipLaunchKernelGGL(scan_total_kernel, dim3(1), dim3(1), 0, st, out, static_cast<int64_t>(0), in);
+    return hipGetLastError();
+  }
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  int64_t* sums = tmp;
+  int64_t* offs = tmp + nb;
+  hipLaunchKernelGGL(scan_block_kernel, dim3(static_cast<unsigned>(nb)), dim3(kScanBlock), 0, st, in,
+                     out, n, sums);
+  if (nb > 1) {
+    hipError_t e = scan_exclusive(sums, offs, nb, offs + nb + 1, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_add_kernel, dim3(static_cast<unsigned>(nb)), dim3(kScanBlock), 0, st,
+                       out, n, offs);
+  }
+  hipLaunchKernelGGL(scan_total_kernel, dim3(1), dim3(1), 0, st, out, n, in);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- host side
+struct GenLayout {
+  int64_t R, M, K, nblk, RM;
+  size_t off[16];
+  size_t bytes;
+};
+
+static GenLayout layout(const xl_gen_params* p) {
+  GenLayout L;
+  L.R = p->n_rays;
+  L.M = p->grid[0] + p->grid[1] + p->grid[2] - 2;
+  if (L.M < 1) L.M = 1;
+  L.K = static_cast<int64_t>(p->grid[0]) * p->grid[1] * p->grid[2];
+  L.nblk = (L.R + kRayBlock - 1) / kRayBlock;
+  L.RM = L.R * L.M;
+  const int64_t KB = L.K * L.nblk;
+  const size_t sizes[] = {
+      sizeof(int32_t) * L.R,           // nseg
+      sizeof(int32_t) * L.RM,          // seg_box
+      sizeof(int32_t) * L.RM,          // seg_len
+      sizeof(int64_t) * L.RM,          // seg_pid
+      sizeof(double) * L.R,            // scale
+      sizeof(double) * L.R,            // s0
+      sizeof(int64_t) * L.R,           // nseg64
+      sizeof(int64_t) * (L.R + 1),     // ray_off
+      sizeof(int64_t) * KB,            // blk_cnt
+      sizeof(int64_t) * (KB + 1),      // blk_base
+      sizeof(int64_t) * L.RM,          // plen
+      sizeof(int64_t) * (L.RM + 1),    // seg_off
+      sizeof(int64_t) * L.RM,          // seg_ids
+      sizeof(int64_t) * (scan_tmp_elems(L.RM > KB ? (L.RM > L.R ? L.RM : L.R) : (KB > L.R ? KB : L.R))),
+      sizeof(int32_t) * 4,             // err
+  };
+  size_t o = 0;
+  for (int i = 0; i < 15; ++i) {
+    L.off[i] = o;
+    o += (sizes[i] + 255) & ~static_cast<size_t>(255);
+  }
+  L.bytes = o;
+  return L;
+}
+
+static GenWs views(const GenLayout& L, void* ws) {
+  char* b = static_cast<char*>(ws);
+  GenWs w;
+  w.nseg = reinterpret_cast<int32_t*>(b + L.off[0]);
+  w.seg_box = reinterpret_cast<int32_t*>(b + L.off[1]);
+  w.seg_len = reinterpret_cast<int32_t*>(b + L.off[2]);
+  w.seg_pid = reinterpret_cast<int64_t*>(b + L.off[3]);
+  w.scale = reinterpret_cast<double*>(b + L.off[4]);
+  w.s0 = reinterpret_cast<double*>(b + L.off[5]);
+  w.nseg64 = reinterpret_cast<int64_t*>(b + L.off[6]);
+  w.ray_off = reinterpret_cast<int64_t*>(b + L.off[7]);
+  w.blk_cnt = reinterpret_cast<int64_t*>(b + L.off[8]);
+  w.blk_base = reinterpret_cast<int64_t*>(b + L.off[9]);
+  w.plen = reinterpret_cast<int64_t*>(b + L.off[10]);
+  w.seg_off = reinterpret_cast<int64_t*>(b + L.off[11]);
+  w.seg_ids = reinterpret_cast<int64_t*>(b + L.off[12]);
+  w.scan_tmp = reinterpret_cast<int64_t*>(b + L.off[13]);
+  w.err = reinterpret_cast<int32_t*>(b + L.off[14]);
+  return w;
+}
+
+static GenDev dev_params(const xl_gen_params* p, const GenLayout& L) {
+  GenDev g;
+  g.n_rays = p->n_rays;
+  g.ray0 = p->ray0;
+  g.n_min = p->n_min;
+  g.n_max = p->n_max;
+  g.gx = p->grid[0];
+  g.gy = p->grid[1];
+  g.gz = p->grid[2];
+  g.max_segs = static_cast<int32_t>(L.M);
+  g.wm = static_cast<float>(p->width_mean);
+  g.mu = static_cast<float>(p->sigma_mu);
+  g.sg = static_cast<float>(p->sigma_s);
+  g.zero_frac = p->zero_frac;
+  g.t_far = p->t_far;
+  g.seedkey = mix64(p->seed);
+  return g;
+}
+
+size_t gen_workspace_bytes(const xl_gen_params* p) { return layout(p).bytes; }
+
+int64_t gen_max_segments(const xl_gen_params* p) { return layout(p).RM; }
+
+static inline unsigned blocks(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
+
+hipError_t gen_plan(const xl_gen_params* p, void* ws, hipStream_t st, int64_t* n_samples,
+                    int64_t* n_seg, int* overflow) {
+  const GenLayout L = layout(p);
+  const GenWs w = views(L, ws);
+  const GenDev g = dev_params(p, L);
+  hipError_t e = hipMemsetAsync(w.err, 0, sizeof(int32_t), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gen_struct_kernel, dim3(blocks(L.R, 128)), dim3(128), 0, st, g, w);
+  hipLaunchKernelGGL(block_hist_kernel, dim3(static_cast<unsigned>(L.nblk)), dim3(kRayBlock), 0, st,
+                     g, w, L.nblk, static_cast<int>(L.K));
+  if ((e = scan_exclusive(w.nseg64, w.ray_off, L.R, w.scan_tmp, st)) != hipSuccess) return e;
+  if ((e = scan_exclusive(w.blk_cnt, w.blk_base, L.K * L.nblk, w.scan_tmp, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(gen_rank_kernel, dim3(static_cast<unsigned>(L.nblk)), dim3(kRayBlock), 0, st, g,
+                     w, L.nblk, static_cast<int>(L.K));
+  int64_t ns = 0;
+  if ((e = hipMemcpyAsync(&ns, w.ray_off + L.R, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  if ((e = scan_exclusive(w.plen, w.seg_off, ns, w.scan_tmp, st)) != hipSuccess) return e;
+  int64_t n = 0;
+  int err = 0;
+  if ((e = hipMemcpyAsync(&n, w.seg_off + ns, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(&err, w.err, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  *n_samples = n;
+  *n_seg = ns;
+  *overflow = err;
+  return hipSuccess;
+}
+
+hipError_t gen_fill(const xl_gen_params* p, int dtype, void* ws, int64_t n_seg, void* sigma, void* rgb,
+                    float* t_start, float* t_end, int64_t* seg_offsets, int64_t* ray_offsets,
+                    int64_t* seg_ids, hipStream_t st) {
+  const GenLayout L = layout(p);
+  const GenWs w = views(L, ws);
+  const GenDev g = dev_params(p, L);
+  const dim3 grid(blocks(L.R, 128));
+  switch (dtype) {
+    case kF32:
+      hipLaunchKernelGGL(gen_fill_kernel<kF32>, grid, dim3(128), 0, st, g, w, sigma, rgb, t_start, t_end);
+      break;
+    case kBF16:
+      hipLaunchKernelGGL(gen_fill_kernel<kBF16>, grid, dim3(128), 0, st, g, w, sigma, rgb, t_start, t_end);
+      break;
+    default:
+      hipLaunchKernelGGL(gen_fill_kernel<kF16>, grid, dim3(128), 0, st, g, w, sigma, rgb, t_start, t_end);
+      break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (seg_offsets && (e = hipMemcpyAsync(seg_offsets, w.seg_off, sizeof(int64_t) * (n_seg + 1),
+                                         hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return e;
+  if (ray_offsets && (e = hipMemcpyAsync(ray_offsets, w.ray_off, sizeof(int64_t) * (L.R + 1),
+                                         hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return e;
+  if (seg_ids && (e = hipMemcpyAsync(seg_ids, w.seg_ids, sizeof(int64_t) * n_seg,
+                                     hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+
+}  // namespace xl

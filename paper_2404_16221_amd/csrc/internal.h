@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/xl.h"
+
 namespace xl {
 
 struct SamplesDev {
@@ -36,5 +38,17 @@ hipError_t launch_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* 
 hipError_t launch_check(const SamplesDev& s, const int64_t* seg_offsets, int64_t n_seg,
                         const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
                         int* code_dev, hipStream_t stream);
+
+// Thread-local error message for xl_last_error (api.cpp); returns `code`.
+int set_error(int code, const char* fmt, ...);
+int clear_error();
+
+// Device generator (gen.hip).
+size_t gen_workspace_bytes(const xl_gen_params* p);
+hipError_t gen_plan(const xl_gen_params* p, void* ws, hipStream_t st, int64_t* n_samples,
+                    int64_t* n_seg, int* overflow);
+hipError_t gen_fill(const xl_gen_params* p, int dtype, void* ws, int64_t n_seg, void* sigma,
+                    void* rgb, float* t_start, float* t_end, int64_t* seg_offsets,
+                    int64_t* ray_offsets, int64_t* seg_ids, hipStream_t st);
 
 }  // namespace xl

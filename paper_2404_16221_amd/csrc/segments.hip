@@ -94,74 +94,80 @@ __device__ __forceinline__ void stage_ends(const int64_t* __restrict__ off, int6
   }
 }
 
-template <int DT>
-__global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
-                                                         const int64_t* __restrict__ off,
-                                                         int64_t n_seg, int64_t n_tiles,
-                                                         float* __restrict__ seg_out,
-                                                         TileRec* __restrict__ recs) {
-  __shared__ int endloc_all[kWavesPerBlock][kTile];
-  __shared__ int64_t tailseg_all[kWavesPerBlock];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
-  const bool active = t < n_tiles;
-  int* endloc = endloc_all[wave];
+// Per-lane view of one tile: the lane's kRun samples and the segment ends
+// among them.  FULL = every sample of the tile exists (all tiles but a ragged
+// last one); otherwise missing samples act as one-sample segments of their own
+// that are never written.
+template <int DT, bool FULL>
+struct LaneRun {
+  Smp x[kRun];
+  int ends[kRun];   // local id of the segment ending at sample j, or -1
+  bool endf[kRun];  // sample j ends a segment (or does not exist)
+  bool h0;          // sample 0 starts a segment
+  int cnt;          // samples that exist (kRun when FULL)
+  int64_t i0;       // index of sample 0
+
+  __device__ __forceinline__ void load(const SamplesDev& s, const int* endloc, int lane,
+                                       bool start_head, int64_t base) {
+    i0 = base + static_cast<int64_t>(lane) * kRun;
+    if (FULL) {
+      cnt = kRun;
+    } else {
+      const int64_t rem = s.n - i0;
+      cnt = rem <= 0 ? 0 : (rem >= kRun ? kRun : static_cast<int>(rem));
+    }
 #pragma unroll
-  for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
-  if (lane == 0) tailseg_all[wave] = -1;
-  __syncthreads();
-  const int64_t n = s.n;
-  const int64_t base = t * kTile;
-  int64_t s_lo = 0;
-  bool start_head = false;
-  if (active) {
-    s_lo = recs[t].first_seg;
-    stage_ends<true>(off, n_seg, n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], seg_out);
-    start_head = (off[s_lo] == base);
+    for (int j = 0; j < kRun; ++j) ends[j] = endloc[lane * kRun + j];
+    h0 = lane == 0 ? start_head : (endloc[lane * kRun - 1] >= 0);
+    if (!FULL && cnt == 0) h0 = true;
+    float sg[kRun], c[3 * kRun], a[kRun], b[kRun];
+    if (FULL || cnt > 0) load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, i0, FULL ? kRun : cnt, sg, c, a, b);
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+      x[j] = make_sample(sg[j], c[3 * j], c[3 * j + 1], c[3 * j + 2], a[j], b[j]);
+      endf[j] = (ends[j] >= 0) || (!FULL && j >= cnt);
+    }
   }
-  __syncthreads();
-  if (!active) return;
+  __device__ __forceinline__ bool head(int j) const { return j == 0 ? h0 : endf[j - 1]; }
+};
 
-  int ends[kRun];
-#pragma unroll
-  for (int j = 0; j < kRun; ++j) ends[j] = endloc[lane * kRun + j];
-  const bool h0 = lane == 0 ? start_head : (endloc[lane * kRun - 1] >= 0);
+template <int DT, bool FULL>
+__device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int64_t t,
+                                         int64_t s_lo, bool start_head, int lane,
+                                         const int* endloc, int64_t tailseg,
+                                         float* __restrict__ seg_out, TileRec* __restrict__ recs) {
+  LaneRun<DT, FULL> R;
+  R.load(s, endloc, lane, start_head, t * kTile);
 
-  const int64_t i0 = base + static_cast<int64_t>(lane) * kRun;
-  const int64_t rem = n - i0;
-  const int cnt = rem <= 0 ? 0 : (rem >= kRun ? kRun : static_cast<int>(rem));
-  float sg[kRun], c[3 * kRun], a[kRun], b[kRun];
-  if (cnt > 0) load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, i0, cnt, sg, c, a, b);
-
-  Range cur = range_identity(), pend = range_identity();
-  bool have = false, cur_head = false, has_pend = false, any_end = false, any_head = false;
+  // Serial fold of the lane's samples; a head restarts the open range.
+  Range cur = range_of(R.x[0]), pend = range_identity();
+  float Tc = R.x[0].e;
+  bool cur_head = R.h0, has_pend = false, any_end = false, any_head = R.h0;
   int pend_seg = -1;
 #pragma unroll
   for (int j = 0; j < kRun; ++j) {
-    if (j < cnt) {
-      const Smp x = make_sample(sg[j], c[3 * j], c[3 * j + 1], c[3 * j + 2], a[j], b[j]);
-      const bool head = j == 0 ? h0 : (ends[j - 1] >= 0);
-      any_head |= head;
-      if (!have || head) {
-        cur = range_of(x);
-        cur_head = head;
-        have = true;
-      } else {
-        append(cur, x);
-      }
-      if (ends[j] >= 0) {
-        any_end = true;
+    if (j > 0) {
+      const bool hd = R.head(j);
+      append(cur, Tc, R.x[j]);
+      cur = select(hd, range_of(R.x[j]), cur);
+      Tc = hd ? R.x[j].e : Tc;
+      cur_head = cur_head || hd;
+      any_head = any_head || hd;
+    }
+    if (R.endf[j]) {
+      any_end = true;
+      if (R.ends[j] >= 0) {
         if (cur_head) {
-          write_tuple(seg_out, n_seg, s_lo + ends[j], cur);
+          write_tuple(seg_out, n_seg, s_lo + R.ends[j], cur);
         } else {
           pend = cur;
-          pend_seg = ends[j];
+          pend_seg = R.ends[j];
           has_pend = true;
         }
-        have = false;
       }
     }
   }
+  const bool have = !R.endf[kRun - 1];
 
   // Carry the open range across lanes.
   Range inc = have ? cur : range_identity();
@@ -184,10 +190,41 @@ __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
     const int flags = (start_head ? kStartHead : 0) | (end_mask ? kHasEnd : 0) |
                       (head_mask ? kHasHead : 0) | (have ? kTailOpen : 0);
     recs[t].flags = flags;
-    recs[t].tail_seg = tailseg_all[wave];
+    recs[t].tail_seg = tailseg;
     if (have) recs[t].tail = inc;
     if (!start_head && !end_mask) recs[t].head = inc;
   }
+}
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
+                                                         const int64_t* __restrict__ off,
+                                                         int64_t n_seg, int64_t n_tiles,
+                                                         float* __restrict__ seg_out,
+                                                         TileRec* __restrict__ recs) {
+  __shared__ int endloc_all[kWavesPerBlock][kTile];
+  __shared__ int64_t tailseg_all[kWavesPerBlock];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
+  const bool active = t < n_tiles;
+  int* endloc = endloc_all[wave];
+#pragma unroll
+  for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
+  if (lane == 0) tailseg_all[wave] = -1;
+  __syncthreads();
+  int64_t s_lo = 0;
+  bool start_head = false;
+  if (active) {
+    s_lo = recs[t].first_seg;
+    stage_ends<true>(off, n_seg, s.n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], seg_out);
+    start_head = (off[s_lo] == t * kTile);
+  }
+  __syncthreads();
+  if (!active) return;
+  if ((t + 1) * kTile <= s.n)
+    fwd_tile<DT, true>(s, n_seg, t, s_lo, start_head, lane, endloc, tailseg_all[wave], seg_out, recs);
+  else
+    fwd_tile<DT, false>(s, n_seg, t, s_lo, start_head, lane, endloc, tailseg_all[wave], seg_out, recs);
 }
 
 // Completes segments that cross tile boundaries and leaves, in every tile
@@ -222,122 +259,100 @@ __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restri
   }
 }
 
-template <int DT>
-__global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
-    SamplesDev s, const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
-    const TileRec* __restrict__ recs, const float* __restrict__ gseg, void* __restrict__ gsig_p,
-    void* __restrict__ grgb_p) {
-  __shared__ int endloc_all[kWavesPerBlock][kTile];
-  __shared__ int64_t tailseg_all[kWavesPerBlock];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
-  const bool active = t < n_tiles;
-  int* endloc = endloc_all[wave];
-#pragma unroll
-  for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
-  if (lane == 0) tailseg_all[wave] = -1;
-  __syncthreads();
-  const int64_t n = s.n;
-  const int64_t base = t * kTile;
-  int64_t s_lo = 0;
-  if (active) {
-    s_lo = recs[t].first_seg;
-    stage_ends<false>(off, n_seg, n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], nullptr);
-  }
-  __syncthreads();
-  if (!active) return;
-
+template <int DT, bool FULL>
+__device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int64_t t,
+                                         int64_t s_lo, int lane, const int* endloc,
+                                         const TileRec* __restrict__ recs,
+                                         const float* __restrict__ gseg, void* __restrict__ gsig_p,
+                                         void* __restrict__ grgb_p) {
   const int flags = recs[t].flags;
   const bool start_head = (flags & kStartHead) != 0;
   const bool tail_open = (flags & kTailOpen) != 0;
-  int ends[kRun];
-#pragma unroll
-  for (int j = 0; j < kRun; ++j) ends[j] = endloc[lane * kRun + j];
-  const bool h0 = lane == 0 ? start_head : (endloc[lane * kRun - 1] >= 0);
+  LaneRun<DT, FULL> R;
+  R.load(s, endloc, lane, start_head, t * kTile);
 
-  const int64_t i0 = base + static_cast<int64_t>(lane) * kRun;
-  const int64_t rem = n - i0;
-  const int cnt = rem <= 0 ? 0 : (rem >= kRun ? kRun : static_cast<int>(rem));
-  float sg[kRun], c[3 * kRun], a[kRun], b[kRun];
-  if (cnt > 0) load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, i0, cnt, sg, c, a, b);
-  Smp x[kRun];
-#pragma unroll
-  for (int j = 0; j < kRun; ++j) x[j] = make_sample(sg[j], c[3 * j], c[3 * j + 1], c[3 * j + 2], a[j], b[j]);
-
-  // Pass 1: lane ranges for both scans.
-  Range cur = range_identity(), first = range_identity();
-  bool have = false, cur_head = false, has_end = false;
+  // Pass 1: serial fold.  Records, for every sample, the transmittance,
+  // opacity and sum_{k<j} w_k (m_j - m_k) in front of it, relative to the
+  // start of the open range (the lane start for samples before the lane's
+  // first head), and keeps the lane's first range (up to its first segment end)
+  // for the reverse scan.
+  float Tl[kRun], Al[kRun], Zl[kRun];
+  Range cur = range_of(R.x[0]), first = range_identity();
+  float Tc = R.x[0].e;
+  bool cur_head = R.h0, seen_end = false;
   int first_end = -1;
+  int fhp = R.h0 ? 0 : kRun;  // position of the lane's first head
+  Tl[0] = 1.f; Al[0] = 0.f; Zl[0] = 0.f;
 #pragma unroll
   for (int j = 0; j < kRun; ++j) {
-    if (j < cnt) {
-      const bool head = j == 0 ? h0 : (ends[j - 1] >= 0);
-      if (!have || head) {
-        cur = range_of(x[j]);
-        cur_head = head;
-        have = true;
-      } else {
-        append(cur, x[j]);
-      }
-      if (ends[j] >= 0) {
-        if (!has_end) {
-          first = cur;
-          first_end = ends[j];
-          has_end = true;
-        }
-        have = false;
-      }
+    if (j > 0) {
+      const bool hd = R.head(j);
+      Tl[j] = hd ? 1.f : Tc;
+      Al[j] = hd ? 0.f : cur.A;
+      Zl[j] = hd ? 0.f : fmaf(cur.A, R.x[j].m - cur.m1, cur.B);
+      append(cur, Tc, R.x[j]);
+      cur = select(hd, range_of(R.x[j]), cur);
+      Tc = hd ? R.x[j].e : Tc;
+      cur_head = cur_head || hd;
+      fhp = (hd && fhp == kRun) ? j : fhp;
+    }
+    if (R.endf[j] && !seen_end) {
+      first = cur;
+      first_end = R.ends[j];
+      seen_end = true;
     }
   }
-  Range inc = have ? cur : range_identity();
+  const bool have = !R.endf[kRun - 1];
+  Pre inc = have ? pre_of(cur) : pre_identity();
   bool fin = have ? cur_head : true;
-  Range rinc = has_end ? first : (cnt > 0 ? cur : range_identity());
-  bool rfl = has_end || cnt == 0;
-  int rseg = has_end ? first_end : -1;
-  scan_up(inc, fin, lane);
+  Range rinc = seen_end ? first : cur;
+  bool rfl = seen_end;
+  int rseg = seen_end ? first_end : -1;
+  scan_up_pre(inc, fin, lane);
   scan_down(rinc, rfl, rseg, lane);
-  const Range ex = shfl_up_range(inc, 1);
+  Pre ex;
+  ex.tau = __shfl_up(inc.tau, 1); ex.A = __shfl_up(inc.A, 1);
+  ex.B = __shfl_up(inc.B, 1); ex.m1 = __shfl_up(inc.m1, 1);
   const int exf = __shfl_up(static_cast<int>(fin), 1);
   const Range sx = shfl_down_range(rinc, 1);
   const int sxf = __shfl_down(static_cast<int>(rfl), 1);
   const int sxseg = __shfl_down(rseg, 1);
 
-  // Prefix carried into this lane's first sample (used unless it is a head).
-  Range pc = range_identity();
-  if (lane > 0 && exf) {
-    pc = ex;
-  } else if (!start_head) {
-    pc = lane > 0 ? combine(recs[t].pre, ex) : recs[t].pre;
+  // Prefix of the segment in front of the lane (identity if sample 0 is a head).
+  Pre pc = pre_identity();
+  if (!R.h0) {
+    if (lane > 0 && exf) pc = ex;
+    else if (!start_head) pc = lane > 0 ? combine_pre(pre_of(recs[t].pre), ex) : pre_of(recs[t].pre);
   }
-  // Suffix carried out of this lane's last sample (used unless it is an end),
-  // as a range in its own frame (transmittance 1 at its first sample).
+  // Suffix behind the lane's last sample, in its own frame (unused if that
+  // sample ends its segment).
   Range sc = range_identity();
   int64_t cseg = -1;
-  if (lane < kWave - 1 && sxf) {
-    sc = sx;
-    cseg = s_lo + sxseg;
-  } else if (tail_open) {
-    sc = lane < kWave - 1 ? combine(sx, recs[t].suf) : recs[t].suf;
-    cseg = recs[t].tail_seg;
-  }
-
-  // Pass 2: exclusive prefix state of every sample inside its segment:
-  // optical depth, opacity and sum_{k<j} w_k (m_j - m_k).
-  float Pt[kRun], PA[kRun], PZ[kRun];
-  Range P = pc;
-#pragma unroll
-  for (int j = 0; j < kRun; ++j) {
-    const bool head = j == 0 ? h0 : (ends[j - 1] >= 0);
-    if (head) {
-      Pt[j] = 0.f; PA[j] = 0.f; PZ[j] = 0.f;
-      P = range_of(x[j]);
-    } else {
-      Pt[j] = P.tau; PA[j] = P.A; PZ[j] = fmaf(P.A, x[j].m - P.m1, P.B);
-      append(P, x[j]);
+  if (have) {
+    if (lane < kWave - 1 && sxf) {
+      sc = sx;
+      cseg = s_lo + sxseg;
+    } else if (tail_open) {
+      sc = lane < kWave - 1 ? combine(sx, recs[t].suf) : recs[t].suf;
+      cseg = recs[t].tail_seg;
     }
   }
 
-  // Pass 3: reverse sweep.  The suffix sums are weighted with each sample's
+  // Samples before the lane's first head continue the carried prefix.
+  const float Tp = exp_neg(pc.tau);
+  float PT[kRun], PA[kRun], PZ[kRun];
+#pragma unroll
+  for (int j = 0; j < kRun; ++j) {
+    const bool inF = j < fhp;
+    const float Tm = inF ? Tp : 1.f;
+    const float Am = inF ? pc.A : 0.f;
+    const float Bm = inF ? fmaf(pc.A, R.x[j].m - pc.m1, pc.B) : 0.f;
+    PT[j] = Tm * Tl[j];
+    PA[j] = fmaf(Tm, Al[j], Am);
+    PZ[j] = fmaf(Tm, Zl[j], Bm);
+  }
+
+  // Pass 3: reverse sweep.  Suffix sums are weighted with each sample's
   // transmittance from the start of its segment:
   //   SC = sum_{k>j} w_k c_k, SA = sum_{k>j} w_k, SF = sum_{k>j} w_k (m_k - mf),
   //   SL = distortion of the samples after j,
@@ -348,12 +363,11 @@ __global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
   // taken before it is multiplied.
   float g[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float SCr = 0.f, SCg = 0.f, SCb = 0.f, SA = 0.f, SF = 0.f, SL = 0.f, mf = 0.f, TN = 1.f;
-  if (cnt > 0 && ends[cnt - 1] < 0) {
-    const float tq = Pt[cnt - 1] + x[cnt - 1].tau;
-    const float Tq = exp_neg(tq);
+  if (have) {
+    const float Tq = PT[kRun - 1] * R.x[kRun - 1].e;
     SCr = Tq * sc.cr; SCg = Tq * sc.cg; SCb = Tq * sc.cb;
     SA = Tq * sc.A; SF = Tq * sc.F; SL = Tq * Tq * sc.L; mf = sc.m0;
-    TN = exp_neg(tq + sc.tau);
+    TN = Tq * exp_neg(sc.tau);
     if (cseg >= 0 && cseg < n_seg) {
 #pragma unroll
       for (int k = 0; k < 7; ++k) g[k] = gseg[k * n_seg + cseg];
@@ -362,41 +376,41 @@ __global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
   float dsg[kRun], dc[3 * kRun];
 #pragma unroll
   for (int j = kRun - 1; j >= 0; --j) {
-    dsg[j] = 0.f; dc[3 * j] = dc[3 * j + 1] = dc[3 * j + 2] = 0.f;
-    if (j < cnt) {
-      const Smp& q = x[j];
-      if (ends[j] >= 0) {
-        SCr = SCg = SCb = 0.f; SA = 0.f; SF = 0.f; SL = 0.f; mf = q.m;
-        TN = exp_neg(Pt[j] + q.tau);
-        const int64_t sgi = s_lo + ends[j];
+    const Smp& q = R.x[j];
+    const float Ti1 = PT[j] * q.e;
+    const bool e = R.endf[j];  // sample j closes its segment: the suffix restarts
+    SCr = e ? 0.f : SCr; SCg = e ? 0.f : SCg; SCb = e ? 0.f : SCb;
+    SA = e ? 0.f : SA; SF = e ? 0.f : SF; SL = e ? 0.f : SL;
+    mf = e ? q.m : mf;
+    TN = e ? Ti1 : TN;
+    if (R.ends[j] >= 0) {
+      const int64_t sgi = s_lo + R.ends[j];
 #pragma unroll
-        for (int k = 0; k < 7; ++k) g[k] = gseg[k * n_seg + sgi];
-      }
-      const float Ti = exp_neg(Pt[j]);
-      const float Ti1 = exp_neg(Pt[j] + q.tau);
-      const float w = Ti * q.alpha;
-      const float Zs = fmaf(SA, mf - q.m, SF);
-      const float wd3 = w * q.delta * (1.f / 3.f);
-      const float cdot = g[1] * fmaf(Ti1, q.c0, -SCr) + g[2] * fmaf(Ti1, q.c1, -SCg) +
-                         g[3] * fmaf(Ti1, q.c2, -SCb);
-      const float dL = 2.f * (TN * PZ[j] - PA[j] * Zs - SL + (Ti1 - w) * Zs) + 2.f * Ti1 * wd3;
-      const float dtau = g[0] + cdot + g[4] * TN + g[5] * fmaf(q.m, TN, -Zs) + g[6] * dL;
-      dsg[j] = q.delta * dtau;
-      dc[3 * j] = w * g[1];
-      dc[3 * j + 1] = w * g[2];
-      dc[3 * j + 2] = w * g[3];
-      // sample j joins the suffix
-      SCr = fmaf(w, q.c0, SCr);
-      SCg = fmaf(w, q.c1, SCg);
-      SCb = fmaf(w, q.c2, SCb);
-      SL = fmaf(2.f * w, Zs, SL + w * wd3);
-      SF = Zs;
-      SA += w;
-      mf = q.m;
+      for (int k = 0; k < 7; ++k) g[k] = gseg[k * n_seg + sgi];
     }
+    const float w = PT[j] * q.alpha;
+    const float Zs = fmaf(SA, mf - q.m, SF);
+    const float wd3 = w * q.delta * (1.f / 3.f);
+    const float cdot = g[1] * fmaf(Ti1, q.c0, -SCr) + g[2] * fmaf(Ti1, q.c1, -SCg) +
+                       g[3] * fmaf(Ti1, q.c2, -SCb);
+    const float dL = 2.f * (TN * PZ[j] - PA[j] * Zs - SL + (Ti1 - w) * Zs) + 2.f * Ti1 * wd3;
+    const float dtau = g[0] + cdot + g[4] * TN + g[5] * fmaf(q.m, TN, -Zs) + g[6] * dL;
+    dsg[j] = q.delta * dtau;
+    dc[3 * j] = w * g[1];
+    dc[3 * j + 1] = w * g[2];
+    dc[3 * j + 2] = w * g[3];
+    // sample j joins the suffix
+    SCr = fmaf(w, q.c0, SCr);
+    SCg = fmaf(w, q.c1, SCg);
+    SCb = fmaf(w, q.c2, SCb);
+    SL = fmaf(2.f * w, Zs, SL + w * wd3);
+    SF = Zs;
+    SA += w;
+    mf = q.m;
   }
 
-  if (cnt == kRun) {
+  const int64_t i0 = R.i0;
+  if (FULL || R.cnt == kRun) {
     if (DT == kF32) {
       float4* GS = reinterpret_cast<float4*>(static_cast<float*>(gsig_p) + i0);
       float4* GC = reinterpret_cast<float4*>(static_cast<float*>(grgb_p) + 3 * i0);
@@ -413,25 +427,21 @@ __global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
       for (int q = 0; q < kRun / 8; ++q) {
         uint32_t w[4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h)
-          w[h] = static_cast<uint32_t>(from_f32<DT>(dsg[8 * q + 2 * h])) |
-                 (static_cast<uint32_t>(from_f32<DT>(dsg[8 * q + 2 * h + 1])) << 16);
+        for (int h = 0; h < 4; ++h) w[h] = pack2<DT>(dsg[8 * q + 2 * h], dsg[8 * q + 2 * h + 1]);
         GS[q] = make_uint4(w[0], w[1], w[2], w[3]);
       }
 #pragma unroll
       for (int q = 0; q < 3 * kRun / 8; ++q) {
         uint32_t w[4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h)
-          w[h] = static_cast<uint32_t>(from_f32<DT>(dc[8 * q + 2 * h])) |
-                 (static_cast<uint32_t>(from_f32<DT>(dc[8 * q + 2 * h + 1])) << 16);
+        for (int h = 0; h < 4; ++h) w[h] = pack2<DT>(dc[8 * q + 2 * h], dc[8 * q + 2 * h + 1]);
         GC[q] = make_uint4(w[0], w[1], w[2], w[3]);
       }
     }
   } else {
 #pragma unroll
     for (int j = 0; j < kRun; ++j) {
-      if (j < cnt) {
+      if (j < R.cnt) {
         const int64_t i = i0 + j;
         if (DT == kF32) {
           static_cast<float*>(gsig_p)[i] = dsg[j];
@@ -447,6 +457,34 @@ __global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
       }
     }
   }
+}
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
+    SamplesDev s, const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
+    const TileRec* __restrict__ recs, const float* __restrict__ gseg, void* __restrict__ gsig_p,
+    void* __restrict__ grgb_p) {
+  __shared__ int endloc_all[kWavesPerBlock][kTile];
+  __shared__ int64_t tailseg_all[kWavesPerBlock];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
+  const bool active = t < n_tiles;
+  int* endloc = endloc_all[wave];
+#pragma unroll
+  for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
+  if (lane == 0) tailseg_all[wave] = -1;
+  __syncthreads();
+  int64_t s_lo = 0;
+  if (active) {
+    s_lo = recs[t].first_seg;
+    stage_ends<false>(off, n_seg, s.n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], nullptr);
+  }
+  __syncthreads();
+  if (!active) return;
+  if ((t + 1) * kTile <= s.n)
+    bwd_tile<DT, true>(s, n_seg, t, s_lo, lane, endloc, recs, gseg, gsig_p, grgb_p);
+  else
+    bwd_tile<DT, false>(s, n_seg, t, s_lo, lane, endloc, recs, gseg, gsig_p, grgb_p);
 }
 
 static inline unsigned grid_for(int64_t count, int block) {

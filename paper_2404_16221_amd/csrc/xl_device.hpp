@@ -85,7 +85,7 @@ __device__ __forceinline__ Range combine(const Range& x, const Range& y) {
 
 // One sample, reduced to what the composite needs.
 struct Smp {
-  float tau, alpha, m, delta, c0, c1, c2;
+  float tau, e, alpha, m, delta, c0, c1, c2;  // e = exp(-tau)
 };
 
 // 1 - exp(-tau) without cancellation: Taylor series (Horner form, error below
@@ -102,7 +102,8 @@ __device__ __forceinline__ Smp make_sample(float sigma, float c0, float c1, floa
   s.delta = t1 - t0;
   s.m = 0.5f * (t0 + t1);
   s.tau = sigma * s.delta;
-  s.alpha = one_minus_exp_neg(s.tau, exp_neg(s.tau));
+  s.e = exp_neg(s.tau);
+  s.alpha = one_minus_exp_neg(s.tau, s.e);
   s.c0 = c0; s.c1 = c1; s.c2 = c2;
   return s;
 }
@@ -117,9 +118,12 @@ __device__ __forceinline__ Range range_of(const Smp& s) {
   return r;
 }
 
-// Append one sample behind range r.
-__device__ __forceinline__ void append(Range& r, const Smp& s) {
-  const float w = exp_neg(r.tau) * s.alpha;
+// Append one sample behind range r whose transmittance is Tr (updated).
+// Inside one lane Tr is a product of at most kRun per-sample factors, so its
+// rounding error stays bounded; across lanes and tiles transmittance is always
+// exp(-tau) (see combine).
+__device__ __forceinline__ void append(Range& r, float& Tr, const Smp& s) {
+  const float w = Tr * s.alpha;
   const float Z = fmaf(r.A, s.m - r.m1, r.B);  // sum_{j<i} w_j (m_i - m_j)
   r.L = fmaf(w, fmaf(2.f, Z, w * s.delta * (1.f / 3.f)), r.L);
   r.F = fmaf(w, s.m - r.m0, r.F);
@@ -130,17 +134,19 @@ __device__ __forceinline__ void append(Range& r, const Smp& s) {
   r.A += w;
   r.tau += s.tau;
   r.m1 = s.m;
+  Tr *= s.e;
 }
 
 // ---------------------------------------------------------------- storage
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
   return __uint_as_float(static_cast<uint32_t>(h) << 16);
 }
-__device__ __forceinline__ uint16_t f32_to_bf16(float x) {  // round to nearest even
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+// Round to nearest even (gfx950 converts two values per instruction).
+__device__ __forceinline__ uint16_t f32_to_bf16(float x) {
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(x));
 }
 __device__ __forceinline__ float f16_to_f32(uint16_t h) {
   return static_cast<float>(__builtin_bit_cast(_Float16, h));
@@ -156,6 +162,13 @@ __device__ __forceinline__ float to_f32(uint16_t h) {
 template <int DT>
 __device__ __forceinline__ uint16_t from_f32(float x) {
   return DT == kBF16 ? f32_to_bf16(x) : f32_to_f16(x);
+}
+// Two values rounded to nearest even and packed (first in the low half).
+template <int DT>
+__device__ __forceinline__ uint32_t pack2(float a, float b) {
+  const f32x2 v = {a, b};
+  if (DT == kBF16) return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
 }
 
 // Load kRun consecutive samples starting at index i (i % kRun == 0) into
@@ -257,17 +270,26 @@ __device__ __forceinline__ Range shfl_down_range(const Range& x, int d) {
   return y;
 }
 
+__device__ __forceinline__ Range select(bool c, const Range& a, const Range& b) {
+  Range r;
+  r.tau = c ? a.tau : b.tau;
+  r.cr = c ? a.cr : b.cr; r.cg = c ? a.cg : b.cg; r.cb = c ? a.cb : b.cb;
+  r.A = c ? a.A : b.A; r.F = c ? a.F : b.F; r.B = c ? a.B : b.B; r.L = c ? a.L : b.L;
+  r.m0 = c ? a.m0 : b.m0; r.m1 = c ? a.m1 : b.m1;
+  return r;
+}
+
 // Inclusive segmented scan in lane order.  A lane whose flag is set starts a
-// new segment: nothing from lower lanes is combined into it.
+// new segment: nothing from lower lanes is combined into it.  Each step is
+// branch-free (combine, then select) so the wave never splits.
 __device__ __forceinline__ void scan_up(Range& x, bool& f, int lane) {
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) {
     const Range y = shfl_up_range(x, d);
     const int fy = __shfl_up(static_cast<int>(f), d);
-    if (lane >= d) {
-      if (!f) x = combine(y, x);
-      f = f || (fy != 0);
-    }
+    const bool ok = lane >= d;
+    x = select(ok && !f, combine(y, x), x);
+    f = f || (ok && fy != 0);
   }
 }
 
@@ -280,13 +302,42 @@ __device__ __forceinline__ void scan_down(Range& x, bool& f, int& seg, int lane)
     const Range y = shfl_down_range(x, d);
     const int fy = __shfl_down(static_cast<int>(f), d);
     const int sy = __shfl_down(seg, d);
-    if (lane + d < kWave) {
-      if (!f) {
-        x = combine(x, y);
-        seg = sy;
-      }
-      f = f || (fy != 0);
-    }
+    const bool ok = lane + d < kWave;
+    const bool use = ok && !f;
+    x = select(use, combine(x, y), x);
+    seg = use ? sy : seg;
+    f = f || (ok && fy != 0);
+  }
+}
+
+// The part of a range that the backward's prefix needs: optical depth,
+// opacity and the back-relative depth at the last midpoint.
+struct Pre {
+  float tau, A, B, m1;
+};
+__device__ __forceinline__ Pre pre_of(const Range& r) { return Pre{r.tau, r.A, r.B, r.m1}; }
+__device__ __forceinline__ Pre pre_identity() { return Pre{0.f, 0.f, 0.f, 0.f}; }
+__device__ __forceinline__ Pre combine_pre(const Pre& x, const Pre& y) {
+  const float T1 = exp_neg(x.tau);
+  Pre r;
+  r.tau = x.tau + y.tau;
+  r.A = fmaf(T1, y.A, x.A);
+  r.B = fmaf(T1, y.B, fmaf(x.A, y.m1 - x.m1, x.B));
+  r.m1 = y.m1;
+  return r;
+}
+__device__ __forceinline__ void scan_up_pre(Pre& x, bool& f, int lane) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    Pre y;
+    y.tau = __shfl_up(x.tau, d); y.A = __shfl_up(x.A, d);
+    y.B = __shfl_up(x.B, d); y.m1 = __shfl_up(x.m1, d);
+    const int fy = __shfl_up(static_cast<int>(f), d);
+    const bool use = lane >= d && !f;
+    const Pre z = combine_pre(y, x);
+    x.tau = use ? z.tau : x.tau; x.A = use ? z.A : x.A;
+    x.B = use ? z.B : x.B; x.m1 = use ? z.m1 : x.m1;
+    f = f || (lane >= d && fy != 0);
   }
 }
 

@@ -21,18 +21,27 @@ pseudorandom number generators", OOPSLA 2014) and ``key(r) = mix64(mix64(seed)
 + r * GAMMA)``.
 
 Per ray (slots 0..255):
-  * origin o ~ U[-1, 1)^3                                   (slots 0, 1, 2)
+  * origin o ~ U[-1, 1)^3 (53-bit uniforms)                 (slots 0, 1, 2)
   * sample count N ~ U{n_min..n_max} (multiply-shift range)  (slot 3)
   * start offset u                                          (slot 4)
   * direction: uniform on the sphere by rejection from the cube (tries j, slots
     16 + 3j .. 16 + 3j + 2, at most 64 tries)
-Per sample i (slots 256 + 8 i + k):
-  * width   delta = -width_mean * log(u), u in (0, 1]       (k = 0)
-  * density sigma = exp(mu + s * z), z by Box-Muller         (k = 1, 2)
-            zeroed when u < zero_frac                        (k = 3)
-  * colour  rgb ~ U[0, 1)^3                                  (k = 4, 5, 6)
+Per sample i, two draws (slots 256 + 2 i and 256 + 2 i + 1), cut into fields:
+  * first draw, bits 63..40: width delta = -width_mean * log(u), u in (0, 1]
+    bits 39..20 and 19..0: density sigma = exp(mu + s z) with
+    z = sqrt(-2 ln u1) cos(2 pi u2), u1 in (0, 1], u2 in [0, 1)
+  * second draw, 16-bit fields: bits 63..48 zero the density when below
+    zero_frac; bits 47..32, 31..16, 15..0: colour r, g, b in [0, 1)
 Widths are rescaled to sum to t_far when they exceed it; the intervals are
 contiguous from a start drawn uniformly in [0, t_far - sum].
+
+Bit-exact reproducibility where it matters: the interval ends decide the
+segment structure and the kernels' delta = t_end - t_start, so they are built
+only from IEEE-exact operations -- the width's logarithm is the float32
+function ``log_f32`` below (atanh series, fixed operation order, no fused
+multiply-add), the sums are sequential float64 additions -- and a device twin
+of this generator yields identical t_start, t_end, box tags and layout.
+Densities use library transcendentals and may differ in the last float32 bit.
 """
 from __future__ import annotations
 
@@ -50,8 +59,48 @@ _INV53 = 1.0 / 9007199254740992.0  # 2^-53
 
 SEED_BASE = 2404_16221
 RAY_SLOTS = 256
-SAMPLE_STRIDE = 8
+SAMPLE_STRIDE = 2
 DIR_TRIES = 64
+_S40 = np.uint64(40)
+_LO32 = np.uint64(0xFFFFFFFF)
+_INV32 = 1.0 / 4294967296.0  # 2^-32
+_INV24 = np.float32(1.0 / 16777216.0)  # 2^-24
+# float32 constants of log_f32, given as exact bit patterns
+_F32 = lambda bits: np.array([bits], dtype=np.uint32).view(np.float32)[0]
+_SQRT2 = _F32(0x3FB504F3)     # 1.41421354
+_THIRD = _F32(0x3EAAAAAB)     # 1/3
+_FIFTH = _F32(0x3E4CCCCD)     # 1/5
+_SEVENTH = _F32(0x3E124925)   # 1/7
+_NINTH = _F32(0x3DE38E39)     # 1/9
+_LN2 = _F32(0x3F317218)       # ln 2
+_ONE = np.float32(1.0)
+_TWO = np.float32(2.0)
+_HALF = np.float32(0.5)
+
+
+def log_f32(u: np.ndarray) -> np.ndarray:
+    """Natural log of positive normal float32 values, float32 IEEE operations only.
+
+    u = 2^e x with x in [sqrt(1/2), sqrt(2)); log x = 2 atanh(s), s = (x-1)/(x+1),
+    summed as 2 (s + s^3/3 + s^5/5 + s^7/7 + s^9/9) (|s| < 0.172).  Every step is
+    one correctly rounded float32 operation in a fixed order, so any IEEE twin
+    gives the same bits.
+    """
+    u = np.asarray(u, dtype=np.float32)
+    bits = u.view(np.int32)
+    e = ((bits >> 23) & 0xFF).astype(np.int32) - 127
+    x = ((bits & 0x7FFFFF) | 0x3F800000).view(np.float32)
+    big = x > _SQRT2
+    x = np.where(big, x * _HALF, x).astype(np.float32)
+    e = e + big.astype(np.int32)
+    s = (x - _ONE) / (x + _ONE)
+    s2 = s * s
+    p = _SEVENTH + s2 * _NINTH
+    p = _FIFTH + s2 * p
+    p = _THIRD + s2 * p
+    p = s2 * p
+    lx = _TWO * (s + s * p)
+    return (e.astype(np.float32) * _LN2 + lx).astype(np.float32)
 
 
 def mix64(z: np.ndarray) -> np.ndarray:
@@ -84,6 +133,17 @@ def u01(v: np.ndarray) -> np.ndarray:
 def u01_open0(v: np.ndarray) -> np.ndarray:
     """Uniform double in (0, 1]."""
     return ((v >> _S11) + np.uint64(1)).astype(np.float64) * _INV53
+
+
+def field(v: np.ndarray, shift: int, bits: int) -> np.ndarray:
+    """Bits [shift, shift + bits) of v as a uniform double k / 2^bits in [0, 1)."""
+    k = (v >> np.uint64(shift)) & np.uint64((1 << bits) - 1)
+    return k.astype(np.float64) * (1.0 / float(1 << bits))
+
+
+def u24_open0(v: np.ndarray) -> np.ndarray:
+    """Upper 24 bits as a uniform float32 in (0, 1] (exact)."""
+    return ((v >> _S40) + np.uint64(1)).astype(np.float32) * _INV24
 
 
 @dataclass(frozen=True)
@@ -206,15 +266,16 @@ def _gen_ray_major(w: Workload, rays: np.ndarray):
     sk = keys[ray_of]
     base = np.uint64(RAY_SLOTS) + idx.astype(np.uint64) * np.uint64(SAMPLE_STRIDE)
 
-    width = -w.width_mean * np.log(u01_open0(draw(sk, base + np.uint64(0))))
-    u1 = u01_open0(draw(sk, base + np.uint64(1)))
-    u2 = u01(draw(sk, base + np.uint64(2)))
-    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    wm = np.float32(w.width_mean)
+    v1 = draw(sk, base)
+    v2 = draw(sk, base + np.uint64(1))
+    width = (-(wm * log_f32(u24_open0(v1)))).astype(np.float64)
+    z = np.sqrt(-2.0 * np.log(field(v1, 20, 20) + 2.0 ** -20)) * np.cos(2.0 * np.pi * field(v1, 0, 20))
     sigma = np.exp(w.sigma_mu + w.sigma_s * z)
     if w.zero_frac > 0.0:
-        sigma[u01(draw(sk, base + np.uint64(3))) < w.zero_frac] = 0.0
-    rgb = np.stack([u01(draw(sk, base + np.uint64(4 + c))) for c in range(3)], axis=1)
-    del sk, base, u1, u2, z
+        sigma[field(v2, 48, 16) < w.zero_frac] = 0.0
+    rgb = np.stack([field(v2, 32, 16), field(v2, 16, 16), field(v2, 0, 16)], axis=1)
+    del sk, base, v1, v2, z
 
     # Per-ray width sums and starts; positions by a sequential per-ray sum.
     nmax = int(cnt.max()) if R else 0
@@ -223,8 +284,7 @@ def _gen_ray_major(w: Workload, rays: np.ndarray):
     tot = np.cumsum(pad, axis=1)[:, -1] if nmax else np.zeros(R)
     scale = np.where(tot > w.t_far, w.t_far / np.where(tot > 0, tot, 1.0), 1.0)
     pad *= scale[:, None]
-    tot = np.cumsum(pad, axis=1)[:, -1] if nmax else np.zeros(R)
-    s0 = u_start * np.maximum(w.t_far - tot, 0.0)
+    s0 = u_start * np.maximum(w.t_far - tot * scale, 0.0)
     # Sample i ends at s0 + (delta_0 + ... + delta_i), summed left to right, and
     # starts where sample i-1 ends, so consecutive intervals share an end point.
     pad[:, 0] += s0

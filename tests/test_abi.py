@@ -1,0 +1,82 @@
+"""C ABI checks that need no GPU: exported symbols and host-side argument errors."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2404_16221_amd import _lib as xl
+from paper_2404_16221_amd import serve, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "xl.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xl_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported():
+    names = declared_functions()
+    assert len(names) >= 18, names
+    L = ctypes.CDLL(xl.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_bindings_cover_the_header():
+    bound = set(xl.SIGNATURES) | set(serve.SERVE_SIGNATURES)
+    assert set(declared_functions()) <= bound | {"xl_serve_create"}
+
+
+def _fwd(s, seg_offsets=None, n_seg=1, seg_out=None, ws=None, wsb=0):
+    return xl.lib().xl_render_segments_fwd(ctypes.byref(s) if s is not None else None,
+                                           seg_offsets, n_seg, seg_out, ws, wsb, None)
+
+
+def test_host_side_argument_errors():
+    L = xl.lib()
+    assert _fwd(None) == xl.XL_EINVAL
+    s = xl.XLSamples(7, 16, 16, 16, 16, 4)
+    assert _fwd(s, 16) == xl.XL_EINVAL and "dtype" in L.xl_last_error().decode()
+    s = xl.XLSamples(0, 16, 16, 16, 16, -1)
+    assert _fwd(s, 16) == xl.XL_EINVAL and "negative" in L.xl_last_error().decode()
+    s = xl.XLSamples(0, 0x1004, 16, 16, 16, 4)
+    assert _fwd(s, 16, 1, 16, 16, 1 << 20) == xl.XL_EINVAL and "aligned" in L.xl_last_error().decode()
+    s = xl.XLSamples(0, 16, 16, 16, 16, 4)
+    assert _fwd(s, 16, 0) == xl.XL_EINVAL and "no segments" in L.xl_last_error().decode()
+    assert _fwd(s, 16, 1, 16, 16, 1) == xl.XL_EINVAL and "too small" in L.xl_last_error().decode()
+    assert L.xl_merge_fwd(16, 1, 16, 16, 1, 16, 4, None) == xl.XL_EINVAL
+    assert L.xl_merge_bwd(16, -1, 16, 16, 1, 16, 16, 0, None) == xl.XL_EINVAL
+    assert L.xl_render_segments_bwd(ctypes.byref(s), 16, 1, None, 0, 16, 16, 16, None) == xl.XL_EINVAL
+
+
+def test_workspace_sizes():
+    L = xl.lib()
+    rec = L.xl_segments_workspace_bytes(512)
+    assert rec > 0 and rec % 16 == 0
+    assert L.xl_segments_workspace_bytes(513) == 2 * rec
+    assert L.xl_segments_workspace_bytes(0) == rec
+    p = xl.gen_params(synth.WORKLOADS[2])
+    assert L.xl_gen_workspace_bytes(ctypes.byref(p)) > 262144 * 8
+    bad = xl.gen_params(synth.WORKLOADS[2])
+    bad.grid[0] = 0
+    assert L.xl_gen_workspace_bytes(ctypes.byref(bad)) == 0
+    n, ns = ctypes.c_int64(), ctypes.c_int64()
+    assert L.xl_gen_plan(ctypes.byref(bad), None, 0, ctypes.byref(n), ctypes.byref(ns), None) == xl.XL_EINVAL
+
+
+def test_serve_argument_errors():
+    L = serve._bind()
+    cfg = serve.XLServeConfig(1 << 30, 0, 4, 0, 0, 0, 0)
+    h = ctypes.c_void_p()
+    assert L.xl_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == xl.XL_EINVAL
+    cfg = serve.XLServeConfig(1 << 30, 1, 4, 0, 9, 0, 0)
+    assert L.xl_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == xl.XL_EINVAL
+    t = ctypes.c_uint64()
+    req = serve.request(4, 4)
+    assert L.xl_serve_submit(None, ctypes.byref(req), ctypes.byref(t)) == xl.XL_EINVAL
+    r = serve.XLResult()
+    assert L.xl_serve_poll(None, 1, ctypes.byref(r), 0) == xl.XL_EINVAL
+    assert L.xl_serve_release(None, 1) == xl.XL_EINVAL

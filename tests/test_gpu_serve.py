@@ -1,0 +1,111 @@
+"""Render server on the GPU: correctness, alone-vs-mix equality, admission, failures."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import render as O
+from paper_2404_16221_amd import synth
+from paper_2404_16221_amd.serve import Server, request
+from tests.parity import assert_tuples, quantize, sample_rays
+
+pytestmark = pytest.mark.gpu
+
+SCENE = dict(grid=(4, 4, 2), n_min=16, n_max=512, sigma_mu=0.0, sigma_s=1.5)
+
+
+def workload_of(width, height, seed):
+    return synth.Workload(f"req-{width}x{height}", width * height, SCENE["n_min"], SCENE["n_max"],
+                          SCENE["sigma_mu"], SCENE["sigma_s"], 0.0, SCENE["grid"], seed)
+
+
+def wait_all(srv, tickets):
+    return {t: srv.poll(t, timeout_us=60_000_000) for t in tickets}
+
+
+def test_served_view_matches_oracle():
+    with Server(max_slots=2, dtype=torch.float16) as srv:
+        t = srv.submit(request(64, 48, seed=11, **SCENE))
+        r = srv.poll(t, timeout_us=60_000_000)
+        assert r["rc"] == 0, r
+        out = srv.result(t, r["n_rays"]).cpu().numpy()
+        srv.release(t)
+    w = workload_of(64, 48, 11)
+    rays = sample_rays(w.n_rays, 300, 1)
+    b = synth.generate(w, rays=rays)
+    assert r["n_rays"] == 64 * 48
+    dq = quantize(b, torch.float16)
+    ref = O.render_rays_single(dq[0], dq[1], b.t_start, b.t_end, b.seg_offsets, b.ray_offsets,
+                               b.seg_ids)
+    assert_tuples(out[:, rays], ref, "ray", "served view vs oracle (FP16 inputs)")
+
+
+def test_result_is_the_same_alone_and_in_a_mix():
+    target = request(200, 150, seed=5, **SCENE)
+    with Server(max_slots=1, dtype=torch.float16) as srv:
+        t = srv.submit(target)
+        assert srv.poll(t, timeout_us=60_000_000)["rc"] == 0
+        alone = srv.result(t, 200 * 150)
+        srv.release(t)
+    others = [request(w, h, seed=100 + k, **SCENE)
+              for k, (w, h) in enumerate([(256, 256), (300, 200), (128, 128), (512, 256), (64, 64)])]
+    with Server(max_slots=4, dtype=torch.float16) as srv:
+        ts = [srv.submit(q) for q in others[:3]]
+        tt = srv.submit(target)
+        ts += [srv.submit(q) for q in others[3:]]
+        res = wait_all(srv, ts + [tt])
+        assert all(v["rc"] == 0 for v in res.values()), res
+        mixed = srv.result(tt, 200 * 150)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, mixed)
+        st = srv.stats()
+        assert st["completed"] == 6 and st["p99_latency_us"] >= st["p50_latency_us"] > 0
+        for t in ts + [tt]:
+            srv.release(t)
+
+
+def test_queue_full_returns_eagain_and_accepted_requests_finish():
+    with Server(max_slots=1, max_queue=2, dtype=torch.float16) as srv:
+        tickets, rejected = [], 0
+        for k in range(12):
+            t = srv.submit(request(256, 256, seed=200 + k, **SCENE))
+            if t is None:
+                rejected += 1
+            else:
+                tickets.append(t)
+        assert rejected > 0
+        res = wait_all(srv, tickets)
+        assert all(v["rc"] == 0 for v in res.values())
+        for t in tickets:
+            srv.release(t)
+
+
+def test_budget_admission_and_injected_fault():
+    # 24 MB: a 256x256 view (~17M samples) cannot fit, a 32x32 view can
+    with Server(hbm_budget_bytes=24 << 20, max_slots=2, dtype=torch.float16) as srv:
+        big = srv.submit(request(256, 256, seed=1, **SCENE))
+        bad = srv.submit(request(32, 32, seed=2, inject_fault=True, **SCENE))
+        small = [srv.submit(request(32, 32, seed=3 + k, **SCENE)) for k in range(4)]
+        rb = srv.poll(big, timeout_us=60_000_000)
+        rf = srv.poll(bad, timeout_us=60_000_000)
+        assert rb["rc"] == -2 and "budget" in rb["error"]
+        assert rf["rc"] == -5
+        for t in small:
+            r = srv.poll(t, timeout_us=60_000_000)
+            assert r["rc"] == 0 and r["footprint_bytes"] <= 24 << 20
+            srv.release(t)
+        st = srv.stats()
+        assert st["completed"] == 4 and st["failed"] == 2 and st["budget_used_bytes"] == 0
+
+
+def test_continuous_batching_overlaps_requests():
+    """Requests submitted while others run are admitted into free slots at once."""
+    with Server(max_slots=4, dtype=torch.float16) as srv:
+        ts = [srv.submit(request(512, 512, seed=300 + k, **SCENE)) for k in range(4)]
+        res = wait_all(srv, ts)
+        assert all(v["rc"] == 0 for v in res.values())
+        # all four were admitted without waiting for each other to finish
+        assert max(v["queue_us"] for v in res.values()) < min(v["latency_us"] for v in res.values())
+        for t in ts:
+            srv.release(t)
