@@ -156,8 +156,7 @@ int xl_check_inputs(const xl_samples* s, const int64_t* seg_offsets, int64_t n_s
  * Synthetic workload generator on the device (the stand-in for per-region
  * NeRF evaluation): rays [ray0, ray0 + n_rays) of a seeded workload, packed
  * region-major exactly as the input contract above requires.  Bit-identical
- * to the host generator (synth.py) in t_start, t_end and the layout; densities
- * agree to about 1e-6 relative.  grid[0]*grid[1]*grid[2] <= 256 regions,
+ * to the host generator (synth.py) in every sample and in the layout.  grid[0]*grid[1]*grid[2] <= 256 regions,
  * grid[0]+grid[1]+grid[2] <= 18.
  */
 typedef struct xl_gen_params {

@@ -2,11 +2,10 @@
 // evaluation in the serving loop, and the fast path for large benchmark
 // inputs.  It is the device twin of the host generator in synth.py: the same
 // counter-based draws (SplitMix64 output function, Steele, Lea & Flood 2014),
-// the same float32 logarithm for interval widths (atanh series in a fixed
-// operation order), the same sequential float64 position sums and box tags,
-// so t_start, t_end, the segment structure and the region-major layout are
-// bit-identical to the host's; densities use float32 library functions and
-// agree to about 1e-6 relative.
+// the same float32 log/exp/cos built from IEEE operations in a fixed order
+// (no fused multiply-add), the same sequential float64 position sums and box
+// tags, so every sample, the segment structure and the region-major layout
+// are bit-identical to the host's.
 //
 // Pipeline for a batch of rays (all asynchronous on one stream):
 //   gen_struct   one lane per ray: widths, positions and box tags -> the ray's
@@ -72,6 +71,49 @@ __device__ __forceinline__ float log_f32(float u) {
   p = __fmul_rn(s2, p);
   const float lx = __fmul_rn(2.f, __fadd_rn(s, __fmul_rn(s, p)));
   return __fadd_rn(__fmul_rn(static_cast<float>(e), __int_as_float(0x3F317218)), lx);
+}
+
+// exp of float32 values in (-87, 88) from IEEE operations only (twin of the host
+// generator's exp_f32): k = rint(y / ln 2), r = (y - k ln2_hi) - k ln2_lo
+// (Cody & Waite), exp r by its Taylor series to r^7 (Horner), times 2^k.
+__device__ __forceinline__ float exp_f32(float y) {
+  const float k = rintf(__fmul_rn(y, __int_as_float(0x3FB8AA3B)));
+  const float r = __fsub_rn(__fsub_rn(y, __fmul_rn(k, __int_as_float(0x3F317200))),
+                            __fmul_rn(k, __int_as_float(0x35BFBE8E)));
+  float p = __fadd_rn(1.f, __fmul_rn(r, static_cast<float>(1.0 / 7.0)));
+  p = __fadd_rn(1.f, __fmul_rn(__fmul_rn(r, static_cast<float>(1.0 / 6.0)), p));
+  p = __fadd_rn(1.f, __fmul_rn(__fmul_rn(r, static_cast<float>(1.0 / 5.0)), p));
+  p = __fadd_rn(1.f, __fmul_rn(__fmul_rn(r, static_cast<float>(1.0 / 4.0)), p));
+  p = __fadd_rn(1.f, __fmul_rn(__fmul_rn(r, static_cast<float>(1.0 / 3.0)), p));
+  p = __fadd_rn(1.f, __fmul_rn(__fmul_rn(r, static_cast<float>(1.0 / 2.0)), p));
+  p = __fadd_rn(1.f, __fmul_rn(__fmul_rn(r, 1.f), p));
+  return ldexpf(p, static_cast<int>(k));
+}
+
+// cos(2 pi u) for u in [0, 1) from IEEE operations only (twin of cos2pi_f32):
+// exact quadrant split of 4u, angle in [0, pi/4], Taylor series to a^9 / a^8.
+__device__ __forceinline__ float cos2pi_f32(float u) {
+  const float t = __fmul_rn(u, 4.f);
+  const float n = floorf(t);
+  const float f = __fsub_rn(t, n);
+  const bool flip = f > 0.5f;
+  const float a = __fmul_rn(flip ? __fsub_rn(1.f, f) : f, __int_as_float(0x3FC90FDB));
+  const float a2 = __fmul_rn(a, a);
+  // cos a = 1 - (a2/2)(1 - (a2/12)(1 - (a2/30)(1 - a2/56)))
+  float c = __fsub_rn(1.f, __fmul_rn(a2, static_cast<float>(1.0 / 56.0)));
+  c = __fsub_rn(1.f, __fmul_rn(__fmul_rn(a2, static_cast<float>(1.0 / 30.0)), c));
+  c = __fsub_rn(1.f, __fmul_rn(__fmul_rn(a2, static_cast<float>(1.0 / 12.0)), c));
+  c = __fsub_rn(1.f, __fmul_rn(__fmul_rn(a2, 0.5f), c));
+  // sin a = a (1 - (a2/6)(1 - (a2/20)(1 - (a2/42)(1 - a2/72))))
+  float sn = __fsub_rn(1.f, __fmul_rn(a2, static_cast<float>(1.0 / 72.0)));
+  sn = __fsub_rn(1.f, __fmul_rn(__fmul_rn(a2, static_cast<float>(1.0 / 42.0)), sn));
+  sn = __fsub_rn(1.f, __fmul_rn(__fmul_rn(a2, static_cast<float>(1.0 / 20.0)), sn));
+  sn = __fsub_rn(1.f, __fmul_rn(__fmul_rn(a2, static_cast<float>(1.0 / 6.0)), sn));
+  sn = __fmul_rn(a, sn);
+  const float ca = flip ? sn : c;
+  const float sa = flip ? c : sn;
+  const int q = static_cast<int>(n) & 3;
+  return q == 0 ? ca : (q == 1 ? -sa : (q == 2 ? -ca : sa));
 }
 
 struct GenDev {
@@ -273,7 +315,6 @@ __global__ void gen_fill_kernel(GenDev g, GenWs w, void* __restrict__ sigma, voi
   const int ns = w.nseg[r];
   int k = 0, left = ns > 0 ? w.seg_len[r * M] : 0;
   int64_t dst = ns > 0 ? w.seg_off[w.seg_pid[r * M]] : 0;
-  const float two_pi = 6.283185307179586f;
   for (int i = 0; i < count; ++i) {
     if (left == 0 && k + 1 < ns) {
       ++k;
@@ -286,8 +327,8 @@ __global__ void gen_fill_kernel(GenDev g, GenWs w, void* __restrict__ sigma, voi
     const uint64_t v1 = draw(key, base), v2 = draw(key, base + 1);
     const float u1 = static_cast<float>(field(v1, 20, 20) + 0x1p-20);
     const float u2 = static_cast<float>(field(v1, 0, 20));
-    const float z = sqrtf(-2.f * logf(u1)) * cosf(two_pi * u2);
-    float sg = expf(g.mu + g.sg * z);
+    const float z = __fmul_rn(__fsqrt_rn(__fmul_rn(-2.f, log_f32(u1))), cos2pi_f32(u2));
+    float sg = exp_f32(__fadd_rn(g.mu, __fmul_rn(g.sg, z)));
     if (field(v2, 48, 16) < g.zero_frac) sg = 0.f;
     put_sample<DT>(sigma, rgb, dst, sg, static_cast<float>(field(v2, 32, 16)),
                    static_cast<float>(field(v2, 16, 16)), static_cast<float>(field(v2, 0, 16)));

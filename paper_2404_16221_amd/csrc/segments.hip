@@ -62,12 +62,16 @@ __device__ __forceinline__ void write_tuple(float* __restrict__ out, int64_t n_s
 // Stage the segment ends of tile t in LDS.  endloc[p] = local id (segment -
 // s_lo) of the segment whose last sample is base + p, or -1.  Empty segments
 // owned by this tile get the identity tuple when WRITE_EMPTY.
+constexpr int kStagedSegs = 64;  // segment gradients staged in LDS per tile (backward)
+
 template <bool WRITE_EMPTY>
 __device__ __forceinline__ void stage_ends(const int64_t* __restrict__ off, int64_t n_seg,
                                            int64_t n, int64_t t, int64_t n_tiles, int64_t s_lo,
                                            int lane, int* __restrict__ endloc,
                                            int64_t* __restrict__ tailseg,
-                                           float* __restrict__ seg_out) {
+                                           float* __restrict__ seg_out,
+                                           const float* __restrict__ gseg = nullptr,
+                                           float* __restrict__ gl = nullptr) {
   const int64_t base = t * kTile;
   const int64_t tile_end = base + kTile < n ? base + kTile : n;
   const int64_t last = tile_end - 1;
@@ -85,7 +89,14 @@ __device__ __forceinline__ void stage_ends(const int64_t* __restrict__ off, int6
           }
         } else {
           const int64_t e = e1 - 1;
-          if (e >= base && e < tile_end) endloc[e - base] = static_cast<int>(sg - s_lo);
+          if (e >= base && e < tile_end) {
+            const int loc = static_cast<int>(sg - s_lo);
+            endloc[e - base] = loc;
+            if (gl != nullptr && loc < kStagedSegs) {
+#pragma unroll
+              for (int k = 0; k < 7; ++k) gl[k * kStagedSegs + loc] = gseg[k * n_seg + sg];
+            }
+          }
           if (a <= last && last <= e) *tailseg = sg;
         }
       }
@@ -134,13 +145,15 @@ struct LaneRun {
 template <int DT, bool FULL>
 __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int64_t t,
                                          int64_t s_lo, bool start_head, int lane,
-                                         const int* endloc, int64_t tailseg,
+                                         const int* endloc, int64_t tailseg, float* park,
                                          float* __restrict__ seg_out, TileRec* __restrict__ recs) {
   LaneRun<DT, FULL> R;
   R.load(s, endloc, lane, start_head, t * kTile);
 
-  // Serial fold of the lane's samples; a head restarts the open range.
-  Range cur = range_of(R.x[0]), pend = range_identity();
+  // Serial fold of the lane's samples; a head restarts the open range.  The
+  // lane's first range, when it continues a segment from an earlier lane, is
+  // parked in LDS until the scan has produced what precedes it.
+  Range cur = range_of(R.x[0]);
   float Tc = R.x[0].e;
   bool cur_head = R.h0, has_pend = false, any_end = false, any_head = R.h0;
   int pend_seg = -1;
@@ -160,7 +173,7 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
         if (cur_head) {
           write_tuple(seg_out, n_seg, s_lo + R.ends[j], cur);
         } else {
-          pend = cur;
+          park_range(park, lane, cur);
           pend_seg = R.ends[j];
           has_pend = true;
         }
@@ -176,6 +189,7 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
   const Range ex = shfl_up_range(inc, 1);
   const int exf = __shfl_up(static_cast<int>(fin), 1);
   if (has_pend) {
+    const Range pend = unpark_range(park, lane);
     if (lane > 0 && exf) {
       write_tuple(seg_out, n_seg, s_lo + pend_seg, combine(ex, pend));
     } else {
@@ -196,17 +210,23 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
   }
 }
 
-template <int DT>
+// FULL instances process tiles [t_first, t_first + gridDim.x * kWavesPerBlock)
+// that are complete; the ragged last tile (if any) is a separate launch with
+// FULL = false, so the common instance carries no tail handling (and no
+// register cost for it).
+template <int DT, bool FULL>
 __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
                                                          const int64_t* __restrict__ off,
                                                          int64_t n_seg, int64_t n_tiles,
+                                                         int64_t t_first, int64_t t_end,
                                                          float* __restrict__ seg_out,
                                                          TileRec* __restrict__ recs) {
   __shared__ int endloc_all[kWavesPerBlock][kTile];
+  __shared__ float park_all[kWavesPerBlock][kRangeFields * kWave];
   __shared__ int64_t tailseg_all[kWavesPerBlock];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
-  const bool active = t < n_tiles;
+  const int64_t t = t_first + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
+  const bool active = t < t_end;
   int* endloc = endloc_all[wave];
 #pragma unroll
   for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
@@ -221,10 +241,8 @@ __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
   }
   __syncthreads();
   if (!active) return;
-  if ((t + 1) * kTile <= s.n)
-    fwd_tile<DT, true>(s, n_seg, t, s_lo, start_head, lane, endloc, tailseg_all[wave], seg_out, recs);
-  else
-    fwd_tile<DT, false>(s, n_seg, t, s_lo, start_head, lane, endloc, tailseg_all[wave], seg_out, recs);
+  fwd_tile<DT, FULL>(s, n_seg, t, s_lo, start_head, lane, endloc, tailseg_all[wave], park_all[wave],
+                     seg_out, recs);
 }
 
 // Completes segments that cross tile boundaries and leaves, in every tile
@@ -259,9 +277,54 @@ __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restri
   }
 }
 
+// One step of the backward's reverse sweep for sample q (see bwd_tile).
+__device__ __forceinline__ void reverse_step(const Smp& q, float PTj, float PAj, float PZj, bool endf,
+                                             int endloc_j, int64_t s_lo, int64_t n_seg,
+                                             const float* __restrict__ gl,
+                                             const float* __restrict__ gseg, float (&g)[7],
+                                             float& SCr, float& SCg, float& SCb, float& SA,
+                                             float& SF, float& SL, float& mf, float& TN,
+                                             float& dsg, float& dc0, float& dc1, float& dc2) {
+  const float Ti1 = PTj * q.e;
+  SCr = endf ? 0.f : SCr; SCg = endf ? 0.f : SCg; SCb = endf ? 0.f : SCb;
+  SA = endf ? 0.f : SA; SF = endf ? 0.f : SF; SL = endf ? 0.f : SL;
+  mf = endf ? q.m : mf;
+  TN = endf ? Ti1 : TN;
+  if (endloc_j >= 0) {
+    if (endloc_j < kStagedSegs) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) g[k] = gl[k * kStagedSegs + endloc_j];
+    } else {
+      const int64_t sgi = s_lo + endloc_j;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) g[k] = gseg[k * n_seg + sgi];
+    }
+  }
+  const float w = PTj * q.alpha;
+  const float Zs = fmaf(SA, mf - q.m, SF);  // sum_{k>j} w_k (m_k - m_j)
+  const float wd3 = w * q.delta * (1.f / 3.f);
+  const float cdot = g[1] * fmaf(Ti1, q.c0, -SCr) + g[2] * fmaf(Ti1, q.c1, -SCg) +
+                     g[3] * fmaf(Ti1, q.c2, -SCb);
+  const float dL = 2.f * (TN * PZj - PAj * Zs - SL + (Ti1 - w) * Zs) + 2.f * Ti1 * wd3;
+  const float dtau = g[0] + cdot + g[4] * TN + g[5] * fmaf(q.m, TN, -Zs) + g[6] * dL;
+  dsg = q.delta * dtau;
+  dc0 = w * g[1];
+  dc1 = w * g[2];
+  dc2 = w * g[3];
+  // sample j joins the suffix
+  SCr = fmaf(w, q.c0, SCr);
+  SCg = fmaf(w, q.c1, SCg);
+  SCb = fmaf(w, q.c2, SCb);
+  SL = fmaf(2.f * w, Zs, SL + w * wd3);
+  SF = Zs;
+  SA += w;
+  mf = q.m;
+}
+
 template <int DT, bool FULL>
 __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int64_t t,
                                          int64_t s_lo, int lane, const int* endloc,
+                                         const float* __restrict__ gl, float* park,
                                          const TileRec* __restrict__ recs,
                                          const float* __restrict__ gseg, void* __restrict__ gsig_p,
                                          void* __restrict__ grgb_p) {
@@ -277,7 +340,7 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   // first head), and keeps the lane's first range (up to its first segment end)
   // for the reverse scan.
   float Tl[kRun], Al[kRun], Zl[kRun];
-  Range cur = range_of(R.x[0]), first = range_identity();
+  Range cur = range_of(R.x[0]);
   float Tc = R.x[0].e;
   bool cur_head = R.h0, seen_end = false;
   int first_end = -1;
@@ -297,7 +360,7 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
       fhp = (hd && fhp == kRun) ? j : fhp;
     }
     if (R.endf[j] && !seen_end) {
-      first = cur;
+      park_range(park, lane, cur);
       first_end = R.ends[j];
       seen_end = true;
     }
@@ -305,7 +368,7 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   const bool have = !R.endf[kRun - 1];
   Pre inc = have ? pre_of(cur) : pre_identity();
   bool fin = have ? cur_head : true;
-  Range rinc = seen_end ? first : cur;
+  Range rinc = seen_end ? unpark_range(park, lane) : cur;
   bool rfl = seen_end;
   int rseg = seen_end ? first_end : -1;
   scan_up_pre(inc, fin, lane);
@@ -373,40 +436,51 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
       for (int k = 0; k < 7; ++k) g[k] = gseg[k * n_seg + cseg];
     }
   }
+#ifndef XL_PASS3_RELOAD
+#define XL_PASS3_RELOAD 1
+#endif
+  if constexpr (FULL && XL_PASS3_RELOAD != 0) {
+    // Full tile: re-read the lane's samples (they were just loaded and are
+    // cache-resident) instead of keeping them live through the scans, and
+    // store each pair of gradients as soon as it is complete.  This keeps the
+    // kernel at 4 waves per SIMD.
+    float sg2[kRun], c2[3 * kRun], a2[kRun], b2[kRun];
+    asm volatile("" ::: "memory");
+    load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, R.i0, kRun, sg2, c2, a2, b2);
+    float dsg[kRun], dc[3 * kRun];
+#pragma unroll
+    for (int j = kRun - 1; j >= 0; --j) {
+#if XL_PASS3_RELOAD == 1
+      const Smp q = make_sample(sg2[j], c2[3 * j], c2[3 * j + 1], c2[3 * j + 2], a2[j], b2[j]);
+#else
+      Smp q;
+      q.e = R.x[j].e; q.alpha = R.x[j].alpha;
+      q.delta = b2[j] - a2[j]; q.m = 0.5f * (a2[j] + b2[j]);
+      q.c0 = c2[3 * j]; q.c1 = c2[3 * j + 1]; q.c2 = c2[3 * j + 2];
+#endif
+      reverse_step(q, PT[j], PA[j], PZ[j], R.endf[j], R.ends[j], s_lo, n_seg, gl, gseg, g, SCr, SCg,
+                   SCb, SA, SF, SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
+      if ((j & 1) == 0) {
+        if (DT == kF32)
+          *reinterpret_cast<float2*>(static_cast<float*>(gsig_p) + R.i0 + j) = make_float2(dsg[j], dsg[j + 1]);
+        else
+          *reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(gsig_p) + R.i0 + j) = pack2<DT>(dsg[j], dsg[j + 1]);
+      }
+#pragma unroll
+      for (int qq = (3 * j + 1) / 2; qq < (3 * (j + 1) + 1) / 2; ++qq) {
+        if (DT == kF32)
+          *reinterpret_cast<float2*>(static_cast<float*>(grgb_p) + 3 * R.i0 + 2 * qq) = make_float2(dc[2 * qq], dc[2 * qq + 1]);
+        else
+          *reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(grgb_p) + 3 * R.i0 + 2 * qq) = pack2<DT>(dc[2 * qq], dc[2 * qq + 1]);
+      }
+    }
+    return;
+  }
   float dsg[kRun], dc[3 * kRun];
 #pragma unroll
   for (int j = kRun - 1; j >= 0; --j) {
-    const Smp& q = R.x[j];
-    const float Ti1 = PT[j] * q.e;
-    const bool e = R.endf[j];  // sample j closes its segment: the suffix restarts
-    SCr = e ? 0.f : SCr; SCg = e ? 0.f : SCg; SCb = e ? 0.f : SCb;
-    SA = e ? 0.f : SA; SF = e ? 0.f : SF; SL = e ? 0.f : SL;
-    mf = e ? q.m : mf;
-    TN = e ? Ti1 : TN;
-    if (R.ends[j] >= 0) {
-      const int64_t sgi = s_lo + R.ends[j];
-#pragma unroll
-      for (int k = 0; k < 7; ++k) g[k] = gseg[k * n_seg + sgi];
-    }
-    const float w = PT[j] * q.alpha;
-    const float Zs = fmaf(SA, mf - q.m, SF);
-    const float wd3 = w * q.delta * (1.f / 3.f);
-    const float cdot = g[1] * fmaf(Ti1, q.c0, -SCr) + g[2] * fmaf(Ti1, q.c1, -SCg) +
-                       g[3] * fmaf(Ti1, q.c2, -SCb);
-    const float dL = 2.f * (TN * PZ[j] - PA[j] * Zs - SL + (Ti1 - w) * Zs) + 2.f * Ti1 * wd3;
-    const float dtau = g[0] + cdot + g[4] * TN + g[5] * fmaf(q.m, TN, -Zs) + g[6] * dL;
-    dsg[j] = q.delta * dtau;
-    dc[3 * j] = w * g[1];
-    dc[3 * j + 1] = w * g[2];
-    dc[3 * j + 2] = w * g[3];
-    // sample j joins the suffix
-    SCr = fmaf(w, q.c0, SCr);
-    SCg = fmaf(w, q.c1, SCg);
-    SCb = fmaf(w, q.c2, SCb);
-    SL = fmaf(2.f * w, Zs, SL + w * wd3);
-    SF = Zs;
-    SA += w;
-    mf = q.m;
+    reverse_step(R.x[j], PT[j], PA[j], PZ[j], R.endf[j], R.ends[j], s_lo, n_seg, gl, gseg, g, SCr, SCg,
+                 SCb, SA, SF, SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
   }
 
   const int64_t i0 = R.i0;
@@ -459,17 +533,20 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   }
 }
 
-template <int DT>
+template <int DT, bool FULL>
 __global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
     SamplesDev s, const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
-    const TileRec* __restrict__ recs, const float* __restrict__ gseg, void* __restrict__ gsig_p,
-    void* __restrict__ grgb_p) {
+    int64_t t_first, int64_t t_end, const TileRec* __restrict__ recs,
+    const float* __restrict__ gseg, void* __restrict__ gsig_p, void* __restrict__ grgb_p) {
   __shared__ int endloc_all[kWavesPerBlock][kTile];
+  __shared__ float gl_all[kWavesPerBlock][7 * kStagedSegs];
+  __shared__ float park_all[kWavesPerBlock][kRangeFields * kWave];
   __shared__ int64_t tailseg_all[kWavesPerBlock];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
-  const bool active = t < n_tiles;
+  const int64_t t = t_first + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
+  const bool active = t < t_end;
   int* endloc = endloc_all[wave];
+  float* gl = gl_all[wave];
 #pragma unroll
   for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
   if (lane == 0) tailseg_all[wave] = -1;
@@ -477,18 +554,44 @@ __global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
   int64_t s_lo = 0;
   if (active) {
     s_lo = recs[t].first_seg;
-    stage_ends<false>(off, n_seg, s.n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], nullptr);
+    stage_ends<false>(off, n_seg, s.n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], nullptr,
+                      gseg, gl);
   }
   __syncthreads();
   if (!active) return;
-  if ((t + 1) * kTile <= s.n)
-    bwd_tile<DT, true>(s, n_seg, t, s_lo, lane, endloc, recs, gseg, gsig_p, grgb_p);
-  else
-    bwd_tile<DT, false>(s, n_seg, t, s_lo, lane, endloc, recs, gseg, gsig_p, grgb_p);
+  bwd_tile<DT, FULL>(s, n_seg, t, s_lo, lane, endloc, gl, park_all[wave], recs, gseg, gsig_p, grgb_p);
 }
 
 static inline unsigned grid_for(int64_t count, int block) {
   return static_cast<unsigned>((count + block - 1) / block);
+}
+
+// Launches FULL tiles [0, n_full) and the ragged tile n_full (if any).
+template <int DT>
+static void launch_fwd_dt(const SamplesDev& s, const int64_t* off, int64_t n_seg, int64_t nt,
+                          float* seg_out, TileRec* recs, hipStream_t st) {
+  const int64_t n_full = s.n / kTile;
+  if (n_full > 0)
+    hipLaunchKernelGGL((seg_fwd_kernel<DT, true>), dim3(grid_for(n_full, kWavesPerBlock)),
+                       dim3(kBlock), 0, st, s, off, n_seg, nt, static_cast<int64_t>(0), n_full,
+                       seg_out, recs);
+  if (n_full < nt)
+    hipLaunchKernelGGL((seg_fwd_kernel<DT, false>), dim3(1), dim3(kBlock), 0, st, s, off, n_seg, nt,
+                       n_full, nt, seg_out, recs);
+}
+
+template <int DT>
+static void launch_bwd_dt(const SamplesDev& s, const int64_t* off, int64_t n_seg, int64_t nt,
+                          const TileRec* recs, const float* gseg, void* gs, void* gc,
+                          hipStream_t st) {
+  const int64_t n_full = s.n / kTile;
+  if (n_full > 0)
+    hipLaunchKernelGGL((seg_bwd_kernel<DT, true>), dim3(grid_for(n_full, kWavesPerBlock)),
+                       dim3(kBlock), 0, st, s, off, n_seg, nt, static_cast<int64_t>(0), n_full, recs,
+                       gseg, gs, gc);
+  if (n_full < nt)
+    hipLaunchKernelGGL((seg_bwd_kernel<DT, false>), dim3(1), dim3(kBlock), 0, st, s, off, n_seg, nt,
+                       n_full, nt, recs, gseg, gs, gc);
 }
 
 hipError_t launch_segments_fwd(const SamplesDev& s, const int64_t* off, int64_t n_seg,
@@ -502,20 +605,10 @@ hipError_t launch_segments_fwd(const SamplesDev& s, const int64_t* off, int64_t 
   const int64_t nt = num_tiles(s.n);
   hipLaunchKernelGGL(plan_kernel, dim3(grid_for(nt, 256)), dim3(256), 0, stream, off, n_seg, nt,
                      recs);
-  const dim3 grid(grid_for(nt, kWavesPerBlock));
   switch (s.dtype) {
-    case kF32:
-      hipLaunchKernelGGL(seg_fwd_kernel<kF32>, grid, dim3(kBlock), 0, stream, s, off, n_seg, nt,
-                         seg_out, recs);
-      break;
-    case kBF16:
-      hipLaunchKernelGGL(seg_fwd_kernel<kBF16>, grid, dim3(kBlock), 0, stream, s, off, n_seg, nt,
-                         seg_out, recs);
-      break;
-    default:
-      hipLaunchKernelGGL(seg_fwd_kernel<kF16>, grid, dim3(kBlock), 0, stream, s, off, n_seg, nt,
-                         seg_out, recs);
-      break;
+    case kF32: launch_fwd_dt<kF32>(s, off, n_seg, nt, seg_out, recs, stream); break;
+    case kBF16: launch_fwd_dt<kBF16>(s, off, n_seg, nt, seg_out, recs, stream); break;
+    default: launch_fwd_dt<kF16>(s, off, n_seg, nt, seg_out, recs, stream); break;
   }
   hipLaunchKernelGGL(seg_fixup_kernel, dim3(grid_for(nt, 256)), dim3(256), 0, stream, nt, n_seg,
                      seg_out, recs);
@@ -527,20 +620,10 @@ hipError_t launch_segments_bwd(const SamplesDev& s, const int64_t* off, int64_t 
                                void* grad_rgb, hipStream_t stream) {
   if (s.n == 0 || n_seg == 0) return hipSuccess;
   const int64_t nt = num_tiles(s.n);
-  const dim3 grid(grid_for(nt, kWavesPerBlock));
   switch (s.dtype) {
-    case kF32:
-      hipLaunchKernelGGL(seg_bwd_kernel<kF32>, grid, dim3(kBlock), 0, stream, s, off, n_seg, nt,
-                         recs, grad_seg, grad_sigma, grad_rgb);
-      break;
-    case kBF16:
-      hipLaunchKernelGGL(seg_bwd_kernel<kBF16>, grid, dim3(kBlock), 0, stream, s, off, n_seg, nt,
-                         recs, grad_seg, grad_sigma, grad_rgb);
-      break;
-    default:
-      hipLaunchKernelGGL(seg_bwd_kernel<kF16>, grid, dim3(kBlock), 0, stream, s, off, n_seg, nt,
-                         recs, grad_seg, grad_sigma, grad_rgb);
-      break;
+    case kF32: launch_bwd_dt<kF32>(s, off, n_seg, nt, recs, grad_seg, grad_sigma, grad_rgb, stream); break;
+    case kBF16: launch_bwd_dt<kBF16>(s, off, n_seg, nt, recs, grad_seg, grad_sigma, grad_rgb, stream); break;
+    default: launch_bwd_dt<kF16>(s, off, n_seg, nt, recs, grad_seg, grad_sigma, grad_rgb, stream); break;
   }
   return hipGetLastError();
 }

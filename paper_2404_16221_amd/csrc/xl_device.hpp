@@ -341,6 +341,21 @@ __device__ __forceinline__ void scan_up_pre(Pre& x, bool& f, int lane) {
   }
 }
 
-__device__ __forceinline__ void store_range(Range* dst, const Range& r) { *dst = r; }
+// A range parked in LDS, structure of arrays over the 64 lanes of a wave.
+constexpr int kRangeFields = 10;
+__device__ __forceinline__ void park_range(float* __restrict__ lds, int lane, const Range& r) {
+  lds[0 * kWave + lane] = r.tau; lds[1 * kWave + lane] = r.cr; lds[2 * kWave + lane] = r.cg;
+  lds[3 * kWave + lane] = r.cb; lds[4 * kWave + lane] = r.A; lds[5 * kWave + lane] = r.F;
+  lds[6 * kWave + lane] = r.B; lds[7 * kWave + lane] = r.L; lds[8 * kWave + lane] = r.m0;
+  lds[9 * kWave + lane] = r.m1;
+}
+__device__ __forceinline__ Range unpark_range(const float* __restrict__ lds, int lane) {
+  Range r;
+  r.tau = lds[0 * kWave + lane]; r.cr = lds[1 * kWave + lane]; r.cg = lds[2 * kWave + lane];
+  r.cb = lds[3 * kWave + lane]; r.A = lds[4 * kWave + lane]; r.F = lds[5 * kWave + lane];
+  r.B = lds[6 * kWave + lane]; r.L = lds[7 * kWave + lane]; r.m0 = lds[8 * kWave + lane];
+  r.m1 = lds[9 * kWave + lane];
+  return r;
+}
 
 }  // namespace xl

@@ -35,13 +35,11 @@ Per sample i, two draws (slots 256 + 2 i and 256 + 2 i + 1), cut into fields:
 Widths are rescaled to sum to t_far when they exceed it; the intervals are
 contiguous from a start drawn uniformly in [0, t_far - sum].
 
-Bit-exact reproducibility where it matters: the interval ends decide the
-segment structure and the kernels' delta = t_end - t_start, so they are built
-only from IEEE-exact operations -- the width's logarithm is the float32
-function ``log_f32`` below (atanh series, fixed operation order, no fused
-multiply-add), the sums are sequential float64 additions -- and a device twin
-of this generator yields identical t_start, t_end, box tags and layout.
-Densities use library transcendentals and may differ in the last float32 bit.
+Bit-exact reproducibility: every value is built only from IEEE operations in a
+fixed order -- float32 ``log_f32``, ``exp_f32`` and ``cos2pi_f32`` below (series
+with exact range reductions, no fused multiply-add), correctly rounded square
+roots and divisions, sequential float64 position sums -- so the device twin of
+this generator yields bit-identical samples, box tags and layout.
 """
 from __future__ import annotations
 
@@ -76,6 +74,49 @@ _LN2 = _F32(0x3F317218)       # ln 2
 _ONE = np.float32(1.0)
 _TWO = np.float32(2.0)
 _HALF = np.float32(0.5)
+
+
+_INV_LN2 = _F32(0x3FB8AA3B)   # 1/ln 2
+_LN2_HI = _F32(0x3F317200)    # ln 2, high part (few mantissa bits: k * hi is exact)
+_LN2_LO = _F32(0x35BFBE8E)    # ln 2 - hi
+_PI_2 = _F32(0x3FC90FDB)      # pi / 2
+
+
+def exp_f32(y: np.ndarray) -> np.ndarray:
+    """exp of float32 values in (-87, 88), float32 IEEE operations only.
+
+    k = rint(y / ln 2), r = (y - k ln2_hi) - k ln2_lo (Cody & Waite), exp r by its
+    Taylor series to r^7 in Horner form, times 2^k (exact)."""
+    y = np.asarray(y, dtype=np.float32)
+    k = np.rint(y * _INV_LN2).astype(np.float32)
+    r = (y - k * _LN2_HI) - k * _LN2_LO
+    p = np.float32(1.0) + r * np.float32(1.0 / 7.0)
+    for d in (6, 5, 4, 3, 2, 1):
+        p = np.float32(1.0) + (r * np.float32(1.0 / d)) * p
+    return np.ldexp(p, k.astype(np.int32)).astype(np.float32)
+
+
+def cos2pi_f32(u: np.ndarray) -> np.ndarray:
+    """cos(2 pi u) for float32 u in [0, 1), float32 IEEE operations only.
+
+    Quadrant n and fraction f of 4u are exact; the angle a in [0, pi/4] is f or
+    1 - f times pi/2; sin a and cos a by their Taylor series to a^9 and a^8."""
+    u = np.asarray(u, dtype=np.float32)
+    t = u * np.float32(4.0)
+    n = np.floor(t)
+    f = t - n
+    flip = f > np.float32(0.5)
+    a = np.where(flip, np.float32(1.0) - f, f).astype(np.float32) * _PI_2
+    a2 = a * a
+    c = np.float32(1.0) - (a2 * np.float32(0.5)) * (np.float32(1.0) - (a2 * np.float32(1.0 / 12.0)) * (
+        np.float32(1.0) - (a2 * np.float32(1.0 / 30.0)) * (np.float32(1.0) - a2 * np.float32(1.0 / 56.0))))
+    sn = a * (np.float32(1.0) - (a2 * np.float32(1.0 / 6.0)) * (np.float32(1.0) - (a2 * np.float32(1.0 / 20.0)) * (
+        np.float32(1.0) - (a2 * np.float32(1.0 / 42.0)) * (np.float32(1.0) - a2 * np.float32(1.0 / 72.0)))))
+    ca = np.where(flip, sn, c)   # cos of the quadrant's angle
+    sa = np.where(flip, c, sn)   # sin of the quadrant's angle
+    n = n.astype(np.int32) & 3
+    out = np.where(n == 0, ca, np.where(n == 1, -sa, np.where(n == 2, -ca, sa)))
+    return out.astype(np.float32)
 
 
 def log_f32(u: np.ndarray) -> np.ndarray:
@@ -270,8 +311,10 @@ def _gen_ray_major(w: Workload, rays: np.ndarray):
     v1 = draw(sk, base)
     v2 = draw(sk, base + np.uint64(1))
     width = (-(wm * log_f32(u24_open0(v1)))).astype(np.float64)
-    z = np.sqrt(-2.0 * np.log(field(v1, 20, 20) + 2.0 ** -20)) * np.cos(2.0 * np.pi * field(v1, 0, 20))
-    sigma = np.exp(w.sigma_mu + w.sigma_s * z)
+    u1 = (field(v1, 20, 20) + 2.0 ** -20).astype(np.float32)   # exact: 20-bit values
+    u2 = field(v1, 0, 20).astype(np.float32)
+    z = np.sqrt(np.float32(-2.0) * log_f32(u1)) * cos2pi_f32(u2)
+    sigma = exp_f32(np.float32(w.sigma_mu) + np.float32(w.sigma_s) * z).astype(np.float64)
     if w.zero_frac > 0.0:
         sigma[field(v2, 48, 16) < w.zero_frac] = 0.0
     rgb = np.stack([field(v2, 32, 16), field(v2, 16, 16), field(v2, 0, 16)], axis=1)
