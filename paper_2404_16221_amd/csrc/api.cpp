@@ -180,7 +180,8 @@ int xl_check_inputs(const xl_samples* s, const int64_t* seg_offsets, int64_t n_s
   int host = big;
   if (e == hipSuccess) e = hipMemcpyAsync(&host, code, sizeof(int), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  hipFree(code);
+  const hipError_t ef = hipFree(code);
+  if (e == hipSuccess) e = ef;
   if (e != hipSuccess) return fail(XL_EHIP, "xl_check_inputs: %s", hipGetErrorString(e));
   static const char* what[] = {"",
                                "seg_offsets[0] != 0",

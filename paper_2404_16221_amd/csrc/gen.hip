@@ -22,7 +22,25 @@
 #include "internal.h"
 #include "xl_device.hpp"
 
+// Every floating-point operation in this file rounds on its own, as on the
+// host, which never fuses a multiply into an add.  The __*_rn wrappers of the
+// HIP headers are plain operators that the compiler still contracts into
+// fused multiply-adds, so the generator uses these, defined where contraction
+// is off.
+#pragma clang fp contract(off)
+
 namespace xl {
+
+__device__ __forceinline__ float f_mul(float a, float b) { return a * b; }
+__device__ __forceinline__ float f_add(float a, float b) { return a + b; }
+__device__ __forceinline__ float f_sub(float a, float b) { return a - b; }
+__device__ __forceinline__ float f_div(float a, float b) { return a / b; }
+__device__ __forceinline__ float f_sqrt(float a) { return __fsqrt_rn(a); }
+__device__ __forceinline__ double d_mul(double a, double b) { return a * b; }
+__device__ __forceinline__ double d_add(double a, double b) { return a + b; }
+__device__ __forceinline__ double d_sub(double a, double b) { return a - b; }
+__device__ __forceinline__ double d_div(double a, double b) { return a / b; }
+__device__ __forceinline__ double d_sqrt(double a) { return __dsqrt_rn(a); }
 
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
 constexpr int kRayBlock = 256;
@@ -49,7 +67,7 @@ __device__ __forceinline__ double field(uint64_t v, int shift, int bits) {
   return static_cast<double>((v >> shift) & ((1ull << bits) - 1ull)) * ldexp(1.0, -bits);
 }
 __device__ __forceinline__ float u24_open0(uint64_t v) {
-  return __fmul_rn(static_cast<float>((v >> 40) + 1ull), 0x1p-24f);
+  return f_mul(static_cast<float>((v >> 40) + 1ull), 0x1p-24f);
 }
 
 // float32 natural log from IEEE operations only: u = 2^e x, x in
@@ -60,56 +78,56 @@ __device__ __forceinline__ float log_f32(float u) {
   int e = ((bits >> 23) & 0xff) - 127;
   float x = __int_as_float((bits & 0x7fffff) | 0x3f800000);
   if (x > __int_as_float(0x3FB504F3)) {
-    x = __fmul_rn(x, 0.5f);
+    x = f_mul(x, 0.5f);
     e += 1;
   }
-  const float s = __fdiv_rn(__fsub_rn(x, 1.f), __fadd_rn(x, 1.f));
-  const float s2 = __fmul_rn(s, s);
-  float p = __fadd_rn(__int_as_float(0x3E124925), __fmul_rn(s2, __int_as_float(0x3DE38E39)));
-  p = __fadd_rn(__int_as_float(0x3E4CCCCD), __fmul_rn(s2, p));
-  p = __fadd_rn(__int_as_float(0x3EAAAAAB), __fmul_rn(s2, p));
-  p = __fmul_rn(s2, p);
-  const float lx = __fmul_rn(2.f, __fadd_rn(s, __fmul_rn(s, p)));
-  return __fadd_rn(__fmul_rn(static_cast<float>(e), __int_as_float(0x3F317218)), lx);
+  const float s = f_div(f_sub(x, 1.f), f_add(x, 1.f));
+  const float s2 = f_mul(s, s);
+  float p = f_add(__int_as_float(0x3E124925), f_mul(s2, __int_as_float(0x3DE38E39)));
+  p = f_add(__int_as_float(0x3E4CCCCD), f_mul(s2, p));
+  p = f_add(__int_as_float(0x3EAAAAAB), f_mul(s2, p));
+  p = f_mul(s2, p);
+  const float lx = f_mul(2.f, f_add(s, f_mul(s, p)));
+  return f_add(f_mul(static_cast<float>(e), __int_as_float(0x3F317218)), lx);
 }
 
 // exp of float32 values in (-87, 88) from IEEE operations only (twin of the host
 // generator's exp_f32): k = rint(y / ln 2), r = (y - k ln2_hi) - k ln2_lo
 // (Cody & Waite), exp r by its Taylor series to r^7 (Horner), times 2^k.
 __device__ __forceinline__ float exp_f32(float y) {
-  const float k = rintf(__fmul_rn(y, __int_as_float(0x3FB8AA3B)));
-  const float r = __fsub_rn(__fsub_rn(y, __fmul_rn(k, __int_as_float(0x3F317200))),
-                            __fmul_rn(k, __int_as_float(0x35BFBE8E)));
-  float p = __fadd_rn(1.f, __fmul_rn(r, static_cast<float>(1.0 / 7.0)));
-  p = __fadd_rn(1.f, __fmul_rn(__fmul_rn(r, static_cast<float>(1.0 / 6.0)), p));
-  p = __fadd_rn(1.f, __fmul_rn(__fmul_rn(r, static_cast<float>(1.0 / 5.0)), p));
-  p = __fadd_rn(1.f, __fmul_rn(__fmul_rn(r, static_cast<float>(1.0 / 4.0)), p));
-  p = __fadd_rn(1.f, __fmul_rn(__fmul_rn(r, static_cast<float>(1.0 / 3.0)), p));
-  p = __fadd_rn(1.f, __fmul_rn(__fmul_rn(r, static_cast<float>(1.0 / 2.0)), p));
-  p = __fadd_rn(1.f, __fmul_rn(__fmul_rn(r, 1.f), p));
+  const float k = rintf(f_mul(y, __int_as_float(0x3FB8AA3B)));
+  const float r = f_sub(f_sub(y, f_mul(k, __int_as_float(0x3F317200))),
+                            f_mul(k, __int_as_float(0x35BFBE8E)));
+  float p = f_add(1.f, f_mul(r, static_cast<float>(1.0 / 7.0)));
+  p = f_add(1.f, f_mul(f_mul(r, static_cast<float>(1.0 / 6.0)), p));
+  p = f_add(1.f, f_mul(f_mul(r, static_cast<float>(1.0 / 5.0)), p));
+  p = f_add(1.f, f_mul(f_mul(r, static_cast<float>(1.0 / 4.0)), p));
+  p = f_add(1.f, f_mul(f_mul(r, static_cast<float>(1.0 / 3.0)), p));
+  p = f_add(1.f, f_mul(f_mul(r, static_cast<float>(1.0 / 2.0)), p));
+  p = f_add(1.f, f_mul(f_mul(r, 1.f), p));
   return ldexpf(p, static_cast<int>(k));
 }
 
 // cos(2 pi u) for u in [0, 1) from IEEE operations only (twin of cos2pi_f32):
 // exact quadrant split of 4u, angle in [0, pi/4], Taylor series to a^9 / a^8.
 __device__ __forceinline__ float cos2pi_f32(float u) {
-  const float t = __fmul_rn(u, 4.f);
+  const float t = f_mul(u, 4.f);
   const float n = floorf(t);
-  const float f = __fsub_rn(t, n);
+  const float f = f_sub(t, n);
   const bool flip = f > 0.5f;
-  const float a = __fmul_rn(flip ? __fsub_rn(1.f, f) : f, __int_as_float(0x3FC90FDB));
-  const float a2 = __fmul_rn(a, a);
+  const float a = f_mul(flip ? f_sub(1.f, f) : f, __int_as_float(0x3FC90FDB));
+  const float a2 = f_mul(a, a);
   // cos a = 1 - (a2/2)(1 - (a2/12)(1 - (a2/30)(1 - a2/56)))
-  float c = __fsub_rn(1.f, __fmul_rn(a2, static_cast<float>(1.0 / 56.0)));
-  c = __fsub_rn(1.f, __fmul_rn(__fmul_rn(a2, static_cast<float>(1.0 / 30.0)), c));
-  c = __fsub_rn(1.f, __fmul_rn(__fmul_rn(a2, static_cast<float>(1.0 / 12.0)), c));
-  c = __fsub_rn(1.f, __fmul_rn(__fmul_rn(a2, 0.5f), c));
+  float c = f_sub(1.f, f_mul(a2, static_cast<float>(1.0 / 56.0)));
+  c = f_sub(1.f, f_mul(f_mul(a2, static_cast<float>(1.0 / 30.0)), c));
+  c = f_sub(1.f, f_mul(f_mul(a2, static_cast<float>(1.0 / 12.0)), c));
+  c = f_sub(1.f, f_mul(f_mul(a2, 0.5f), c));
   // sin a = a (1 - (a2/6)(1 - (a2/20)(1 - (a2/42)(1 - a2/72))))
-  float sn = __fsub_rn(1.f, __fmul_rn(a2, static_cast<float>(1.0 / 72.0)));
-  sn = __fsub_rn(1.f, __fmul_rn(__fmul_rn(a2, static_cast<float>(1.0 / 42.0)), sn));
-  sn = __fsub_rn(1.f, __fmul_rn(__fmul_rn(a2, static_cast<float>(1.0 / 20.0)), sn));
-  sn = __fsub_rn(1.f, __fmul_rn(__fmul_rn(a2, static_cast<float>(1.0 / 6.0)), sn));
-  sn = __fmul_rn(a, sn);
+  float sn = f_sub(1.f, f_mul(a2, static_cast<float>(1.0 / 72.0)));
+  sn = f_sub(1.f, f_mul(f_mul(a2, static_cast<float>(1.0 / 42.0)), sn));
+  sn = f_sub(1.f, f_mul(f_mul(a2, static_cast<float>(1.0 / 20.0)), sn));
+  sn = f_sub(1.f, f_mul(f_mul(a2, static_cast<float>(1.0 / 6.0)), sn));
+  sn = f_mul(a, sn);
   const float ca = flip ? sn : c;
   const float sa = flip ? c : sn;
   const int q = static_cast<int>(n) & 3;
@@ -135,7 +153,7 @@ __device__ __forceinline__ RayState ray_state(const GenDev& g, int64_t r) {
   RayState s;
   s.key = mix64(g.seedkey + static_cast<uint64_t>(g.ray0 + r) * kGamma);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) s.o[c] = __dsub_rn(__dmul_rn(2.0, u53(draw(s.key, c))), 1.0);
+  for (int c = 0; c < 3; ++c) s.o[c] = d_sub(d_mul(2.0, u53(draw(s.key, c))), 1.0);
   const uint64_t span = static_cast<uint64_t>(g.n_max - g.n_min + 1);
   s.count = g.n_min + static_cast<int32_t>(((draw(s.key, 3) >> 32) * span) >> 32);
   s.u_start = u53(draw(s.key, 4));
@@ -144,13 +162,13 @@ __device__ __forceinline__ RayState ray_state(const GenDev& g, int64_t r) {
     double v[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      v[c] = __dsub_rn(__dmul_rn(2.0, u53(draw(s.key, 16 + 3 * j + c))), 1.0);
-    const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(v[0], v[0]), __dmul_rn(v[1], v[1])),
-                                __dmul_rn(v[2], v[2]));
+      v[c] = d_sub(d_mul(2.0, u53(draw(s.key, 16 + 3 * j + c))), 1.0);
+    const double r2 = d_add(d_add(d_mul(v[0], v[0]), d_mul(v[1], v[1])),
+                                d_mul(v[2], v[2]));
     if (r2 > 1e-12 && r2 <= 1.0) {
-      const double q = __dsqrt_rn(r2);
+      const double q = d_sqrt(r2);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) s.d[c] = __ddiv_rn(v[c], q);
+      for (int c = 0; c < 3; ++c) s.d[c] = d_div(v[c], q);
       break;
     }
   }
@@ -159,17 +177,17 @@ __device__ __forceinline__ RayState ray_state(const GenDev& g, int64_t r) {
 
 __device__ __forceinline__ double width_of(const GenDev& g, uint64_t key, int i) {
   const uint64_t v = draw(key, kRaySlots + static_cast<uint64_t>(kSampleStride) * i);
-  return static_cast<double>(-__fmul_rn(g.wm, log_f32(u24_open0(v))));
+  return static_cast<double>(-f_mul(g.wm, log_f32(u24_open0(v))));
 }
 
 __device__ __forceinline__ int box_of(const GenDev& g, const RayState& s, float t0, float t1) {
-  const double mid = __dmul_rn(0.5, __dadd_rn(static_cast<double>(t0), static_cast<double>(t1)));
+  const double mid = d_mul(0.5, d_add(static_cast<double>(t0), static_cast<double>(t1)));
   const int gsz[3] = {g.gx, g.gy, g.gz};
   int cell[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double p = __dadd_rn(s.o[c], __dmul_rn(mid, s.d[c]));
-    const double f = floor(__dmul_rn(__dmul_rn(__dadd_rn(p, 1.0), 0.5), static_cast<double>(gsz[c])));
+    const double p = d_add(s.o[c], d_mul(mid, s.d[c]));
+    const double f = floor(d_mul(d_mul(d_add(p, 1.0), 0.5), static_cast<double>(gsz[c])));
     int64_t k = static_cast<int64_t>(f);
     k = k < 0 ? 0 : (k > gsz[c] - 1 ? gsz[c] - 1 : k);
     cell[c] = static_cast<int>(k);
@@ -202,10 +220,10 @@ __global__ void gen_struct_kernel(GenDev g, GenWs w) {
   if (r >= g.n_rays) return;
   const RayState s = ray_state(g, r);
   double tot = 0.0;
-  for (int i = 0; i < s.count; ++i) tot = __dadd_rn(tot, width_of(g, s.key, i));
-  const double scale = tot > g.t_far ? __ddiv_rn(g.t_far, tot) : 1.0;
-  const double rest = __dsub_rn(g.t_far, __dmul_rn(tot, scale));
-  const double s0 = __dmul_rn(s.u_start, rest > 0.0 ? rest : 0.0);
+  for (int i = 0; i < s.count; ++i) tot = d_add(tot, width_of(g, s.key, i));
+  const double scale = tot > g.t_far ? d_div(g.t_far, tot) : 1.0;
+  const double rest = d_sub(g.t_far, d_mul(tot, scale));
+  const double s0 = d_mul(s.u_start, rest > 0.0 ? rest : 0.0);
   w.scale[r] = scale;
   w.s0[r] = s0;
   const int M = g.max_segs;
@@ -213,7 +231,7 @@ __global__ void gen_struct_kernel(GenDev g, GenWs w) {
   double run = s0;
   for (int i = 0; i < s.count; ++i) {
     const double t0 = run;
-    run = __dadd_rn(run, __dmul_rn(width_of(g, s.key, i), scale));
+    run = d_add(run, d_mul(width_of(g, s.key, i), scale));
     const int b = box_of(g, s, static_cast<float>(t0), static_cast<float>(run));
     if (b != cur) {
       if (k + 1 < M) {
@@ -322,13 +340,13 @@ __global__ void gen_fill_kernel(GenDev g, GenWs w, void* __restrict__ sigma, voi
       dst = w.seg_off[w.seg_pid[r * M + k]];
     }
     const double t0 = run;
-    run = __dadd_rn(run, __dmul_rn(width_of(g, key, i), scale));
+    run = d_add(run, d_mul(width_of(g, key, i), scale));
     const uint64_t base = kRaySlots + static_cast<uint64_t>(kSampleStride) * i;
     const uint64_t v1 = draw(key, base), v2 = draw(key, base + 1);
     const float u1 = static_cast<float>(field(v1, 20, 20) + 0x1p-20);
     const float u2 = static_cast<float>(field(v1, 0, 20));
-    const float z = __fmul_rn(__fsqrt_rn(__fmul_rn(-2.f, log_f32(u1))), cos2pi_f32(u2));
-    float sg = exp_f32(__fadd_rn(g.mu, __fmul_rn(g.sg, z)));
+    const float z = f_mul(f_sqrt(f_mul(-2.f, log_f32(u1))), cos2pi_f32(u2));
+    float sg = exp_f32(f_add(g.mu, f_mul(g.sg, z)));
     if (field(v2, 48, 16) < g.zero_frac) sg = 0.f;
     put_sample<DT>(sigma, rgb, dst, sg, static_cast<float>(field(v2, 32, 16)),
                    static_cast<float>(field(v2, 16, 16)), static_cast<float>(field(v2, 0, 16)));
@@ -383,18 +401,20 @@ __global__ void scan_total_kernel(int64_t* __restrict__ out, int64_t n, const in
   out[n] = n > 0 ? out[n - 1] + in[n - 1] : 0;
 }
 
+// Elements of tmp that scan_exclusive(in, out, n, tmp) writes: a level with
+// nb > 1 blocks keeps nb block sums and their nb + 1 scanned offsets, then
+// scans the sums with the space after them; one block writes one sum.
 size_t scan_tmp_elems(int64_t n) {
-  size_t total = 0;
-  int64_t m = n;
-  while (m > 1) {
-    m = (m + kScanBlock - 1) / kScanBlock;
-    total += static_cast<size_t>(m) + 1;
-  }
-  return total + 2;
+  if (n <= 0) return 0;
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb == 1) return 1;
+  return static_cast<size_t>(2 * nb + 1) + scan_tmp_elems(nb);
 }
 
 // out has n + 1 entries; tmp has scan_tmp_elems(n) entries.
-hipError_t scan_exclusive(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t st) {
+hipError_t scan_exclusive(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, size_t tmp_elems,
+                          hipStream_t st) {
+  if (scan_tmp_elems(n) > tmp_elems) return hipErrorInvalidValue;
   if (n <= 0) {
     hipLaunchKernelGGL(scan_total_kernel, dim3(1), dim3(1), 0, st, out, static_cast<int64_t>(0), in);
     return hipGetLastError();
@@ -405,7 +425,7 @@ hipError_t scan_exclusive(const int64_t* in, int64_t* out, int64_t n, int64_t* t
   hipLaunchKernelGGL(scan_block_kernel, dim3(static_cast<unsigned>(nb)), dim3(kScanBlock), 0, st, in,
                      out, n, sums);
   if (nb > 1) {
-    hipError_t e = scan_exclusive(sums, offs, nb, offs + nb + 1, st);
+    hipError_t e = scan_exclusive(sums, offs, nb, offs + nb + 1, tmp_elems - (2 * nb + 1), st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(scan_add_kernel, dim3(static_cast<unsigned>(nb)), dim3(kScanBlock), 0, st,
                        out, n, offs);
@@ -417,6 +437,7 @@ hipError_t scan_exclusive(const int64_t* in, int64_t* out, int64_t n, int64_t* t
 // ---------------------------------------------------------------- host side
 struct GenLayout {
   int64_t R, M, K, nblk, RM;
+  size_t scan_elems;  // scan scratch, enough for the longest of the three scans
   size_t off[16];
   size_t bytes;
 };
@@ -430,6 +451,8 @@ static GenLayout layout(const xl_gen_params* p) {
   L.nblk = (L.R + kRayBlock - 1) / kRayBlock;
   L.RM = L.R * L.M;
   const int64_t KB = L.K * L.nblk;
+  const int64_t longest = L.RM > KB ? (L.RM > L.R ? L.RM : L.R) : (KB > L.R ? KB : L.R);
+  L.scan_elems = scan_tmp_elems(longest);
   const size_t sizes[] = {
       sizeof(int32_t) * L.R,           // nseg
       sizeof(int32_t) * L.RM,          // seg_box
@@ -444,7 +467,7 @@ static GenLayout layout(const xl_gen_params* p) {
       sizeof(int64_t) * L.RM,          // plen
       sizeof(int64_t) * (L.RM + 1),    // seg_off
       sizeof(int64_t) * L.RM,          // seg_ids
-      sizeof(int64_t) * (scan_tmp_elems(L.RM > KB ? (L.RM > L.R ? L.RM : L.R) : (KB > L.R ? KB : L.R))),
+      sizeof(int64_t) * L.scan_elems,  // scan_tmp
       sizeof(int32_t) * 4,             // err
   };
   size_t o = 0;
@@ -512,15 +535,16 @@ hipError_t gen_plan(const xl_gen_params* p, void* ws, hipStream_t st, int64_t* n
   hipLaunchKernelGGL(gen_struct_kernel, dim3(blocks(L.R, 128)), dim3(128), 0, st, g, w);
   hipLaunchKernelGGL(block_hist_kernel, dim3(static_cast<unsigned>(L.nblk)), dim3(kRayBlock), 0, st,
                      g, w, L.nblk, static_cast<int>(L.K));
-  if ((e = scan_exclusive(w.nseg64, w.ray_off, L.R, w.scan_tmp, st)) != hipSuccess) return e;
-  if ((e = scan_exclusive(w.blk_cnt, w.blk_base, L.K * L.nblk, w.scan_tmp, st)) != hipSuccess) return e;
+  if ((e = scan_exclusive(w.nseg64, w.ray_off, L.R, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
+  if ((e = scan_exclusive(w.blk_cnt, w.blk_base, L.K * L.nblk, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(gen_rank_kernel, dim3(static_cast<unsigned>(L.nblk)), dim3(kRayBlock), 0, st, g,
                      w, L.nblk, static_cast<int>(L.K));
   int64_t ns = 0;
   if ((e = hipMemcpyAsync(&ns, w.ray_off + L.R, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
     return e;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-  if ((e = scan_exclusive(w.plen, w.seg_off, ns, w.scan_tmp, st)) != hipSuccess) return e;
+  if (ns < 0 || ns > L.RM) return hipErrorInvalidValue;  // at most max_segs per ray
+  if ((e = scan_exclusive(w.plen, w.seg_off, ns, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
   int64_t n = 0;
   int err = 0;
   if ((e = hipMemcpyAsync(&n, w.seg_off + ns, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)

@@ -129,8 +129,8 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
   int64_t n = 0, n_seg = 0;
   int overflow = 0;
   if (gen_plan(&p, ws, st, &n, &n_seg, &overflow) != hipSuccess || overflow) {
-    hipFreeAsync(ws, st);
-    hipStreamSynchronize(st);
+    (void)hipFreeAsync(ws, st);  // cleanup on a path that already reports failure
+    (void)hipStreamSynchronize(st);
     finish(s, j, XL_EHIP, "generator plan failed");
     return;
   }
@@ -148,8 +148,8 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
     std::unique_lock<std::mutex> lk(s->mu);
     if (fp > s->cfg.hbm_budget_bytes) {
       lk.unlock();
-      hipFreeAsync(ws, st);
-      hipStreamSynchronize(st);
+      (void)hipFreeAsync(ws, st);
+      (void)hipStreamSynchronize(st);
       char m[160];
       std::snprintf(m, sizeof(m), "request needs %llu bytes, budget is %llu",
                     static_cast<unsigned long long>(fp),
@@ -168,10 +168,10 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
   int64_t* ro = nullptr;
   if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&ro), b_ro, st);
   if (e != hipSuccess) {
-    if (big) hipFreeAsync(big, st);
-    if (out) hipFreeAsync(out, st);
-    hipFreeAsync(ws, st);
-    hipStreamSynchronize(st);
+    if (big) (void)hipFreeAsync(big, st);
+    if (out) (void)hipFreeAsync(out, st);
+    (void)hipFreeAsync(ws, st);
+    (void)hipStreamSynchronize(st);
     {
       std::lock_guard<std::mutex> lk(s->mu);
       s->budget_used -= fp;
@@ -190,20 +190,21 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
   float* seg_out = reinterpret_cast<float*>(c); c += b_seg;
   TileRec* recs = reinterpret_cast<TileRec*>(c);
 
-  hipEventRecord(e0, st);
-  e = gen_fill(&p, dtype, ws, n_seg, sigma, rgb, t0, t1, off, ro, ids, st);
+  e = hipEventRecord(e0, st);
+  if (e == hipSuccess) e = gen_fill(&p, dtype, ws, n_seg, sigma, rgb, t0, t1, off, ro, ids, st);
   SamplesDev sd{dtype, sigma, rgb, t0, t1, n};
   if (e == hipSuccess) e = launch_segments_fwd(sd, off, n_seg, seg_out, recs, st);
   if (e == hipSuccess)
     e = launch_merge_fwd(seg_out, n_seg, ro, ids, p.n_rays, static_cast<float*>(out),
                          s->cfg.merge_fp64 != 0, st);
-  hipEventRecord(e1, st);
-  hipFreeAsync(big, st);
-  hipFreeAsync(ro, st);
-  hipFreeAsync(ws, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  hipError_t ef = hipFreeAsync(big, st);
+  if (ef == hipSuccess) ef = hipFreeAsync(ro, st);
+  if (ef == hipSuccess) ef = hipFreeAsync(ws, st);
+  if (e == hipSuccess) e = ef;
   const hipError_t es2 = hipStreamSynchronize(st);
   float ms = 0.f;
-  hipEventElapsedTime(&ms, e0, e1);
+  if (e == hipSuccess && es2 == hipSuccess && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 0.f;
   j->device_ms = ms;
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -211,8 +212,8 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
     s->cv_budget.notify_all();
   }
   if (e != hipSuccess || es2 != hipSuccess) {
-    hipFreeAsync(out, st);
-    hipStreamSynchronize(st);
+    (void)hipFreeAsync(out, st);
+    (void)hipStreamSynchronize(st);
     {
       std::lock_guard<std::mutex> lk(s->mu);
       s->budget_used -= b_out;
@@ -226,12 +227,12 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
 }
 
 static void worker(Server* s) {
-  hipSetDevice(s->cfg.device);
-  hipStream_t st;
-  hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  // A slot whose stream or events cannot be made fails every request it takes.
+  const bool ready = hipSetDevice(s->cfg.device) == hipSuccess &&
+                     hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+                     hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
   for (;;) {
     std::shared_ptr<Job> j;
     {
@@ -242,11 +243,14 @@ static void worker(Server* s) {
       s->queue.pop_front();
       j->t_admit = now_us();
     }
-    run_job(s, st, e0, e1, j);
+    if (ready)
+      run_job(s, st, e0, e1, j);
+    else
+      finish(s, j, XL_EHIP, "serving slot has no stream or events");
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipStreamDestroy(st);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) (void)hipStreamDestroy(st);
 }
 
 }  // namespace xl
@@ -259,15 +263,21 @@ int xl_serve_create(const xl_serve_config* cfg, xl_server** out) {
     return xl::set_error(XL_EINVAL, "max_slots and max_queue must be >= 1");
   if (cfg->dtype != XL_F32 && cfg->dtype != XL_BF16 && cfg->dtype != XL_F16)
     return xl::set_error(XL_EINVAL, "unknown sample dtype %d", cfg->dtype);
-  auto* s = new xl::Server();
-  s->cfg = *cfg;
-  hipSetDevice(cfg->device);
+  hipError_t e = hipSetDevice(cfg->device);
+  if (e != hipSuccess) return xl::set_error(XL_EHIP, "device %d: %s", cfg->device, hipGetErrorString(e));
   hipMemPool_t pool;
   if (hipDeviceGetDefaultMemPool(&pool, cfg->device) == hipSuccess) {
+    // Keep freed request buffers in the pool (a performance hint only).
     uint64_t keep = UINT64_MAX;
-    hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
   }
-  hipStreamCreateWithFlags(&s->release_stream, hipStreamNonBlocking);
+  auto* s = new xl::Server();
+  s->cfg = *cfg;
+  e = hipStreamCreateWithFlags(&s->release_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete s;
+    return xl::set_error(XL_EHIP, "release stream: %s", hipGetErrorString(e));
+  }
   for (int i = 0; i < cfg->max_slots; ++i) s->workers.emplace_back(xl::worker, s);
   *out = reinterpret_cast<xl_server*>(s);
   return xl::clear_error();
@@ -358,13 +368,16 @@ int xl_serve_release(xl_server* srv, uint64_t ticket) {
     s->jobs.erase(it);
   }
   if (j->ray_out) {
-    hipFreeAsync(j->ray_out, s->release_stream);
-    hipStreamSynchronize(s->release_stream);
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->budget_used -= j->result_bytes;
-    s->cv_budget.notify_all();
+    hipError_t e = hipFreeAsync(j->ray_out, s->release_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->release_stream);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->budget_used -= j->result_bytes;
+      s->cv_budget.notify_all();
+    }
+    if (e != hipSuccess) return xl::set_error(XL_EHIP, "release: %s", hipGetErrorString(e));
   }
-  return XL_OK;
+  return xl::clear_error();
 }
 
 int xl_serve_stats_get(xl_server* srv, xl_serve_stats* out) {
@@ -402,12 +415,14 @@ int xl_serve_destroy(xl_server* srv) {
     s->cv_budget.notify_all();
   }
   for (auto& t : s->workers) t.join();
+  hipError_t e = hipSuccess;
   for (auto& kv : s->jobs)
-    if (kv.second->ray_out) hipFreeAsync(kv.second->ray_out, s->release_stream);
-  hipStreamSynchronize(s->release_stream);
-  hipStreamDestroy(s->release_stream);
+    if (kv.second->ray_out && e == hipSuccess) e = hipFreeAsync(kv.second->ray_out, s->release_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->release_stream);
+  (void)hipStreamDestroy(s->release_stream);
   delete s;
-  return XL_OK;
+  if (e != hipSuccess) return xl::set_error(XL_EHIP, "destroy: %s", hipGetErrorString(e));
+  return xl::clear_error();
 }
 
 }  // extern "C"
