@@ -26,7 +26,7 @@
 // host, which never fuses a multiply into an add.  The __*_rn wrappers of the
 // HIP headers are plain operators that the compiler still contracts into
 // fused multiply-adds, so the generator uses these, defined where contraction
-// is off.
+// is off.  Division and square root are the correctly rounded ones.
 #pragma clang fp contract(off)
 
 namespace xl {
@@ -35,12 +35,14 @@ __device__ __forceinline__ float f_mul(float a, float b) { return a * b; }
 __device__ __forceinline__ float f_add(float a, float b) { return a + b; }
 __device__ __forceinline__ float f_sub(float a, float b) { return a - b; }
 __device__ __forceinline__ float f_div(float a, float b) { return a / b; }
-__device__ __forceinline__ float f_sqrt(float a) { return __fsqrt_rn(a); }
+// (__fsqrt_rn is the approximate hardware square root in these headers; the
+// builtin is correctly rounded.)
+__device__ __forceinline__ float f_sqrt(float a) { return __builtin_sqrtf(a); }
 __device__ __forceinline__ double d_mul(double a, double b) { return a * b; }
 __device__ __forceinline__ double d_add(double a, double b) { return a + b; }
 __device__ __forceinline__ double d_sub(double a, double b) { return a - b; }
 __device__ __forceinline__ double d_div(double a, double b) { return a / b; }
-__device__ __forceinline__ double d_sqrt(double a) { return __dsqrt_rn(a); }
+__device__ __forceinline__ double d_sqrt(double a) { return __builtin_sqrt(a); }
 
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
 constexpr int kRayBlock = 256;

@@ -10,9 +10,10 @@
 // respect to its own tuple only (the per-region differentiation rule of Sec.
 // 4.2 and App. A.2): for segment k with exclusive prefix fold P and suffix fold
 // S, the merged tuple is P (+) x_k (+) S, and the chain rule through the two
-// (+) operations gives the per-component gradients below.  The suffix folds
-// are computed first by a reverse sweep and parked in grad_seg, which the
-// forward sweep then overwrites with the gradients.
+// (+) operations gives the per-component gradients below.  Rays with up to
+// kCached segments hold their tuples and suffix folds in registers; longer rays
+// compute the suffix folds by a reverse sweep and park them in grad_seg, which
+// the forward sweep then overwrites with the gradients.
 #include "internal.h"
 #include "xl_device.hpp"
 
@@ -28,13 +29,24 @@ __device__ __forceinline__ double exp_neg_t<double>(double x) { return exp(-x); 
 template <typename R>
 struct Tup {
   R tau, cr, cg, cb, A, D, L;
+  R tlo;  // compensation of tau (the exact optical depth is tau + tlo)
 };
+
+// Compensated accumulation of optical depths (Knuth's TwoSum on the high parts).
+template <typename R>
+__device__ __forceinline__ void add_tau_t(R& tau, R& tlo, R hi, R lo) {
+  const R s = tau + hi;
+  const R bb = s - tau;
+  tlo += ((tau - (s - bb)) + (hi - bb)) + lo;
+  tau = s;
+}
 
 template <typename R>
 __device__ __forceinline__ Tup<R> load_tup(const float* __restrict__ p, int64_t n_seg, int64_t s) {
   Tup<R> x;
   x.tau = p[s]; x.cr = p[n_seg + s]; x.cg = p[2 * n_seg + s]; x.cb = p[3 * n_seg + s];
   x.A = p[4 * n_seg + s]; x.D = p[5 * n_seg + s]; x.L = p[6 * n_seg + s];
+  x.tlo = 0;
   return x;
 }
 
@@ -42,7 +54,8 @@ __device__ __forceinline__ Tup<R> load_tup(const float* __restrict__ p, int64_t 
 template <typename R>
 __device__ __forceinline__ Tup<R> fold(const Tup<R>& x, R Tx, const Tup<R>& y) {
   Tup<R> r;
-  r.tau = x.tau + y.tau;
+  r.tau = x.tau; r.tlo = x.tlo;
+  add_tau_t<R>(r.tau, r.tlo, y.tau, y.tlo);
   r.cr = x.cr + Tx * y.cr; r.cg = x.cg + Tx * y.cg; r.cb = x.cb + Tx * y.cb;
   r.A = x.A + Tx * y.A;
   r.D = x.D + Tx * y.D;
@@ -69,7 +82,7 @@ __global__ __launch_bounds__(256) void merge_fwd_kernel(const float* __restrict_
   int64_t k0, k1;
   clamp_range(ro, r, n_seg, k0, k1);
   // Alg. 1/2 state: T(t_1 -> t_k) and C, A, D, L accumulated so far.
-  R tau = 0, Tpre = 1, cr = 0, cg = 0, cb = 0, A = 0, D = 0, L = 0;
+  R tau = 0, tlo = 0, Tpre = 1, cr = 0, cg = 0, cb = 0, A = 0, D = 0, L = 0;
   for (int64_t k = k0; k < k1; ++k) {
     const int64_t s = ids[k];
     if (s < 0 || s >= n_seg) continue;
@@ -79,8 +92,8 @@ __global__ __launch_bounds__(256) void merge_fwd_kernel(const float* __restrict_
     cr += Tpre * x.cr; cg += Tpre * x.cg; cb += Tpre * x.cb;  // Eq. 3
     A += Tpre * x.A;                                  // Eq. 5
     D += Tpre * x.D;                                  // Eq. 6
-    tau += x.tau;
-    Tpre = exp_neg_t<R>(tau);                         // Eq. 4
+    add_tau_t<R>(tau, tlo, x.tau, R(0));
+    Tpre = exp_neg_t<R>(tau + tlo);                   // Eq. 4
   }
   out[r] = static_cast<float>(Tpre);
   out[n_rays + r] = static_cast<float>(cr);
@@ -90,6 +103,32 @@ __global__ __launch_bounds__(256) void merge_fwd_kernel(const float* __restrict_
   out[5 * n_rays + r] = static_cast<float>(D);
   out[6 * n_rays + r] = static_cast<float>(L);
 }
+
+// Gradient of P (+) x (+) S with respect to x, written to gseg[:, s].
+template <typename R>
+__device__ __forceinline__ void write_seg_grad(float* __restrict__ gseg, int64_t n_seg, int64_t s,
+                                               const Tup<R>& P, R PT, const Tup<R>& x,
+                                               const Tup<R>& Sk, R gT, R gCr, R gCg, R gCb, R gA,
+                                               R gD, R gL) {
+  const R Tk = exp_neg_t<R>(x.tau);
+  const R ST = exp_neg_t<R>(Sk.tau + Sk.tlo);
+  const R gA_k = PT * (gA + R(2) * gL * (PT * Tk * Sk.D - P.D));
+  const R gD_k = PT * (gD + R(2) * gL * (P.A - PT * Tk * Sk.A));
+  const R gL_k = gL * PT * PT;
+  const R gT_k = PT * gT * ST + PT * (gCr * Sk.cr + gCg * Sk.cg + gCb * Sk.cb) +
+                 (PT * gA - R(2) * gL * PT * P.D) * Sk.A +
+                 (PT * gD + R(2) * gL * PT * P.A) * Sk.D +
+                 gL * PT * PT * (R(2) * Tk * Sk.L + R(2) * (Sk.D * x.A - Sk.A * x.D));
+  gseg[s] = static_cast<float>(-Tk * gT_k);
+  gseg[n_seg + s] = static_cast<float>(PT * gCr);
+  gseg[2 * n_seg + s] = static_cast<float>(PT * gCg);
+  gseg[3 * n_seg + s] = static_cast<float>(PT * gCb);
+  gseg[4 * n_seg + s] = static_cast<float>(gA_k);
+  gseg[5 * n_seg + s] = static_cast<float>(gD_k);
+  gseg[6 * n_seg + s] = static_cast<float>(gL_k);
+}
+
+constexpr int kCached = 8;
 
 template <typename R>
 __global__ __launch_bounds__(256) void merge_bwd_kernel(const float* __restrict__ seg_out,
@@ -106,12 +145,40 @@ __global__ __launch_bounds__(256) void merge_bwd_kernel(const float* __restrict_
   const R gT = gray[r], gCr = gray[n_rays + r], gCg = gray[2 * n_rays + r],
           gCb = gray[3 * n_rays + r], gA = gray[4 * n_rays + r], gD = gray[5 * n_rays + r],
           gL = gray[6 * n_rays + r];
+  if (k1 - k0 <= kCached) {
+    Tup<R> x[kCached];
+    int64_t sid[kCached];
+#pragma unroll
+    for (int q = 0; q < kCached; ++q) {
+      const int64_t k = k0 + q;
+      sid[q] = (k < k1) ? ids[k] : -1;
+      const bool ok = sid[q] >= 0 && sid[q] < n_seg;
+      if (!ok) sid[q] = -1;
+      x[q] = ok ? load_tup<R>(seg_out, n_seg, sid[q]) : Tup<R>{0, 0, 0, 0, 0, 0, 0};
+    }
+    Tup<R> S[kCached];
+    Tup<R> acc{0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int q = kCached - 1; q >= 0; --q) {
+      S[q] = acc;
+      acc = fold<R>(x[q], exp_neg_t<R>(x[q].tau), acc);  // empty slots are identities
+    }
+    Tup<R> P{0, 0, 0, 0, 0, 0, 0};
+    R PT = 1;
+#pragma unroll
+    for (int q = 0; q < kCached; ++q) {
+      if (sid[q] >= 0) write_seg_grad<R>(gseg, n_seg, sid[q], P, PT, x[q], S[q], gT, gCr, gCg, gCb, gA, gD, gL);
+      P = fold<R>(P, PT, x[q]);
+      PT = exp_neg_t<R>(P.tau + P.tlo);
+    }
+    return;
+  }
   // Reverse sweep: exclusive suffix fold of every segment, parked in gseg.
   Tup<R> S{0, 0, 0, 0, 0, 0, 0};
   for (int64_t k = k1 - 1; k >= k0; --k) {
     const int64_t s = ids[k];
     if (s < 0 || s >= n_seg) continue;
-    gseg[s] = static_cast<float>(S.tau);
+    gseg[s] = static_cast<float>(S.tau + S.tlo);
     gseg[n_seg + s] = static_cast<float>(S.cr);
     gseg[2 * n_seg + s] = static_cast<float>(S.cg);
     gseg[3 * n_seg + s] = static_cast<float>(S.cb);
@@ -129,24 +196,9 @@ __global__ __launch_bounds__(256) void merge_bwd_kernel(const float* __restrict_
     if (s < 0 || s >= n_seg) continue;
     const Tup<R> x = load_tup<R>(seg_out, n_seg, s);
     const Tup<R> Sk = load_tup<R>(gseg, n_seg, s);
-    const R Tk = exp_neg_t<R>(x.tau);
-    const R ST = exp_neg_t<R>(Sk.tau);
-    const R gA_k = PT * (gA + R(2) * gL * (PT * Tk * Sk.D - P.D));
-    const R gD_k = PT * (gD + R(2) * gL * (P.A - PT * Tk * Sk.A));
-    const R gL_k = gL * PT * PT;
-    const R gT_k = PT * gT * ST + PT * (gCr * Sk.cr + gCg * Sk.cg + gCb * Sk.cb) +
-                   (PT * gA - R(2) * gL * PT * P.D) * Sk.A +
-                   (PT * gD + R(2) * gL * PT * P.A) * Sk.D +
-                   gL * PT * PT * (R(2) * Tk * Sk.L + R(2) * (Sk.D * x.A - Sk.A * x.D));
-    gseg[s] = static_cast<float>(-Tk * gT_k);
-    gseg[n_seg + s] = static_cast<float>(PT * gCr);
-    gseg[2 * n_seg + s] = static_cast<float>(PT * gCg);
-    gseg[3 * n_seg + s] = static_cast<float>(PT * gCb);
-    gseg[4 * n_seg + s] = static_cast<float>(gA_k);
-    gseg[5 * n_seg + s] = static_cast<float>(gD_k);
-    gseg[6 * n_seg + s] = static_cast<float>(gL_k);
+    write_seg_grad<R>(gseg, n_seg, s, P, PT, x, Sk, gT, gCr, gCg, gCb, gA, gD, gL);
     P = fold<R>(P, PT, x);
-    PT = exp_neg_t<R>(P.tau);
+    PT = exp_neg_t<R>(P.tau + P.tlo);
   }
 }
 

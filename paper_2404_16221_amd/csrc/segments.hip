@@ -50,7 +50,7 @@ __global__ void fill_zero_kernel(float* __restrict__ p, int64_t count) {
 
 __device__ __forceinline__ void write_tuple(float* __restrict__ out, int64_t n_seg, int64_t s,
                                             const Range& r) {
-  out[s] = r.tau;
+  out[s] = r.tau + r.tlo;
   out[n_seg + s] = r.cr;
   out[2 * n_seg + s] = r.cg;
   out[3 * n_seg + s] = r.cb;
@@ -94,7 +94,8 @@ __device__ __forceinline__ void stage_ends(const int64_t* __restrict__ off, int6
             endloc[e - base] = loc;
             if (gl != nullptr && loc < kStagedSegs) {
 #pragma unroll
-              for (int k = 0; k < 7; ++k) gl[k * kStagedSegs + loc] = gseg[k * n_seg + sg];
+              for (int k = 0; k < 6; ++k) gl[k * kStagedSegs + loc] = gseg[k * n_seg + sg];
+              gl[6 * kStagedSegs + loc] = 2.f * gseg[6 * n_seg + sg];  // the sweep uses 2 g_L
             }
           }
           if (a <= last && last <= e) *tailseg = sg;
@@ -153,17 +154,18 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
   // Serial fold of the lane's samples; a head restarts the open range.  The
   // lane's first range, when it continues a segment from an earlier lane, is
   // parked in LDS until the scan has produced what precedes it.
-  Range cur = range_of(R.x[0]);
-  float Tc = R.x[0].e;
+  Range cur = range_identity();
+  cur.m0 = R.x[0].m;
+  float Tc = 1.f;
+  append(cur, Tc, R.x[0]);
   bool cur_head = R.h0, has_pend = false, any_end = false, any_head = R.h0;
   int pend_seg = -1;
 #pragma unroll
   for (int j = 0; j < kRun; ++j) {
     if (j > 0) {
       const bool hd = R.head(j);
+      restart_if(hd, cur, Tc, R.x[j].m);
       append(cur, Tc, R.x[j]);
-      cur = select(hd, range_of(R.x[j]), cur);
-      Tc = hd ? R.x[j].e : Tc;
       cur_head = cur_head || hd;
       any_head = any_head || hd;
     }
@@ -186,8 +188,8 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
   Range inc = have ? cur : range_identity();
   bool fin = have ? cur_head : true;
   scan_up(inc, fin, lane);
-  const Range ex = shfl_up_range(inc, 1);
-  const int exf = __shfl_up(static_cast<int>(fin), 1);
+  const Range ex = from_lower(inc);
+  const int exf = from_lower(static_cast<int>(fin));
   if (has_pend) {
     const Range pend = unpark_range(park, lane);
     if (lane > 0 && exf) {
@@ -277,16 +279,17 @@ __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restri
   }
 }
 
-// One step of the backward's reverse sweep for sample q (see bwd_tile).
+// One step of the backward's reverse sweep for sample q (see bwd_tile).  g
+// holds the ending segment's tuple gradient with g[6] doubled.
 __device__ __forceinline__ void reverse_step(const Smp& q, float PTj, float PAj, float PZj, bool endf,
                                              int endloc_j, int64_t s_lo, int64_t n_seg,
                                              const float* __restrict__ gl,
                                              const float* __restrict__ gseg, float (&g)[7],
-                                             float& SCr, float& SCg, float& SCb, float& SA,
-                                             float& SF, float& SL, float& mf, float& TN,
-                                             float& dsg, float& dc0, float& dc1, float& dc2) {
+                                             float& SG, float& SA, float& SF, float& SL, float& mf,
+                                             float& TN, float& dsg, float& dc0, float& dc1,
+                                             float& dc2) {
   const float Ti1 = PTj * q.e;
-  SCr = endf ? 0.f : SCr; SCg = endf ? 0.f : SCg; SCb = endf ? 0.f : SCb;
+  SG = endf ? 0.f : SG;
   SA = endf ? 0.f : SA; SF = endf ? 0.f : SF; SL = endf ? 0.f : SL;
   mf = endf ? q.m : mf;
   TN = endf ? Ti1 : TN;
@@ -297,25 +300,25 @@ __device__ __forceinline__ void reverse_step(const Smp& q, float PTj, float PAj,
     } else {
       const int64_t sgi = s_lo + endloc_j;
 #pragma unroll
-      for (int k = 0; k < 7; ++k) g[k] = gseg[k * n_seg + sgi];
+      for (int k = 0; k < 6; ++k) g[k] = gseg[k * n_seg + sgi];
+      g[6] = 2.f * gseg[6 * n_seg + sgi];
     }
   }
   const float w = PTj * q.alpha;
   const float Zs = fmaf(SA, mf - q.m, SF);  // sum_{k>j} w_k (m_k - m_j)
   const float wd3 = w * q.delta * (1.f / 3.f);
-  const float cdot = g[1] * fmaf(Ti1, q.c0, -SCr) + g[2] * fmaf(Ti1, q.c1, -SCg) +
-                     g[3] * fmaf(Ti1, q.c2, -SCb);
-  const float dL = 2.f * (TN * PZj - PAj * Zs - SL + (Ti1 - w) * Zs) + 2.f * Ti1 * wd3;
-  const float dtau = g[0] + cdot + g[4] * TN + g[5] * fmaf(q.m, TN, -Zs) + g[6] * dL;
+  const float gc = fmaf(g[3], q.c2, fmaf(g[2], q.c1, g[1] * q.c0));  // g_C . c_j
+  // half the distortion term: T_N Zp_j - A_{<j} Zs + (T_{j+1} - w_j) Zs + T_{j+1} w_j delta_j / 3 - SL
+  const float hL = fmaf(TN, PZj, fmaf(Ti1 - w - PAj, Zs, fmaf(Ti1, wd3, -SL)));
+  const float dtau = fmaf(g[6], hL, fmaf(g[5], fmaf(q.m, TN, -Zs),
+                                         fmaf(g[4], TN, g[0] + fmaf(Ti1, gc, -SG))));
   dsg = q.delta * dtau;
   dc0 = w * g[1];
   dc1 = w * g[2];
   dc2 = w * g[3];
   // sample j joins the suffix
-  SCr = fmaf(w, q.c0, SCr);
-  SCg = fmaf(w, q.c1, SCg);
-  SCb = fmaf(w, q.c2, SCb);
-  SL = fmaf(2.f * w, Zs, SL + w * wd3);
+  SG = fmaf(w, gc, SG);
+  SL = fmaf(2.f * w, Zs, fmaf(w, wd3, SL));
   SF = Zs;
   SA += w;
   mf = q.m;
@@ -340,8 +343,10 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   // first head), and keeps the lane's first range (up to its first segment end)
   // for the reverse scan.
   float Tl[kRun], Al[kRun], Zl[kRun];
-  Range cur = range_of(R.x[0]);
-  float Tc = R.x[0].e;
+  Range cur = range_identity();
+  cur.m0 = R.x[0].m;
+  float Tc = 1.f;
+  append(cur, Tc, R.x[0]);
   bool cur_head = R.h0, seen_end = false;
   int first_end = -1;
   int fhp = R.h0 ? 0 : kRun;  // position of the lane's first head
@@ -353,9 +358,8 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
       Tl[j] = hd ? 1.f : Tc;
       Al[j] = hd ? 0.f : cur.A;
       Zl[j] = hd ? 0.f : fmaf(cur.A, R.x[j].m - cur.m1, cur.B);
+      restart_if(hd, cur, Tc, R.x[j].m);
       append(cur, Tc, R.x[j]);
-      cur = select(hd, range_of(R.x[j]), cur);
-      Tc = hd ? R.x[j].e : Tc;
       cur_head = cur_head || hd;
       fhp = (hd && fhp == kRun) ? j : fhp;
     }
@@ -371,21 +375,19 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   Range rinc = seen_end ? unpark_range(park, lane) : cur;
   bool rfl = seen_end;
   int rseg = seen_end ? first_end : -1;
-  scan_up_pre(inc, fin, lane);
+  scan_up(inc, fin, lane);
   scan_down(rinc, rfl, rseg, lane);
-  Pre ex;
-  ex.tau = __shfl_up(inc.tau, 1); ex.A = __shfl_up(inc.A, 1);
-  ex.B = __shfl_up(inc.B, 1); ex.m1 = __shfl_up(inc.m1, 1);
-  const int exf = __shfl_up(static_cast<int>(fin), 1);
-  const Range sx = shfl_down_range(rinc, 1);
-  const int sxf = __shfl_down(static_cast<int>(rfl), 1);
-  const int sxseg = __shfl_down(rseg, 1);
+  const Pre ex = from_lower(inc);
+  const int exf = from_lower(static_cast<int>(fin));
+  const Range sx = from_upper(rinc);
+  const int sxf = from_upper(static_cast<int>(rfl));
+  const int sxseg = from_upper(rseg);
 
   // Prefix of the segment in front of the lane (identity if sample 0 is a head).
   Pre pc = pre_identity();
   if (!R.h0) {
     if (lane > 0 && exf) pc = ex;
-    else if (!start_head) pc = lane > 0 ? combine_pre(pre_of(recs[t].pre), ex) : pre_of(recs[t].pre);
+    else if (!start_head) pc = lane > 0 ? combine(pre_of(recs[t].pre), ex) : pre_of(recs[t].pre);
   }
   // Suffix behind the lane's last sample, in its own frame (unused if that
   // sample ends its segment).
@@ -402,7 +404,7 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   }
 
   // Samples before the lane's first head continue the carried prefix.
-  const float Tp = exp_neg(pc.tau);
+  const float Tp = exp_neg(pc.tau + pc.tlo);
   float PT[kRun], PA[kRun], PZ[kRun];
 #pragma unroll
   for (int j = 0; j < kRun; ++j) {
@@ -425,16 +427,17 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   // the derivative of the segment tuple with every difference of positions
   // taken before it is multiplied.
   float g[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  float SCr = 0.f, SCg = 0.f, SCb = 0.f, SA = 0.f, SF = 0.f, SL = 0.f, mf = 0.f, TN = 1.f;
+  float SG = 0.f, SA = 0.f, SF = 0.f, SL = 0.f, mf = 0.f, TN = 1.f;
   if (have) {
-    const float Tq = PT[kRun - 1] * R.x[kRun - 1].e;
-    SCr = Tq * sc.cr; SCg = Tq * sc.cg; SCb = Tq * sc.cb;
-    SA = Tq * sc.A; SF = Tq * sc.F; SL = Tq * Tq * sc.L; mf = sc.m0;
-    TN = Tq * exp_neg(sc.tau);
     if (cseg >= 0 && cseg < n_seg) {
 #pragma unroll
       for (int k = 0; k < 7; ++k) g[k] = gseg[k * n_seg + cseg];
+      g[6] *= 2.f;
     }
+    const float Tq = PT[kRun - 1] * R.x[kRun - 1].e;
+    SG = Tq * fmaf(g[3], sc.cb, fmaf(g[2], sc.cg, g[1] * sc.cr));
+    SA = Tq * sc.A; SF = Tq * sc.F; SL = Tq * Tq * sc.L; mf = sc.m0;
+    TN = Tq * exp_neg(sc.tau + sc.tlo);
   }
 #ifndef XL_PASS3_RELOAD
 #define XL_PASS3_RELOAD 1
@@ -458,8 +461,8 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
       q.delta = b2[j] - a2[j]; q.m = 0.5f * (a2[j] + b2[j]);
       q.c0 = c2[3 * j]; q.c1 = c2[3 * j + 1]; q.c2 = c2[3 * j + 2];
 #endif
-      reverse_step(q, PT[j], PA[j], PZ[j], R.endf[j], R.ends[j], s_lo, n_seg, gl, gseg, g, SCr, SCg,
-                   SCb, SA, SF, SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
+      reverse_step(q, PT[j], PA[j], PZ[j], R.endf[j], R.ends[j], s_lo, n_seg, gl, gseg, g, SG, SA, SF,
+                   SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
       if ((j & 1) == 0) {
         if (DT == kF32)
           *reinterpret_cast<float2*>(static_cast<float*>(gsig_p) + R.i0 + j) = make_float2(dsg[j], dsg[j + 1]);
@@ -479,8 +482,8 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   float dsg[kRun], dc[3 * kRun];
 #pragma unroll
   for (int j = kRun - 1; j >= 0; --j) {
-    reverse_step(R.x[j], PT[j], PA[j], PZ[j], R.endf[j], R.ends[j], s_lo, n_seg, gl, gseg, g, SCr, SCg,
-                 SCb, SA, SF, SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
+    reverse_step(R.x[j], PT[j], PA[j], PZ[j], R.endf[j], R.ends[j], s_lo, n_seg, gl, gseg, g, SG, SA, SF,
+                 SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
   }
 
   const int64_t i0 = R.i0;

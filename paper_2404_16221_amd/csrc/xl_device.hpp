@@ -27,6 +27,7 @@ enum Dtype : int { kF32 = 0, kBF16 = 1, kF16 = 2 };
 
 struct Range {
   float tau;        // sum of optical depths sigma * delta; transmittance is exp(-tau)
+  float tlo;        // compensation: the exact sum is tau + tlo (see two_sum)
   float cr, cg, cb; // colour
   float A;          // opacity (sum of weights)
   float F;          // sum w (m - m0)
@@ -54,7 +55,7 @@ constexpr int kTailOpen = 8;   // the last sample's segment continues past the t
 
 __device__ __forceinline__ Range range_identity() {
   Range r;
-  r.tau = 0.f; r.cr = r.cg = r.cb = 0.f; r.A = 0.f;
+  r.tau = 0.f; r.tlo = 0.f; r.cr = r.cg = r.cb = 0.f; r.A = 0.f;
   r.F = 0.f; r.B = 0.f; r.L = 0.f; r.m0 = 0.f; r.m1 = 0.f;
   return r;
 }
@@ -63,13 +64,33 @@ __device__ __forceinline__ float exp_neg(float tau) {
   return __builtin_amdgcn_exp2f(-1.4426950408889634f * tau);
 }
 
+// Error-free transformation of a sum (Knuth's TwoSum): a + b = s + e exactly,
+// for any ordering of magnitudes.  Optical depths are summed in two levels:
+// plainly over a lane's kRun samples, then, whenever two ranges are joined
+// (lanes, tiles, the fixup), as a pair (tau, tlo) with the rounding error of
+// every join kept in tlo.  A segment's log-transmittance thus carries at most
+// kRun roundings per lane-sized block and no error growth across blocks,
+// however many samples it spans.
+__device__ __forceinline__ float two_sum(float a, float b, float& e) {
+  const float s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+  return s;
+}
+__device__ __forceinline__ void add_tau(float& tau, float& tlo, float hi, float lo) {
+  float e;
+  tau = two_sum(tau, hi, e);
+  tlo += e + lo;
+}
+
 // x then y (x in front).  Transmittance is always taken as exp(-sum tau), one
 // rounding, never as a running product of per-sample factors (whose roundings
 // would add up over long segments).
 __device__ __forceinline__ Range combine(const Range& x, const Range& y) {
   Range r;
-  const float T1 = exp_neg(x.tau);
-  r.tau = x.tau + y.tau;
+  const float T1 = exp_neg(x.tau + x.tlo);
+  r.tau = x.tau; r.tlo = x.tlo;
+  add_tau(r.tau, r.tlo, y.tau, y.tlo);
   r.cr = fmaf(T1, y.cr, x.cr);
   r.cg = fmaf(T1, y.cg, x.cg);
   r.cb = fmaf(T1, y.cb, x.cb);
@@ -88,12 +109,15 @@ struct Smp {
   float tau, e, alpha, m, delta, c0, c1, c2;  // e = exp(-tau)
 };
 
-// 1 - exp(-tau) without cancellation: Taylor series (Horner form, error below
-// tau^6/5040 relative) for tau < 1/4, else 1 - exp(-tau).
+// 1 - exp(-tau) without cancellation: for tau < 1/4 the Taylor polynomial to
+// tau^6 (truncation below tau^6/5040 relative), else 1 - exp(-tau).
 __device__ __forceinline__ float one_minus_exp_neg(float tau, float e) {
-  const float p = tau * (1.f - tau * (1.f / 2.f) * (1.f - tau * (1.f / 3.f) * (1.f - tau * (1.f / 4.f) *
-                  (1.f - tau * (1.f / 5.f) * (1.f - tau * (1.f / 6.f))))));
-  return tau < 0.25f ? p : 1.f - e;
+  float q = fmaf(-tau, 1.f / 720.f, 1.f / 120.f);
+  q = fmaf(-tau, q, 1.f / 24.f);
+  q = fmaf(-tau, q, 1.f / 6.f);
+  q = fmaf(-tau, q, 0.5f);
+  q = fmaf(-tau, q, 1.f);
+  return tau < 0.25f ? tau * q : 1.f - e;
 }
 
 __device__ __forceinline__ Smp make_sample(float sigma, float c0, float c1, float c2, float t0,
@@ -110,12 +134,26 @@ __device__ __forceinline__ Smp make_sample(float sigma, float c0, float c1, floa
 
 __device__ __forceinline__ Range range_of(const Smp& s) {
   Range r;
-  r.tau = s.tau;
+  r.tau = s.tau; r.tlo = 0.f;
   r.cr = s.alpha * s.c0; r.cg = s.alpha * s.c1; r.cb = s.alpha * s.c2;
   r.A = s.alpha; r.F = 0.f; r.B = 0.f;
   r.L = s.alpha * s.alpha * s.delta * (1.f / 3.f);
   r.m0 = s.m; r.m1 = s.m;
   return r;
+}
+
+// Restart r as the empty range at midpoint m when `head` (a segment starts at
+// the next sample appended); Tr is the range's transmittance.
+__device__ __forceinline__ void restart_if(bool head, Range& r, float& Tr, float m) {
+  r.tau = head ? 0.f : r.tau;
+  r.tlo = head ? 0.f : r.tlo;
+  r.cr = head ? 0.f : r.cr; r.cg = head ? 0.f : r.cg; r.cb = head ? 0.f : r.cb;
+  r.A = head ? 0.f : r.A;
+  r.F = head ? 0.f : r.F;
+  r.B = head ? 0.f : r.B;
+  r.L = head ? 0.f : r.L;
+  r.m0 = head ? m : r.m0;
+  Tr = head ? 1.f : Tr;
 }
 
 // Append one sample behind range r whose transmittance is Tr (updated).
@@ -132,7 +170,7 @@ __device__ __forceinline__ void append(Range& r, float& Tr, const Smp& s) {
   r.cg = fmaf(w, s.c1, r.cg);
   r.cb = fmaf(w, s.c2, r.cb);
   r.A += w;
-  r.tau += s.tau;
+  r.tau += s.tau;  // at most kRun terms; ranges are joined with two_sum
   r.m1 = s.m;
   Tr *= s.e;
 }
@@ -253,108 +291,168 @@ __device__ __forceinline__ void load_run(const void* __restrict__ sigma_p,
 }
 
 // ---------------------------------------------------------------- wave scans
-__device__ __forceinline__ Range shfl_up_range(const Range& x, int d) {
-  Range y;
-  y.tau = __shfl_up(x.tau, d);
-  y.cr = __shfl_up(x.cr, d); y.cg = __shfl_up(x.cg, d); y.cb = __shfl_up(x.cb, d);
-  y.A = __shfl_up(x.A, d); y.F = __shfl_up(x.F, d); y.B = __shfl_up(x.B, d);
-  y.L = __shfl_up(x.L, d); y.m0 = __shfl_up(x.m0, d); y.m1 = __shfl_up(x.m1, d);
-  return y;
-}
-__device__ __forceinline__ Range shfl_down_range(const Range& x, int d) {
-  Range y;
-  y.tau = __shfl_down(x.tau, d);
-  y.cr = __shfl_down(x.cr, d); y.cg = __shfl_down(x.cg, d); y.cb = __shfl_down(x.cb, d);
-  y.A = __shfl_down(x.A, d); y.F = __shfl_down(x.F, d); y.B = __shfl_down(x.B, d);
-  y.L = __shfl_down(x.L, d); y.m0 = __shfl_down(x.m0, d); y.m1 = __shfl_down(x.m1, d);
-  return y;
-}
-
-__device__ __forceinline__ Range select(bool c, const Range& a, const Range& b) {
-  Range r;
-  r.tau = c ? a.tau : b.tau;
-  r.cr = c ? a.cr : b.cr; r.cg = c ? a.cg : b.cg; r.cb = c ? a.cb : b.cb;
-  r.A = c ? a.A : b.A; r.F = c ? a.F : b.F; r.B = c ? a.B : b.B; r.L = c ? a.L : b.L;
-  r.m0 = c ? a.m0 : b.m0; r.m1 = c ? a.m1 : b.m1;
-  return r;
-}
-
-// Inclusive segmented scan in lane order.  A lane whose flag is set starts a
-// new segment: nothing from lower lanes is combined into it.  Each step is
-// branch-free (combine, then select) so the wave never splits.
-__device__ __forceinline__ void scan_up(Range& x, bool& f, int lane) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const Range y = shfl_up_range(x, d);
-    const int fy = __shfl_up(static_cast<int>(f), d);
-    const bool ok = lane >= d;
-    x = select(ok && !f, combine(y, x), x);
-    f = f || (ok && fy != 0);
-  }
-}
-
-// Inclusive segmented scan against lane order (suffix).  A lane whose flag is
-// set ends its segment: nothing from higher lanes is combined into it.  `seg`
-// travels with the range (the segment whose end closes it).
-__device__ __forceinline__ void scan_down(Range& x, bool& f, int& seg, int lane) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const Range y = shfl_down_range(x, d);
-    const int fy = __shfl_down(static_cast<int>(f), d);
-    const int sy = __shfl_down(seg, d);
-    const bool ok = lane + d < kWave;
-    const bool use = ok && !f;
-    x = select(use, combine(x, y), x);
-    seg = use ? sy : seg;
-    f = f || (ok && fy != 0);
-  }
-}
-
 // The part of a range that the backward's prefix needs: optical depth,
 // opacity and the back-relative depth at the last midpoint.
 struct Pre {
-  float tau, A, B, m1;
+  float tau, tlo, A, B, m1;
 };
-__device__ __forceinline__ Pre pre_of(const Range& r) { return Pre{r.tau, r.A, r.B, r.m1}; }
-__device__ __forceinline__ Pre pre_identity() { return Pre{0.f, 0.f, 0.f, 0.f}; }
-__device__ __forceinline__ Pre combine_pre(const Pre& x, const Pre& y) {
-  const float T1 = exp_neg(x.tau);
+__device__ __forceinline__ Pre pre_of(const Range& r) { return Pre{r.tau, r.tlo, r.A, r.B, r.m1}; }
+__device__ __forceinline__ Pre pre_identity() { return Pre{0.f, 0.f, 0.f, 0.f, 0.f}; }
+__device__ __forceinline__ Pre combine(const Pre& x, const Pre& y) {
+  const float T1 = exp_neg(x.tau + x.tlo);
   Pre r;
-  r.tau = x.tau + y.tau;
+  r.tau = x.tau; r.tlo = x.tlo;
+  add_tau(r.tau, r.tlo, y.tau, y.tlo);
   r.A = fmaf(T1, y.A, x.A);
   r.B = fmaf(T1, y.B, fmaf(x.A, y.m1 - x.m1, x.B));
   r.m1 = y.m1;
   return r;
 }
-__device__ __forceinline__ void scan_up_pre(Pre& x, bool& f, int lane) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    Pre y;
-    y.tau = __shfl_up(x.tau, d); y.A = __shfl_up(x.A, d);
-    y.B = __shfl_up(x.B, d); y.m1 = __shfl_up(x.m1, d);
-    const int fy = __shfl_up(static_cast<int>(f), d);
-    const bool use = lane >= d && !f;
-    const Pre z = combine_pre(y, x);
-    x.tau = use ? z.tau : x.tau; x.A = use ? z.A : x.A;
-    x.B = use ? z.B : x.B; x.m1 = use ? z.m1 : x.m1;
-    f = f || (lane >= d && fy != 0);
-  }
+
+// Field-wise maps: a lane move of a whole range, a branch-free select.
+template <typename Op>
+__device__ __forceinline__ Range map_fields(const Range& x, Op op) {
+  Range y;
+  y.tau = op(x.tau); y.tlo = op(x.tlo);
+  y.cr = op(x.cr); y.cg = op(x.cg); y.cb = op(x.cb);
+  y.A = op(x.A); y.F = op(x.F); y.B = op(x.B); y.L = op(x.L);
+  y.m0 = op(x.m0); y.m1 = op(x.m1);
+  return y;
+}
+template <typename Op>
+__device__ __forceinline__ Pre map_fields(const Pre& x, Op op) {
+  return Pre{op(x.tau), op(x.tlo), op(x.A), op(x.B), op(x.m1)};
+}
+__device__ __forceinline__ Range select(bool c, const Range& a, const Range& b) {
+  Range r;
+  r.tau = c ? a.tau : b.tau; r.tlo = c ? a.tlo : b.tlo;
+  r.cr = c ? a.cr : b.cr; r.cg = c ? a.cg : b.cg; r.cb = c ? a.cb : b.cb;
+  r.A = c ? a.A : b.A; r.F = c ? a.F : b.F; r.B = c ? a.B : b.B; r.L = c ? a.L : b.L;
+  r.m0 = c ? a.m0 : b.m0; r.m1 = c ? a.m1 : b.m1;
+  return r;
+}
+__device__ __forceinline__ Pre select(bool c, const Pre& a, const Pre& b) {
+  return Pre{c ? a.tau : b.tau, c ? a.tlo : b.tlo, c ? a.A : b.A, c ? a.B : b.B,
+             c ? a.m1 : b.m1};
+}
+
+// Lane moves.  DPP (GFX9 controls) moves a register between lanes inside the
+// VALU instruction itself: row shifts stay within a row of 16 lanes, the row
+// broadcasts copy lane 15 of each row into the next row and lane 31 into rows
+// 2-3, and the wave shifts move every lane by one.  Moves with no DPP form
+// (lane 16(r+1) into row r, lane 32 into rows 0-1) use ds_bpermute.
+constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0x108;
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_i(int v) {
+  // Lanes of disabled rows are left undefined and lanes whose source is
+  // outside the row or wave read 0; the scans never use either.
+  return __builtin_amdgcn_mov_dpp(v, CTRL, ROW_MASK, 0xF, true);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, dpp_i<CTRL, ROW_MASK>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL, int ROW_MASK, typename T>
+__device__ __forceinline__ T dpp_fields(const T& x) {
+  return map_fields(x, [](float v) { return dpp_f<CTRL, ROW_MASK>(v); });
+}
+template <typename T>
+__device__ __forceinline__ T lane_fields(const T& x, int src) {
+  return map_fields(x, [src](float v) { return __shfl(v, src); });
+}
+
+// Value of lane - 1 (lane 0: unspecified) and of lane + 1 (lane 63: unspecified).
+template <typename T>
+__device__ __forceinline__ T from_lower(const T& x) { return dpp_fields<kWaveShr1, 0xF>(x); }
+__device__ __forceinline__ int from_lower(int v) { return dpp_i<kWaveShr1, 0xF>(v); }
+template <typename T>
+__device__ __forceinline__ T from_upper(const T& x) { return dpp_fields<kWaveShl1, 0xF>(x); }
+__device__ __forceinline__ int from_upper(int v) { return dpp_i<kWaveShl1, 0xF>(v); }
+
+// One step of the prefix scan: y is what precedes x's window; `ok` says the
+// lane received one.
+template <typename T>
+__device__ __forceinline__ void up_apply(T& x, bool& f, const T& y, int fy, bool ok) {
+  x = select(ok && !f, combine(y, x), x);
+  f = f || (ok && fy != 0);
+}
+template <int CTRL, int ROW_MASK, typename T>
+__device__ __forceinline__ void up_step(T& x, bool& f, bool ok) {
+  const T y = dpp_fields<CTRL, ROW_MASK>(x);
+  const int fy = dpp_i<CTRL, ROW_MASK>(static_cast<int>(f));
+  up_apply(x, f, y, fy, ok);
+}
+
+// Inclusive segmented scan in lane order.  A lane whose flag is set starts a
+// new segment: nothing from lower lanes is combined into it.  Each step is
+// branch-free (combine, then select) so the wave never splits.  Rows of 16
+// lanes scan by shifts of 1, 2, 4, 8; then row r takes the total of row r - 1
+// (rows 1 and 3) and rows 2-3 the total of lanes 0..31.
+template <typename T>
+__device__ __forceinline__ void scan_up(T& x, bool& f, int lane) {
+  const int r = lane & 15;
+  up_step<kRowShr1, 0xF>(x, f, r >= 1);
+  up_step<kRowShr2, 0xF>(x, f, r >= 2);
+  up_step<kRowShr4, 0xF>(x, f, r >= 4);
+  up_step<kRowShr8, 0xF>(x, f, r >= 8);
+  up_step<kRowBcast15, 0xA>(x, f, (lane & 16) != 0);
+  up_step<kRowBcast31, 0xC>(x, f, lane >= 32);
+}
+
+__device__ __forceinline__ void down_apply(Range& x, bool& f, int& seg, const Range& y, int fy,
+                                           int sy, bool ok) {
+  const bool use = ok && !f;
+  x = select(use, combine(x, y), x);
+  seg = use ? sy : seg;
+  f = f || (ok && fy != 0);
+}
+template <int CTRL>
+__device__ __forceinline__ void down_step(Range& x, bool& f, int& seg, bool ok) {
+  const Range y = dpp_fields<CTRL, 0xF>(x);
+  const int fy = dpp_i<CTRL, 0xF>(static_cast<int>(f));
+  const int sy = dpp_i<CTRL, 0xF>(seg);
+  down_apply(x, f, seg, y, fy, sy, ok);
+}
+__device__ __forceinline__ void down_step_from(Range& x, bool& f, int& seg, int src, bool ok) {
+  const Range y = lane_fields(x, src);
+  const int fy = __shfl(static_cast<int>(f), src);
+  const int sy = __shfl(seg, src);
+  down_apply(x, f, seg, y, fy, sy, ok);
+}
+
+// Inclusive segmented scan against lane order (suffix).  A lane whose flag is
+// set ends its segment: nothing from higher lanes is combined into it.  `seg`
+// travels with the range (the segment whose end closes it).  Rows scan by
+// shifts of 1, 2, 4, 8 toward lane 0; rows 0 and 2 then take the first lane of
+// the next row, and rows 0-1 take lane 32.
+__device__ __forceinline__ void scan_down(Range& x, bool& f, int& seg, int lane) {
+  const int r = lane & 15;
+  down_step<kRowShl1>(x, f, seg, r + 1 < 16);
+  down_step<kRowShl2>(x, f, seg, r + 2 < 16);
+  down_step<kRowShl4>(x, f, seg, r + 4 < 16);
+  down_step<kRowShl8>(x, f, seg, r + 8 < 16);
+  down_step_from(x, f, seg, (lane | 15) + 1, (lane & 16) == 0);
+  down_step_from(x, f, seg, 32, lane < 32);
 }
 
 // A range parked in LDS, structure of arrays over the 64 lanes of a wave.
-constexpr int kRangeFields = 10;
+constexpr int kRangeFields = 11;
 __device__ __forceinline__ void park_range(float* __restrict__ lds, int lane, const Range& r) {
   lds[0 * kWave + lane] = r.tau; lds[1 * kWave + lane] = r.cr; lds[2 * kWave + lane] = r.cg;
   lds[3 * kWave + lane] = r.cb; lds[4 * kWave + lane] = r.A; lds[5 * kWave + lane] = r.F;
   lds[6 * kWave + lane] = r.B; lds[7 * kWave + lane] = r.L; lds[8 * kWave + lane] = r.m0;
-  lds[9 * kWave + lane] = r.m1;
+  lds[9 * kWave + lane] = r.m1; lds[10 * kWave + lane] = r.tlo;
 }
 __device__ __forceinline__ Range unpark_range(const float* __restrict__ lds, int lane) {
   Range r;
   r.tau = lds[0 * kWave + lane]; r.cr = lds[1 * kWave + lane]; r.cg = lds[2 * kWave + lane];
   r.cb = lds[3 * kWave + lane]; r.A = lds[4 * kWave + lane]; r.F = lds[5 * kWave + lane];
   r.B = lds[6 * kWave + lane]; r.L = lds[7 * kWave + lane]; r.m0 = lds[8 * kWave + lane];
-  r.m1 = lds[9 * kWave + lane];
+  r.m1 = lds[9 * kWave + lane]; r.tlo = lds[10 * kWave + lane];
   return r;
 }
 
