@@ -13,6 +13,7 @@ Prints one JSON line.  Options: --steps K --warmup W --gpus 1 [--no-cpu-baseline
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +27,39 @@ sys.path.insert(0, HERE)
 
 METRIC = "composited samples/s (fwd+bwd) at K regions vs FP32 plain; p50/p99 render ms"
 HBM_PEAK_GBS = 8000.0
+# Sources that define the segment kernels; HBM traffic measured with rocprofv3
+# counters is reported only while these are unchanged.
+KERNEL_SOURCES = ("paper_2404_16221_amd/csrc/segments.hip", "paper_2404_16221_amd/csrc/xl_device.hpp")
+TRAFFIC_PROFILE = "profiles/seg_bwd_kernel_k16-262144r_bf16_traffic.md"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a
+    1 GiB device copy), or None if the kernel sources changed since."""
+    path = os.path.join(HERE, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.strip().startswith("- "):
+                k, v = line.strip()[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -283,7 +317,9 @@ def main():
         "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in results.items()},
         "roofline": {"bound": "hbm", "achieved": hr["seg_bwd_gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": hr["seg_bwd_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": hr["seg_bwd_gbs"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if head == "bf16" else None,
+                     "algorithmic_bytes": hf.bytes_seg_bwd(),
                      "kernel": "seg_bwd_kernel", "step_achieved": hr["step_gbs"],
                      "step_frac": hr["step_gbs"] / HBM_PEAK_GBS},
     }

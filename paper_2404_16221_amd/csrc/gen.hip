@@ -321,41 +321,95 @@ __device__ __forceinline__ void put_sample(void* sigma, void* rgb, int64_t i, fl
   }
 }
 
+// Samples are written in aligned groups of kGroup packed slots, so a group that
+// lies inside one segment is a handful of 16-byte stores instead of six
+// scattered scalar stores per sample (each lane writes its own ray's samples,
+// so lanes never share a store).
+constexpr int kGroup = 8;
+
+template <int DT>
+__device__ __forceinline__ void store_group(void* sigma, void* rgb, float* t_start, float* t_end,
+                                            int64_t g0, const float (&sg)[kGroup],
+                                            const float (&c)[3 * kGroup], const float (&a)[kGroup],
+                                            const float (&b)[kGroup]) {
+  if (DT == kF32) {
+    float4* S = reinterpret_cast<float4*>(static_cast<float*>(sigma) + g0);
+    float4* C = reinterpret_cast<float4*>(static_cast<float*>(rgb) + 3 * g0);
+#pragma unroll
+    for (int q = 0; q < kGroup / 4; ++q)
+      S[q] = make_float4(sg[4 * q], sg[4 * q + 1], sg[4 * q + 2], sg[4 * q + 3]);
+#pragma unroll
+    for (int q = 0; q < 3 * kGroup / 4; ++q)
+      C[q] = make_float4(c[4 * q], c[4 * q + 1], c[4 * q + 2], c[4 * q + 3]);
+  } else {
+    uint4* S = reinterpret_cast<uint4*>(static_cast<uint16_t*>(sigma) + g0);
+    uint4* C = reinterpret_cast<uint4*>(static_cast<uint16_t*>(rgb) + 3 * g0);
+    *S = make_uint4(pack2<DT>(sg[0], sg[1]), pack2<DT>(sg[2], sg[3]), pack2<DT>(sg[4], sg[5]),
+                    pack2<DT>(sg[6], sg[7]));
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      C[q] = make_uint4(pack2<DT>(c[8 * q], c[8 * q + 1]), pack2<DT>(c[8 * q + 2], c[8 * q + 3]),
+                        pack2<DT>(c[8 * q + 4], c[8 * q + 5]), pack2<DT>(c[8 * q + 6], c[8 * q + 7]));
+  }
+  float4* A = reinterpret_cast<float4*>(t_start + g0);
+  float4* B = reinterpret_cast<float4*>(t_end + g0);
+#pragma unroll
+  for (int q = 0; q < kGroup / 4; ++q) {
+    A[q] = make_float4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
+    B[q] = make_float4(b[4 * q], b[4 * q + 1], b[4 * q + 2], b[4 * q + 3]);
+  }
+}
+
 template <int DT>
 __global__ void gen_fill_kernel(GenDev g, GenWs w, void* __restrict__ sigma, void* __restrict__ rgb,
                                 float* __restrict__ t_start, float* __restrict__ t_end) {
   const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= g.n_rays) return;
   const uint64_t key = mix64(g.seedkey + static_cast<uint64_t>(g.ray0 + r) * kGamma);
-  const uint64_t span = static_cast<uint64_t>(g.n_max - g.n_min + 1);
-  const int count = g.n_min + static_cast<int32_t>(((draw(key, 3) >> 32) * span) >> 32);
   const double scale = w.scale[r];
   double run = w.s0[r];
   const int M = g.max_segs;
   const int ns = w.nseg[r];
-  int k = 0, left = ns > 0 ? w.seg_len[r * M] : 0;
-  int64_t dst = ns > 0 ? w.seg_off[w.seg_pid[r * M]] : 0;
-  for (int i = 0; i < count; ++i) {
-    if (left == 0 && k + 1 < ns) {
-      ++k;
-      left = w.seg_len[r * M + k];
-      dst = w.seg_off[w.seg_pid[r * M + k]];
+  int i = 0;  // sample index along the ray
+  for (int k = 0; k < ns; ++k) {
+    const int64_t d0 = w.seg_off[w.seg_pid[r * M + k]];
+    const int64_t d1 = d0 + w.seg_len[r * M + k];
+    for (int64_t g0 = d0 & ~static_cast<int64_t>(kGroup - 1); g0 < d1; g0 += kGroup) {
+      float sg[kGroup], c[3 * kGroup], a[kGroup], b[kGroup];
+#pragma unroll
+      for (int q = 0; q < kGroup; ++q) {
+        sg[q] = 0.f; c[3 * q] = c[3 * q + 1] = c[3 * q + 2] = 0.f; a[q] = b[q] = 0.f;
+        const int64_t p = g0 + q;
+        if (p < d0 || p >= d1) continue;
+        const double t0 = run;
+        run = d_add(run, d_mul(width_of(g, key, i), scale));
+        const uint64_t base = kRaySlots + static_cast<uint64_t>(kSampleStride) * i;
+        const uint64_t v1 = draw(key, base), v2 = draw(key, base + 1);
+        const float u1 = static_cast<float>(field(v1, 20, 20) + 0x1p-20);
+        const float u2 = static_cast<float>(field(v1, 0, 20));
+        const float z = f_mul(f_sqrt(f_mul(-2.f, log_f32(u1))), cos2pi_f32(u2));
+        const float v = exp_f32(f_add(g.mu, f_mul(g.sg, z)));
+        sg[q] = field(v2, 48, 16) < g.zero_frac ? 0.f : v;
+        c[3 * q] = static_cast<float>(field(v2, 32, 16));
+        c[3 * q + 1] = static_cast<float>(field(v2, 16, 16));
+        c[3 * q + 2] = static_cast<float>(field(v2, 0, 16));
+        a[q] = static_cast<float>(t0);
+        b[q] = static_cast<float>(run);
+        ++i;
+      }
+      if (g0 >= d0 && g0 + kGroup <= d1) {
+        store_group<DT>(sigma, rgb, t_start, t_end, g0, sg, c, a, b);
+      } else {
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+          const int64_t p = g0 + q;
+          if (p < d0 || p >= d1) continue;
+          put_sample<DT>(sigma, rgb, p, sg[q], c[3 * q], c[3 * q + 1], c[3 * q + 2]);
+          t_start[p] = a[q];
+          t_end[p] = b[q];
+        }
+      }
     }
-    const double t0 = run;
-    run = d_add(run, d_mul(width_of(g, key, i), scale));
-    const uint64_t base = kRaySlots + static_cast<uint64_t>(kSampleStride) * i;
-    const uint64_t v1 = draw(key, base), v2 = draw(key, base + 1);
-    const float u1 = static_cast<float>(field(v1, 20, 20) + 0x1p-20);
-    const float u2 = static_cast<float>(field(v1, 0, 20));
-    const float z = f_mul(f_sqrt(f_mul(-2.f, log_f32(u1))), cos2pi_f32(u2));
-    float sg = exp_f32(f_add(g.mu, f_mul(g.sg, z)));
-    if (field(v2, 48, 16) < g.zero_frac) sg = 0.f;
-    put_sample<DT>(sigma, rgb, dst, sg, static_cast<float>(field(v2, 32, 16)),
-                   static_cast<float>(field(v2, 16, 16)), static_cast<float>(field(v2, 0, 16)));
-    t_start[dst] = static_cast<float>(t0);
-    t_end[dst] = static_cast<float>(run);
-    ++dst;
-    --left;
   }
 }
 

@@ -2,13 +2,15 @@
 // its own samples to per-ray partial tuples before anything is exchanged).
 //
 // Work decomposition: the packed sample array is cut into fixed tiles of
-// kTile = 512 samples, one wavefront per tile and kRun = 8 consecutive samples
-// per lane, independent of where segments begin and end.  That keeps every
-// load a full, aligned 16-byte vector access and balances ragged segments
-// (1..1000+ samples) perfectly.  Inside a tile:
+// kTile = 1024 samples, one wavefront per tile and kRun = 16 consecutive
+// samples per lane, independent of where segments begin and end.  That keeps
+// every load a full, aligned 16-byte vector access and balances ragged
+// segments (1..1000+ samples) perfectly; 16 samples per lane spread the cost
+// of the wave scans (six steps per scan) over twice as many samples as 8 would.
+// Inside a tile:
 //   1. the segment boundaries that fall in the tile are staged in LDS (one
 //      entry per sample: local id of the segment ending there, or -1);
-//   2. each lane folds its 8 samples serially into ranges (positive form of
+//   2. each lane folds its 16 samples serially into ranges (positive form of
 //      the merge operator, see xl_device.hpp);
 //   3. a segmented wave scan carries the open range across lanes;
 //   4. segments that cross a tile boundary are completed by a small fixup
@@ -119,8 +121,9 @@ struct LaneRun {
   int cnt;          // samples that exist (kRun when FULL)
   int64_t i0;       // index of sample 0
 
+  // raw: the lane's samples, already loaded (FULL tiles only).
   __device__ __forceinline__ void load(const SamplesDev& s, const int* endloc, int lane,
-                                       bool start_head, int64_t base) {
+                                       bool start_head, int64_t base, const RawRun<DT>* raw) {
     i0 = base + static_cast<int64_t>(lane) * kRun;
     if (FULL) {
       cnt = kRun;
@@ -133,7 +136,11 @@ struct LaneRun {
     h0 = lane == 0 ? start_head : (endloc[lane * kRun - 1] >= 0);
     if (!FULL && cnt == 0) h0 = true;
     float sg[kRun], c[3 * kRun], a[kRun], b[kRun];
-    if (FULL || cnt > 0) load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, i0, FULL ? kRun : cnt, sg, c, a, b);
+    if constexpr (FULL) {
+      raw->decode(sg, c, a, b);
+    } else {
+      if (cnt > 0) load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, i0, cnt, sg, c, a, b);
+    }
 #pragma unroll
     for (int j = 0; j < kRun; ++j) {
       x[j] = make_sample(sg[j], c[3 * j], c[3 * j + 1], c[3 * j + 2], a[j], b[j]);
@@ -147,9 +154,10 @@ template <int DT, bool FULL>
 __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int64_t t,
                                          int64_t s_lo, bool start_head, int lane,
                                          const int* endloc, int64_t tailseg, float* park,
-                                         float* __restrict__ seg_out, TileRec* __restrict__ recs) {
+                                         float* __restrict__ seg_out, TileRec* __restrict__ recs,
+                                         const RawRun<DT>* raw) {
   LaneRun<DT, FULL> R;
-  R.load(s, endloc, lane, start_head, t * kTile);
+  R.load(s, endloc, lane, start_head, t * kTile, raw);
 
   // Serial fold of the lane's samples; a head restarts the open range.  The
   // lane's first range, when it continues a segment from an earlier lane, is
@@ -229,6 +237,9 @@ __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int64_t t = t_first + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
   const bool active = t < t_end;
+  // Issue the sample loads first: their latency overlaps the setup below.
+  RawRun<DT> raw;
+  if (FULL && active) raw.load(s.sigma, s.rgb, s.t0, s.t1, t * kTile + static_cast<int64_t>(lane) * kRun);
   int* endloc = endloc_all[wave];
 #pragma unroll
   for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
@@ -244,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
   __syncthreads();
   if (!active) return;
   fwd_tile<DT, FULL>(s, n_seg, t, s_lo, start_head, lane, endloc, tailseg_all[wave], park_all[wave],
-                     seg_out, recs);
+                     seg_out, recs, &raw);
 }
 
 // Completes segments that cross tile boundaries and leaves, in every tile
@@ -281,7 +292,7 @@ __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restri
 
 // One step of the backward's reverse sweep for sample q (see bwd_tile).  g
 // holds the ending segment's tuple gradient with g[6] doubled.
-__device__ __forceinline__ void reverse_step(const Smp& q, float PTj, float PAj, float PZj, bool endf,
+__device__ __forceinline__ void reverse_step(const Smp& q, float PTj, float PZj, bool endf,
                                              int endloc_j, int64_t s_lo, int64_t n_seg,
                                              const float* __restrict__ gl,
                                              const float* __restrict__ gseg, float (&g)[7],
@@ -308,8 +319,9 @@ __device__ __forceinline__ void reverse_step(const Smp& q, float PTj, float PAj,
   const float Zs = fmaf(SA, mf - q.m, SF);  // sum_{k>j} w_k (m_k - m_j)
   const float wd3 = w * q.delta * (1.f / 3.f);
   const float gc = fmaf(g[3], q.c2, fmaf(g[2], q.c1, g[1] * q.c0));  // g_C . c_j
-  // half the distortion term: T_N Zp_j - A_{<j} Zs + (T_{j+1} - w_j) Zs + T_{j+1} w_j delta_j / 3 - SL
-  const float hL = fmaf(TN, PZj, fmaf(Ti1 - w - PAj, Zs, fmaf(Ti1, wd3, -SL)));
+  // half the distortion term: T_N Zp_j + (T_{j+1} - w_j - A_{<j}) Zs + T_{j+1} w_j delta_j / 3 - SL,
+  // where A_{<j} = 1 - T_j inside the segment makes T_{j+1} - w_j - A_{<j} = 2 T_{j+1} - 1
+  const float hL = fmaf(TN, PZj, fmaf(fmaf(2.f, Ti1, -1.f), Zs, fmaf(Ti1, wd3, -SL)));
   const float dtau = fmaf(g[6], hL, fmaf(g[5], fmaf(q.m, TN, -Zs),
                                          fmaf(g[4], TN, g[0] + fmaf(Ti1, gc, -SG))));
   dsg = q.delta * dtau;
@@ -330,39 +342,54 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
                                          const float* __restrict__ gl, float* park,
                                          const TileRec* __restrict__ recs,
                                          const float* __restrict__ gseg, void* __restrict__ gsig_p,
-                                         void* __restrict__ grgb_p) {
+                                         void* __restrict__ grgb_p, const RawRun<DT>* raw) {
   const int flags = recs[t].flags;
   const bool start_head = (flags & kStartHead) != 0;
   const bool tail_open = (flags & kTailOpen) != 0;
   LaneRun<DT, FULL> R;
-  R.load(s, endloc, lane, start_head, t * kTile);
+  R.load(s, endloc, lane, start_head, t * kTile, raw);
 
-  // Pass 1: serial fold.  Records, for every sample, the transmittance,
-  // opacity and sum_{k<j} w_k (m_j - m_k) in front of it, relative to the
-  // start of the open range (the lane start for samples before the lane's
-  // first head), and keeps the lane's first range (up to its first segment end)
-  // for the reverse scan.
-  float Tl[kRun], Al[kRun], Zl[kRun];
+  // Pass 1: serial fold.  Records, for every sample, the transmittance and
+  // sum_{k<j} w_k (m_j - m_k) in front of it, relative to the start of the
+  // open range (the lane start for samples before the lane's first head), and
+  // keeps the lane's first range (up to its first segment end) for the reverse
+  // scan.  Only the fields the prefix needs (tau, A, B, T) restart at heads: no
+  // head precedes the lane's first end except sample 0, so colour, F and L
+  // extend the same fold unrestarted and are exact wherever they are used.
+  float Tl[kRun], Zl[kRun];
   Range cur = range_identity();
   cur.m0 = R.x[0].m;
+  cur.m1 = R.x[0].m;
   float Tc = 1.f;
-  append(cur, Tc, R.x[0]);
   bool cur_head = R.h0, seen_end = false;
   int first_end = -1;
   int fhp = R.h0 ? 0 : kRun;  // position of the lane's first head
-  Tl[0] = 1.f; Al[0] = 0.f; Zl[0] = 0.f;
 #pragma unroll
   for (int j = 0; j < kRun; ++j) {
+    const Smp& q = R.x[j];
     if (j > 0) {
       const bool hd = R.head(j);
-      Tl[j] = hd ? 1.f : Tc;
-      Al[j] = hd ? 0.f : cur.A;
-      Zl[j] = hd ? 0.f : fmaf(cur.A, R.x[j].m - cur.m1, cur.B);
-      restart_if(hd, cur, Tc, R.x[j].m);
-      append(cur, Tc, R.x[j]);
+      cur.tau = hd ? 0.f : cur.tau;
+      cur.A = hd ? 0.f : cur.A;
+      cur.B = hd ? 0.f : cur.B;
+      Tc = hd ? 1.f : Tc;
       cur_head = cur_head || hd;
       fhp = (hd && fhp == kRun) ? j : fhp;
     }
+    const float Z = fmaf(cur.A, q.m - cur.m1, cur.B);  // sum_{k<j} w_k (m_j - m_k)
+    Tl[j] = Tc;
+    Zl[j] = Z;
+    const float w = Tc * q.alpha;
+    cur.L = fmaf(w, fmaf(2.f, Z, w * q.delta * (1.f / 3.f)), cur.L);
+    cur.F = fmaf(w, q.m - cur.m0, cur.F);
+    cur.cr = fmaf(w, q.c0, cur.cr);
+    cur.cg = fmaf(w, q.c1, cur.cg);
+    cur.cb = fmaf(w, q.c2, cur.cb);
+    cur.B = Z;
+    cur.A += w;
+    cur.tau += q.tau;
+    cur.m1 = q.m;
+    Tc *= q.e;
     if (R.endf[j] && !seen_end) {
       park_range(park, lane, cur);
       first_end = R.ends[j];
@@ -405,15 +432,13 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
 
   // Samples before the lane's first head continue the carried prefix.
   const float Tp = exp_neg(pc.tau + pc.tlo);
-  float PT[kRun], PA[kRun], PZ[kRun];
+  float PT[kRun], PZ[kRun];
 #pragma unroll
   for (int j = 0; j < kRun; ++j) {
     const bool inF = j < fhp;
     const float Tm = inF ? Tp : 1.f;
-    const float Am = inF ? pc.A : 0.f;
     const float Bm = inF ? fmaf(pc.A, R.x[j].m - pc.m1, pc.B) : 0.f;
     PT[j] = Tm * Tl[j];
-    PA[j] = fmaf(Tm, Al[j], Am);
     PZ[j] = fmaf(Tm, Zl[j], Bm);
   }
 
@@ -439,29 +464,29 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
     SA = Tq * sc.A; SF = Tq * sc.F; SL = Tq * Tq * sc.L; mf = sc.m0;
     TN = Tq * exp_neg(sc.tau + sc.tlo);
   }
-#ifndef XL_PASS3_RELOAD
-#define XL_PASS3_RELOAD 1
-#endif
-  if constexpr (FULL && XL_PASS3_RELOAD != 0) {
-    // Full tile: re-read the lane's samples (they were just loaded and are
-    // cache-resident) instead of keeping them live through the scans, and
-    // store each pair of gradients as soon as it is complete.  This keeps the
-    // kernel at 4 waves per SIMD.
+  if constexpr (FULL) {
+    // Full tile.  With 16-bit storage the lane's colours and interval ends are
+    // re-read here (a re-fetch of 6 + 8 bytes per sample) instead of being kept
+    // live through the scans, and only e and alpha are kept: this keeps 4
+    // waves per SIMD.  FP32 storage keeps its samples in registers (its
+    // re-read would cost more bandwidth than the occupancy buys).  Each pair of
+    // gradients is stored as soon as it is complete.
     float sg2[kRun], c2[3 * kRun], a2[kRun], b2[kRun];
-    asm volatile("" ::: "memory");
-    load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, R.i0, kRun, sg2, c2, a2, b2);
+    if constexpr (DT != kF32) {
+      asm volatile("" ::: "memory");
+      load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, R.i0, kRun, sg2, c2, a2, b2);
+    }
     float dsg[kRun], dc[3 * kRun];
 #pragma unroll
     for (int j = kRun - 1; j >= 0; --j) {
-#if XL_PASS3_RELOAD == 1
-      const Smp q = make_sample(sg2[j], c2[3 * j], c2[3 * j + 1], c2[3 * j + 2], a2[j], b2[j]);
-#else
-      Smp q;
-      q.e = R.x[j].e; q.alpha = R.x[j].alpha;
-      q.delta = b2[j] - a2[j]; q.m = 0.5f * (a2[j] + b2[j]);
-      q.c0 = c2[3 * j]; q.c1 = c2[3 * j + 1]; q.c2 = c2[3 * j + 2];
-#endif
-      reverse_step(q, PT[j], PA[j], PZ[j], R.endf[j], R.ends[j], s_lo, n_seg, gl, gseg, g, SG, SA, SF,
+      Smp q = R.x[j];
+      if constexpr (DT != kF32) {
+        q.delta = b2[j] - a2[j];
+        q.m = 0.5f * (a2[j] + b2[j]);
+        q.c0 = c2[3 * j]; q.c1 = c2[3 * j + 1]; q.c2 = c2[3 * j + 2];
+      }
+      const int endj = endloc[lane * kRun + j];  // re-read: frees registers across the scans
+      reverse_step(q, PT[j], PZ[j], endj >= 0, endj, s_lo, n_seg, gl, gseg, g, SG, SA, SF,
                    SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
       if ((j & 1) == 0) {
         if (DT == kF32)
@@ -482,7 +507,7 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   float dsg[kRun], dc[3 * kRun];
 #pragma unroll
   for (int j = kRun - 1; j >= 0; --j) {
-    reverse_step(R.x[j], PT[j], PA[j], PZ[j], R.endf[j], R.ends[j], s_lo, n_seg, gl, gseg, g, SG, SA, SF,
+    reverse_step(R.x[j], PT[j], PZ[j], R.endf[j], R.ends[j], s_lo, n_seg, gl, gseg, g, SG, SA, SF,
                  SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
   }
 
@@ -548,6 +573,8 @@ __global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int64_t t = t_first + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
   const bool active = t < t_end;
+  RawRun<DT> raw;
+  if (FULL && active) raw.load(s.sigma, s.rgb, s.t0, s.t1, t * kTile + static_cast<int64_t>(lane) * kRun);
   int* endloc = endloc_all[wave];
   float* gl = gl_all[wave];
 #pragma unroll
@@ -562,7 +589,8 @@ __global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
   }
   __syncthreads();
   if (!active) return;
-  bwd_tile<DT, FULL>(s, n_seg, t, s_lo, lane, endloc, gl, park_all[wave], recs, gseg, gsig_p, grgb_p);
+  bwd_tile<DT, FULL>(s, n_seg, t, s_lo, lane, endloc, gl, park_all[wave], recs, gseg, gsig_p, grgb_p,
+                     &raw);
 }
 
 static inline unsigned grid_for(int64_t count, int block) {

@@ -290,6 +290,61 @@ __device__ __forceinline__ void load_run(const void* __restrict__ sigma_p,
   }
 }
 
+// The raw storage of kRun consecutive samples (i % kRun == 0, all present),
+// loaded as 16-byte vectors and decoded later: a tile issues these loads
+// before its setup so their latency overlaps it.
+template <int DT>
+struct RawRun {
+  static constexpr int kSigmaVec = DT == kF32 ? kRun / 4 : kRun / 8;
+  static constexpr int kRgbVec = 3 * kSigmaVec;
+  uint4 sg[kSigmaVec];
+  uint4 rgb[kRgbVec];
+  float4 t0[kRun / 4], t1[kRun / 4];
+
+  __device__ __forceinline__ void load(const void* __restrict__ sigma_p, const void* __restrict__ rgb_p,
+                                       const float* __restrict__ t0_p, const float* __restrict__ t1_p,
+                                       int64_t i) {
+    const int es = DT == kF32 ? 4 : 2;
+    const uint4* S = reinterpret_cast<const uint4*>(static_cast<const char*>(sigma_p) + es * i);
+    const uint4* C = reinterpret_cast<const uint4*>(static_cast<const char*>(rgb_p) + 3 * es * i);
+#pragma unroll
+    for (int q = 0; q < kSigmaVec; ++q) sg[q] = S[q];
+#pragma unroll
+    for (int q = 0; q < kRgbVec; ++q) rgb[q] = C[q];
+#pragma unroll
+    for (int q = 0; q < kRun / 4; ++q) {
+      t0[q] = reinterpret_cast<const float4*>(t0_p + i)[q];
+      t1[q] = reinterpret_cast<const float4*>(t1_p + i)[q];
+    }
+  }
+
+  __device__ __forceinline__ void decode(float (&sgf)[kRun], float (&c)[3 * kRun], float (&a)[kRun],
+                                         float (&b)[kRun]) const {
+    auto unpack = [](const uint4* v, int nvec, float* out) {
+#pragma unroll
+      for (int q = 0; q < nvec; ++q) {
+        const uint32_t w[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          if (DT == kF32) {
+            out[4 * q + h] = __uint_as_float(w[h]);
+          } else {
+            out[8 * q + 2 * h] = to_f32<DT>(static_cast<uint16_t>(w[h] & 0xffffu));
+            out[8 * q + 2 * h + 1] = to_f32<DT>(static_cast<uint16_t>(w[h] >> 16));
+          }
+        }
+      }
+    };
+    unpack(sg, kSigmaVec, sgf);
+    unpack(rgb, kRgbVec, c);
+#pragma unroll
+    for (int q = 0; q < kRun / 4; ++q) {
+      a[4 * q] = t0[q].x; a[4 * q + 1] = t0[q].y; a[4 * q + 2] = t0[q].z; a[4 * q + 3] = t0[q].w;
+      b[4 * q] = t1[q].x; b[4 * q + 1] = t1[q].y; b[4 * q + 2] = t1[q].z; b[4 * q + 3] = t1[q].w;
+    }
+  }
+};
+
 // ---------------------------------------------------------------- wave scans
 // The part of a range that the backward's prefix needs: optical depth,
 // opacity and the back-relative depth at the last midpoint.

@@ -54,10 +54,14 @@ def test_host_side_argument_errors():
 
 def test_workspace_sizes():
     L = xl.lib()
-    rec = L.xl_segments_workspace_bytes(512)
+    rec = L.xl_segments_workspace_bytes(1)
     assert rec > 0 and rec % 16 == 0
-    assert L.xl_segments_workspace_bytes(513) == 2 * rec
     assert L.xl_segments_workspace_bytes(0) == rec
+    # one record per tile of a power-of-two number of samples
+    tile = next(n for n in (2 ** k for k in range(6, 16)) if L.xl_segments_workspace_bytes(n + 1) > rec)
+    assert L.xl_segments_workspace_bytes(tile) == rec
+    assert L.xl_segments_workspace_bytes(tile + 1) == 2 * rec
+    assert L.xl_segments_workspace_bytes(3 * tile + 1) == 4 * rec
     p = xl.gen_params(synth.WORKLOADS[2])
     assert L.xl_gen_workspace_bytes(ctypes.byref(p)) > 262144 * 8
     bad = xl.gen_params(synth.WORKLOADS[2])

@@ -233,7 +233,7 @@ def test_edge_cases_forward_backward(shuffle):
     _check_backward(b, d, rays, gseg, gs, gc, grad_ray, "edge")
 
 
-@pytest.mark.parametrize("n_samples", [1, 7, 511, 512, 513, 1100])
+@pytest.mark.parametrize("n_samples", [1, 7, 511, 512, 513, 1023, 1024, 1025, 1100, 2100])
 def test_tiny_and_ragged_sizes(n_samples):
     rng = np.random.default_rng(n_samples)
     # one long ray cut into segments of random length
