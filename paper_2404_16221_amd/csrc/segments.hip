@@ -2,15 +2,15 @@
 // its own samples to per-ray partial tuples before anything is exchanged).
 //
 // Work decomposition: the packed sample array is cut into fixed tiles of
-// kTile = 1024 samples, one wavefront per tile and kRun = 16 consecutive
-// samples per lane, independent of where segments begin and end.  That keeps
-// every load a full, aligned 16-byte vector access and balances ragged
-// segments (1..1000+ samples) perfectly; 16 samples per lane spread the cost
-// of the wave scans (six steps per scan) over twice as many samples as 8 would.
+// kTile = 512 samples, one wavefront per tile and kRun = 8 consecutive samples
+// per lane, independent of where segments begin and end.  That keeps every
+// load a full, aligned 16-byte vector access and balances ragged segments
+// (1..1000+ samples) perfectly.  (16 samples per lane would halve the scan work
+// per sample, but the extra registers cost more waves than the scans save.)
 // Inside a tile:
 //   1. the segment boundaries that fall in the tile are staged in LDS (one
 //      entry per sample: local id of the segment ending there, or -1);
-//   2. each lane folds its 16 samples serially into ranges (positive form of
+//   2. each lane folds its 8 samples serially into ranges (positive form of
 //      the merge operator, see xl_device.hpp);
 //   3. a segmented wave scan carries the open range across lanes;
 //   4. segments that cross a tile boundary are completed by a small fixup
