@@ -17,13 +17,14 @@
  *     anything is launched.
  *   - Return value: XL_OK (0) or a negative error code; xl_last_error() gives
  *     a message for the calling thread.
- *   - Sample layout (the paper's "distribute ray samples among GPUs based on
- *     the bounding box of the tiles", Sec. 4.2): samples of all regions packed
+ *   - Sample layout (Sec. 4.2: each region holds the samples that fall in its
+ *     axis-aligned box): samples of all regions packed
  *     region-major; segment s owns samples [seg_offsets[s], seg_offsets[s+1]),
  *     which belong to one ray and one region, sorted by t, with
  *     non-overlapping intervals [t_start, t_end].  Density sigma >= 0 and
  *     finite; colour in any finite range.
- *   - Segment tuple (the per-region "locally integrated data", App. A.2):
+ *   - Segment tuple (what each region reduces its samples to before any
+ *     exchange, App. A.2):
  *     seg_out is structure-of-arrays float32 [7][n_seg]:
  *       0 tau = sum sigma_i delta_i  (segment transmittance is exp(-tau))
  *       1-3 C = sum w_i c_i, 4 A = sum w_i, 5 D = sum w_i m_i (unnormalised),
@@ -84,8 +85,8 @@ const char* xl_last_error(void);
 size_t xl_segments_workspace_bytes(int64_t n);
 
 /*
- * Per-segment composite, forward (Sec. 4.3: "reduce the per-sample data into
- * per-tile data in parallel within each GPU"; Eq. 1-2 evaluated per segment).
+ * Per-segment composite, forward (Sec. 4.3: each region first reduces its own
+ * samples to one partial tuple per ray segment; Eq. 1-2 evaluated per segment).
  *   s            samples (device arrays, see conventions)
  *   seg_offsets  device int64 [n_seg + 1], non-decreasing, seg_offsets[0] = 0,
  *                seg_offsets[n_seg] = s->n

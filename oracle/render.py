@@ -15,9 +15,9 @@ What it computes (plain, slow, obviously correct; float64 throughout):
   A = sum w_i; unnormalised depth D = sum w_i m_i with m_i the interval
   midpoint; distortion L = sum_i sum_j w_i w_j |m_i - m_j| + 1/3 sum_i w_i^2
   delta_i (the discretisation of Mip-NeRF 360, which the paper cites for
-  Eq. 2).  Applied to a segment it gives the per-region partial tuple the paper
-  calls "locally integrated data" (App. A.2); applied to a whole ray it is the
-  single-pass render.
+  Eq. 2).  Applied to a segment it gives the partial tuple that a region
+  reduces its samples to before any exchange (App. A.2); applied to a whole ray
+  it is the single-pass render.
 * ``merge``: Eq. 3-8 of Sec. 4.3 written out as sums: the exclusive product of
   segment transmittances (Eq. 4) weights each segment's colour, opacity and
   depth (Eq. 3, 5, 6), and the distortion loss is 2 sum_k T_{<k} S_k + sum_k
