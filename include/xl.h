@@ -197,15 +197,19 @@ int xl_gen_fill(const xl_gen_params* p, int32_t dtype, void* workspace, size_t w
  * Requests are generated on the device (stand-in for per-region NeRF
  * evaluation), rendered with xl_render_segments_fwd + xl_merge_fwd and kept
  * until released.  Up to max_slots requests run at once, each on its own HIP
- * stream; a request is admitted when a slot is free and its exact HBM
- * footprint (known after generation planning) fits in hbm_budget_bytes next to
- * the requests in flight.  A request's result does not depend on the others.
- * All functions are thread-safe.
+ * stream.  The server allocates hbm_budget_bytes of device memory once, at
+ * creation, and carves every request's buffers out of it: a request is
+ * admitted when a slot is free and an upper bound of its footprint (every ray
+ * at n_max samples, capped at the budget) fits next to the requests in
+ * flight; generation planning then fixes the exact footprint and the rest is
+ * returned at once.  A request larger than the budget fails with XL_ENOMEM.
+ * A request's result does not depend on the others.  All functions are
+ * thread-safe.
  */
 typedef struct xl_server xl_server;
 
 typedef struct xl_serve_config {
-  uint64_t hbm_budget_bytes; /* device memory in-flight requests may hold */
+  uint64_t hbm_budget_bytes; /* device memory allocated at creation for requests */
   int32_t max_slots;         /* requests processed concurrently (>= 1) */
   int32_t max_queue;         /* requests waiting for a slot; XL_EAGAIN beyond */
   int32_t device;            /* HIP device ordinal */
@@ -242,6 +246,7 @@ typedef struct xl_serve_stats {
   int64_t span_us;           /* first arrival to last completion */
 } xl_serve_stats;
 
+/* XL_ENOMEM if the budget cannot be allocated, XL_EINVAL for bad settings. */
 int xl_serve_create(const xl_serve_config* cfg, xl_server** out);
 /* Non-blocking; XL_EAGAIN when max_queue requests are already waiting. */
 int xl_serve_submit(xl_server* s, const xl_request* req, uint64_t* ticket);
@@ -249,9 +254,10 @@ int xl_serve_submit(xl_server* s, const xl_request* req, uint64_t* ticket);
  * the request's final status (XL_OK or its error) with *out filled in. */
 int xl_serve_poll(xl_server* s, uint64_t ticket, xl_result* out, int64_t timeout_us);
 /* Copies a finished request's ray tuple [7][n_rays] to dst (device), async on
- * `stream`. */
+ * `stream`; a later xl_serve_release waits for the copy. */
 int xl_serve_copy_result(xl_server* s, uint64_t ticket, float* dst, void* stream);
-/* Frees a finished request's result (ray_out becomes invalid). */
+/* Returns a finished request's result to the server's memory once copies made
+ * by xl_serve_copy_result have completed (ray_out becomes invalid). */
 int xl_serve_release(xl_server* s, uint64_t ticket);
 int xl_serve_stats_get(xl_server* s, xl_serve_stats* out);
 /* Finishes queued requests, then frees everything. */

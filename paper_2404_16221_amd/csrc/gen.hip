@@ -136,9 +136,15 @@ __device__ __forceinline__ float cos2pi_f32(float u) {
   return q == 0 ? ca : (q == 1 ? -sa : (q == 2 ? -ca : sa));
 }
 
+// Samples of a ray are generated in chunks of kChunk by independent threads;
+// the structure pass records the running position at every chunk start, so
+// each chunk continues the same sequential float64 sum.
+constexpr int kChunk = 64;
+
 struct GenDev {
   int64_t n_rays, ray0;
   int32_t n_min, n_max, gx, gy, gz, max_segs;
+  int32_t chunks;  // chunks per ray: ceil(n_max / kChunk)
   float wm, mu, sg;
   double zero_frac, t_far;
   uint64_t seedkey;  // mix64(seed)
@@ -215,6 +221,7 @@ struct GenWs {
   int64_t* seg_ids;   // [R * M]
   int64_t* scan_tmp;  // scan scratch
   int32_t* err;       // [1] 1 if some ray had more segments than max_segs
+  double* chunk_run;  // [R * chunks] position at the start of each chunk
 };
 
 __global__ void gen_struct_kernel(GenDev g, GenWs w) {
@@ -232,6 +239,7 @@ __global__ void gen_struct_kernel(GenDev g, GenWs w) {
   int k = -1, cur = -1;
   double run = s0;
   for (int i = 0; i < s.count; ++i) {
+    if (i % kChunk == 0) w.chunk_run[r * g.chunks + i / kChunk] = run;
     const double t0 = run;
     run = d_add(run, d_mul(width_of(g, s.key, i), scale));
     const int b = box_of(g, s, static_cast<float>(t0), static_cast<float>(run));
@@ -360,25 +368,43 @@ __device__ __forceinline__ void store_group(void* sigma, void* rgb, float* t_sta
   }
 }
 
+// One thread per (chunk, ray): chunk c of ray r is samples [c kChunk, (c + 1)
+// kChunk) along the ray; rays index the lanes so a wave holds chunk c of 64
+// rays and every active lane does at most kChunk samples.
 template <int DT>
 __global__ void gen_fill_kernel(GenDev g, GenWs w, void* __restrict__ sigma, void* __restrict__ rgb,
                                 float* __restrict__ t_start, float* __restrict__ t_end) {
   const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
   if (r >= g.n_rays) return;
   const uint64_t key = mix64(g.seedkey + static_cast<uint64_t>(g.ray0 + r) * kGamma);
+  const uint64_t span = static_cast<uint64_t>(g.n_max - g.n_min + 1);
+  const int count = g.n_min + static_cast<int32_t>(((draw(key, 3) >> 32) * span) >> 32);
+  const int i_begin = c * kChunk;
+  if (i_begin >= count) return;
+  const int i_end = i_begin + kChunk < count ? i_begin + kChunk : count;
   const double scale = w.scale[r];
-  double run = w.s0[r];
+  double run = w.chunk_run[r * g.chunks + c];
   const int M = g.max_segs;
   const int ns = w.nseg[r];
-  int i = 0;  // sample index along the ray
-  for (int k = 0; k < ns; ++k) {
-    const int64_t d0 = w.seg_off[w.seg_pid[r * M + k]];
-    const int64_t d1 = d0 + w.seg_len[r * M + k];
+  // the segment holding sample i_begin, and the sample index its run starts at
+  int k = 0, first = 0;
+  while (k + 1 < ns && first + w.seg_len[r * M + k] <= i_begin) {
+    first += w.seg_len[r * M + k];
+    ++k;
+  }
+  int i = i_begin;
+  for (; k < ns && i < i_end; ++k) {
+    const int len = w.seg_len[r * M + k];
+    const int64_t base_slot = w.seg_off[w.seg_pid[r * M + k]];
+    const int64_t d0 = base_slot + (i - first);                       // first slot to write
+    const int64_t d1 = base_slot + ((i_end < first + len ? i_end : first + len) - first);
+    first += len;
     for (int64_t g0 = d0 & ~static_cast<int64_t>(kGroup - 1); g0 < d1; g0 += kGroup) {
-      float sg[kGroup], c[3 * kGroup], a[kGroup], b[kGroup];
+      float sg[kGroup], cl[3 * kGroup], a[kGroup], b[kGroup];
 #pragma unroll
       for (int q = 0; q < kGroup; ++q) {
-        sg[q] = 0.f; c[3 * q] = c[3 * q + 1] = c[3 * q + 2] = 0.f; a[q] = b[q] = 0.f;
+        sg[q] = 0.f; cl[3 * q] = cl[3 * q + 1] = cl[3 * q + 2] = 0.f; a[q] = b[q] = 0.f;
         const int64_t p = g0 + q;
         if (p < d0 || p >= d1) continue;
         const double t0 = run;
@@ -390,21 +416,21 @@ __global__ void gen_fill_kernel(GenDev g, GenWs w, void* __restrict__ sigma, voi
         const float z = f_mul(f_sqrt(f_mul(-2.f, log_f32(u1))), cos2pi_f32(u2));
         const float v = exp_f32(f_add(g.mu, f_mul(g.sg, z)));
         sg[q] = field(v2, 48, 16) < g.zero_frac ? 0.f : v;
-        c[3 * q] = static_cast<float>(field(v2, 32, 16));
-        c[3 * q + 1] = static_cast<float>(field(v2, 16, 16));
-        c[3 * q + 2] = static_cast<float>(field(v2, 0, 16));
+        cl[3 * q] = static_cast<float>(field(v2, 32, 16));
+        cl[3 * q + 1] = static_cast<float>(field(v2, 16, 16));
+        cl[3 * q + 2] = static_cast<float>(field(v2, 0, 16));
         a[q] = static_cast<float>(t0);
         b[q] = static_cast<float>(run);
         ++i;
       }
       if (g0 >= d0 && g0 + kGroup <= d1) {
-        store_group<DT>(sigma, rgb, t_start, t_end, g0, sg, c, a, b);
+        store_group<DT>(sigma, rgb, t_start, t_end, g0, sg, cl, a, b);
       } else {
 #pragma unroll
         for (int q = 0; q < kGroup; ++q) {
           const int64_t p = g0 + q;
           if (p < d0 || p >= d1) continue;
-          put_sample<DT>(sigma, rgb, p, sg[q], c[3 * q], c[3 * q + 1], c[3 * q + 2]);
+          put_sample<DT>(sigma, rgb, p, sg[q], cl[3 * q], cl[3 * q + 1], cl[3 * q + 2]);
           t_start[p] = a[q];
           t_end[p] = b[q];
         }
@@ -492,7 +518,7 @@ hipError_t scan_exclusive(const int64_t* in, int64_t* out, int64_t n, int64_t* t
 
 // ---------------------------------------------------------------- host side
 struct GenLayout {
-  int64_t R, M, K, nblk, RM;
+  int64_t R, M, K, nblk, RM, C;
   size_t scan_elems;  // scan scratch, enough for the longest of the three scans
   size_t off[16];
   size_t bytes;
@@ -504,6 +530,8 @@ static GenLayout layout(const xl_gen_params* p) {
   L.M = p->grid[0] + p->grid[1] + p->grid[2] - 2;
   if (L.M < 1) L.M = 1;
   L.K = static_cast<int64_t>(p->grid[0]) * p->grid[1] * p->grid[2];
+  L.C = (static_cast<int64_t>(p->n_max) + kChunk - 1) / kChunk;
+  if (L.C < 1) L.C = 1;
   L.nblk = (L.R + kRayBlock - 1) / kRayBlock;
   L.RM = L.R * L.M;
   const int64_t KB = L.K * L.nblk;
@@ -525,9 +553,10 @@ static GenLayout layout(const xl_gen_params* p) {
       sizeof(int64_t) * L.RM,          // seg_ids
       sizeof(int64_t) * L.scan_elems,  // scan_tmp
       sizeof(int32_t) * 4,             // err
+      sizeof(double) * L.R * L.C,      // chunk_run
   };
   size_t o = 0;
-  for (int i = 0; i < 15; ++i) {
+  for (int i = 0; i < 16; ++i) {
     L.off[i] = o;
     o += (sizes[i] + 255) & ~static_cast<size_t>(255);
   }
@@ -553,6 +582,7 @@ static GenWs views(const GenLayout& L, void* ws) {
   w.seg_ids = reinterpret_cast<int64_t*>(b + L.off[12]);
   w.scan_tmp = reinterpret_cast<int64_t*>(b + L.off[13]);
   w.err = reinterpret_cast<int32_t*>(b + L.off[14]);
+  w.chunk_run = reinterpret_cast<double*>(b + L.off[15]);
   return w;
 }
 
@@ -566,6 +596,7 @@ static GenDev dev_params(const xl_gen_params* p, const GenLayout& L) {
   g.gy = p->grid[1];
   g.gz = p->grid[2];
   g.max_segs = static_cast<int32_t>(L.M);
+  g.chunks = static_cast<int32_t>(L.C);
   g.wm = static_cast<float>(p->width_mean);
   g.mu = static_cast<float>(p->sigma_mu);
   g.sg = static_cast<float>(p->sigma_s);
@@ -582,7 +613,11 @@ int64_t gen_max_segments(const xl_gen_params* p) { return layout(p).RM; }
 static inline unsigned blocks(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
 
 hipError_t gen_plan(const xl_gen_params* p, void* ws, hipStream_t st, int64_t* n_samples,
-                    int64_t* n_seg, int* overflow) {
+                    int64_t* n_seg, int* overflow, int64_t* pinned) {
+  // The three values read back go through `pinned` (page-locked host memory,
+  // >= 3 int64) when given, so the copies are plain stream work.
+  int64_t local[3];
+  int64_t* h = pinned ? pinned : local;
   const GenLayout L = layout(p);
   const GenWs w = views(L, ws);
   const GenDev g = dev_params(p, L);
@@ -595,21 +630,20 @@ hipError_t gen_plan(const xl_gen_params* p, void* ws, hipStream_t st, int64_t* n
   if ((e = scan_exclusive(w.blk_cnt, w.blk_base, L.K * L.nblk, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(gen_rank_kernel, dim3(static_cast<unsigned>(L.nblk)), dim3(kRayBlock), 0, st, g,
                      w, L.nblk, static_cast<int>(L.K));
-  int64_t ns = 0;
-  if ((e = hipMemcpyAsync(&ns, w.ray_off + L.R, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+  if ((e = hipMemcpyAsync(&h[0], w.ray_off + L.R, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
     return e;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  const int64_t ns = h[0];
   if (ns < 0 || ns > L.RM) return hipErrorInvalidValue;  // at most max_segs per ray
   if ((e = scan_exclusive(w.plen, w.seg_off, ns, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
-  int64_t n = 0;
-  int err = 0;
-  if ((e = hipMemcpyAsync(&n, w.seg_off + ns, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+  h[2] = 0;
+  if ((e = hipMemcpyAsync(&h[1], w.seg_off + ns, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
     return e;
-  if ((e = hipMemcpyAsync(&err, w.err, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(&h[2], w.err, sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-  *n_samples = n;
+  *n_samples = h[1];
   *n_seg = ns;
-  *overflow = err;
+  *overflow = static_cast<int32_t>(h[2]) != 0;
   return hipSuccess;
 }
 
@@ -619,7 +653,7 @@ hipError_t gen_fill(const xl_gen_params* p, int dtype, void* ws, int64_t n_seg, 
   const GenLayout L = layout(p);
   const GenWs w = views(L, ws);
   const GenDev g = dev_params(p, L);
-  const dim3 grid(blocks(L.R, 128));
+  const dim3 grid(blocks(L.R, 128), static_cast<unsigned>(L.C));
   switch (dtype) {
     case kF32:
       hipLaunchKernelGGL(gen_fill_kernel<kF32>, grid, dim3(128), 0, st, g, w, sigma, rgb, t_start, t_end);

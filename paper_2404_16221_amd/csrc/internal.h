@@ -45,8 +45,9 @@ int clear_error();
 
 // Device generator (gen.hip).
 size_t gen_workspace_bytes(const xl_gen_params* p);
+int64_t gen_max_segments(const xl_gen_params* p);  // rays x regions a ray can cross
 hipError_t gen_plan(const xl_gen_params* p, void* ws, hipStream_t st, int64_t* n_samples,
-                    int64_t* n_seg, int* overflow);
+                    int64_t* n_seg, int* overflow, int64_t* pinned = nullptr);
 hipError_t gen_fill(const xl_gen_params* p, int dtype, void* ws, int64_t n_seg, void* sigma,
                     void* rgb, float* t_start, float* t_end, int64_t* seg_offsets,
                     int64_t* ray_offsets, int64_t* seg_ids, hipStream_t st);

@@ -104,7 +104,9 @@ __device__ __forceinline__ void stage_ends(const int64_t* __restrict__ off, int6
         }
       }
     }
-    if (!__any(in)) break;
+    // Segments are sorted by start: once a lane's segment starts past the tile
+    // (or past the last segment), every later one does too.
+    if (!__all(in)) break;
   }
 }
 
@@ -260,33 +262,53 @@ __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
 
 // Completes segments that cross tile boundaries and leaves, in every tile
 // such a segment passes through, the carries the backward needs.  One thread
-// per tile where a segment starts and continues past the tile end.
+// per tile, reading only its neighbours' records:
+//   pre: the part of the tile's first segment that lies before the tile (walk
+//        back over tiles without a head, then the open tail of the tile where
+//        the segment starts);
+//   suf: the part of the tile's last segment that lies after it (walk forward
+//        over tiles without an end, then the head of the tile where it ends);
+//   the tile in which a crossing segment ends writes its tuple, pre (+) head.
+// Segments are shorter than a tile on average, so a walk is one step.
 __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restrict__ seg_out,
                                  TileRec* __restrict__ recs) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n_tiles) return;
   const int fl = recs[t].flags;
-  if (!((fl & kHasHead) && (fl & kTailOpen))) return;
-  Range acc = recs[t].tail;
-  int64_t u = t + 1;
-  bool closed = false;
-  while (u < n_tiles) {
-    recs[u].pre = acc;
-    const int fu = recs[u].flags;
-    acc = combine(acc, recs[u].head);
-    if (fu & kHasEnd) {
-      closed = true;
-      break;
+  // (The empty range is not an identity of combine in the positive form, whose
+  // depths are relative to the ranges' end midpoints, so each walk starts from
+  // its first part.)
+  if (!(fl & kStartHead)) {
+    Range acc;
+    bool have = false, found = false;
+    for (int64_t u = t - 1; u >= 0; --u) {
+      const bool h = (recs[u].flags & kHasHead) != 0;
+      const Range part = h ? recs[u].tail : recs[u].head;
+      acc = have ? combine(part, acc) : part;
+      have = true;
+      if (h) {
+        found = true;
+        break;
+      }
     }
-    ++u;
+    if (found) {
+      recs[t].pre = acc;
+      if (fl & kHasEnd) {
+        const int64_t sgi = recs[t].first_seg;
+        if (sgi >= 0 && sgi < n_seg) write_tuple(seg_out, n_seg, sgi, combine(acc, recs[t].head));
+      }
+    }
   }
-  if (!closed) return;  // malformed offsets: the last segment must end at n
-  const int64_t sgi = recs[t].tail_seg;
-  if (sgi >= 0 && sgi < n_seg) write_tuple(seg_out, n_seg, sgi, acc);
-  Range suf = recs[u].head;
-  for (int64_t v = u - 1; v >= t; --v) {
-    recs[v].suf = suf;
-    if (v > t) suf = combine(recs[v].head, suf);
+  if (fl & kTailOpen) {
+    Range acc;
+    bool have = false;
+    for (int64_t u = t + 1; u < n_tiles; ++u) {
+      const Range part = recs[u].head;
+      acc = have ? combine(acc, part) : part;
+      have = true;
+      if (recs[u].flags & kHasEnd) break;
+    }
+    if (have) recs[t].suf = acc;
   }
 }
 
@@ -465,26 +487,12 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
     TN = Tq * exp_neg(sc.tau + sc.tlo);
   }
   if constexpr (FULL) {
-    // Full tile.  With 16-bit storage the lane's colours and interval ends are
-    // re-read here (a re-fetch of 6 + 8 bytes per sample) instead of being kept
-    // live through the scans, and only e and alpha are kept: this keeps 4
-    // waves per SIMD.  FP32 storage keeps its samples in registers (its
-    // re-read would cost more bandwidth than the occupancy buys).  Each pair of
-    // gradients is stored as soon as it is complete.
-    float sg2[kRun], c2[3 * kRun], a2[kRun], b2[kRun];
-    if constexpr (DT != kF32) {
-      asm volatile("" ::: "memory");
-      load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, R.i0, kRun, sg2, c2, a2, b2);
-    }
+    // Full tile: the lane's samples stay in registers from pass 1 (no
+    // re-read), and each pair of gradients is stored as soon as it is complete.
     float dsg[kRun], dc[3 * kRun];
 #pragma unroll
     for (int j = kRun - 1; j >= 0; --j) {
-      Smp q = R.x[j];
-      if constexpr (DT != kF32) {
-        q.delta = b2[j] - a2[j];
-        q.m = 0.5f * (a2[j] + b2[j]);
-        q.c0 = c2[3 * j]; q.c1 = c2[3 * j + 1]; q.c2 = c2[3 * j + 2];
-      }
+      const Smp& q = R.x[j];
       const int endj = endloc[lane * kRun + j];  // re-read: frees registers across the scans
       reverse_step(q, PT[j], PZ[j], endj >= 0, endj, s_lo, n_seg, gl, gseg, g, SG, SA, SF,
                    SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);

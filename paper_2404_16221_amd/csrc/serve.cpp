@@ -10,20 +10,25 @@
 // Structure:
 //   * xl_serve_submit puts a request on a bounded FIFO queue (XL_EAGAIN when
 //     full) and stamps its arrival time.
+//   * Device memory is one arena of hbm_budget_bytes, allocated when the
+//     server starts and carved per request (arena.hpp): no driver allocation
+//     or free happens per request, so the workers never serialise on the
+//     allocator.
 //   * max_slots worker threads, each owning one HIP stream (default priority),
-//     take requests in arrival order.  A worker first runs the generator's plan
-//     phase, which fixes the request's exact HBM footprint (samples, segment
-//     arrays, tuples, workspaces, result), then waits until the footprint fits
-//     into the byte budget next to the requests already in flight, allocates
-//     stream-ordered memory and launches generation, segment composite and
-//     merge.  Requests therefore join while others are on the GPU as soon as a
-//     slot and memory free up, and the kernels of different requests overlap
-//     on the device.
+//     take requests in arrival order.  A worker reserves an upper bound of the
+//     request's footprint (every ray at n_max samples), waiting until it fits
+//     next to the requests in flight; runs the generator's plan phase, which
+//     fixes the exact footprint (samples, segment arrays, tuples, workspaces,
+//     result); gives the excess back; and launches generation, segment
+//     composite and merge.  Requests therefore join while others are on the
+//     GPU as soon as a slot and memory free up, and the kernels of different
+//     requests overlap on the device.
 //   * Each request has its own buffers and runs the same kernels, so its result
 //     does not depend on what else is in flight (bit for bit).
 //   * xl_serve_poll waits for a ticket (bounded by a timeout) and reports the
 //     result, its latency (completion minus arrival, host monotonic clock) and
-//     its device time; xl_serve_release frees the result buffer.
+//     its device time; xl_serve_release returns the result buffer to the arena
+//     (after any copy of it made by xl_serve_copy_result has completed).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,6 +44,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "arena.hpp"
 #include "internal.h"
 
 namespace xl {
@@ -56,6 +62,8 @@ struct Job {
   int32_t status = XL_PENDING;
   bool done = false;
   float* ray_out = nullptr;
+  size_t arena_off = 0;         // the result block [arena_off, arena_off + result_bytes)
+  hipEvent_t copied = nullptr;  // after the last xl_serve_copy_result copy
   int64_t n_rays = 0, n_samples = 0, n_seg = 0;
   uint64_t footprint = 0, result_bytes = 0;
   float device_ms = 0.f;
@@ -69,8 +77,8 @@ struct Server {
   std::deque<std::shared_ptr<Job>> queue;
   std::unordered_map<uint64_t, std::shared_ptr<Job>> jobs;
   std::vector<std::thread> workers;
-  hipStream_t release_stream = nullptr;
-  uint64_t budget_used = 0;
+  char* base = nullptr;  // device arena
+  Arena arena;
   uint64_t next_ticket = 1;
   bool stop = false;
   std::vector<int64_t> latencies;  // of completed requests
@@ -97,7 +105,13 @@ static void finish(Server* s, const std::shared_ptr<Job>& j, int32_t status, con
   s->cv_done.notify_all();
 }
 
-static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+static void release_block(Server* s, size_t off, size_t bytes) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->arena.release(off, bytes);
+  s->cv_budget.notify_all();
+}
+
+static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int64_t* pinned,
                     const std::shared_ptr<Job>& j) {
   const xl_request& q = j->req;
   if (q.inject_fault) {
@@ -120,119 +134,106 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
   const int dtype = s->cfg.dtype;
   const size_t es = dtype == XL_F32 ? 4 : 2;
 
+  // Block layout: [result | generator workspace | ray offsets | samples, segment
+  // arrays, tuples, tile records].
+  const size_t b_out = round256(4 * 7 * p.n_rays), b_ro = round256(8 * (p.n_rays + 1));
   const size_t ws_b = round256(gen_workspace_bytes(&p));
-  void* ws = nullptr;
-  if (hipMallocAsync(&ws, ws_b, st) != hipSuccess) {
-    finish(s, j, XL_ENOMEM, "generator workspace allocation failed");
+  const size_t head = b_out + ws_b + b_ro;
+  auto body = [&](int64_t n, int64_t n_seg) -> size_t {
+    return round256(n * es) + round256(3 * n * es) + 2 * round256(4 * n) + round256(8 * (n_seg + 1)) +
+           round256(8 * n_seg) + round256(4 * 7 * n_seg) + round256(xl_segments_workspace_bytes(n));
+  };
+  const size_t bound = head + body(p.n_rays * static_cast<int64_t>(p.n_max), gen_max_segments(&p));
+  char m[200];
+  if (head > s->arena.size()) {
+    std::snprintf(m, sizeof(m), "request needs more than %llu bytes, budget is %llu",
+                  static_cast<unsigned long long>(head),
+                  static_cast<unsigned long long>(s->arena.size()));
+    finish(s, j, XL_ENOMEM, m);
     return;
   }
+  const size_t reserve = std::min(bound, s->arena.size());
+  size_t off = 0;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    bool got = false;
+    s->cv_budget.wait(lk, [&] { return s->stop || (got = s->arena.alloc(reserve, &off)); });
+    if (!got) {
+      lk.unlock();
+      finish(s, j, XL_EAGAIN, "server stopped before the request was admitted");
+      return;
+    }
+  }
+  char* blk = s->base + off;
+  float* out = reinterpret_cast<float*>(blk);
+  void* ws = blk + b_out;
+  int64_t* ro = reinterpret_cast<int64_t*>(blk + b_out + ws_b);
+  char* c = blk + head;
+
   int64_t n = 0, n_seg = 0;
   int overflow = 0;
-  if (gen_plan(&p, ws, st, &n, &n_seg, &overflow) != hipSuccess || overflow) {
-    (void)hipFreeAsync(ws, st);  // cleanup on a path that already reports failure
-    (void)hipStreamSynchronize(st);
+  if (gen_plan(&p, ws, st, &n, &n_seg, &overflow, pinned) != hipSuccess || overflow) {
+    (void)hipStreamSynchronize(st);  // cleanup on a path that already reports failure
+    release_block(s, off, reserve);
     finish(s, j, XL_EHIP, "generator plan failed");
     return;
   }
   j->n_samples = n;
   j->n_seg = n_seg;
-  const size_t b_sigma = round256(n * es), b_rgb = round256(3 * n * es), b_t = round256(4 * n);
-  const size_t b_off = round256(8 * (n_seg + 1)), b_ro = round256(8 * (p.n_rays + 1));
-  const size_t b_ids = round256(8 * n_seg), b_seg = round256(4 * 7 * n_seg);
-  const size_t b_rec = round256(xl_segments_workspace_bytes(n));
-  const size_t b_out = round256(4 * 7 * p.n_rays);
-  const uint64_t fp = ws_b + b_sigma + b_rgb + 2 * b_t + b_off + b_ro + b_ids + b_seg + b_rec + b_out;
+  const size_t fp = head + body(n, n_seg);
   j->footprint = fp;
   j->result_bytes = b_out;
-  {
-    std::unique_lock<std::mutex> lk(s->mu);
-    if (fp > s->cfg.hbm_budget_bytes) {
-      lk.unlock();
-      (void)hipFreeAsync(ws, st);
-      (void)hipStreamSynchronize(st);
-      char m[160];
-      std::snprintf(m, sizeof(m), "request needs %llu bytes, budget is %llu",
-                    static_cast<unsigned long long>(fp),
-                    static_cast<unsigned long long>(s->cfg.hbm_budget_bytes));
-      finish(s, j, XL_ENOMEM, m);
-      return;
-    }
-    s->cv_budget.wait(lk, [&] { return s->stop || s->budget_used + fp <= s->cfg.hbm_budget_bytes; });
-    s->budget_used += fp;
-  }
-  char* big = nullptr;
-  const size_t b_tmp = b_sigma + b_rgb + 2 * b_t + b_off + b_ids + b_seg + b_rec;
-  void* out = nullptr;
-  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&big), b_tmp, st);
-  if (e == hipSuccess) e = hipMallocAsync(&out, b_out, st);
-  int64_t* ro = nullptr;
-  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&ro), b_ro, st);
-  if (e != hipSuccess) {
-    if (big) (void)hipFreeAsync(big, st);
-    if (out) (void)hipFreeAsync(out, st);
-    (void)hipFreeAsync(ws, st);
-    (void)hipStreamSynchronize(st);
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->budget_used -= fp;
-      s->cv_budget.notify_all();
-    }
-    finish(s, j, XL_ENOMEM, "request buffer allocation failed");
+  if (fp > reserve) {
+    release_block(s, off, reserve);
+    std::snprintf(m, sizeof(m), "request needs %llu bytes, budget is %llu",
+                  static_cast<unsigned long long>(fp),
+                  static_cast<unsigned long long>(s->arena.size()));
+    finish(s, j, XL_ENOMEM, m);
     return;
   }
-  char* c = big;
-  void* sigma = c; c += b_sigma;
-  void* rgb = c; c += b_rgb;
-  float* t0 = reinterpret_cast<float*>(c); c += b_t;
-  float* t1 = reinterpret_cast<float*>(c); c += b_t;
-  int64_t* off = reinterpret_cast<int64_t*>(c); c += b_off;
-  int64_t* ids = reinterpret_cast<int64_t*>(c); c += b_ids;
-  float* seg_out = reinterpret_cast<float*>(c); c += b_seg;
+  if (fp < reserve) release_block(s, off + fp, reserve - fp);
+
+  void* sigma = c; c += round256(n * es);
+  void* rgb = c; c += round256(3 * n * es);
+  float* t0 = reinterpret_cast<float*>(c); c += round256(4 * n);
+  float* t1 = reinterpret_cast<float*>(c); c += round256(4 * n);
+  int64_t* so = reinterpret_cast<int64_t*>(c); c += round256(8 * (n_seg + 1));
+  int64_t* ids = reinterpret_cast<int64_t*>(c); c += round256(8 * n_seg);
+  float* seg_out = reinterpret_cast<float*>(c); c += round256(4 * 7 * n_seg);
   TileRec* recs = reinterpret_cast<TileRec*>(c);
 
-  e = hipEventRecord(e0, st);
-  if (e == hipSuccess) e = gen_fill(&p, dtype, ws, n_seg, sigma, rgb, t0, t1, off, ro, ids, st);
+  hipError_t e = hipEventRecord(e0, st);
+  if (e == hipSuccess) e = gen_fill(&p, dtype, ws, n_seg, sigma, rgb, t0, t1, so, ro, ids, st);
   SamplesDev sd{dtype, sigma, rgb, t0, t1, n};
-  if (e == hipSuccess) e = launch_segments_fwd(sd, off, n_seg, seg_out, recs, st);
+  if (e == hipSuccess) e = launch_segments_fwd(sd, so, n_seg, seg_out, recs, st);
   if (e == hipSuccess)
-    e = launch_merge_fwd(seg_out, n_seg, ro, ids, p.n_rays, static_cast<float*>(out),
-                         s->cfg.merge_fp64 != 0, st);
+    e = launch_merge_fwd(seg_out, n_seg, ro, ids, p.n_rays, out, s->cfg.merge_fp64 != 0, st);
   if (e == hipSuccess) e = hipEventRecord(e1, st);
-  hipError_t ef = hipFreeAsync(big, st);
-  if (ef == hipSuccess) ef = hipFreeAsync(ro, st);
-  if (ef == hipSuccess) ef = hipFreeAsync(ws, st);
-  if (e == hipSuccess) e = ef;
   const hipError_t es2 = hipStreamSynchronize(st);
   float ms = 0.f;
   if (e == hipSuccess && es2 == hipSuccess && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 0.f;
   j->device_ms = ms;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->budget_used -= fp - b_out;  // the result stays charged until released
-    s->cv_budget.notify_all();
-  }
   if (e != hipSuccess || es2 != hipSuccess) {
-    (void)hipFreeAsync(out, st);
-    (void)hipStreamSynchronize(st);
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->budget_used -= b_out;
-      s->cv_budget.notify_all();
-    }
+    release_block(s, off, fp);
     finish(s, j, XL_EHIP, hipGetErrorString(e != hipSuccess ? e : es2));
     return;
   }
-  j->ray_out = static_cast<float*>(out);
+  release_block(s, off + b_out, fp - b_out);  // the result stays until released
+  j->ray_out = out;
+  j->arena_off = off;
   finish(s, j, XL_OK, nullptr);
 }
 
 static void worker(Server* s) {
   hipStream_t st = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  // A slot whose stream or events cannot be made fails every request it takes.
+  int64_t* pinned = nullptr;  // the plan phase's readback values
+  // A slot whose stream, events or buffer cannot be made fails every request it takes.
   const bool ready = hipSetDevice(s->cfg.device) == hipSuccess &&
                      hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
-                     hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+                     hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+                     hipHostMalloc(reinterpret_cast<void**>(&pinned), 4 * sizeof(int64_t),
+                                   hipHostMallocDefault) == hipSuccess;
   for (;;) {
     std::shared_ptr<Job> j;
     {
@@ -244,10 +245,11 @@ static void worker(Server* s) {
       j->t_admit = now_us();
     }
     if (ready)
-      run_job(s, st, e0, e1, j);
+      run_job(s, st, e0, e1, pinned, j);
     else
       finish(s, j, XL_EHIP, "serving slot has no stream or events");
   }
+  if (pinned) (void)hipHostFree(pinned);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (st) (void)hipStreamDestroy(st);
@@ -263,21 +265,19 @@ int xl_serve_create(const xl_serve_config* cfg, xl_server** out) {
     return xl::set_error(XL_EINVAL, "max_slots and max_queue must be >= 1");
   if (cfg->dtype != XL_F32 && cfg->dtype != XL_BF16 && cfg->dtype != XL_F16)
     return xl::set_error(XL_EINVAL, "unknown sample dtype %d", cfg->dtype);
+  if (cfg->hbm_budget_bytes < xl::Arena::kAlign)
+    return xl::set_error(XL_EINVAL, "hbm_budget_bytes must be at least %zu", xl::Arena::kAlign);
   hipError_t e = hipSetDevice(cfg->device);
   if (e != hipSuccess) return xl::set_error(XL_EHIP, "device %d: %s", cfg->device, hipGetErrorString(e));
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, cfg->device) == hipSuccess) {
-    // Keep freed request buffers in the pool (a performance hint only).
-    uint64_t keep = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-  }
   auto* s = new xl::Server();
   s->cfg = *cfg;
-  e = hipStreamCreateWithFlags(&s->release_stream, hipStreamNonBlocking);
+  e = hipMalloc(reinterpret_cast<void**>(&s->base), cfg->hbm_budget_bytes);
   if (e != hipSuccess) {
     delete s;
-    return xl::set_error(XL_EHIP, "release stream: %s", hipGetErrorString(e));
+    return xl::set_error(XL_ENOMEM, "arena of %llu bytes: %s",
+                         static_cast<unsigned long long>(cfg->hbm_budget_bytes), hipGetErrorString(e));
   }
+  s->arena.reset(cfg->hbm_budget_bytes);
   for (int i = 0; i < cfg->max_slots; ++i) s->workers.emplace_back(xl::worker, s);
   *out = reinterpret_cast<xl_server*>(s);
   return xl::clear_error();
@@ -349,8 +349,12 @@ int xl_serve_copy_result(xl_server* srv, uint64_t ticket, float* dst, void* stre
       return xl::set_error(XL_EINVAL, "ticket %llu has no result", (unsigned long long)ticket);
     j = it->second;
   }
-  const hipError_t e = hipMemcpyAsync(dst, j->ray_out, sizeof(float) * 7 * j->n_rays,
-                                      hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream));
+  hipError_t e = hipMemcpyAsync(dst, j->ray_out, sizeof(float) * 7 * j->n_rays,
+                                hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream));
+  // The result block may not be reused before this copy has read it.
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (e == hipSuccess && !j->copied) e = hipEventCreateWithFlags(&j->copied, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(j->copied, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return xl::set_error(XL_EHIP, "copy: %s", hipGetErrorString(e));
   return xl::clear_error();
 }
@@ -367,16 +371,14 @@ int xl_serve_release(xl_server* srv, uint64_t ticket) {
     j = it->second;
     s->jobs.erase(it);
   }
-  if (j->ray_out) {
-    hipError_t e = hipFreeAsync(j->ray_out, s->release_stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->release_stream);
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->budget_used -= j->result_bytes;
-      s->cv_budget.notify_all();
-    }
-    if (e != hipSuccess) return xl::set_error(XL_EHIP, "release: %s", hipGetErrorString(e));
+  hipError_t e = hipSuccess;
+  if (j->copied) {
+    e = hipEventSynchronize(j->copied);
+    (void)hipEventDestroy(j->copied);
+    j->copied = nullptr;
   }
+  if (j->ray_out) xl::release_block(s, j->arena_off, j->result_bytes);
+  if (e != hipSuccess) return xl::set_error(XL_EHIP, "release: %s", hipGetErrorString(e));
   return xl::clear_error();
 }
 
@@ -389,7 +391,7 @@ int xl_serve_stats_get(xl_server* srv, xl_serve_stats* out) {
   out->failed = s->failed;
   out->queued = static_cast<int64_t>(s->queue.size());
   out->samples = s->samples_done;
-  out->budget_used_bytes = s->budget_used;
+  out->budget_used_bytes = s->arena.used();
   std::vector<int64_t> v = s->latencies;
   if (!v.empty()) {
     std::sort(v.begin(), v.end());
@@ -416,10 +418,15 @@ int xl_serve_destroy(xl_server* srv) {
   }
   for (auto& t : s->workers) t.join();
   hipError_t e = hipSuccess;
-  for (auto& kv : s->jobs)
-    if (kv.second->ray_out && e == hipSuccess) e = hipFreeAsync(kv.second->ray_out, s->release_stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(s->release_stream);
-  (void)hipStreamDestroy(s->release_stream);
+  for (auto& kv : s->jobs) {
+    if (kv.second->copied) {
+      const hipError_t ec = hipEventSynchronize(kv.second->copied);
+      if (e == hipSuccess) e = ec;
+      (void)hipEventDestroy(kv.second->copied);
+    }
+  }
+  const hipError_t ef = hipFree(s->base);
+  if (e == hipSuccess) e = ef;
   delete s;
   if (e != hipSuccess) return xl::set_error(XL_EHIP, "destroy: %s", hipGetErrorString(e));
   return xl::clear_error();
