@@ -80,8 +80,7 @@ int xl_version(void) { return 100; }
 const char* xl_last_error(void) { return g_err; }
 
 size_t xl_segments_workspace_bytes(int64_t n) {
-  const int64_t nt = n > 0 ? xl::num_tiles(n) : 1;
-  return static_cast<size_t>(nt) * xl::tile_rec_bytes();
+  return xl::segments_workspace_bytes(n > 0 ? n : 0);
 }
 
 int xl_render_segments_fwd(const xl_samples* s, const int64_t* seg_offsets, int64_t n_seg,
@@ -100,7 +99,7 @@ int xl_render_segments_fwd(const xl_samples* s, const int64_t* seg_offsets, int6
                   xl_segments_workspace_bytes(d.n));
   }
   return hip_status(xl::launch_segments_fwd(d, seg_offsets, n_seg, seg_out,
-                                            static_cast<xl::TileRec*>(workspace),
+                                            workspace,
                                             static_cast<hipStream_t>(stream)),
                     "xl_render_segments_fwd launch");
 }
@@ -122,7 +121,7 @@ int xl_render_segments_bwd(const xl_samples* s, const int64_t* seg_offsets, int6
                   xl_segments_workspace_bytes(d.n));
   }
   return hip_status(xl::launch_segments_bwd(d, seg_offsets, n_seg,
-                                            static_cast<const xl::TileRec*>(workspace), grad_seg,
+                                            workspace, grad_seg,
                                             grad_sigma, grad_rgb, static_cast<hipStream_t>(stream)),
                     "xl_render_segments_bwd launch");
 }

@@ -17,15 +17,14 @@ struct SamplesDev {
   int64_t n;
 };
 
-struct TileRec;
 
 int64_t num_tiles(int64_t n);
-size_t tile_rec_bytes();
+size_t segments_workspace_bytes(int64_t n);  // per-tile records
 
 hipError_t launch_segments_fwd(const SamplesDev& s, const int64_t* seg_offsets, int64_t n_seg,
-                               float* seg_out, TileRec* recs, hipStream_t stream);
+                               float* seg_out, void* workspace, hipStream_t stream);
 hipError_t launch_segments_bwd(const SamplesDev& s, const int64_t* seg_offsets, int64_t n_seg,
-                               const TileRec* recs, const float* grad_seg, void* grad_sigma,
+                               const void* workspace, const float* grad_seg, void* grad_sigma,
                                void* grad_rgb, hipStream_t stream);
 hipError_t launch_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
                             const int64_t* seg_ids, int64_t n_rays, float* ray_out, bool fp64,

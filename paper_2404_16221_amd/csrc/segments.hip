@@ -25,24 +25,22 @@
 namespace xl {
 
 int64_t num_tiles(int64_t n) { return (n + kTile - 1) / kTile; }
-size_t tile_rec_bytes() { return sizeof(TileRec); }
+size_t segments_workspace_bytes(int64_t n) { return TileRecs::bytes(num_tiles(n)); }
 
 // First segment of each tile's window: the segment containing the tile's
 // first sample if it starts before the tile, else the first segment (empty
-// ones included) starting at the tile's first sample.
+// ones included) starting at the tile's first sample.  One thread per
+// segment writes the tiles whose first sample it owns: those starting inside
+// it, and the tile starting at its own first sample if no earlier segment
+// starts there too.  Every tile gets exactly one writer.
 __global__ void plan_kernel(const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
-                            TileRec* __restrict__ recs) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= n_tiles) return;
-  const int64_t base = t * kTile;
-  int64_t lo = 0, hi = n_seg;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (off[mid] < base) lo = mid + 1; else hi = mid;
-  }
-  int64_t w = lo;
-  if (w == n_seg || off[w] > base) w -= 1;
-  recs[t].first_seg = w < 0 ? 0 : w;
+                            TileRecs recs) {
+  const int64_t sg = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (sg >= n_seg) return;
+  const int64_t a = off[sg], e = off[sg + 1];
+  const bool first_at_a = sg == 0 || off[sg - 1] < a;
+  if (first_at_a && a % kTile == 0 && a / kTile < n_tiles) recs.first_seg[a / kTile] = sg;
+  for (int64_t t = a / kTile + 1; t * kTile < e && t < n_tiles; ++t) recs.first_seg[t] = sg;
 }
 
 __global__ void fill_zero_kernel(float* __restrict__ p, int64_t count) {
@@ -156,7 +154,7 @@ template <int DT, bool FULL>
 __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int64_t t,
                                          int64_t s_lo, bool start_head, int lane,
                                          const int* endloc, int64_t tailseg, float* park,
-                                         float* __restrict__ seg_out, TileRec* __restrict__ recs,
+                                         float* __restrict__ seg_out, const TileRecs& recs,
                                          const RawRun<DT>* raw) {
   LaneRun<DT, FULL> R;
   R.load(s, endloc, lane, start_head, t * kTile, raw);
@@ -207,7 +205,7 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
     } else {
       // The tile's first segment end closes a segment that began in an
       // earlier tile: keep the part inside this tile for the fixup.
-      recs[t].head = lane > 0 ? combine(ex, pend) : pend;
+      recs.put(recs.head, t, lane > 0 ? combine(ex, pend) : pend);
     }
   }
   const unsigned long long end_mask = __ballot(any_end);
@@ -215,10 +213,10 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
   if (lane == kWave - 1) {
     const int flags = (start_head ? kStartHead : 0) | (end_mask ? kHasEnd : 0) |
                       (head_mask ? kHasHead : 0) | (have ? kTailOpen : 0);
-    recs[t].flags = flags;
-    recs[t].tail_seg = tailseg;
-    if (have) recs[t].tail = inc;
-    if (!start_head && !end_mask) recs[t].head = inc;
+    recs.flags[t] = flags;
+    recs.tail_seg[t] = tailseg;
+    if (have) recs.put(recs.tail, t, inc);
+    if (!start_head && !end_mask) recs.put(recs.head, t, inc);
   }
 }
 
@@ -232,11 +230,13 @@ __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
                                                          int64_t n_seg, int64_t n_tiles,
                                                          int64_t t_first, int64_t t_end,
                                                          float* __restrict__ seg_out,
-                                                         TileRec* __restrict__ recs) {
+                                                         TileRecs recs) {
   __shared__ int endloc_all[kWavesPerBlock][kTile];
   __shared__ float park_all[kWavesPerBlock][kRangeFields * kWave];
   __shared__ int64_t tailseg_all[kWavesPerBlock];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  // wave index made provably uniform, so per-tile loads go through the scalar unit
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
+  const int lane = threadIdx.x % kWave;
   const int64_t t = t_first + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
   const bool active = t < t_end;
   // Issue the sample loads first: their latency overlaps the setup below.
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
   int64_t s_lo = 0;
   bool start_head = false;
   if (active) {
-    s_lo = recs[t].first_seg;
+    s_lo = recs.first_seg[t];
     stage_ends<true>(off, n_seg, s.n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], seg_out);
     start_head = (off[s_lo] == t * kTile);
   }
@@ -271,10 +271,10 @@ __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
 //   the tile in which a crossing segment ends writes its tuple, pre (+) head.
 // Segments are shorter than a tile on average, so a walk is one step.
 __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restrict__ seg_out,
-                                 TileRec* __restrict__ recs) {
+                                 TileRecs recs) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n_tiles) return;
-  const int fl = recs[t].flags;
+  const int fl = recs.flags[t];
   // (The empty range is not an identity of combine in the positive form, whose
   // depths are relative to the ranges' end midpoints, so each walk starts from
   // its first part.)
@@ -282,8 +282,8 @@ __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restri
     Range acc;
     bool have = false, found = false;
     for (int64_t u = t - 1; u >= 0; --u) {
-      const bool h = (recs[u].flags & kHasHead) != 0;
-      const Range part = h ? recs[u].tail : recs[u].head;
+      const bool h = (recs.flags[u] & kHasHead) != 0;
+      const Range part = recs.get(h ? recs.tail : recs.head, u);
       acc = have ? combine(part, acc) : part;
       have = true;
       if (h) {
@@ -292,10 +292,10 @@ __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restri
       }
     }
     if (found) {
-      recs[t].pre = acc;
+      recs.put(recs.pre, t, acc);
       if (fl & kHasEnd) {
-        const int64_t sgi = recs[t].first_seg;
-        if (sgi >= 0 && sgi < n_seg) write_tuple(seg_out, n_seg, sgi, combine(acc, recs[t].head));
+        const int64_t sgi = recs.first_seg[t];
+        if (sgi >= 0 && sgi < n_seg) write_tuple(seg_out, n_seg, sgi, combine(acc, recs.get(recs.head, t)));
       }
     }
   }
@@ -303,12 +303,12 @@ __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restri
     Range acc;
     bool have = false;
     for (int64_t u = t + 1; u < n_tiles; ++u) {
-      const Range part = recs[u].head;
+      const Range part = recs.get(recs.head, u);
       acc = have ? combine(acc, part) : part;
       have = true;
-      if (recs[u].flags & kHasEnd) break;
+      if (recs.flags[u] & kHasEnd) break;
     }
-    if (have) recs[t].suf = acc;
+    if (have) recs.put(recs.suf, t, acc);
   }
 }
 
@@ -362,10 +362,10 @@ template <int DT, bool FULL>
 __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int64_t t,
                                          int64_t s_lo, int lane, const int* endloc,
                                          const float* __restrict__ gl, float* park,
-                                         const TileRec* __restrict__ recs,
+                                         const TileRecs& recs,
                                          const float* __restrict__ gseg, void* __restrict__ gsig_p,
                                          void* __restrict__ grgb_p, const RawRun<DT>* raw) {
-  const int flags = recs[t].flags;
+  const int flags = recs.flags[t];
   const bool start_head = (flags & kStartHead) != 0;
   const bool tail_open = (flags & kTailOpen) != 0;
   LaneRun<DT, FULL> R;
@@ -436,7 +436,10 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   Pre pc = pre_identity();
   if (!R.h0) {
     if (lane > 0 && exf) pc = ex;
-    else if (!start_head) pc = lane > 0 ? combine(pre_of(recs[t].pre), ex) : pre_of(recs[t].pre);
+    else if (!start_head) {
+      const Pre pt = pre_of(recs.get(recs.pre, t));
+      pc = lane > 0 ? combine(pt, ex) : pt;
+    }
   }
   // Suffix behind the lane's last sample, in its own frame (unused if that
   // sample ends its segment).
@@ -447,8 +450,9 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
       sc = sx;
       cseg = s_lo + sxseg;
     } else if (tail_open) {
-      sc = lane < kWave - 1 ? combine(sx, recs[t].suf) : recs[t].suf;
-      cseg = recs[t].tail_seg;
+      const Range st = recs.get(recs.suf, t);
+      sc = lane < kWave - 1 ? combine(sx, st) : st;
+      cseg = recs.tail_seg[t];
     }
   }
 
@@ -496,17 +500,23 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
       const int endj = endloc[lane * kRun + j];  // re-read: frees registers across the scans
       reverse_step(q, PT[j], PZ[j], endj >= 0, endj, s_lo, n_seg, gl, gseg, g, SG, SA, SF,
                    SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
-      if ((j & 1) == 0) {
-        if (DT == kF32)
-          *reinterpret_cast<float2*>(static_cast<float*>(gsig_p) + R.i0 + j) = make_float2(dsg[j], dsg[j + 1]);
-        else
-          *reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(gsig_p) + R.i0 + j) = pack2<DT>(dsg[j], dsg[j + 1]);
-      }
+      if (DT == kF32) {
+        // FP32: 16-byte stores per four samples (narrower stores leave lines
+        // partly written and cost extra write traffic).
+        if ((j & 3) == 0) {
+          float* gs = static_cast<float*>(gsig_p) + R.i0 + j;
+          float* gc = static_cast<float*>(grgb_p) + 3 * (R.i0 + j);
+          *reinterpret_cast<float4*>(gs) = make_float4(dsg[j], dsg[j + 1], dsg[j + 2], dsg[j + 3]);
 #pragma unroll
-      for (int qq = (3 * j + 1) / 2; qq < (3 * (j + 1) + 1) / 2; ++qq) {
-        if (DT == kF32)
-          *reinterpret_cast<float2*>(static_cast<float*>(grgb_p) + 3 * R.i0 + 2 * qq) = make_float2(dc[2 * qq], dc[2 * qq + 1]);
-        else
+          for (int v = 0; v < 3; ++v)
+            reinterpret_cast<float4*>(gc)[v] = make_float4(dc[3 * j + 4 * v], dc[3 * j + 4 * v + 1],
+                                                           dc[3 * j + 4 * v + 2], dc[3 * j + 4 * v + 3]);
+        }
+      } else {
+        if ((j & 1) == 0)
+          *reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(gsig_p) + R.i0 + j) = pack2<DT>(dsg[j], dsg[j + 1]);
+#pragma unroll
+        for (int qq = (3 * j + 1) / 2; qq < (3 * (j + 1) + 1) / 2; ++qq)
           *reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(grgb_p) + 3 * R.i0 + 2 * qq) = pack2<DT>(dc[2 * qq], dc[2 * qq + 1]);
       }
     }
@@ -572,13 +582,15 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
 template <int DT, bool FULL>
 __global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
     SamplesDev s, const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
-    int64_t t_first, int64_t t_end, const TileRec* __restrict__ recs,
+    int64_t t_first, int64_t t_end, TileRecs recs,
     const float* __restrict__ gseg, void* __restrict__ gsig_p, void* __restrict__ grgb_p) {
   __shared__ int endloc_all[kWavesPerBlock][kTile];
   __shared__ float gl_all[kWavesPerBlock][7 * kStagedSegs];
   __shared__ float park_all[kWavesPerBlock][kRangeFields * kWave];
   __shared__ int64_t tailseg_all[kWavesPerBlock];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  // wave index made provably uniform, so per-tile loads go through the scalar unit
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
+  const int lane = threadIdx.x % kWave;
   const int64_t t = t_first + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
   const bool active = t < t_end;
   RawRun<DT> raw;
@@ -591,7 +603,7 @@ __global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
   __syncthreads();
   int64_t s_lo = 0;
   if (active) {
-    s_lo = recs[t].first_seg;
+    s_lo = recs.first_seg[t];
     stage_ends<false>(off, n_seg, s.n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], nullptr,
                       gseg, gl);
   }
@@ -608,7 +620,7 @@ static inline unsigned grid_for(int64_t count, int block) {
 // Launches FULL tiles [0, n_full) and the ragged tile n_full (if any).
 template <int DT>
 static void launch_fwd_dt(const SamplesDev& s, const int64_t* off, int64_t n_seg, int64_t nt,
-                          float* seg_out, TileRec* recs, hipStream_t st) {
+                          float* seg_out, const TileRecs& recs, hipStream_t st) {
   const int64_t n_full = s.n / kTile;
   if (n_full > 0)
     hipLaunchKernelGGL((seg_fwd_kernel<DT, true>), dim3(grid_for(n_full, kWavesPerBlock)),
@@ -621,7 +633,7 @@ static void launch_fwd_dt(const SamplesDev& s, const int64_t* off, int64_t n_seg
 
 template <int DT>
 static void launch_bwd_dt(const SamplesDev& s, const int64_t* off, int64_t n_seg, int64_t nt,
-                          const TileRec* recs, const float* gseg, void* gs, void* gc,
+                          const TileRecs& recs, const float* gseg, void* gs, void* gc,
                           hipStream_t st) {
   const int64_t n_full = s.n / kTile;
   if (n_full > 0)
@@ -634,7 +646,7 @@ static void launch_bwd_dt(const SamplesDev& s, const int64_t* off, int64_t n_seg
 }
 
 hipError_t launch_segments_fwd(const SamplesDev& s, const int64_t* off, int64_t n_seg,
-                               float* seg_out, TileRec* recs, hipStream_t stream) {
+                               float* seg_out, void* workspace, hipStream_t stream) {
   if (n_seg == 0) return hipSuccess;
   if (s.n == 0) {
     hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(7 * n_seg, 256)), dim3(256), 0, stream,
@@ -642,7 +654,8 @@ hipError_t launch_segments_fwd(const SamplesDev& s, const int64_t* off, int64_t 
     return hipGetLastError();
   }
   const int64_t nt = num_tiles(s.n);
-  hipLaunchKernelGGL(plan_kernel, dim3(grid_for(nt, 256)), dim3(256), 0, stream, off, n_seg, nt,
+  const TileRecs recs = TileRecs::view(workspace, nt);
+  hipLaunchKernelGGL(plan_kernel, dim3(grid_for(n_seg, 256)), dim3(256), 0, stream, off, n_seg, nt,
                      recs);
   switch (s.dtype) {
     case kF32: launch_fwd_dt<kF32>(s, off, n_seg, nt, seg_out, recs, stream); break;
@@ -655,10 +668,11 @@ hipError_t launch_segments_fwd(const SamplesDev& s, const int64_t* off, int64_t 
 }
 
 hipError_t launch_segments_bwd(const SamplesDev& s, const int64_t* off, int64_t n_seg,
-                               const TileRec* recs, const float* grad_seg, void* grad_sigma,
+                               const void* workspace, const float* grad_seg, void* grad_sigma,
                                void* grad_rgb, hipStream_t stream) {
   if (s.n == 0 || n_seg == 0) return hipSuccess;
   const int64_t nt = num_tiles(s.n);
+  const TileRecs recs = TileRecs::view(const_cast<void*>(workspace), nt);
   switch (s.dtype) {
     case kF32: launch_bwd_dt<kF32>(s, off, n_seg, nt, recs, grad_seg, grad_sigma, grad_rgb, stream); break;
     case kBF16: launch_bwd_dt<kBF16>(s, off, n_seg, nt, recs, grad_seg, grad_sigma, grad_rgb, stream); break;

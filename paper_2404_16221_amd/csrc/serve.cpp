@@ -200,7 +200,7 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int
   int64_t* so = reinterpret_cast<int64_t*>(c); c += round256(8 * (n_seg + 1));
   int64_t* ids = reinterpret_cast<int64_t*>(c); c += round256(8 * n_seg);
   float* seg_out = reinterpret_cast<float*>(c); c += round256(4 * 7 * n_seg);
-  TileRec* recs = reinterpret_cast<TileRec*>(c);
+  void* recs = c;  // per-tile records of the segment composite
 
   hipError_t e = hipEventRecord(e0, st);
   if (e == hipSuccess) e = gen_fill(&p, dtype, ws, n_seg, sigma, rgb, t0, t1, so, ro, ids, st);

@@ -36,18 +36,6 @@ struct Range {
   float m0, m1;     // first and last sample midpoints
 };
 
-// Per-tile record kept in the workspace between forward and backward.
-struct alignas(16) TileRec {
-  int64_t first_seg;  // segment containing the tile's first sample (or the
-                      // first segment starting at it, empty ones included)
-  int64_t tail_seg;   // segment containing the tile's last sample
-  int32_t flags;
-  int32_t pad[3];
-  Range head;  // first sample .. first segment end (whole tile if none)
-  Range tail;  // last segment head .. last sample
-  Range pre;   // carry-in: the first sample's segment before this tile
-  Range suf;   // carry-in: the last sample's segment after this tile
-};
 constexpr int kStartHead = 1;  // first sample starts a segment
 constexpr int kHasEnd = 2;     // some segment ends inside the tile
 constexpr int kHasHead = 4;    // some segment starts inside the tile
@@ -510,5 +498,60 @@ __device__ __forceinline__ Range unpark_range(const float* __restrict__ lds, int
   r.m1 = lds[9 * kWave + lane]; r.tlo = lds[10 * kWave + lane];
   return r;
 }
+
+// Per-tile records kept in the workspace between forward and backward, as a
+// structure of arrays over tiles (a thread per tile reads them coalesced).
+// The tile count is padded to a multiple of kRecGroup so that every array
+// starts 256-byte aligned.
+constexpr int64_t kRecGroup = 64;
+constexpr size_t kRecBytesPerTile = 8 + 8 + 4 + 4 * sizeof(float) * kRangeFields;
+
+__host__ __device__ inline int64_t rec_stride(int64_t n_tiles) {
+  const int64_t nt = n_tiles > 0 ? n_tiles : 1;
+  return (nt + kRecGroup - 1) / kRecGroup * kRecGroup;
+}
+
+struct TileRecs {
+  int64_t* first_seg;  // segment containing the tile's first sample (or the
+                       // first segment starting at it, empty ones included)
+  int64_t* tail_seg;   // segment containing the tile's last sample
+  int32_t* flags;      // kStartHead | kHasEnd | kHasHead | kTailOpen
+  float* head;  // [kRangeFields][stride] first sample .. first segment end (whole tile if none)
+  float* tail;  // last segment head .. last sample
+  float* pre;   // carry-in: the first sample's segment before this tile
+  float* suf;   // carry-in: the last sample's segment after this tile
+  int64_t stride;
+
+  __host__ __device__ static TileRecs view(void* ws, int64_t n_tiles) {
+    TileRecs r;
+    r.stride = rec_stride(n_tiles);
+    char* p = static_cast<char*>(ws);
+    r.first_seg = reinterpret_cast<int64_t*>(p); p += 8 * r.stride;
+    r.tail_seg = reinterpret_cast<int64_t*>(p); p += 8 * r.stride;
+    r.flags = reinterpret_cast<int32_t*>(p); p += 4 * r.stride;
+    const int64_t rb = sizeof(float) * kRangeFields * r.stride;
+    r.head = reinterpret_cast<float*>(p); p += rb;
+    r.tail = reinterpret_cast<float*>(p); p += rb;
+    r.pre = reinterpret_cast<float*>(p); p += rb;
+    r.suf = reinterpret_cast<float*>(p);
+    return r;
+  }
+  __host__ __device__ static size_t bytes(int64_t n_tiles) { return kRecBytesPerTile * rec_stride(n_tiles); }
+
+  __device__ Range get(const float* a, int64_t t) const {
+    Range r;
+    r.tau = a[0 * stride + t]; r.cr = a[1 * stride + t]; r.cg = a[2 * stride + t];
+    r.cb = a[3 * stride + t]; r.A = a[4 * stride + t]; r.F = a[5 * stride + t];
+    r.B = a[6 * stride + t]; r.L = a[7 * stride + t]; r.m0 = a[8 * stride + t];
+    r.m1 = a[9 * stride + t]; r.tlo = a[10 * stride + t];
+    return r;
+  }
+  __device__ void put(float* a, int64_t t, const Range& r) const {
+    a[0 * stride + t] = r.tau; a[1 * stride + t] = r.cr; a[2 * stride + t] = r.cg;
+    a[3 * stride + t] = r.cb; a[4 * stride + t] = r.A; a[5 * stride + t] = r.F;
+    a[6 * stride + t] = r.B; a[7 * stride + t] = r.L; a[8 * stride + t] = r.m0;
+    a[9 * stride + t] = r.m1; a[10 * stride + t] = r.tlo;
+  }
+};
 
 }  // namespace xl
