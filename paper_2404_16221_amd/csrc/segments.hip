@@ -59,13 +59,14 @@ __device__ __forceinline__ void write_tuple(float* __restrict__ out, int64_t n_s
   out[6 * n_seg + s] = r.L;
 }
 
-// Stage the segment ends of tile t in LDS.  endloc[p] = local id (segment -
+// Stage the segment ends of tile t in LDS and return how many segments the
+// tile's window holds (from s_lo on).  endloc[p] = local id (segment -
 // s_lo) of the segment whose last sample is base + p, or -1.  Empty segments
 // owned by this tile get the identity tuple when WRITE_EMPTY.
 constexpr int kStagedSegs = 64;  // segment gradients staged in LDS per tile (backward)
 
 template <bool WRITE_EMPTY>
-__device__ __forceinline__ void stage_ends(const int64_t* __restrict__ off, int64_t n_seg,
+__device__ __forceinline__ int64_t stage_ends(const int64_t* __restrict__ off, int64_t n_seg,
                                            int64_t n, int64_t t, int64_t n_tiles, int64_t s_lo,
                                            int lane, int* __restrict__ endloc,
                                            int64_t* __restrict__ tailseg,
@@ -103,8 +104,10 @@ __device__ __forceinline__ void stage_ends(const int64_t* __restrict__ off, int6
       }
     }
     // Segments are sorted by start: once a lane's segment starts past the tile
-    // (or past the last segment), every later one does too.
-    if (!__all(in)) break;
+    // (or past the last segment), every later one does too.  Returns the number
+    // of segments in the tile's window.
+    const unsigned long long m = __ballot(in);
+    if (m != ~0ull) return j0 + __popcll(m);
   }
 }
 
@@ -152,12 +155,36 @@ struct LaneRun {
 
 template <int DT, bool FULL>
 __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int64_t t,
-                                         int64_t s_lo, bool start_head, int lane,
-                                         const int* endloc, int64_t tailseg, float* park,
+                                         int64_t s_lo, int64_t n_win, bool start_head, int lane,
+                                         int* endloc, int64_t tailseg, float* park,
                                          float* __restrict__ seg_out, const TileRecs& recs,
                                          const RawRun<DT>* raw) {
   LaneRun<DT, FULL> R;
   R.load(s, endloc, lane, start_head, t * kTile, raw);
+
+  // The segment ends are in registers now; their LDS space stages the tuples of
+  // segments that end in this tile (slot = local segment id), which are
+  // written to seg_out at the end with one coalesced store per component.
+  static_assert(7 * kStagedSegs + kStagedSegs <= kTile, "staging must fit the end table");
+  // (kept as int so the compiler orders it with the end table's reads)
+  int* obuf = endloc;                      // [7][kStagedSegs] float bits
+  int* ovalid = endloc + 7 * kStagedSegs;  // [kStagedSegs]
+  const bool staged = n_win <= kStagedSegs;  // uniform: no divergence on the path
+  if (lane < kStagedSegs) ovalid[lane] = 0;
+  auto emit = [&](int loc, const Range& r) {
+    if (staged) {
+      obuf[0 * kStagedSegs + loc] = __float_as_int(r.tau + r.tlo);
+      obuf[1 * kStagedSegs + loc] = __float_as_int(r.cr);
+      obuf[2 * kStagedSegs + loc] = __float_as_int(r.cg);
+      obuf[3 * kStagedSegs + loc] = __float_as_int(r.cb);
+      obuf[4 * kStagedSegs + loc] = __float_as_int(r.A);
+      obuf[5 * kStagedSegs + loc] = __float_as_int(fmaf(r.A, r.m0, r.F));
+      obuf[6 * kStagedSegs + loc] = __float_as_int(r.L);
+      ovalid[loc] = 1;
+    } else {
+      write_tuple(seg_out, n_seg, s_lo + loc, r);
+    }
+  };
 
   // Serial fold of the lane's samples; a head restarts the open range.  The
   // lane's first range, when it continues a segment from an earlier lane, is
@@ -181,7 +208,7 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
       any_end = true;
       if (R.ends[j] >= 0) {
         if (cur_head) {
-          write_tuple(seg_out, n_seg, s_lo + R.ends[j], cur);
+          emit(R.ends[j], cur);
         } else {
           park_range(park, lane, cur);
           pend_seg = R.ends[j];
@@ -201,12 +228,19 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
   if (has_pend) {
     const Range pend = unpark_range(park, lane);
     if (lane > 0 && exf) {
-      write_tuple(seg_out, n_seg, s_lo + pend_seg, combine(ex, pend));
+      emit(pend_seg, combine(ex, pend));
     } else {
       // The tile's first segment end closes a segment that began in an
       // earlier tile: keep the part inside this tile for the fixup.
       recs.put(recs.head, t, lane > 0 ? combine(ex, pend) : pend);
     }
+  }
+  // Staged tuples out (LDS operations of one wave complete in order).
+  __builtin_amdgcn_wave_barrier();
+  if (staged && lane < kStagedSegs && ovalid[lane]) {
+    const int64_t sg = s_lo + lane;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) seg_out[k * n_seg + sg] = __int_as_float(obuf[k * kStagedSegs + lane]);
   }
   const unsigned long long end_mask = __ballot(any_end);
   const unsigned long long head_mask = __ballot(any_head);
@@ -247,16 +281,16 @@ __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
   for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
   if (lane == 0) tailseg_all[wave] = -1;
   __syncthreads();
-  int64_t s_lo = 0;
+  int64_t s_lo = 0, n_win = 0;
   bool start_head = false;
   if (active) {
     s_lo = recs.first_seg[t];
-    stage_ends<true>(off, n_seg, s.n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], seg_out);
+    n_win = stage_ends<true>(off, n_seg, s.n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], seg_out);
     start_head = (off[s_lo] == t * kTile);
   }
   __syncthreads();
   if (!active) return;
-  fwd_tile<DT, FULL>(s, n_seg, t, s_lo, start_head, lane, endloc, tailseg_all[wave], park_all[wave],
+  fwd_tile<DT, FULL>(s, n_seg, t, s_lo, n_win, start_head, lane, endloc, tailseg_all[wave], park_all[wave],
                      seg_out, recs, &raw);
 }
 
