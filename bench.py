@@ -41,13 +41,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a
-    1 GiB device copy), or None if the kernel sources changed since."""
+def profile_fields():
+    """Fields of the committed counter summary of the dominant kernel (HBM
+    bytes from FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a
+    1 GiB device copy; VALU busy), or {} if the kernel sources changed since
+    the counters were taken."""
     path = os.path.join(HERE, TRAFFIC_PROFILE)
     if not os.path.exists(path):
-        return None
+        return {}
     fields = {}
     with open(path) as f:
         for line in f:
@@ -55,9 +56,13 @@ def measured_traffic():
                 k, v = line.strip()[2:].split(":", 1)
                 fields[k.strip()] = v.strip().strip("`")
     if fields.get("kernel_source_sha256") != kernel_source_hash():
-        return None
+        return {}
+    return fields
+
+
+def profile_number(key):
     try:
-        return float(fields["hbm_bytes_per_launch"])
+        return float(profile_fields()[key])
     except (KeyError, ValueError):
         return None
 
@@ -328,7 +333,8 @@ def main():
                   for k, v in results.items()},
         "roofline": {"bound": "hbm", "achieved": hr["seg_bwd_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": hr["seg_bwd_gbs"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if head == "bf16" else None,
+                     "traffic": profile_number("hbm_bytes_per_launch") if head == "bf16" else None,
+                     "valu_busy": profile_number("valu_busy") if head == "bf16" else None,
                      "algorithmic_bytes": hf.bytes_seg_bwd(),
                      "kernel": "seg_bwd_kernel", "step_achieved": hr["step_gbs"],
                      "step_frac": hr["step_gbs"] / HBM_PEAK_GBS},
