@@ -222,6 +222,9 @@ struct GenWs {
   int64_t* scan_tmp;  // scan scratch
   int32_t* err;       // [1] 1 if some ray had more segments than max_segs
   double* chunk_run;  // [R * chunks] position at the start of each chunk
+  int64_t* nchunk;    // [R]      chunks of each ray (scan input)
+  int64_t* chunk_base;// [R + 1]  first compact chunk of each ray (scan output)
+  int32_t* chunk_ray; // [R * chunks] ray of each compact chunk
 };
 
 __global__ void gen_struct_kernel(GenDev g, GenWs w) {
@@ -257,6 +260,15 @@ __global__ void gen_struct_kernel(GenDev g, GenWs w) {
   }
   w.nseg[r] = k + 1;
   w.nseg64[r] = k + 1;
+  w.nchunk[r] = (s.count + kChunk - 1) / kChunk;
+}
+
+// Ray of every compact chunk (the chunks of all rays, ray after ray).
+__global__ void chunk_map_kernel(GenDev g, GenWs w) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= g.n_rays) return;
+  const int64_t b = w.chunk_base[r], e = w.chunk_base[r + 1];
+  for (int64_t i = b; i < e; ++i) w.chunk_ray[i] = static_cast<int32_t>(r);
 }
 
 // Segments per box in each block of kRayBlock rays (box-major layout).
@@ -368,15 +380,17 @@ __device__ __forceinline__ void store_group(void* sigma, void* rgb, float* t_sta
   }
 }
 
-// One thread per (chunk, ray): chunk c of ray r is samples [c kChunk, (c + 1)
-// kChunk) along the ray; rays index the lanes so a wave holds chunk c of 64
-// rays and every active lane does at most kChunk samples.
+// One thread per compact chunk: chunk c of ray r is samples [c kChunk,
+// (c + 1) kChunk) along the ray, and the chunks of all rays are numbered ray
+// after ray, so every thread below the total has a full chunk of work (but a
+// ray's last) and the threads above it leave at once.
 template <int DT>
 __global__ void gen_fill_kernel(GenDev g, GenWs w, void* __restrict__ sigma, void* __restrict__ rgb,
                                 float* __restrict__ t_start, float* __restrict__ t_end) {
-  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
-  if (r >= g.n_rays) return;
+  const int64_t ci = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (ci >= w.chunk_base[g.n_rays]) return;
+  const int64_t r = w.chunk_ray[ci];
+  const int c = static_cast<int>(ci - w.chunk_base[r]);
   const uint64_t key = mix64(g.seedkey + static_cast<uint64_t>(g.ray0 + r) * kGamma);
   const uint64_t span = static_cast<uint64_t>(g.n_max - g.n_min + 1);
   const int count = g.n_min + static_cast<int32_t>(((draw(key, 3) >> 32) * span) >> 32);
@@ -520,7 +534,7 @@ hipError_t scan_exclusive(const int64_t* in, int64_t* out, int64_t n, int64_t* t
 struct GenLayout {
   int64_t R, M, K, nblk, RM, C;
   size_t scan_elems;  // scan scratch, enough for the longest of the three scans
-  size_t off[16];
+  size_t off[19];
   size_t bytes;
 };
 
@@ -554,9 +568,12 @@ static GenLayout layout(const xl_gen_params* p) {
       sizeof(int64_t) * L.scan_elems,  // scan_tmp
       sizeof(int32_t) * 4,             // err
       sizeof(double) * L.R * L.C,      // chunk_run
+      sizeof(int64_t) * L.R,           // nchunk
+      sizeof(int64_t) * (L.R + 1),     // chunk_base
+      sizeof(int32_t) * L.R * L.C,     // chunk_ray
   };
   size_t o = 0;
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 0; i < 19; ++i) {
     L.off[i] = o;
     o += (sizes[i] + 255) & ~static_cast<size_t>(255);
   }
@@ -583,6 +600,9 @@ static GenWs views(const GenLayout& L, void* ws) {
   w.scan_tmp = reinterpret_cast<int64_t*>(b + L.off[13]);
   w.err = reinterpret_cast<int32_t*>(b + L.off[14]);
   w.chunk_run = reinterpret_cast<double*>(b + L.off[15]);
+  w.nchunk = reinterpret_cast<int64_t*>(b + L.off[16]);
+  w.chunk_base = reinterpret_cast<int64_t*>(b + L.off[17]);
+  w.chunk_ray = reinterpret_cast<int32_t*>(b + L.off[18]);
   return w;
 }
 
@@ -623,13 +643,20 @@ hipError_t gen_plan(const xl_gen_params* p, void* ws, hipStream_t st, int64_t* n
   const GenDev g = dev_params(p, L);
   hipError_t e = hipMemsetAsync(w.err, 0, sizeof(int32_t), st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gen_struct_kernel, dim3(blocks(L.R, 128)), dim3(128), 0, st, g, w);
-  hipLaunchKernelGGL(block_hist_kernel, dim3(static_cast<unsigned>(L.nblk)), dim3(kRayBlock), 0, st,
-                     g, w, L.nblk, static_cast<int>(L.K));
+  const bool any = L.R > 0;  // (an empty grid is not a valid launch)
+  if (any) {
+    hipLaunchKernelGGL(gen_struct_kernel, dim3(blocks(L.R, 128)), dim3(128), 0, st, g, w);
+    hipLaunchKernelGGL(block_hist_kernel, dim3(static_cast<unsigned>(L.nblk)), dim3(kRayBlock), 0, st,
+                       g, w, L.nblk, static_cast<int>(L.K));
+  }
   if ((e = scan_exclusive(w.nseg64, w.ray_off, L.R, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
+  if ((e = scan_exclusive(w.nchunk, w.chunk_base, L.R, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
+  if (any) hipLaunchKernelGGL(chunk_map_kernel, dim3(blocks(L.R, 128)), dim3(128), 0, st, g, w);
   if ((e = scan_exclusive(w.blk_cnt, w.blk_base, L.K * L.nblk, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(gen_rank_kernel, dim3(static_cast<unsigned>(L.nblk)), dim3(kRayBlock), 0, st, g,
-                     w, L.nblk, static_cast<int>(L.K));
+  if (any)
+    hipLaunchKernelGGL(gen_rank_kernel, dim3(static_cast<unsigned>(L.nblk)), dim3(kRayBlock), 0, st, g,
+                       w, L.nblk, static_cast<int>(L.K));
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(&h[0], w.ray_off + L.R, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
     return e;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
@@ -653,8 +680,8 @@ hipError_t gen_fill(const xl_gen_params* p, int dtype, void* ws, int64_t n_seg, 
   const GenLayout L = layout(p);
   const GenWs w = views(L, ws);
   const GenDev g = dev_params(p, L);
-  const dim3 grid(blocks(L.R, 128), static_cast<unsigned>(L.C));
-  switch (dtype) {
+  const dim3 grid(blocks(L.R * L.C, 128));  // at least the compact chunk count
+  if (L.R > 0) switch (dtype) {
     case kF32:
       hipLaunchKernelGGL(gen_fill_kernel<kF32>, grid, dim3(128), 0, st, g, w, sigma, rgb, t_start, t_end);
       break;
