@@ -49,14 +49,18 @@ __global__ void fill_zero_kernel(float* __restrict__ p, int64_t count) {
 }
 
 __device__ __forceinline__ void write_tuple(float* __restrict__ out, int64_t n_seg, int64_t s,
-                                            const Range& r) {
-  out[s] = r.tau + r.tlo;
+                                            const Range& r, float tlo = 0.f) {
+  out[s] = r.tau + tlo;
   out[n_seg + s] = r.cr;
   out[2 * n_seg + s] = r.cg;
   out[3 * n_seg + s] = r.cb;
   out[4 * n_seg + s] = r.A;
   out[5 * n_seg + s] = fmaf(r.A, r.m0, r.F);  // D = sum w m
   out[6 * n_seg + s] = r.L;
+}
+__device__ __forceinline__ void write_tuple(float* __restrict__ out, int64_t n_seg, int64_t s,
+                                            const Part& p) {
+  write_tuple(out, n_seg, s, p.r, p.tlo);
 }
 
 // Stage the segment ends of tile t in LDS and return how many segments the
@@ -173,7 +177,7 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
   if (lane < kStagedSegs) ovalid[lane] = 0;
   auto emit = [&](int loc, const Range& r) {
     if (staged) {
-      obuf[0 * kStagedSegs + loc] = __float_as_int(r.tau + r.tlo);
+      obuf[0 * kStagedSegs + loc] = __float_as_int(r.tau);
       obuf[1 * kStagedSegs + loc] = __float_as_int(r.cr);
       obuf[2 * kStagedSegs + loc] = __float_as_int(r.cg);
       obuf[3 * kStagedSegs + loc] = __float_as_int(r.cb);
@@ -313,11 +317,11 @@ __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restri
   // depths are relative to the ranges' end midpoints, so each walk starts from
   // its first part.)
   if (!(fl & kStartHead)) {
-    Range acc;
+    Part acc;
     bool have = false, found = false;
     for (int64_t u = t - 1; u >= 0; --u) {
       const bool h = (recs.flags[u] & kHasHead) != 0;
-      const Range part = recs.get(h ? recs.tail : recs.head, u);
+      const Part part = recs.get(h ? recs.tail : recs.head, u);
       acc = have ? combine(part, acc) : part;
       have = true;
       if (h) {
@@ -334,10 +338,10 @@ __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restri
     }
   }
   if (fl & kTailOpen) {
-    Range acc;
+    Part acc;
     bool have = false;
     for (int64_t u = t + 1; u < n_tiles; ++u) {
-      const Range part = recs.get(recs.head, u);
+      const Part part = recs.get(recs.head, u);
       acc = have ? combine(acc, part) : part;
       have = true;
       if (recs.flags[u] & kHasEnd) break;
@@ -471,7 +475,7 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   if (!R.h0) {
     if (lane > 0 && exf) pc = ex;
     else if (!start_head) {
-      const Pre pt = pre_of(recs.get(recs.pre, t));
+      const Pre pt = pre_of(range_of(recs.get(recs.pre, t)));
       pc = lane > 0 ? combine(pt, ex) : pt;
     }
   }
@@ -484,14 +488,14 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
       sc = sx;
       cseg = s_lo + sxseg;
     } else if (tail_open) {
-      const Range st = recs.get(recs.suf, t);
+      const Range st = range_of(recs.get(recs.suf, t));
       sc = lane < kWave - 1 ? combine(sx, st) : st;
       cseg = recs.tail_seg[t];
     }
   }
 
   // Samples before the lane's first head continue the carried prefix.
-  const float Tp = exp_neg(pc.tau + pc.tlo);
+  const float Tp = exp_neg(pc.tau);
   float PT[kRun], PZ[kRun];
 #pragma unroll
   for (int j = 0; j < kRun; ++j) {
@@ -522,7 +526,7 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
     const float Tq = PT[kRun - 1] * R.x[kRun - 1].e;
     SG = Tq * fmaf(g[3], sc.cb, fmaf(g[2], sc.cg, g[1] * sc.cr));
     SA = Tq * sc.A; SF = Tq * sc.F; SL = Tq * Tq * sc.L; mf = sc.m0;
-    TN = Tq * exp_neg(sc.tau + sc.tlo);
+    TN = Tq * exp_neg(sc.tau);
   }
   if constexpr (FULL) {
     // Full tile: the lane's samples stay in registers from pass 1 (no
@@ -614,9 +618,9 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
 }
 
 template <int DT, bool FULL>
-__global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
-    SamplesDev s, const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
-    int64_t t_first, int64_t t_end, TileRecs recs,
+__device__ __forceinline__ void seg_bwd_body(
+    const SamplesDev& s, const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
+    int64_t t_first, int64_t t_end, const TileRecs& recs,
     const float* __restrict__ gseg, void* __restrict__ gsig_p, void* __restrict__ grgb_p) {
   __shared__ int endloc_all[kWavesPerBlock][kTile];
   __shared__ float gl_all[kWavesPerBlock][7 * kStagedSegs];
@@ -647,6 +651,23 @@ __global__ __launch_bounds__(kBlock) void seg_bwd_kernel(
                      &raw);
 }
 
+// Full tiles, held to 128 registers so that four waves share each SIMD; the
+// ragged last tile has its own unconstrained instance.
+template <int DT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void seg_bwd_kernel(
+    SamplesDev s, const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
+    int64_t t_first, int64_t t_end, TileRecs recs,
+    const float* __restrict__ gseg, void* __restrict__ gsig_p, void* __restrict__ grgb_p) {
+  seg_bwd_body<DT, true>(s, off, n_seg, n_tiles, t_first, t_end, recs, gseg, gsig_p, grgb_p);
+}
+template <int DT>
+__global__ __launch_bounds__(kBlock) void seg_bwd_tail_kernel(
+    SamplesDev s, const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
+    int64_t t_first, int64_t t_end, TileRecs recs,
+    const float* __restrict__ gseg, void* __restrict__ gsig_p, void* __restrict__ grgb_p) {
+  seg_bwd_body<DT, false>(s, off, n_seg, n_tiles, t_first, t_end, recs, gseg, gsig_p, grgb_p);
+}
+
 static inline unsigned grid_for(int64_t count, int block) {
   return static_cast<unsigned>((count + block - 1) / block);
 }
@@ -671,11 +692,11 @@ static void launch_bwd_dt(const SamplesDev& s, const int64_t* off, int64_t n_seg
                           hipStream_t st) {
   const int64_t n_full = s.n / kTile;
   if (n_full > 0)
-    hipLaunchKernelGGL((seg_bwd_kernel<DT, true>), dim3(grid_for(n_full, kWavesPerBlock)),
+    hipLaunchKernelGGL((seg_bwd_kernel<DT>), dim3(grid_for(n_full, kWavesPerBlock)),
                        dim3(kBlock), 0, st, s, off, n_seg, nt, static_cast<int64_t>(0), n_full, recs,
                        gseg, gs, gc);
   if (n_full < nt)
-    hipLaunchKernelGGL((seg_bwd_kernel<DT, false>), dim3(1), dim3(kBlock), 0, st, s, off, n_seg, nt,
+    hipLaunchKernelGGL((seg_bwd_tail_kernel<DT>), dim3(1), dim3(kBlock), 0, st, s, off, n_seg, nt,
                        n_full, nt, recs, gseg, gs, gc);
 }
 

@@ -27,7 +27,6 @@ enum Dtype : int { kF32 = 0, kBF16 = 1, kF16 = 2 };
 
 struct Range {
   float tau;        // sum of optical depths sigma * delta; transmittance is exp(-tau)
-  float tlo;        // compensation: the exact sum is tau + tlo (see two_sum)
   float cr, cg, cb; // colour
   float A;          // opacity (sum of weights)
   float F;          // sum w (m - m0)
@@ -43,7 +42,7 @@ constexpr int kTailOpen = 8;   // the last sample's segment continues past the t
 
 __device__ __forceinline__ Range range_identity() {
   Range r;
-  r.tau = 0.f; r.tlo = 0.f; r.cr = r.cg = r.cb = 0.f; r.A = 0.f;
+  r.tau = 0.f; r.cr = r.cg = r.cb = 0.f; r.A = 0.f;
   r.F = 0.f; r.B = 0.f; r.L = 0.f; r.m0 = 0.f; r.m1 = 0.f;
   return r;
 }
@@ -53,12 +52,15 @@ __device__ __forceinline__ float exp_neg(float tau) {
 }
 
 // Error-free transformation of a sum (Knuth's TwoSum): a + b = s + e exactly,
-// for any ordering of magnitudes.  Optical depths are summed in two levels:
-// plainly over a lane's kRun samples, then, whenever two ranges are joined
-// (lanes, tiles, the fixup), as a pair (tau, tlo) with the rounding error of
-// every join kept in tlo.  A segment's log-transmittance thus carries at most
-// kRun roundings per lane-sized block and no error growth across blocks,
-// however many samples it spans.
+// for any ordering of magnitudes.  Optical depths are summed in two levels.
+// Inside a tile the sum is plain: serial over a lane's kRun samples, then a
+// tree of log2(kWave) levels in the wave scan, so a tile's partial depth has
+// at most kRun - 1 + 6 roundings on any path.  Across tiles (the fixup) and
+// across segments (the merge), where the number of joins grows with the
+// length of a segment or ray, partial depths are joined as pairs (tau, tlo)
+// that keep the rounding error of every join in tlo.  A segment's
+// log-transmittance therefore has a relative error bounded independently of
+// how many samples and tiles it spans.
 __device__ __forceinline__ float two_sum(float a, float b, float& e) {
   const float s = a + b;
   const float bb = s - a;
@@ -71,14 +73,8 @@ __device__ __forceinline__ void add_tau(float& tau, float& tlo, float hi, float 
   tlo += e + lo;
 }
 
-// x then y (x in front).  Transmittance is always taken as exp(-sum tau), one
-// rounding, never as a running product of per-sample factors (whose roundings
-// would add up over long segments).
-__device__ __forceinline__ Range combine(const Range& x, const Range& y) {
-  Range r;
-  const float T1 = exp_neg(x.tau + x.tlo);
-  r.tau = x.tau; r.tlo = x.tlo;
-  add_tau(r.tau, r.tlo, y.tau, y.tlo);
+// Every field but the optical depth, x then y, where T1 is x's transmittance.
+__device__ __forceinline__ void combine_rest(Range& r, const Range& x, const Range& y, float T1) {
   r.cr = fmaf(T1, y.cr, x.cr);
   r.cg = fmaf(T1, y.cg, x.cg);
   r.cb = fmaf(T1, y.cb, x.cb);
@@ -89,7 +85,38 @@ __device__ __forceinline__ Range combine(const Range& x, const Range& y) {
   r.L = fmaf(T1 * T1, y.L, fmaf(2.f * T1, cross, x.L));
   r.m0 = x.m0;
   r.m1 = y.m1;
+}
+
+// x then y (x in front), inside a tile.  Transmittance across lanes is taken
+// as exp(-sum tau), one rounding, never as a running product of per-sample
+// factors (whose roundings would add up).
+__device__ __forceinline__ Range combine(const Range& x, const Range& y) {
+  Range r;
+  r.tau = x.tau + y.tau;
+  combine_rest(r, x, y, exp_neg(x.tau));
   return r;
+}
+
+// A range kept across tiles: its optical depth is the compensated pair
+// r.tau + tlo.
+struct Part {
+  Range r;
+  float tlo;
+};
+__device__ __forceinline__ Part part_of(const Range& r) { return Part{r, 0.f}; }
+// The in-tile form (the pair rounded to one float).
+__device__ __forceinline__ Range range_of(const Part& p) {
+  Range r = p.r;
+  r.tau = p.r.tau + p.tlo;
+  return r;
+}
+__device__ __forceinline__ Part combine(const Part& x, const Part& y) {
+  Part p;
+  p.r.tau = x.r.tau;
+  p.tlo = x.tlo;
+  add_tau(p.r.tau, p.tlo, y.r.tau, y.tlo);
+  combine_rest(p.r, x.r, y.r, exp_neg(x.r.tau + x.tlo));
+  return p;
 }
 
 // One sample, reduced to what the composite needs.
@@ -120,21 +147,10 @@ __device__ __forceinline__ Smp make_sample(float sigma, float c0, float c1, floa
   return s;
 }
 
-__device__ __forceinline__ Range range_of(const Smp& s) {
-  Range r;
-  r.tau = s.tau; r.tlo = 0.f;
-  r.cr = s.alpha * s.c0; r.cg = s.alpha * s.c1; r.cb = s.alpha * s.c2;
-  r.A = s.alpha; r.F = 0.f; r.B = 0.f;
-  r.L = s.alpha * s.alpha * s.delta * (1.f / 3.f);
-  r.m0 = s.m; r.m1 = s.m;
-  return r;
-}
-
 // Restart r as the empty range at midpoint m when `head` (a segment starts at
 // the next sample appended); Tr is the range's transmittance.
 __device__ __forceinline__ void restart_if(bool head, Range& r, float& Tr, float m) {
   r.tau = head ? 0.f : r.tau;
-  r.tlo = head ? 0.f : r.tlo;
   r.cr = head ? 0.f : r.cr; r.cg = head ? 0.f : r.cg; r.cb = head ? 0.f : r.cb;
   r.A = head ? 0.f : r.A;
   r.F = head ? 0.f : r.F;
@@ -158,7 +174,7 @@ __device__ __forceinline__ void append(Range& r, float& Tr, const Smp& s) {
   r.cg = fmaf(w, s.c1, r.cg);
   r.cb = fmaf(w, s.c2, r.cb);
   r.A += w;
-  r.tau += s.tau;  // at most kRun terms; ranges are joined with two_sum
+  r.tau += s.tau;  // at most kRun terms (see two_sum)
   r.m1 = s.m;
   Tr *= s.e;
 }
@@ -337,15 +353,14 @@ struct RawRun {
 // The part of a range that the backward's prefix needs: optical depth,
 // opacity and the back-relative depth at the last midpoint.
 struct Pre {
-  float tau, tlo, A, B, m1;
+  float tau, A, B, m1;
 };
-__device__ __forceinline__ Pre pre_of(const Range& r) { return Pre{r.tau, r.tlo, r.A, r.B, r.m1}; }
-__device__ __forceinline__ Pre pre_identity() { return Pre{0.f, 0.f, 0.f, 0.f, 0.f}; }
+__device__ __forceinline__ Pre pre_of(const Range& r) { return Pre{r.tau, r.A, r.B, r.m1}; }
+__device__ __forceinline__ Pre pre_identity() { return Pre{0.f, 0.f, 0.f, 0.f}; }
 __device__ __forceinline__ Pre combine(const Pre& x, const Pre& y) {
-  const float T1 = exp_neg(x.tau + x.tlo);
+  const float T1 = exp_neg(x.tau);
   Pre r;
-  r.tau = x.tau; r.tlo = x.tlo;
-  add_tau(r.tau, r.tlo, y.tau, y.tlo);
+  r.tau = x.tau + y.tau;
   r.A = fmaf(T1, y.A, x.A);
   r.B = fmaf(T1, y.B, fmaf(x.A, y.m1 - x.m1, x.B));
   r.m1 = y.m1;
@@ -356,7 +371,7 @@ __device__ __forceinline__ Pre combine(const Pre& x, const Pre& y) {
 template <typename Op>
 __device__ __forceinline__ Range map_fields(const Range& x, Op op) {
   Range y;
-  y.tau = op(x.tau); y.tlo = op(x.tlo);
+  y.tau = op(x.tau);
   y.cr = op(x.cr); y.cg = op(x.cg); y.cb = op(x.cb);
   y.A = op(x.A); y.F = op(x.F); y.B = op(x.B); y.L = op(x.L);
   y.m0 = op(x.m0); y.m1 = op(x.m1);
@@ -364,19 +379,18 @@ __device__ __forceinline__ Range map_fields(const Range& x, Op op) {
 }
 template <typename Op>
 __device__ __forceinline__ Pre map_fields(const Pre& x, Op op) {
-  return Pre{op(x.tau), op(x.tlo), op(x.A), op(x.B), op(x.m1)};
+  return Pre{op(x.tau), op(x.A), op(x.B), op(x.m1)};
 }
 __device__ __forceinline__ Range select(bool c, const Range& a, const Range& b) {
   Range r;
-  r.tau = c ? a.tau : b.tau; r.tlo = c ? a.tlo : b.tlo;
+  r.tau = c ? a.tau : b.tau;
   r.cr = c ? a.cr : b.cr; r.cg = c ? a.cg : b.cg; r.cb = c ? a.cb : b.cb;
   r.A = c ? a.A : b.A; r.F = c ? a.F : b.F; r.B = c ? a.B : b.B; r.L = c ? a.L : b.L;
   r.m0 = c ? a.m0 : b.m0; r.m1 = c ? a.m1 : b.m1;
   return r;
 }
 __device__ __forceinline__ Pre select(bool c, const Pre& a, const Pre& b) {
-  return Pre{c ? a.tau : b.tau, c ? a.tlo : b.tlo, c ? a.A : b.A, c ? a.B : b.B,
-             c ? a.m1 : b.m1};
+  return Pre{c ? a.tau : b.tau, c ? a.A : b.A, c ? a.B : b.B, c ? a.m1 : b.m1};
 }
 
 // Lane moves.  DPP (GFX9 controls) moves a register between lanes inside the
@@ -483,19 +497,19 @@ __device__ __forceinline__ void scan_down(Range& x, bool& f, int& seg, int lane)
 }
 
 // A range parked in LDS, structure of arrays over the 64 lanes of a wave.
-constexpr int kRangeFields = 11;
+constexpr int kRangeFields = 10;
 __device__ __forceinline__ void park_range(float* __restrict__ lds, int lane, const Range& r) {
   lds[0 * kWave + lane] = r.tau; lds[1 * kWave + lane] = r.cr; lds[2 * kWave + lane] = r.cg;
   lds[3 * kWave + lane] = r.cb; lds[4 * kWave + lane] = r.A; lds[5 * kWave + lane] = r.F;
   lds[6 * kWave + lane] = r.B; lds[7 * kWave + lane] = r.L; lds[8 * kWave + lane] = r.m0;
-  lds[9 * kWave + lane] = r.m1; lds[10 * kWave + lane] = r.tlo;
+  lds[9 * kWave + lane] = r.m1;
 }
 __device__ __forceinline__ Range unpark_range(const float* __restrict__ lds, int lane) {
   Range r;
   r.tau = lds[0 * kWave + lane]; r.cr = lds[1 * kWave + lane]; r.cg = lds[2 * kWave + lane];
   r.cb = lds[3 * kWave + lane]; r.A = lds[4 * kWave + lane]; r.F = lds[5 * kWave + lane];
   r.B = lds[6 * kWave + lane]; r.L = lds[7 * kWave + lane]; r.m0 = lds[8 * kWave + lane];
-  r.m1 = lds[9 * kWave + lane]; r.tlo = lds[10 * kWave + lane];
+  r.m1 = lds[9 * kWave + lane];
   return r;
 }
 
@@ -504,7 +518,8 @@ __device__ __forceinline__ Range unpark_range(const float* __restrict__ lds, int
 // The tile count is padded to a multiple of kRecGroup so that every array
 // starts 256-byte aligned.
 constexpr int64_t kRecGroup = 64;
-constexpr size_t kRecBytesPerTile = 8 + 8 + 4 + 4 * sizeof(float) * kRangeFields;
+constexpr int kPartFields = kRangeFields + 1;
+constexpr size_t kRecBytesPerTile = 8 + 8 + 4 + 4 * sizeof(float) * kPartFields;
 
 __host__ __device__ inline int64_t rec_stride(int64_t n_tiles) {
   const int64_t nt = n_tiles > 0 ? n_tiles : 1;
@@ -529,7 +544,7 @@ struct TileRecs {
     r.first_seg = reinterpret_cast<int64_t*>(p); p += 8 * r.stride;
     r.tail_seg = reinterpret_cast<int64_t*>(p); p += 8 * r.stride;
     r.flags = reinterpret_cast<int32_t*>(p); p += 4 * r.stride;
-    const int64_t rb = sizeof(float) * kRangeFields * r.stride;
+    const int64_t rb = sizeof(float) * kPartFields * r.stride;
     r.head = reinterpret_cast<float*>(p); p += rb;
     r.tail = reinterpret_cast<float*>(p); p += rb;
     r.pre = reinterpret_cast<float*>(p); p += rb;
@@ -538,20 +553,23 @@ struct TileRecs {
   }
   __host__ __device__ static size_t bytes(int64_t n_tiles) { return kRecBytesPerTile * rec_stride(n_tiles); }
 
-  __device__ Range get(const float* a, int64_t t) const {
-    Range r;
+  __device__ Part get(const float* a, int64_t t) const {
+    Part p;
+    Range& r = p.r;
     r.tau = a[0 * stride + t]; r.cr = a[1 * stride + t]; r.cg = a[2 * stride + t];
     r.cb = a[3 * stride + t]; r.A = a[4 * stride + t]; r.F = a[5 * stride + t];
     r.B = a[6 * stride + t]; r.L = a[7 * stride + t]; r.m0 = a[8 * stride + t];
-    r.m1 = a[9 * stride + t]; r.tlo = a[10 * stride + t];
-    return r;
+    r.m1 = a[9 * stride + t]; p.tlo = a[10 * stride + t];
+    return p;
   }
-  __device__ void put(float* a, int64_t t, const Range& r) const {
+  __device__ void put(float* a, int64_t t, const Part& p) const {
+    const Range& r = p.r;
     a[0 * stride + t] = r.tau; a[1 * stride + t] = r.cr; a[2 * stride + t] = r.cg;
     a[3 * stride + t] = r.cb; a[4 * stride + t] = r.A; a[5 * stride + t] = r.F;
     a[6 * stride + t] = r.B; a[7 * stride + t] = r.L; a[8 * stride + t] = r.m0;
-    a[9 * stride + t] = r.m1; a[10 * stride + t] = r.tlo;
+    a[9 * stride + t] = r.m1; a[10 * stride + t] = p.tlo;
   }
+  __device__ void put(float* a, int64_t t, const Range& r) const { put(a, t, part_of(r)); }
 };
 
 }  // namespace xl
