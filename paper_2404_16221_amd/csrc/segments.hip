@@ -146,7 +146,8 @@ struct LaneRun {
     if constexpr (FULL) {
       raw->decode(sg, c, a, b);
     } else {
-      if (cnt > 0) load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, i0, cnt, sg, c, a, b);
+      // Missing samples are zeros (finite, as the scans' masked joins need).
+      load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, i0, cnt, sg, c, a, b);
     }
 #pragma unroll
     for (int j = 0; j < kRun; ++j) {
@@ -351,7 +352,9 @@ __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restri
 }
 
 // One step of the backward's reverse sweep for sample q (see bwd_tile).  g
-// holds the ending segment's tuple gradient with g[6] doubled.
+// holds the ending segment's tuple gradient with g[6] doubled.  BRANCH: the
+// restart at a segment end is a branch around rare work rather than selects.
+template <bool BRANCH>
 __device__ __forceinline__ void reverse_step(const Smp& q, float PTj, float PZj, bool endf,
                                              int endloc_j, int64_t s_lo, int64_t n_seg,
                                              const float* __restrict__ gl,
@@ -360,19 +363,28 @@ __device__ __forceinline__ void reverse_step(const Smp& q, float PTj, float PZj,
                                              float& TN, float& dsg, float& dc0, float& dc1,
                                              float& dc2) {
   const float Ti1 = PTj * q.e;
-  SG = endf ? 0.f : SG;
-  SA = endf ? 0.f : SA; SF = endf ? 0.f : SF; SL = endf ? 0.f : SL;
-  mf = endf ? q.m : mf;
-  TN = endf ? Ti1 : TN;
-  if (endloc_j >= 0) {
-    if (endloc_j < kStagedSegs) {
+  if (!BRANCH) {
+    SG = endf ? 0.f : SG;
+    SA = endf ? 0.f : SA; SF = endf ? 0.f : SF; SL = endf ? 0.f : SL;
+    mf = endf ? q.m : mf;
+    TN = endf ? Ti1 : TN;
+  }
+  if (!BRANCH || endf) {  // sample j ends its segment: the suffix restarts
+    if (BRANCH) {
+      SG = 0.f; SA = 0.f; SF = 0.f; SL = 0.f;
+      mf = q.m;
+      TN = Ti1;
+    }
+    if (endloc_j >= 0) {
+      if (endloc_j < kStagedSegs) {
 #pragma unroll
-      for (int k = 0; k < 7; ++k) g[k] = gl[k * kStagedSegs + endloc_j];
-    } else {
-      const int64_t sgi = s_lo + endloc_j;
+        for (int k = 0; k < 7; ++k) g[k] = gl[k * kStagedSegs + endloc_j];
+      } else {
+        const int64_t sgi = s_lo + endloc_j;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) g[k] = gseg[k * n_seg + sgi];
-      g[6] = 2.f * gseg[6 * n_seg + sgi];
+        for (int k = 0; k < 6; ++k) g[k] = gseg[k * n_seg + sgi];
+        g[6] = 2.f * gseg[6 * n_seg + sgi];
+      }
     }
   }
   const float w = PTj * q.alpha;
@@ -398,14 +410,36 @@ __device__ __forceinline__ void reverse_step(const Smp& q, float PTj, float PZj,
 
 template <int DT, bool FULL>
 __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int64_t t,
+                                         int flags, int64_t ts,
                                          int64_t s_lo, int lane, const int* endloc,
                                          const float* __restrict__ gl, float* park,
                                          const TileRecs& recs,
                                          const float* __restrict__ gseg, void* __restrict__ gsig_p,
                                          void* __restrict__ grgb_p, const RawRun<DT>* raw) {
-  const int flags = recs.flags[t];
   const bool start_head = (flags & kStartHead) != 0;
   const bool tail_open = (flags & kTailOpen) != 0;
+  // The 16-bit forms are bound by instruction issue and latency; the FP32 form
+  // moves half again as many bytes and sits at the register limit.  Only the
+  // former spend registers on requesting the tile carries before the lane
+  // work and on branching around rare restarts (measured: each helps them by
+  // a few percent and slows the FP32 form by more).
+  constexpr bool kEager = DT != kF32;
+  // Tile-uniform carries: the prefix into the tile, the suffix out of it and
+  // the gradient of the segment that leaves it (g_L doubled, as in the sweep).
+  Part pre_t, suf_t;
+  float gt[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  auto load_carries = [&]() {
+    if (!start_head) pre_t = recs.get(recs.pre, t);
+    if (tail_open) {
+      suf_t = recs.get(recs.suf, t);
+      if (ts >= 0 && ts < n_seg) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) gt[k] = gseg[k * n_seg + ts];
+        gt[6] *= 2.f;
+      }
+    }
+  };
+  if (kEager) load_carries();
   LaneRun<DT, FULL> R;
   R.load(s, endloc, lane, start_head, t * kTile, raw);
 
@@ -427,7 +461,16 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
 #pragma unroll
   for (int j = 0; j < kRun; ++j) {
     const Smp& q = R.x[j];
-    if (j > 0) {
+    if (kEager) {
+      if (j > 0 && R.head(j)) {  // (a branch: heads are rare)
+        cur.tau = 0.f;
+        cur.A = 0.f;
+        cur.B = 0.f;
+        Tc = 1.f;
+        cur_head = true;
+        fhp = fhp == kRun ? j : fhp;
+      }
+    } else if (j > 0) {
       const bool hd = R.head(j);
       cur.tau = hd ? 0.f : cur.tau;
       cur.A = hd ? 0.f : cur.A;
@@ -470,27 +513,38 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   const int sxf = from_upper(static_cast<int>(rfl));
   const int sxseg = from_upper(rseg);
 
+  if (!kEager) load_carries();
+
   // Prefix of the segment in front of the lane (identity if sample 0 is a head).
   Pre pc = pre_identity();
   if (!R.h0) {
     if (lane > 0 && exf) pc = ex;
     else if (!start_head) {
-      const Pre pt = pre_of(range_of(recs.get(recs.pre, t)));
+      const Pre pt = pre_of(range_of(pre_t));
       pc = lane > 0 ? combine(pt, ex) : pt;
     }
   }
   // Suffix behind the lane's last sample, in its own frame (unused if that
-  // sample ends its segment).
+  // sample ends its segment), and the gradient of the segment it belongs to.
   Range sc = range_identity();
-  int64_t cseg = -1;
+  float g[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (have) {
     if (lane < kWave - 1 && sxf) {
       sc = sx;
-      cseg = s_lo + sxseg;
+      if (kEager && sxseg < kStagedSegs) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) g[k] = gl[k * kStagedSegs + sxseg];
+      } else {
+        const int64_t cseg = s_lo + sxseg;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) g[k] = gseg[k * n_seg + cseg];
+        g[6] *= 2.f;
+      }
     } else if (tail_open) {
-      const Range st = range_of(recs.get(recs.suf, t));
+      const Range st = range_of(suf_t);
       sc = lane < kWave - 1 ? combine(sx, st) : st;
-      cseg = recs.tail_seg[t];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) g[k] = gt[k];
     }
   }
 
@@ -515,14 +569,8 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   // with Zs = sum_{k>j} w_k (m_k - m_j) and T_N the segment's transmittance:
   // the derivative of the segment tuple with every difference of positions
   // taken before it is multiplied.
-  float g[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float SG = 0.f, SA = 0.f, SF = 0.f, SL = 0.f, mf = 0.f, TN = 1.f;
   if (have) {
-    if (cseg >= 0 && cseg < n_seg) {
-#pragma unroll
-      for (int k = 0; k < 7; ++k) g[k] = gseg[k * n_seg + cseg];
-      g[6] *= 2.f;
-    }
     const float Tq = PT[kRun - 1] * R.x[kRun - 1].e;
     SG = Tq * fmaf(g[3], sc.cb, fmaf(g[2], sc.cg, g[1] * sc.cr));
     SA = Tq * sc.A; SF = Tq * sc.F; SL = Tq * Tq * sc.L; mf = sc.m0;
@@ -536,7 +584,7 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
     for (int j = kRun - 1; j >= 0; --j) {
       const Smp& q = R.x[j];
       const int endj = endloc[lane * kRun + j];  // re-read: frees registers across the scans
-      reverse_step(q, PT[j], PZ[j], endj >= 0, endj, s_lo, n_seg, gl, gseg, g, SG, SA, SF,
+      reverse_step<kEager>(q, PT[j], PZ[j], endj >= 0, endj, s_lo, n_seg, gl, gseg, g, SG, SA, SF,
                    SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
       if (DT == kF32) {
         // FP32: 16-byte stores per four samples (narrower stores leave lines
@@ -563,7 +611,7 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   float dsg[kRun], dc[3 * kRun];
 #pragma unroll
   for (int j = kRun - 1; j >= 0; --j) {
-    reverse_step(R.x[j], PT[j], PZ[j], R.endf[j], R.ends[j], s_lo, n_seg, gl, gseg, g, SG, SA, SF,
+    reverse_step<false>(R.x[j], PT[j], PZ[j], R.endf[j], R.ends[j], s_lo, n_seg, gl, gseg, g, SG, SA, SF,
                  SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
   }
 
@@ -633,6 +681,9 @@ __device__ __forceinline__ void seg_bwd_body(
   const bool active = t < t_end;
   RawRun<DT> raw;
   if (FULL && active) raw.load(s.sigma, s.rgb, s.t0, s.t1, t * kTile + static_cast<int64_t>(lane) * kRun);
+  // (requested here so that their latency overlaps the staging below)
+  const int flags = active ? recs.flags[t] : 0;
+  const int64_t ts = active ? recs.tail_seg[t] : -1;
   int* endloc = endloc_all[wave];
   float* gl = gl_all[wave];
 #pragma unroll
@@ -647,7 +698,7 @@ __device__ __forceinline__ void seg_bwd_body(
   }
   __syncthreads();
   if (!active) return;
-  bwd_tile<DT, FULL>(s, n_seg, t, s_lo, lane, endloc, gl, park_all[wave], recs, gseg, gsig_p, grgb_p,
+  bwd_tile<DT, FULL>(s, n_seg, t, flags, ts, s_lo, lane, endloc, gl, park_all[wave], recs, gseg, gsig_p, grgb_p,
                      &raw);
 }
 

@@ -430,18 +430,64 @@ template <typename T>
 __device__ __forceinline__ T from_upper(const T& x) { return dpp_fields<kWaveShl1, 0xF>(x); }
 __device__ __forceinline__ int from_upper(int v) { return dpp_i<kWaveShl1, 0xF>(v); }
 
-// One step of the prefix scan: y is what precedes x's window; `ok` says the
-// lane received one.
-template <typename T>
-__device__ __forceinline__ void up_apply(T& x, bool& f, const T& y, int fy, bool ok) {
-  x = select(ok && !f, combine(y, x), x);
-  f = f || (ok && fy != 0);
+// Masked combines.  A scan step either joins the received range y to the
+// lane's own x or leaves x as it is.  Instead of computing the join and then
+// selecting field by field, the choice is folded into the arithmetic: y's
+// additive fields are scaled by k in {0, 1} (and, behind x, y's weight T1 is
+// zeroed), which reproduces x exactly when k = 0 because every received value
+// is finite (row shifts with bound_ctrl read 0 outside the row).  One select
+// remains per join, for the midpoint the join would move.
+//
+// y in front of x (prefix scans), or x unchanged.
+__device__ __forceinline__ Pre join_front(const Pre& y, const Pre& x, bool use) {
+  const float k = use ? 1.f : 0.f;
+  const Pre z{k * y.tau, k * y.A, k * y.B, y.m1};  // y, or a left identity of x
+  return combine(z, x);
 }
+__device__ __forceinline__ Range join_front(const Range& y, const Range& x, bool use) {
+  const float k = use ? 1.f : 0.f;
+  Range z;  // y, or a left identity of x
+  z.tau = k * y.tau;
+  z.cr = k * y.cr; z.cg = k * y.cg; z.cb = k * y.cb;
+  z.A = k * y.A; z.F = k * y.F; z.B = k * y.B; z.L = k * y.L;
+  z.m0 = use ? y.m0 : x.m0;
+  z.m1 = y.m1;
+  return combine(z, x);
+}
+// y behind x (suffix scan), or x unchanged.
+__device__ __forceinline__ Range join_back(const Range& x, const Range& y, bool use) {
+  const float k = use ? 1.f : 0.f;
+  const float T1 = use ? exp_neg(x.tau) : 0.f;
+  const float m1 = use ? y.m1 : x.m1;
+  Range r;
+  r.tau = fmaf(k, y.tau, x.tau);
+  r.cr = fmaf(T1, y.cr, x.cr);
+  r.cg = fmaf(T1, y.cg, x.cg);
+  r.cb = fmaf(T1, y.cb, x.cb);
+  r.A = fmaf(T1, y.A, x.A);
+  r.F = fmaf(T1, fmaf(y.A, y.m0 - x.m0, y.F), x.F);
+  r.B = fmaf(T1, y.B, fmaf(x.A, m1 - x.m1, x.B));
+  const float cross = fmaf(x.A, fmaf(y.A, y.m0 - x.m1, y.F), y.A * x.B);
+  r.L = fmaf(T1 * T1, y.L, fmaf(2.f * T1, cross, x.L));
+  r.m0 = x.m0;
+  r.m1 = m1;
+  return r;
+}
+
+// One step of the prefix scan: y is what precedes x's window; `ok` says the
+// lane received one.  Row shifts use the masked join; the row broadcasts
+// leave the lanes of disabled rows undefined, so they select instead.
 template <int CTRL, int ROW_MASK, typename T>
 __device__ __forceinline__ void up_step(T& x, bool& f, bool ok) {
   const T y = dpp_fields<CTRL, ROW_MASK>(x);
   const int fy = dpp_i<CTRL, ROW_MASK>(static_cast<int>(f));
-  up_apply(x, f, y, fy, ok);
+  const bool use = ok && !f;
+  if constexpr (ROW_MASK == 0xF) {
+    x = join_front(y, x, use);
+  } else {
+    x = select(use, combine(y, x), x);
+  }
+  f = f || (ok && fy != 0);
 }
 
 // Inclusive segmented scan in lane order.  A lane whose flag is set starts a
@@ -463,7 +509,7 @@ __device__ __forceinline__ void scan_up(T& x, bool& f, int lane) {
 __device__ __forceinline__ void down_apply(Range& x, bool& f, int& seg, const Range& y, int fy,
                                            int sy, bool ok) {
   const bool use = ok && !f;
-  x = select(use, combine(x, y), x);
+  x = join_back(x, y, use);
   seg = use ? sy : seg;
   f = f || (ok && fy != 0);
 }
