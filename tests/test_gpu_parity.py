@@ -298,3 +298,47 @@ def test_autograd_finite_differences_through_library():
         fd = (f(sp) - f(sm)) / (2 * h)
         g = float(s.grad[i])
         assert abs(fd - g) <= 2e-3 * max(1.0, abs(g)) + 1e-3, (i, fd, g)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_crowded_tiles(dtype):
+    """Tiles whose windows hold far more than 64 segments (1-4 sample segments
+    and empty ones), so segment tuples and gradients take the paths that do
+    not stage them in LDS."""
+    rng = np.random.default_rng(41)
+    empty = (np.zeros(0), np.zeros((0, 3)), np.zeros(0), np.zeros(0))
+    rays = []
+    for r in range(400):
+        ray, t = [], 0.1
+        for k in range(int(rng.integers(1, 5))):
+            if rng.random() < 0.2:
+                ray.append(empty)
+            n = int(rng.integers(1, 5))
+            ray.append(_seg(rng, n, t))
+            t += 0.02 * n + 0.05
+        rays.append(ray)
+    b = _hand_batch(rays, shuffle_seed=7)
+    per_tile = np.bincount(np.minimum(b.seg_offsets[:-1] // 512, max(b.n - 1, 0) // 512))
+    say("crowded batch: n", b.n, "segments", b.n_seg, "max segments starting in a tile", per_tile.max())
+    assert per_tile.max() > 64
+    d = to_dev(b, dtype)
+    dq = None if dtype == torch.float32 else quantize(b, dtype)
+    seg_out, ws, ray_out = run_fwd(d)
+    s_in, c_in = (b.sigma, b.rgb) if dq is None else dq
+    assert_tuples(seg_out.cpu().numpy(), O.render_segments(s_in, c_in, b.t_start, b.t_end, b.seg_offsets),
+                  "seg", f"crowded {dtype} segments")
+    rays_all = np.arange(b.n_rays)
+    assert_tuples(ray_out.cpu().numpy(), oracle_rays(b, rays_all, s_in, c_in), "ray", f"crowded {dtype} rays")
+    grad_ray = np.random.default_rng(42).normal(size=(7, b.n_rays))
+    gseg, gs, gc = run_bwd(d, seg_out, ws, grad_ray)
+    if dq is None:
+        _check_backward(b, d, rays_all, gseg, gs, gc, grad_ray, f"crowded {dtype}")
+    else:
+        g_seg_ref, segs, idx, ds_ref, dc_ref = O.backward_partitioned(
+            s_in, c_in, b.t_start, b.t_end, b.seg_offsets, b.ray_offsets, b.seg_ids, grad_ray, rays_all)
+        assert_grads(gseg.cpu().numpy()[:, segs], g_seg_ref, "crowded grad_seg")
+        ulp = 2.0 ** -8
+        assert_grads(gs.float().cpu().numpy()[idx], ds_ref, "crowded dsigma", rtol=ulp, floor=1e-5,
+                     norm_tol=ulp)
+        assert_grads(gc.float().cpu().numpy()[idx], dc_ref, "crowded drgb", rtol=ulp, floor=1e-5,
+                     norm_tol=ulp)
