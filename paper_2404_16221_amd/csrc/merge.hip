@@ -22,7 +22,7 @@ namespace xl {
 template <typename R>
 __device__ __forceinline__ R exp_neg_t(R x);
 template <>
-__device__ __forceinline__ float exp_neg_t<float>(float x) { return expf(-x); }
+__device__ __forceinline__ float exp_neg_t<float>(float x) { return exp_neg(x); }  // as in the segment kernels
 template <>
 __device__ __forceinline__ double exp_neg_t<double>(double x) { return exp(-x); }
 
@@ -71,6 +71,9 @@ __device__ __forceinline__ void clamp_range(const int64_t* __restrict__ ro, int6
   k1 = k1 < k0 ? k0 : (k1 > n_seg ? n_seg : k1);
 }
 
+// Rays with up to kCached segments are handled with all their tuples in registers.
+constexpr int kCached = 8;
+
 template <typename R>
 __global__ __launch_bounds__(256) void merge_fwd_kernel(const float* __restrict__ seg_out,
                                                         int64_t n_seg,
@@ -83,10 +86,7 @@ __global__ __launch_bounds__(256) void merge_fwd_kernel(const float* __restrict_
   clamp_range(ro, r, n_seg, k0, k1);
   // Alg. 1/2 state: T(t_1 -> t_k) and C, A, D, L accumulated so far.
   R tau = 0, tlo = 0, Tpre = 1, cr = 0, cg = 0, cb = 0, A = 0, D = 0, L = 0;
-  for (int64_t k = k0; k < k1; ++k) {
-    const int64_t s = ids[k];
-    if (s < 0 || s >= n_seg) continue;
-    const Tup<R> x = load_tup<R>(seg_out, n_seg, s);
+  auto step = [&](const Tup<R>& x) {
     const R S = x.D * A - x.A * D;                    // Eq. 8
     L += Tpre * Tpre * x.L + R(2) * Tpre * S;         // Eq. 7
     cr += Tpre * x.cr; cg += Tpre * x.cg; cb += Tpre * x.cb;  // Eq. 3
@@ -94,6 +94,30 @@ __global__ __launch_bounds__(256) void merge_fwd_kernel(const float* __restrict_
     D += Tpre * x.D;                                  // Eq. 6
     add_tau_t<R>(tau, tlo, x.tau, R(0));
     Tpre = exp_neg_t<R>(tau + tlo);                   // Eq. 4
+  };
+  const int64_t n = k1 - k0;
+  if (n <= kCached) {
+    // All of the ray's tuples are requested at once (two dependent loads in
+    // flight per ray instead of two per segment).
+    int64_t sid[kCached];
+    Tup<R> x[kCached];
+#pragma unroll
+    for (int q = 0; q < kCached; ++q) {
+      const int64_t s = q < n ? ids[k0 + q] : -1;
+      sid[q] = (s >= 0 && s < n_seg) ? s : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kCached; ++q)
+      if (sid[q] >= 0) x[q] = load_tup<R>(seg_out, n_seg, sid[q]);
+#pragma unroll
+    for (int q = 0; q < kCached; ++q)
+      if (sid[q] >= 0) step(x[q]);
+  } else {
+    for (int64_t k = k0; k < k1; ++k) {
+      const int64_t s = ids[k];
+      if (s < 0 || s >= n_seg) continue;
+      step(load_tup<R>(seg_out, n_seg, s));
+    }
   }
   out[r] = static_cast<float>(Tpre);
   out[n_rays + r] = static_cast<float>(cr);
@@ -128,8 +152,6 @@ __device__ __forceinline__ void write_seg_grad(float* __restrict__ gseg, int64_t
   gseg[6 * n_seg + s] = static_cast<float>(gL_k);
 }
 
-constexpr int kCached = 8;
-
 template <typename R>
 __global__ __launch_bounds__(256) void merge_bwd_kernel(const float* __restrict__ seg_out,
                                                         int64_t n_seg,
@@ -156,20 +178,27 @@ __global__ __launch_bounds__(256) void merge_bwd_kernel(const float* __restrict_
       if (!ok) sid[q] = -1;
       x[q] = ok ? load_tup<R>(seg_out, n_seg, sid[q]) : Tup<R>{0, 0, 0, 0, 0, 0, 0};
     }
+    // Slots past the ray's last segment are skipped (by the whole wave when
+    // no ray of it has that many); invalid ids inside it are identities.
+    const int64_t n = k1 - k0;
     Tup<R> S[kCached];
     Tup<R> acc{0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int q = kCached - 1; q >= 0; --q) {
-      S[q] = acc;
-      acc = fold<R>(x[q], exp_neg_t<R>(x[q].tau), acc);  // empty slots are identities
+      if (q < n) {
+        S[q] = acc;
+        acc = fold<R>(x[q], exp_neg_t<R>(x[q].tau), acc);
+      }
     }
     Tup<R> P{0, 0, 0, 0, 0, 0, 0};
     R PT = 1;
 #pragma unroll
     for (int q = 0; q < kCached; ++q) {
-      if (sid[q] >= 0) write_seg_grad<R>(gseg, n_seg, sid[q], P, PT, x[q], S[q], gT, gCr, gCg, gCb, gA, gD, gL);
-      P = fold<R>(P, PT, x[q]);
-      PT = exp_neg_t<R>(P.tau + P.tlo);
+      if (q < n) {
+        if (sid[q] >= 0) write_seg_grad<R>(gseg, n_seg, sid[q], P, PT, x[q], S[q], gT, gCr, gCg, gCb, gA, gD, gL);
+        P = fold<R>(P, PT, x[q]);
+        PT = exp_neg_t<R>(P.tau + P.tlo);
+      }
     }
     return;
   }
