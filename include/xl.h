@@ -21,8 +21,10 @@
  *     axis-aligned box): samples of all regions packed
  *     region-major; segment s owns samples [seg_offsets[s], seg_offsets[s+1]),
  *     which belong to one ray and one region, sorted by t, with
- *     non-overlapping intervals [t_start, t_end].  Density sigma >= 0 and
- *     finite; colour in any finite range.
+ *     non-overlapping intervals [t_start, t_end].  Density sigma >= 0 with
+ *     every optical depth sigma * (t_end - t_start) finite (the wave scans
+ *     scale partial sums by 0 and 1 instead of selecting between them);
+ *     colour and interval ends in any finite range.
  *   - Segment tuple (what each region reduces its samples to before any
  *     exchange, App. A.2):
  *     seg_out is structure-of-arrays float32 [7][n_seg]:
