@@ -599,12 +599,28 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
                                                            dc[3 * j + 4 * v + 2], dc[3 * j + 4 * v + 3]);
         }
       } else {
-        if ((j & 1) == 0)
-          *reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(gsig_p) + R.i0 + j) = pack2<DT>(dsg[j], dsg[j + 1]);
+        // 16-bit: each pair of gradients goes to the LDS image of the tile's
+        // gradient block (dsigma, then drgb), written out below with full,
+        // contiguous 16-byte stores.
+        if ((j & 1) == 0) {
+          uint32_t* img = reinterpret_cast<uint32_t*>(park);
+          img[(lane * kRun + j) / 2] = pack2<DT>(dsg[j], dsg[j + 1]);
 #pragma unroll
-        for (int qq = (3 * j + 1) / 2; qq < (3 * (j + 1) + 1) / 2; ++qq)
-          *reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(grgb_p) + 3 * R.i0 + 2 * qq) = pack2<DT>(dc[2 * qq], dc[2 * qq + 1]);
+          for (int v = 0; v < 3; ++v)
+            img[kTile / 2 + (3 * (lane * kRun + j)) / 2 + v] = pack2<DT>(dc[3 * j + 2 * v], dc[3 * j + 2 * v + 1]);
+        }
       }
+    }
+    if (DT != kF32) {
+      __builtin_amdgcn_wave_barrier();  // (LDS operations of one wave complete in order)
+      const uint4* img = reinterpret_cast<const uint4*>(park);
+      uint4* gs = reinterpret_cast<uint4*>(static_cast<uint16_t*>(gsig_p) + t * kTile);
+      uint4* gc = reinterpret_cast<uint4*>(static_cast<uint16_t*>(grgb_p) + 3 * t * kTile);
+      constexpr int kSigVec = kTile * 2 / 16;  // 16-byte vectors of dsigma per tile
+      static_assert(kSigVec == kWave, "one vector of dsigma per lane");
+      gs[lane] = img[lane];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) gc[q * kWave + lane] = img[kSigVec + q * kWave + lane];
     }
     return;
   }
@@ -672,7 +688,11 @@ __device__ __forceinline__ void seg_bwd_body(
     const float* __restrict__ gseg, void* __restrict__ gsig_p, void* __restrict__ grgb_p) {
   __shared__ int endloc_all[kWavesPerBlock][kTile];
   __shared__ float gl_all[kWavesPerBlock][7 * kStagedSegs];
-  __shared__ float park_all[kWavesPerBlock][kRangeFields * kWave];
+  // Parked ranges during the scans; in 16-bit storage, afterwards, the image of
+  // the tile's gradients (2 + 6 bytes per sample).
+  constexpr int kParkWords =
+      DT != kF32 && 2 * kTile > kRangeFields * kWave ? 2 * kTile : kRangeFields * kWave;
+  __shared__ __align__(16) float park_all[kWavesPerBlock][kParkWords];
   __shared__ int64_t tailseg_all[kWavesPerBlock];
   // wave index made provably uniform, so per-tile loads go through the scalar unit
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
