@@ -241,7 +241,7 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
     }
   }
   // Staged tuples out (LDS operations of one wave complete in order).
-  __builtin_amdgcn_wave_barrier();
+  wave_lds_fence();
   if (staged && lane < kStagedSegs && ovalid[lane]) {
     const int64_t sg = s_lo + lane;
 #pragma unroll
@@ -612,7 +612,7 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
       }
     }
     if (DT != kF32) {
-      __builtin_amdgcn_wave_barrier();  // (LDS operations of one wave complete in order)
+      wave_lds_fence();
       const uint4* img = reinterpret_cast<const uint4*>(park);
       uint4* gs = reinterpret_cast<uint4*>(static_cast<uint16_t*>(gsig_p) + t * kTile);
       uint4* gc = reinterpret_cast<uint4*>(static_cast<uint16_t*>(grgb_p) + 3 * t * kTile);

@@ -179,6 +179,12 @@ __device__ __forceinline__ void append(Range& r, float& Tr, const Smp& s) {
   Tr *= s.e;
 }
 
+// Orders the calling wave's LDS accesses for the compiler; the hardware
+// already performs one wave's LDS operations in order.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 // ---------------------------------------------------------------- storage
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
   return __uint_as_float(static_cast<uint32_t>(h) << 16);
