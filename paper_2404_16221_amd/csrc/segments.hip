@@ -419,10 +419,10 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   const bool start_head = (flags & kStartHead) != 0;
   const bool tail_open = (flags & kTailOpen) != 0;
   // The 16-bit forms are bound by instruction issue and latency; the FP32 form
-  // moves half again as many bytes and sits at the register limit.  Only the
-  // former spend registers on requesting the tile carries before the lane
-  // work and on branching around rare restarts (measured: each helps them by
-  // a few percent and slows the FP32 form by more).
+  // moves half again as many bytes and runs three waves per SIMD (its 8 KB
+  // gradient image fills the LDS).  Only the former request the tile carries
+  // before the lane work and branch around rare restarts (measured: each
+  // helps them by a few percent and slows the FP32 form).
   constexpr bool kEager = DT != kF32;
   // Tile-uniform carries: the prefix into the tile, the suffix out of it and
   // the gradient of the segment that leaves it (g_L doubled, as in the sweep).
@@ -578,7 +578,11 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
   }
   if constexpr (FULL) {
     // Full tile: the lane's samples stay in registers from pass 1 (no
-    // re-read), and each pair of gradients is stored as soon as it is complete.
+    // re-read).  Each gradient goes to the LDS image of the tile's gradient
+    // block (dsigma, then drgb, as laid out in memory) as soon as it is
+    // complete; the image is then written with full, contiguous 16-byte
+    // stores (stores straight from the lanes, each covering a few bytes of
+    // many cache lines, cost the backward 15-20 %).
     float dsg[kRun], dc[3 * kRun];
 #pragma unroll
     for (int j = kRun - 1; j >= 0; --j) {
@@ -587,22 +591,14 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
       reverse_step<kEager>(q, PT[j], PZ[j], endj >= 0, endj, s_lo, n_seg, gl, gseg, g, SG, SA, SF,
                    SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
       if (DT == kF32) {
-        // FP32: 16-byte stores per four samples (narrower stores leave lines
-        // partly written and cost extra write traffic).
-        if ((j & 3) == 0) {
-          float* gs = static_cast<float*>(gsig_p) + R.i0 + j;
-          float* gc = static_cast<float*>(grgb_p) + 3 * (R.i0 + j);
-          *reinterpret_cast<float4*>(gs) = make_float4(dsg[j], dsg[j + 1], dsg[j + 2], dsg[j + 3]);
-#pragma unroll
-          for (int v = 0; v < 3; ++v)
-            reinterpret_cast<float4*>(gc)[v] = make_float4(dc[3 * j + 4 * v], dc[3 * j + 4 * v + 1],
-                                                           dc[3 * j + 4 * v + 2], dc[3 * j + 4 * v + 3]);
-        }
+        float* img = park;  // [kTile] dsigma, then [kTile][3] drgb
+        const int i = lane * kRun + j;
+        img[i] = dsg[j];
+        img[kTile + 3 * i] = dc[3 * j];
+        img[kTile + 3 * i + 1] = dc[3 * j + 1];
+        img[kTile + 3 * i + 2] = dc[3 * j + 2];
       } else {
-        // 16-bit: each pair of gradients goes to the LDS image of the tile's
-        // gradient block (dsigma, then drgb), written out below with full,
-        // contiguous 16-byte stores.
-        if ((j & 1) == 0) {
+        if ((j & 1) == 0) {  // pairs of 16-bit values
           uint32_t* img = reinterpret_cast<uint32_t*>(park);
           img[(lane * kRun + j) / 2] = pack2<DT>(dsg[j], dsg[j + 1]);
 #pragma unroll
@@ -611,7 +607,16 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
         }
       }
     }
-    if (DT != kF32) {
+    if (DT == kF32) {
+      wave_lds_fence();
+      const uint4* img = reinterpret_cast<const uint4*>(park);
+      uint4* gs = reinterpret_cast<uint4*>(static_cast<float*>(gsig_p) + t * kTile);
+      uint4* gc = reinterpret_cast<uint4*>(static_cast<float*>(grgb_p) + 3 * t * kTile);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) gs[q * kWave + lane] = img[q * kWave + lane];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) gc[q * kWave + lane] = img[2 * kWave + q * kWave + lane];
+    } else {
       wave_lds_fence();
       const uint4* img = reinterpret_cast<const uint4*>(park);
       uint4* gs = reinterpret_cast<uint4*>(static_cast<uint16_t*>(gsig_p) + t * kTile);
@@ -688,10 +693,9 @@ __device__ __forceinline__ void seg_bwd_body(
     const float* __restrict__ gseg, void* __restrict__ gsig_p, void* __restrict__ grgb_p) {
   __shared__ int endloc_all[kWavesPerBlock][kTile];
   __shared__ float gl_all[kWavesPerBlock][7 * kStagedSegs];
-  // Parked ranges during the scans; in 16-bit storage, afterwards, the image of
-  // the tile's gradients (2 + 6 bytes per sample).
-  constexpr int kParkWords =
-      DT != kF32 && 2 * kTile > kRangeFields * kWave ? 2 * kTile : kRangeFields * kWave;
+  // Parked ranges during the scans; afterwards the image of the tile's
+  // gradients (8 or 16 bytes per sample).
+  constexpr int kParkWords = DT == kF32 ? 4 * kTile : 2 * kTile;
   __shared__ __align__(16) float park_all[kWavesPerBlock][kParkWords];
   __shared__ int64_t tailseg_all[kWavesPerBlock];
   // wave index made provably uniform, so per-tile loads go through the scalar unit
