@@ -565,13 +565,16 @@ __device__ __forceinline__ Range unpark_range(const float* __restrict__ lds, int
   return r;
 }
 
-// Per-tile records kept in the workspace between forward and backward, as a
-// structure of arrays over tiles (a thread per tile reads them coalesced).
-// The tile count is padded to a multiple of kRecGroup so that every array
-// starts 256-byte aligned.
+// Per-tile records kept in the workspace between forward and backward.  The
+// scalar fields are arrays over tiles (a thread per tile reads them
+// coalesced); each partial range is one 48-byte record (three 16-byte
+// vectors), so that the one lane that writes it issues three stores instead of
+// one per field, and the backward reads it with two scalar loads.  The tile
+// count is padded to a multiple of kRecGroup so that every array starts
+// 256-byte aligned.
 constexpr int64_t kRecGroup = 64;
-constexpr int kPartFields = kRangeFields + 1;
-constexpr size_t kRecBytesPerTile = 8 + 8 + 4 + 4 * sizeof(float) * kPartFields;
+constexpr int kPartVecs = 3;  // (tau, r, g, b), (A, F, B, L), (m0, m1, tlo, 0)
+constexpr size_t kRecBytesPerTile = 8 + 8 + 4 + 4 * 16 * kPartVecs;
 
 __host__ __device__ inline int64_t rec_stride(int64_t n_tiles) {
   const int64_t nt = n_tiles > 0 ? n_tiles : 1;
@@ -583,10 +586,10 @@ struct TileRecs {
                        // first segment starting at it, empty ones included)
   int64_t* tail_seg;   // segment containing the tile's last sample
   int32_t* flags;      // kStartHead | kHasEnd | kHasHead | kTailOpen
-  float* head;  // [kRangeFields][stride] first sample .. first segment end (whole tile if none)
-  float* tail;  // last segment head .. last sample
-  float* pre;   // carry-in: the first sample's segment before this tile
-  float* suf;   // carry-in: the last sample's segment after this tile
+  float4* head;  // [stride][kPartVecs] first sample .. first segment end (whole tile if none)
+  float4* tail;  // last segment head .. last sample
+  float4* pre;   // carry-in: the first sample's segment before this tile
+  float4* suf;   // carry-in: the last sample's segment after this tile
   int64_t stride;
 
   __host__ __device__ static TileRecs view(void* ws, int64_t n_tiles) {
@@ -596,32 +599,31 @@ struct TileRecs {
     r.first_seg = reinterpret_cast<int64_t*>(p); p += 8 * r.stride;
     r.tail_seg = reinterpret_cast<int64_t*>(p); p += 8 * r.stride;
     r.flags = reinterpret_cast<int32_t*>(p); p += 4 * r.stride;
-    const int64_t rb = sizeof(float) * kPartFields * r.stride;
-    r.head = reinterpret_cast<float*>(p); p += rb;
-    r.tail = reinterpret_cast<float*>(p); p += rb;
-    r.pre = reinterpret_cast<float*>(p); p += rb;
-    r.suf = reinterpret_cast<float*>(p);
+    const int64_t rb = 16 * kPartVecs * r.stride;
+    r.head = reinterpret_cast<float4*>(p); p += rb;
+    r.tail = reinterpret_cast<float4*>(p); p += rb;
+    r.pre = reinterpret_cast<float4*>(p); p += rb;
+    r.suf = reinterpret_cast<float4*>(p);
     return r;
   }
   __host__ __device__ static size_t bytes(int64_t n_tiles) { return kRecBytesPerTile * rec_stride(n_tiles); }
 
-  __device__ Part get(const float* a, int64_t t) const {
+  __device__ Part get(const float4* a, int64_t t) const {
+    const float4 u = a[kPartVecs * t], v = a[kPartVecs * t + 1], w = a[kPartVecs * t + 2];
     Part p;
     Range& r = p.r;
-    r.tau = a[0 * stride + t]; r.cr = a[1 * stride + t]; r.cg = a[2 * stride + t];
-    r.cb = a[3 * stride + t]; r.A = a[4 * stride + t]; r.F = a[5 * stride + t];
-    r.B = a[6 * stride + t]; r.L = a[7 * stride + t]; r.m0 = a[8 * stride + t];
-    r.m1 = a[9 * stride + t]; p.tlo = a[10 * stride + t];
+    r.tau = u.x; r.cr = u.y; r.cg = u.z; r.cb = u.w;
+    r.A = v.x; r.F = v.y; r.B = v.z; r.L = v.w;
+    r.m0 = w.x; r.m1 = w.y; p.tlo = w.z;
     return p;
   }
-  __device__ void put(float* a, int64_t t, const Part& p) const {
+  __device__ void put(float4* a, int64_t t, const Part& p) const {
     const Range& r = p.r;
-    a[0 * stride + t] = r.tau; a[1 * stride + t] = r.cr; a[2 * stride + t] = r.cg;
-    a[3 * stride + t] = r.cb; a[4 * stride + t] = r.A; a[5 * stride + t] = r.F;
-    a[6 * stride + t] = r.B; a[7 * stride + t] = r.L; a[8 * stride + t] = r.m0;
-    a[9 * stride + t] = r.m1; a[10 * stride + t] = p.tlo;
+    a[kPartVecs * t] = make_float4(r.tau, r.cr, r.cg, r.cb);
+    a[kPartVecs * t + 1] = make_float4(r.A, r.F, r.B, r.L);
+    a[kPartVecs * t + 2] = make_float4(r.m0, r.m1, p.tlo, 0.f);
   }
-  __device__ void put(float* a, int64_t t, const Range& r) const { put(a, t, part_of(r)); }
+  __device__ void put(float4* a, int64_t t, const Range& r) const { put(a, t, part_of(r)); }
 };
 
 }  // namespace xl
