@@ -83,7 +83,7 @@ const char* xl_last_error(void);
 
 /* Bytes of device workspace that xl_render_segments_fwd fills and
  * xl_render_segments_bwd reads for n samples (per-tile partial tuples and
- * carries; about 0.4 byte per sample). */
+ * carries; about 0.41 byte per sample). */
 size_t xl_segments_workspace_bytes(int64_t n);
 
 /*
