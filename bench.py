@@ -266,7 +266,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="bf16,fp32,plain")
+    ap.add_argument("--forms", default="bf16,fp32,plain,k64")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="measured serving requests (0 skips the serving run)")
     ap.add_argument("--serve-warmup", type=int, default=30)
@@ -297,14 +297,15 @@ def main():
     grad_ray = torch.from_numpy(
         np.random.default_rng(3).normal(size=(7, w.n_rays)).astype(np.float32)).to(dev)
 
-    def make(name, workload, dtype, regions):
+    def make(name, workload, dtype, regions, fp64=False, grad=None):
         t = time.perf_counter()
         g = xl.xl_gen(workload, dtype)
         torch.cuda.synchronize()
         log(f"generated {name} on the device: {g['sigma'].shape[0]} samples, "
             f"{g['seg_ids'].shape[0]} segments in {time.perf_counter() - t:.2f} s")
         return Form(name, g["sigma"], g["rgb"], g["t_start"], g["t_end"], g["seg_offsets"],
-                    g["ray_offsets"], g["seg_ids"], grad_ray, regions)
+                    g["ray_offsets"], g["seg_ids"], grad_ray if grad is None else grad, regions,
+                    fp64=fp64)
 
     if "bf16" in want:
         forms["bf16"] = make("k16-bf16", w, torch.bfloat16, 16)
@@ -312,6 +313,13 @@ def main():
         forms["fp32"] = make("k16-fp32", w, torch.float32, 16)
     if "plain" in want:
         forms["plain"] = make("k1-plain-fp32", w.plain(), torch.float32, 1)
+    if "k64" in want:
+        # the large partition, all 4,194,304 rays resident at once (18 GB of
+        # BF16/FP32 samples fit in HBM), with the FP64 cross-segment merge
+        w64 = synth.WORKLOADS[4]
+        g64 = torch.from_numpy(
+            np.random.default_rng(4).normal(size=(7, w64.n_rays)).astype(np.float32)).to(dev)
+        forms["k64"] = make("k64-bf16-fp64merge", w64, torch.bfloat16, 64, fp64=True, grad=g64)
     for key, f in forms.items():
         ms, kms, wall = time_form(f, args.steps, args.warmup)
         results[key] = dict(name=f.name, ms_per_step=ms, samples_per_s=f.n / (ms * 1e-3),

@@ -33,12 +33,13 @@ def run(g, grad_ray, fp64=False):
 
 def ray_sample_positions(g, rays):
     """Device sample indices of each listed ray, front to back (integer layout only)."""
-    so = g["seg_offsets"].cpu().numpy()
     ro = g["ray_offsets"].cpu().numpy()
-    ids = g["seg_ids"].cpu().numpy()
     out = []
     for r in rays:
-        out.append(np.concatenate([np.arange(so[s], so[s + 1]) for s in ids[ro[r]:ro[r + 1]]]))
+        ids = g["seg_ids"][ro[r]:ro[r + 1]]
+        so = torch.stack([g["seg_offsets"][ids], g["seg_offsets"][ids + 1]]).cpu().numpy()
+        out.append(np.concatenate([np.arange(a, b) for a, b in so.T]) if so.shape[1]
+                   else np.zeros(0, np.int64))
     return out
 
 
@@ -62,15 +63,18 @@ def check_sampled(w, g, ray0, rays_local, ray_out, gs, gc, grad_ray_np, dtype, w
     ref_at = np.empty(h.n, np.int64)
     ref_at[idx] = np.arange(idx.size)
     hp = np.concatenate(host_pos)
-    gs_dev = gs.float().cpu().numpy()
-    gc_dev = gc.float().cpu().numpy()
+    # gather the sampled rays' gradients on the device (the full arrays can be
+    # tens of GB)
+    at = torch.from_numpy(order[hp]).to(gs.device)
+    gs_dev = gs[at].float().cpu().numpy()
+    gc_dev = gc[at].float().cpu().numpy()
     if dtype == torch.float32:
         rtol, floor, nt = 1e-5, 1e-6, 1e-5
     else:
         rtol = 2.0 ** -8 if dtype == torch.bfloat16 else 2.0 ** -11
         floor, nt = 1e-5, rtol
-    assert_grads(gs_dev[order[hp]], ds_ref[ref_at[hp]], what + " dsigma", rtol, floor, nt)
-    assert_grads(gc_dev[order[hp]], dc_ref[ref_at[hp]], what + " drgb", rtol, floor, nt)
+    assert_grads(gs_dev, ds_ref[ref_at[hp]], what + " dsigma", rtol, floor, nt)
+    assert_grads(gc_dev, dc_ref[ref_at[hp]], what + " drgb", rtol, floor, nt)
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
@@ -110,3 +114,16 @@ def test_k64_chunk_bf16_fp64_merge(chunk):
     rays = sample_rays(synth.CHUNK_RAYS_K64, 40, 41 + chunk)
     check_sampled(w, g, ray0, rays, ray_out, gs, gc, grad_np.astype(np.float64), torch.bfloat16,
                   f"k64 chunk {chunk}")
+
+
+def test_k64_all_rays_one_launch_bf16_fp64_merge():
+    """The large partition as the benchmark runs it: all 4,194,304 rays in one
+    launch of each kernel (about 1.1G samples), sampled rays against the oracle."""
+    w = synth.WORKLOADS[4]
+    g = xl.xl_gen(w, torch.bfloat16)
+    say(f"k64 all rays: {g['sigma'].shape[0]} samples, {g['seg_ids'].shape[0]} segments")
+    grad_np = np.random.default_rng(44).normal(size=(7, w.n_rays)).astype(np.float32)
+    ray_out, gs, gc = run(g, torch.from_numpy(grad_np).cuda(), fp64=True)
+    rays = sample_rays(w.n_rays, 40, 45)
+    check_sampled(w, g, 0, rays, ray_out, gs, gc, grad_np.astype(np.float64), torch.bfloat16,
+                  "k64 all rays")
