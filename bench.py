@@ -290,6 +290,7 @@ def main():
     import paper_2404_16221_amd  # noqa: F401  (fails loudly without libxl.so)
     from paper_2404_16221_amd import _lib as xl
     from paper_2404_16221_amd import synth
+    from paper_2404_16221_amd.exchange import allgather_bytes
     dev = torch.device("cuda:0")
     w = synth.WORKLOADS[2]
     want = args.forms.split(",")
@@ -326,6 +327,12 @@ def main():
                             step_gbs=f.bytes_step() / (ms * 1e-3) / 1e9,
                             seg_bwd_ms=kms, seg_bwd_gbs=f.bytes_seg_bwd() / (kms * 1e-3) / 1e9,
                             wall_s=wall)
+        # bytes the K regions would all-gather per training step (one GPU
+        # moves none): per-sample (sigma, rgb) in the storage type vs FP32
+        # segment tuples
+        xb = allgather_bytes(f.n, f.n_seg, f.regions, 4 * f.sigma.element_size())
+        results[key]["exchange_sample_mb"] = xb["sample_based"] / 1e6
+        results[key]["exchange_tuple_mb"] = xb["segment_based"] / 1e6
         log(key, json.dumps(results[key]))
     head = "bf16" if "bf16" in results else next(iter(results))
     hf, hr = forms[head], results[head]
