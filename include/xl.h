@@ -194,6 +194,76 @@ int xl_gen_fill(const xl_gen_params* p, int32_t dtype, void* workspace, size_t w
                 int64_t* seg_offsets, int64_t* ray_offsets, int64_t* seg_ids, void* stream);
 
 /*
+ * Spatial partitioning (Sec. 4.4, App. A.3), on the host.  Splits space
+ * `levels` times (0 <= levels <= 6, so K = 2^levels <= 64 boxes) at planes
+ * where the per-axis CDF of `points` reaches one half: at each node, for each
+ * axis, the plane is the node's point coordinate of rank floor(m/2) (0-based,
+ * m points; a node without points takes the middle of its box), and the axis
+ * kept is the one whose two children have the smaller worst aspect ratio
+ * (longest over shortest extent, extents clipped to the bounding box of all
+ * points; ties go to x, then y).  Points below the plane go to the low child.
+ *   points  host float32 [n_points][3], finite
+ *   axis    host int32 [K - 1], written: split axis (0, 1, 2) of each node
+ *   plane   host float32 [K - 1], written: split coordinate of each node
+ * The tree is heap-ordered: node i has children 2i+1 (coordinate < plane)
+ * and 2i+2 (coordinate >= plane); box b is leaf node b + K - 1.  The
+ * outermost boxes extend to infinity.  Errors: XL_EINVAL for levels out of
+ * range, n_points < 0, NULL arrays or a non-finite point.  Synchronous; no
+ * device work.
+ */
+int xl_partition_build(const float* points, int64_t n_points, int32_t levels, int32_t* axis,
+                       float* plane);
+
+/* Rays and their samples before distribution, ray-major (device arrays). */
+typedef struct xl_rays {
+  const float* origins;        /* device float32 [n_rays][3] */
+  const float* dirs;           /* device float32 [n_rays][3] (any length, not all 0) */
+  const float* t_start;        /* device float32 [n] */
+  const float* t_end;          /* device float32 [n] */
+  const int64_t* ray_offsets;  /* device int64 [n_rays + 1]: ray r owns samples
+                                  [ray_offsets[r], ray_offsets[r+1]), sorted:
+                                  t_start <= t_end <= next t_start */
+  int64_t n_rays;
+} xl_rays;
+
+/* Device workspace bytes for xl_pack_plan / xl_pack_fill: about
+ * 32 * 2^levels + 16 bytes per ray. */
+size_t xl_pack_workspace_bytes(int64_t n_rays, int32_t levels);
+
+/*
+ * Sample distribution (Sec. 4.2), phase 1 (synchronises `stream`).  Cuts every
+ * sample interval at the points where its ray crosses a face of the boxes of
+ * the tree (axis, plane: device copies of xl_partition_build's output),
+ * tags the pieces with their box and plans their region-major layout.  Box
+ * b's interval on a ray is [t_in, t_out) from a float64 slab test, each face
+ * parameter being (face - origin) / direction, rounded to float32; the piece
+ * of sample [s, e) is [max(s, t_in), min(e, t_out)) when that has positive
+ * length; a zero-length sample stays whole in the box whose interval holds s.
+ * Returns the number of pieces and of segments (one per ray and box with
+ * pieces) to allocate.  Errors: XL_EINVAL for NULL arrays, levels out of range
+ * or a small workspace; XL_EHIP for launch or copy failures.
+ */
+int xl_pack_plan(const xl_rays* rays, const int32_t* axis, const float* plane, int32_t levels,
+                 void* workspace, size_t workspace_bytes, int64_t* n_pieces, int64_t* n_seg,
+                 void* stream);
+
+/*
+ * Phase 2 (asynchronous), from the workspace that xl_pack_plan filled for the
+ * same rays and tree: writes the pieces in the sample layout of the composite
+ * calls above -- t_start, t_end [n_pieces], seg_offsets [n_seg + 1], box b's
+ * segments (rays in order) before box b+1's -- plus ray_offsets [n_rays + 1]
+ * and seg_ids [n_seg] listing each ray's segments front to back.  Optional
+ * (may be NULL): src [n_pieces] int64, the input sample each piece comes from
+ * (for evaluating the owning region's field there), and seg_box [n_seg]
+ * int32.  n_seg must be the plan's.  Samples that break the sortedness
+ * contract give unspecified pieces, never stores outside these arrays.
+ */
+int xl_pack_fill(const xl_rays* rays, const int32_t* axis, const float* plane, int32_t levels,
+                 void* workspace, size_t workspace_bytes, int64_t n_seg, float* t_start,
+                 float* t_end, int64_t* src, int64_t* seg_offsets, int64_t* ray_offsets,
+                 int64_t* seg_ids, int32_t* seg_box, void* stream);
+
+/*
  * Render server: continuous batching of novel-view requests (the inference
  * path of App. A.2: per-region composite, then the merge on one device).
  * Requests are generated on the device (stand-in for per-region NeRF

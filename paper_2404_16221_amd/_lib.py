@@ -40,6 +40,11 @@ class XLGenParams(_c.Structure):
                 ("t_far", _c.c_double), ("seed", _c.c_uint64)]
 
 
+class XLRays(_c.Structure):
+    _fields_ = [("origins", _vp), ("dirs", _vp), ("t_start", _vp), ("t_end", _vp),
+                ("ray_offsets", _vp), ("n_rays", _i64)]
+
+
 class XLError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libxl error {code}: {msg}")
@@ -64,6 +69,12 @@ SIGNATURES = {
                                _c.POINTER(_i64), _vp]),
     "xl_gen_fill": (_c.c_int, [_c.POINTER(XLGenParams), _i32, _vp, _sz, _i64, _vp, _vp, _vp, _vp,
                                _vp, _vp, _vp, _vp]),
+    "xl_partition_build": (_c.c_int, [_vp, _i64, _i32, _vp, _vp]),
+    "xl_pack_workspace_bytes": (_sz, [_i64, _i32]),
+    "xl_pack_plan": (_c.c_int, [_c.POINTER(XLRays), _vp, _vp, _i32, _vp, _sz, _c.POINTER(_i64),
+                                _c.POINTER(_i64), _vp]),
+    "xl_pack_fill": (_c.c_int, [_c.POINTER(XLRays), _vp, _vp, _i32, _vp, _sz, _i64, _vp, _vp, _vp,
+                                _vp, _vp, _vp, _vp, _vp]),
 }
 
 
@@ -238,4 +249,69 @@ def xl_gen(w, dtype=torch.float32, ray0: int = 0, n_rays: Optional[int] = None,
                          _dev(out["t_start"], "t_start"), _dev(out["t_end"], "t_end"),
                          _dev(out["seg_offsets"], "seg_offsets"), _dev(out["ray_offsets"], "ray_offsets"),
                          _dev(out["seg_ids"], "seg_ids"), _stream()))
+    return out
+
+
+def xl_partition_build(points, levels: int):
+    """(axis int32 [2^levels - 1], plane float32 [...]) of the CDF partition of
+    `points` (host array-like [n, 3], float32).  Runs on the host."""
+    import numpy as np
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.float32).reshape(-1, 3))
+    k1 = max((1 << levels) - 1, 0) if 0 <= levels <= 30 else 0
+    axis = np.zeros(max(k1, 1), dtype=np.int32)
+    plane = np.zeros(max(k1, 1), dtype=np.float32)
+    _check(lib().xl_partition_build(pts.ctypes.data if pts.size else None, pts.shape[0], levels,
+                                    axis.ctypes.data, plane.ctypes.data))
+    return axis[:k1], plane[:k1]
+
+
+def _tree(axis, plane, device):
+    a = torch.as_tensor(axis, dtype=torch.int32).to(device).contiguous()
+    p = torch.as_tensor(plane, dtype=torch.float32).to(device).contiguous()
+    if a.numel() == 0:  # the one-box tree: the kernels read nothing
+        a = torch.zeros(1, dtype=torch.int32, device=device)
+        p = torch.zeros(1, dtype=torch.float32, device=device)
+    return a, p
+
+
+def xl_pack(origins, dirs, t_start, t_end, ray_offsets, axis, plane, levels: int,
+            with_src: bool = True) -> dict:
+    """Cut, tag and pack ray-major samples region-major (xl_pack_plan + xl_pack_fill).
+
+    origins, dirs: device float32 [R, 3]; t_start, t_end: device float32 [n];
+    ray_offsets: device int64 [R + 1]; axis, plane: the partition tree (host or
+    device).  Returns device tensors t_start, t_end, src (or None),
+    seg_offsets, ray_offsets, seg_ids, seg_box."""
+    dev = origins.device
+    R = origins.shape[0]
+    if origins.shape != (R, 3) or dirs.shape != (R, 3) or ray_offsets.shape != (R + 1,):
+        raise ValueError("shapes must be origins[R,3], dirs[R,3], ray_offsets[R+1]")
+    if t_start.shape != t_end.shape or t_start.dim() != 1:
+        raise ValueError("t_start and t_end must be 1-D of one length")
+    a, p = _tree(axis, plane, dev)
+    if t_start.numel() == 0:  # rays without samples: any readable address will do
+        t_start = t_end = torch.zeros(1, dtype=torch.float32, device=dev)
+    rays = XLRays(_dev(origins, "origins", torch.float32), _dev(dirs, "dirs", torch.float32),
+                  _dev(t_start, "t_start", torch.float32), _dev(t_end, "t_end", torch.float32),
+                  _dev(ray_offsets, "ray_offsets", torch.int64), R)
+    L = lib()
+    wsb = L.xl_pack_workspace_bytes(R, levels)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    npc, nseg = _i64(0), _i64(0)
+    _check(L.xl_pack_plan(ctypes.byref(rays), a.data_ptr(), p.data_ptr(), levels, ws.data_ptr(), wsb,
+                          ctypes.byref(npc), ctypes.byref(nseg), _stream()))
+    n, n_seg = npc.value, nseg.value
+    out = dict(t_start=torch.empty(n, dtype=torch.float32, device=dev),
+               t_end=torch.empty(n, dtype=torch.float32, device=dev),
+               src=torch.empty(n, dtype=torch.int64, device=dev) if with_src else None,
+               seg_offsets=torch.empty(n_seg + 1, dtype=torch.int64, device=dev),
+               ray_offsets=torch.empty(R + 1, dtype=torch.int64, device=dev),
+               seg_ids=torch.empty(n_seg, dtype=torch.int64, device=dev),
+               seg_box=torch.empty(n_seg, dtype=torch.int32, device=dev))
+    _check(L.xl_pack_fill(ctypes.byref(rays), a.data_ptr(), p.data_ptr(), levels, ws.data_ptr(), wsb,
+                          n_seg, _dev(out["t_start"], "t_start"), _dev(out["t_end"], "t_end"),
+                          _dev(out["src"], "src") if with_src else None,
+                          _dev(out["seg_offsets"], "seg_offsets"),
+                          _dev(out["ray_offsets"], "ray_offsets"), _dev(out["seg_ids"], "seg_ids"),
+                          _dev(out["seg_box"], "seg_box"), _stream()))
     return out

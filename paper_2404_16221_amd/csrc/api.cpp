@@ -244,4 +244,63 @@ int xl_gen_fill(const xl_gen_params* p, int32_t dtype, void* workspace, size_t w
                     "xl_gen_fill");
 }
 
+int xl_partition_build(const float* points, int64_t n_points, int32_t levels, int32_t* axis,
+                       float* plane) {
+  if (levels < 0 || levels > 6) return fail(XL_EINVAL, "levels must be in [0, 6], got %d", levels);
+  if (n_points < 0) return fail(XL_EINVAL, "negative point count");
+  if (n_points > 0 && points == nullptr) return fail(XL_EINVAL, "points is NULL");
+  if (levels > 0 && (axis == nullptr || plane == nullptr))
+    return fail(XL_EINVAL, "axis or plane is NULL");
+  if (xl::partition_build(points, n_points, levels, axis, plane) != XL_OK)
+    return fail(XL_EINVAL, "points must be finite");
+  return ok();
+}
+
+static int check_pack(const xl_rays* rays, const int32_t* axis, const float* plane, int32_t levels,
+                      void* workspace, size_t workspace_bytes) {
+  if (rays == nullptr) return fail(XL_EINVAL, "rays descriptor is NULL");
+  if (levels < 0 || levels > 6) return fail(XL_EINVAL, "levels must be in [0, 6], got %d", levels);
+  if (rays->n_rays < 0) return fail(XL_EINVAL, "negative ray count");
+  if (rays->ray_offsets == nullptr) return fail(XL_EINVAL, "ray_offsets is NULL");
+  if (rays->n_rays > 0 && (!rays->origins || !rays->dirs || !rays->t_start || !rays->t_end))
+    return fail(XL_EINVAL, "NULL ray or sample array");
+  if (levels > 0 && (axis == nullptr || plane == nullptr))
+    return fail(XL_EINVAL, "axis or plane is NULL");
+  if (workspace == nullptr || workspace_bytes < xl::pack_workspace_bytes(rays->n_rays, levels))
+    return fail(XL_EINVAL, "workspace missing or too small (%zu < %zu bytes)", workspace_bytes,
+                xl::pack_workspace_bytes(rays->n_rays, levels));
+  return XL_OK;
+}
+
+size_t xl_pack_workspace_bytes(int64_t n_rays, int32_t levels) {
+  if (n_rays < 0 || levels < 0 || levels > 6) return 0;
+  return xl::pack_workspace_bytes(n_rays, levels);
+}
+
+int xl_pack_plan(const xl_rays* rays, const int32_t* axis, const float* plane, int32_t levels,
+                 void* workspace, size_t workspace_bytes, int64_t* n_pieces, int64_t* n_seg,
+                 void* stream) {
+  int rc = check_pack(rays, axis, plane, levels, workspace, workspace_bytes);
+  if (rc) return rc;
+  if (!n_pieces || !n_seg) return fail(XL_EINVAL, "NULL outputs");
+  return hip_status(xl::pack_plan(rays, axis, plane, levels, workspace,
+                                  static_cast<hipStream_t>(stream), n_pieces, n_seg),
+                    "xl_pack_plan");
+}
+
+int xl_pack_fill(const xl_rays* rays, const int32_t* axis, const float* plane, int32_t levels,
+                 void* workspace, size_t workspace_bytes, int64_t n_seg, float* t_start,
+                 float* t_end, int64_t* src, int64_t* seg_offsets, int64_t* ray_offsets,
+                 int64_t* seg_ids, int32_t* seg_box, void* stream) {
+  int rc = check_pack(rays, axis, plane, levels, workspace, workspace_bytes);
+  if (rc) return rc;
+  if (n_seg < 0) return fail(XL_EINVAL, "negative segment count");
+  if (!seg_offsets || !ray_offsets || (n_seg > 0 && (!t_start || !t_end || !seg_ids)))
+    return fail(XL_EINVAL, "NULL output array");
+  return hip_status(xl::pack_fill(rays, axis, plane, levels, workspace, n_seg, t_start, t_end, src,
+                                  seg_offsets, ray_offsets, seg_ids, seg_box,
+                                  static_cast<hipStream_t>(stream)),
+                    "xl_pack_fill");
+}
+
 }  // extern "C"

@@ -51,4 +51,20 @@ hipError_t gen_fill(const xl_gen_params* p, int dtype, void* ws, int64_t n_seg, 
                     void* rgb, float* t_start, float* t_end, int64_t* seg_offsets,
                     int64_t* ray_offsets, int64_t* seg_ids, hipStream_t st);
 
+// Exclusive scan of int64 (gen.hip): out[0..n] with out[n] = total; tmp holds
+// scan_tmp_elems(n) entries.
+size_t scan_tmp_elems(int64_t n);
+hipError_t scan_exclusive(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, size_t tmp_elems,
+                          hipStream_t st);
+
+// Spatial partitioning (partition.cpp, host) and sample distribution (pack.hip).
+int partition_build(const float* points, int64_t n, int levels, int32_t* axis, float* plane);
+size_t pack_workspace_bytes(int64_t n_rays, int levels);
+hipError_t pack_plan(const xl_rays* rays, const int32_t* axis, const float* plane, int levels,
+                     void* ws, hipStream_t st, int64_t* n_pieces, int64_t* n_seg);
+hipError_t pack_fill(const xl_rays* rays, const int32_t* axis, const float* plane, int levels,
+                     void* ws, int64_t n_seg, float* t_start, float* t_end, int64_t* src,
+                     int64_t* seg_offsets, int64_t* ray_offsets, int64_t* seg_ids, int32_t* seg_box,
+                     hipStream_t st);
+
 }  // namespace xl

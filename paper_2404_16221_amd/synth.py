@@ -425,3 +425,82 @@ def serve_workload(width: int, height: int, seed: int) -> Workload:
     """The serving scene (K=32) at one image size: one ray per pixel."""
     return replace(WORKLOADS[3], name=f"k32-serve-{width}x{height}", n_rays=width * height,
                    seed=seed)
+
+
+# ---------------------------------------------------------------- ray-major inputs
+# Inputs of the sample-distribution step: rays (origin, direction) and their
+# samples before any region is known.  The same seeded rays as the workloads.
+
+def ray_geometry(w: Workload, rays: Sequence[int]) -> Tuple[np.ndarray, np.ndarray]:
+    """Origins and unit directions (float64 [R, 3]) of rays `rays` of workload w."""
+    rays = np.asarray(rays, dtype=np.int64)
+    keys = ray_keys(w.seed, rays)
+    o = np.stack([2.0 * u01(draw(keys, c)) - 1.0 for c in range(3)], axis=1)
+    return o, _directions(keys)
+
+
+def sample_points(w: Workload, rays: Sequence[int]) -> np.ndarray:
+    """Float32 [n, 3] midpoints of the samples of `rays`: a point cloud from
+    discretised rays, the stand-in for structure-from-motion points."""
+    b = generate(w.plain(), rays=rays)
+    o, d = ray_geometry(w, rays)
+    ray_of = np.repeat(np.arange(len(rays)), np.diff(b.ray_offsets))
+    seg_len = np.diff(b.seg_offsets)
+    sample_ray = np.repeat(ray_of, seg_len)
+    mid = 0.5 * (b.t_start.astype(np.float64) + b.t_end.astype(np.float64))
+    return (o[sample_ray] + mid[:, None] * d[sample_ray]).astype(np.float32)
+
+
+def random_rays(seed: int, n_rays: int, n_max: int, spread: float = 1.0,
+                zero_frac: float = 0.05):
+    """Small random ray batches for parity cases: origins U[-spread, spread)^3,
+    unit directions, 0..n_max samples per ray with exponential widths (mean
+    0.05) and a fraction of zero-length samples.  Returns float32 origins,
+    dirs [R, 3], t_start, t_end [n] and int64 ray_offsets [R + 1]."""
+    rng = np.random.default_rng(seed)
+    o = rng.uniform(-spread, spread, size=(n_rays, 3)).astype(np.float32)
+    d = rng.normal(size=(n_rays, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    cnt = rng.integers(0, n_max + 1, size=n_rays)
+    ro = np.zeros(n_rays + 1, np.int64)
+    np.cumsum(cnt, out=ro[1:])
+    ts, te = [], []
+    for c in cnt:
+        wd = rng.exponential(0.05, size=c)
+        wd[rng.random(c) < zero_frac] = 0.0
+        e = np.cumsum(wd) + rng.uniform(0, 0.5)
+        s = np.concatenate([[e[0] - wd[0]], e[:-1]]) if c else e
+        ts.append(s.astype(np.float32))
+        te.append(e.astype(np.float32))
+    ts = np.concatenate(ts) if ts else np.zeros(0, np.float32)
+    te = np.concatenate(te) if te else np.zeros(0, np.float32)
+    return o, d, ts, np.maximum(te, ts), ro
+
+
+def grid_tree(grid: Tuple[int, int, int], lo: float = -1.0, hi: float = 1.0):
+    """A uniform gx x gy x gz grid over [lo, hi]^3 (power-of-two sides) as a
+    partition tree in heap order: each level halves the axis with the most
+    cells left (ties to x, then y).  Returns (axis, plane, levels)."""
+    g = [int(v) for v in grid]
+    for v in g:
+        if v < 1 or v & (v - 1):
+            raise ValueError("grid sides must be powers of two")
+    levels = sum(v.bit_length() - 1 for v in g)
+    axis = np.zeros((1 << levels) - 1, np.int32)
+    plane = np.zeros((1 << levels) - 1, np.float32)
+
+    def split(node, c0, c1, depth):
+        if depth == levels:
+            return
+        sizes = [c1[a] - c0[a] for a in range(3)]
+        a = int(np.argmax(sizes))
+        m = (c0[a] + c1[a]) // 2
+        axis[node] = a
+        plane[node] = np.float32(lo + (hi - lo) * m / g[a])
+        c1_low, c0_high = list(c1), list(c0)
+        c1_low[a] = c0_high[a] = m
+        split(2 * node + 1, c0, c1_low, depth + 1)
+        split(2 * node + 2, c0_high, c1, depth + 1)
+
+    split(0, [0, 0, 0], g, 0)
+    return axis, plane, levels

@@ -1,0 +1,156 @@
+"""GPU sample distribution (tag / split / pack) against the oracle: bit-exact
+integer layout and piece ends, then the whole partitioned render of the cut
+samples against the oracle's render of the oracle's cut samples."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import partition as P
+from oracle import render as O
+from paper_2404_16221_amd import _lib as xl
+from paper_2404_16221_amd import synth
+from tests.parity import assert_tuples, sample_rays
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("t_start", "t_end", "src", "seg_offsets", "ray_offsets", "seg_ids", "seg_box")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev_pack(o, d, ts, te, ro, axis, plane, levels):
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = xl.xl_pack(T(o), T(d), T(ts), T(te), T(ro), axis, plane, levels)
+    torch.cuda.synchronize()
+    return {k: out[k].cpu().numpy() for k in KEYS}
+
+
+def assert_same_pack(got, ref, what):
+    for k in KEYS:
+        g, r = got[k], ref[k]
+        assert g.shape == r.shape, f"{what} {k}: shape {g.shape} vs {r.shape}"
+        if g.dtype == np.float32:
+            assert np.array_equal(g.view(np.uint32), r.view(np.uint32)), f"{what} {k} differs"
+        else:
+            assert np.array_equal(g, r.astype(g.dtype)), f"{what} {k} differs"
+
+
+def tree_for(levels, seed, scale=0.6):
+    pts = np.random.default_rng(seed).normal(scale=scale, size=(3000, 3)).astype(np.float32)
+    return xl.xl_partition_build(pts, levels)
+
+
+@pytest.mark.parametrize("levels", [0, 1, 3, 4, 6])
+def test_random_rays_bit_exact(levels):
+    say(f"pack random rays, {1 << levels} boxes")
+    o, d, ts, te, ro = synth.random_rays(100 + levels, 200, 70)
+    axis, plane = tree_for(levels, levels)
+    ref = P.tag_split_pack(o, d, ts, te, ro, axis, plane, levels)
+    got = dev_pack(o, d, ts, te, ro, axis, plane, levels)
+    assert_same_pack(got, ref, f"levels {levels}")
+    if levels >= 3:
+        assert got["src"].shape[0] > ts.shape[0]  # samples were cut
+
+
+def test_edge_cases_bit_exact():
+    axis, plane = tree_for(3, 9)
+    # no rays
+    o = np.zeros((0, 3), np.float32)
+    e = np.zeros(0, np.float32)
+    got = dev_pack(o, o, e, e, np.zeros(1, np.int64), axis, plane, 3)
+    assert got["seg_offsets"].tolist() == [0] and got["ray_offsets"].tolist() == [0]
+    # rays without samples, and rays of zero-length samples only
+    say("pack edge cases")
+    o, d, ts, te, ro = synth.random_rays(5, 64, 0)
+    got = dev_pack(o, d, ts, te, ro, axis, plane, 3)
+    assert got["ray_offsets"].tolist() == [0] * 65
+    o, d, ts, te, ro = synth.random_rays(6, 64, 12, zero_frac=1.0)
+    assert_same_pack(dev_pack(o, d, ts, te, ro, axis, plane, 3),
+                     P.tag_split_pack(o, d, ts, te, ro, axis, plane, 3), "zero-length samples")
+    # axis-parallel rays, rays lying in split planes, rays far outside the cloud
+    o, d, ts, te, ro = synth.random_rays(7, 96, 40, spread=4.0)
+    d[0:32] = 0.0
+    d[np.arange(32), np.arange(32) % 3] = np.where(np.arange(32) % 2, 1.0, -1.0)
+    a0 = int(axis[0])
+    o[32:48, a0] = plane[0]
+    d[32:48, a0] = 0.0
+    d[32:48] /= np.linalg.norm(d[32:48], axis=1, keepdims=True).astype(np.float32)
+    ref = P.tag_split_pack(o, d, ts, te, ro, axis, plane, 3)
+    assert_same_pack(dev_pack(o, d, ts, te, ro, axis, plane, 3), ref, "parallel rays")
+
+
+def test_workload_rays_bit_exact_and_render():
+    """k16 rays (8..1024 samples) cut by a 16-box CDF partition built from
+    other rays' samples; then the cut samples, each with its source sample's
+    density and colour, rendered through the composite and merge kernels
+    against the oracle's render of the oracle's cut samples."""
+    w = synth.WORKLOADS[2]
+    rays = np.arange(40, dtype=np.int64)
+    axis, plane = xl.xl_partition_build(synth.sample_points(w, np.arange(1000, 1400)), 4)
+    b = synth.generate(w.plain(), rays=rays)
+    o, d = synth.ray_geometry(w, rays)
+    o, d = o.astype(np.float32), d.astype(np.float32)
+    ro = b.seg_offsets  # one segment per ray (every ray has samples)
+    say(f"pack k16 rays: {b.n} samples")
+    ref = P.tag_split_pack(o, d, b.t_start, b.t_end, ro, axis, plane, 4)
+    got = dev_pack(o, d, b.t_start, b.t_end, ro, axis, plane, 4)
+    assert_same_pack(got, ref, "k16 rays")
+    # render the device's pieces with the library, the oracle's with the oracle
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    src = torch.from_numpy(got["src"]).cuda()
+    sig = T(b.sigma)[src].contiguous()
+    rgb = T(b.rgb)[src].contiguous()
+    seg_out, _ = xl.xl_render_segments_fwd(sig, rgb, T(got["t_start"]), T(got["t_end"]),
+                                           T(got["seg_offsets"]))
+    ray_out = xl.xl_merge_fwd(seg_out, T(got["ray_offsets"]), T(got["seg_ids"]))
+    want = O.render_rays_single(b.sigma[ref["src"]], b.rgb[ref["src"]], ref["t_start"],
+                                ref["t_end"], ref["seg_offsets"], ref["ray_offsets"],
+                                ref["seg_ids"])
+    assert_tuples(ray_out.cpu().numpy(), want, "ray", "k16 cut samples rendered")
+
+
+def test_k16_all_rays_full_size():
+    """All 262,144 k16 rays (135M samples) in one pack, as the benchmark runs
+    it; sampled rays against the oracle run on those rays alone."""
+    w = synth.WORKLOADS[2]
+    g = xl.xl_gen(w.plain(), torch.float32)
+    o, d = synth.ray_geometry(w, np.arange(w.n_rays))
+    axis, plane = xl.xl_partition_build(synth.sample_points(w, np.arange(0, w.n_rays, 64)), 4)
+    say(f"pack k16 full size: {g['t_start'].shape[0]} samples")
+    out = xl.xl_pack(torch.from_numpy(o.astype(np.float32)).cuda(),
+                     torch.from_numpy(d.astype(np.float32)).cuda(),
+                     g["t_start"], g["t_end"], g["seg_offsets"], axis, plane, 4)
+    torch.cuda.synchronize()
+    n_in = g["t_start"].shape[0]
+    n = out["t_start"].shape[0]
+    say(f"  {n} pieces, {out['seg_ids'].shape[0]} segments")
+    assert n >= n_in
+    # region-major: box ids never decrease along the segments
+    assert bool((out["seg_box"][1:] >= out["seg_box"][:-1]).all())
+    # the pieces of every sample tile it: lengths add up per source sample
+    ln = (out["t_end"] - out["t_start"]).double()
+    per_src = torch.zeros(n_in, dtype=torch.float64, device="cuda").index_add_(0, out["src"], ln)
+    full = (g["t_end"] - g["t_start"]).double()
+    assert float((per_src - full).abs().max()) <= 1e-5
+    # sampled rays, bit-exact against the oracle on those rays
+    rays = sample_rays(w.n_rays, 24, 77)
+    h = synth.generate(w.plain(), rays=rays)
+    ref = P.tag_split_pack(o[rays].astype(np.float32), d[rays].astype(np.float32), h.t_start,
+                           h.t_end, h.seg_offsets, axis, plane, 4)
+    ro, so = out["ray_offsets"].cpu().numpy(), out["seg_offsets"]
+    base_in = g["seg_offsets"].cpu().numpy()
+    for k, r in enumerate(rays):
+        segs = out["seg_ids"][ro[r]:ro[r + 1]]
+        rsegs = ref["seg_ids"][ref["ray_offsets"][k]:ref["ray_offsets"][k + 1]]
+        assert segs.shape[0] == rsegs.shape[0], f"ray {r}: segment count"
+        assert np.array_equal(out["seg_box"][segs].cpu().numpy(), ref["seg_box"][rsegs])
+        for s, rs in zip(segs.cpu().numpy(), rsegs):
+            a, b = so[s].item(), so[s + 1].item()
+            ra, rb = ref["seg_offsets"][rs], ref["seg_offsets"][rs + 1]
+            assert np.array_equal(out["t_start"][a:b].cpu().numpy(), ref["t_start"][ra:rb])
+            assert np.array_equal(out["t_end"][a:b].cpu().numpy(), ref["t_end"][ra:rb])
+            src_local = out["src"][a:b].cpu().numpy() - base_in[r]
+            ref_local = ref["src"][ra:rb] - h.seg_offsets[k]
+            assert np.array_equal(src_local, ref_local), f"ray {r}: sources"

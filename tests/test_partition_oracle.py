@@ -4,6 +4,8 @@ import numpy as np
 import pytest
 
 from oracle import partition as P
+from oracle import render as O
+from paper_2404_16221_amd import synth
 
 
 def lattice(n):
@@ -110,30 +112,9 @@ def test_ray_on_a_plane_parallel_to_it_goes_high():
     assert out["seg_box"].tolist() == [1] and out["seg_offsets"].tolist() == [0, 2]
 
 
-def random_rays(rng, R, nmax, spread=1.0):
-    o = rng.uniform(-spread, spread, size=(R, 3)).astype(np.float32)
-    d = rng.normal(size=(R, 3))
-    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
-    cnt = rng.integers(0, nmax + 1, size=R)
-    ro = np.zeros(R + 1, np.int64)
-    np.cumsum(cnt, out=ro[1:])
-    ts, te = [], []
-    for c in cnt:
-        w = rng.exponential(0.05, size=c)
-        w[rng.random(c) < 0.05] = 0.0          # some zero-width samples
-        e = np.cumsum(w) + rng.uniform(0, 0.5)
-        s = np.concatenate([[e[0] - w[0]], e[:-1]]) if c else e
-        ts.append(s.astype(np.float32))
-        te.append(e.astype(np.float32))
-    ts = np.concatenate(ts) if ts else np.zeros(0, np.float32)
-    te = np.concatenate(te) if te else np.zeros(0, np.float32)
-    te = np.maximum(te, ts)
-    return o, d, ts, te, ro
-
-
 def test_pieces_tile_samples_and_lie_in_their_boxes():
     rng = np.random.default_rng(7)
-    o, d, ts, te, ro = random_rays(rng, 60, 40)
+    o, d, ts, te, ro = synth.random_rays(7, 60, 40)
     pts = rng.normal(scale=0.6, size=(2000, 3)).astype(np.float32)
     axis, plane = P.cdf_partition(pts, 3)
     out = P.tag_split_pack(o, d, ts, te, ro, axis, plane, 3)
@@ -179,11 +160,32 @@ def test_pieces_tile_samples_and_lie_in_their_boxes():
 
 
 def test_one_box_returns_the_input():
-    rng = np.random.default_rng(8)
-    o, d, ts, te, ro = random_rays(rng, 30, 20)
+    o, d, ts, te, ro = synth.random_rays(8, 30, 20)
     out = P.tag_split_pack(o, d, ts, te, ro, np.zeros(0, np.int32), np.zeros(0, np.float32), 0)
     assert np.array_equal(out["t_start"], ts) and np.array_equal(out["t_end"], te)
     assert np.array_equal(out["src"], np.arange(ts.shape[0]))
     nonempty = np.flatnonzero(np.diff(ro) > 0)
     assert np.array_equal(out["seg_offsets"], np.append(ro[nonempty], ro[-1]))
     assert np.array_equal(np.diff(out["ray_offsets"]), (np.diff(ro) > 0).astype(np.int64))
+
+
+def test_splitting_keeps_transmittance_colour_and_opacity():
+    # a piece inherits its sample's density and colour: cutting [s, e) at u
+    # multiplies the transmittances exp(-sigma (u - s)) exp(-sigma (e - u)) and
+    # splits the alpha-weighted colour exactly, so T, C and A of every ray
+    # are unchanged (depth and distortion use piece midpoints and may move)
+    o, d, ts, te, ro = synth.random_rays(9, 40, 30)
+    rng = np.random.default_rng(9)
+    sig = rng.lognormal(0.0, 1.5, size=ts.shape[0])
+    rgb = rng.random((ts.shape[0], 3))
+    pts = rng.normal(scale=0.5, size=(500, 3)).astype(np.float32)
+    axis, plane = P.cdf_partition(pts, 4)
+    out = P.tag_split_pack(o, d, ts, te, ro, axis, plane, 4)
+    assert out["src"].shape[0] > ts.shape[0]
+    split = O.render_rays_single(sig[out["src"]], rgb[out["src"]], out["t_start"], out["t_end"],
+                                 out["seg_offsets"], out["ray_offsets"], out["seg_ids"])
+    R = o.shape[0]
+    has = np.diff(ro) > 0
+    whole = O.render_rays_single(sig, rgb, ts, te, np.append(ro[:-1][has], ro[-1]),
+                                 np.concatenate([[0], np.cumsum(has)]), np.arange(int(has.sum())))
+    np.testing.assert_allclose(split[:5], whole[:5], rtol=1e-12, atol=1e-14)
