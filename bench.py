@@ -260,6 +260,56 @@ def serving(n_req, warmup, rate):
     return out
 
 
+def distribution(steps, warmup):
+    """Sample distribution (tag / split / pack) of all k16 rays (ray-major, 135M
+    samples) into 16 boxes, for the uniform 4x2x2 grid and for the CDF
+    partition built from the samples of every 64th ray; time per pack (plan,
+    whose size read-back synchronises, plus fill) and samples per box."""
+    from paper_2404_16221_amd import _lib as xl
+    from paper_2404_16221_amd import synth
+    w = synth.WORKLOADS[2]
+    g = xl.xl_gen(w.plain(), torch.float32)
+    o, d = synth.ray_geometry(w, np.arange(w.n_rays))
+    o = torch.from_numpy(o.astype(np.float32)).cuda()
+    d = torch.from_numpy(d.astype(np.float32)).cuda()
+    t = time.perf_counter()
+    pts = synth.sample_points(w, np.arange(0, w.n_rays, 64))
+    t_pts = time.perf_counter() - t
+    t = time.perf_counter()
+    cdf = xl.xl_partition_build(pts, 4)
+    t_build = time.perf_counter() - t
+    grid_axis, grid_plane, _ = synth.grid_tree(w.grid)
+    n_in = g["t_start"].shape[0]
+    res = {"workload": f"{w.name} rays, ray-major, {n_in} samples, 16 boxes",
+           "cdf_points": int(pts.shape[0]), "cdf_build_s": t_build, "cdf_points_s": t_pts}
+    for name, (axis, plane) in (("grid_4x2x2", (grid_axis, grid_plane)), ("cdf", cdf)):
+        def call():
+            return xl.xl_pack(o, d, g["t_start"], g["t_end"], g["seg_offsets"], axis, plane, 4)
+        for _ in range(warmup):
+            out = call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            out = call()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        n, n_seg = out["t_start"].shape[0], out["seg_ids"].shape[0]
+        seg_len = (out["seg_offsets"][1:] - out["seg_offsets"][:-1]).double()
+        per_box = torch.zeros(16, dtype=torch.float64, device="cuda").index_add_(
+            0, out["seg_box"].long(), seg_len).cpu().numpy()
+        alg = n_in * 8 + w.n_rays * (24 + 8 + 8) + n * 16 + n_seg * 20
+        res[name] = {"ms": ms, "samples_per_s": n_in / (ms * 1e-3), "pieces": int(n),
+                     "segments": int(n_seg), "algorithmic_gbs": alg / (ms * 1e-3) / 1e9,
+                     "samples_per_box_max_over_mean": float(per_box.max() / per_box.mean()),
+                     "samples_per_box_min_over_mean": float(per_box.min() / per_box.mean()),
+                     "samples_per_box_cv": float(per_box.std() / per_box.mean())}
+        log("distribution", name, json.dumps(res[name]))
+        del out
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +317,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="bf16,fp32,plain,k64")
+    ap.add_argument("--no-distribution", action="store_true",
+                    help="skip the tag/split/pack timing")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="measured serving requests (0 skips the serving run)")
     ap.add_argument("--serve-warmup", type=int, default=30)
@@ -284,8 +336,8 @@ def main():
                           "bytes_written": y.numel() * 4}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU exchange "
-              "of segment tuples is a design in DESIGN.md, not part of this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the exchange of segment "
+              "tuples between GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
     import paper_2404_16221_amd  # noqa: F401  (fails loudly without libxl.so)
     from paper_2404_16221_amd import _lib as xl
@@ -354,6 +406,8 @@ def main():
                      "kernel": "seg_bwd_kernel", "step_achieved": hr["step_gbs"],
                      "step_frac": hr["step_gbs"] / HBM_PEAK_GBS},
     }
+    if not args.no_distribution:
+        out["distribution"] = distribution(max(args.steps // 2, 3), 2)
     if args.serve_requests > 0:
         for f in forms.values():
             f.release()

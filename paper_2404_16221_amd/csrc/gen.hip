@@ -458,6 +458,7 @@ __global__ void gen_fill_kernel(GenDev g, GenWs w, void* __restrict__ sigma, voi
 // totals scanned recursively (scratch: ceil(n/1024) + ceil(n/1024^2) + ...).
 constexpr int kScanBlock = 1024;
 
+// With a single block (sums == nullptr) the block also writes the total to out[n].
 __global__ __launch_bounds__(kScanBlock) void scan_block_kernel(const int64_t* __restrict__ in,
                                                                 int64_t* __restrict__ out, int64_t n,
                                                                 int64_t* __restrict__ sums) {
@@ -485,12 +486,17 @@ __global__ __launch_bounds__(kScanBlock) void scan_block_kernel(const int64_t* _
   __syncthreads();
   const int64_t before = wave > 0 ? wsum[wave - 1] : 0;
   if (i < n) out[i] = before + v - x;
-  if (threadIdx.x == kScanBlock - 1) sums[blockIdx.x] = wsum[kScanBlock / kWave - 1];
+  if (threadIdx.x == kScanBlock - 1) {
+    if (sums) sums[blockIdx.x] = wsum[kScanBlock / kWave - 1];
+    else out[n] = wsum[kScanBlock / kWave - 1];
+  }
 }
 
+// Adds the scanned block totals; offs has nb + 1 entries, offs[nb] = total.
 __global__ void scan_add_kernel(int64_t* __restrict__ out, int64_t n, const int64_t* __restrict__ offs) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kScanBlock + threadIdx.x;
   if (i < n) out[i] += offs[blockIdx.x];
+  if (i == 0) out[n] = offs[gridDim.x];
 }
 
 __global__ void scan_total_kernel(int64_t* __restrict__ out, int64_t n, const int64_t* __restrict__ in) {
@@ -519,14 +525,13 @@ hipError_t scan_exclusive(const int64_t* in, int64_t* out, int64_t n, int64_t* t
   int64_t* sums = tmp;
   int64_t* offs = tmp + nb;
   hipLaunchKernelGGL(scan_block_kernel, dim3(static_cast<unsigned>(nb)), dim3(kScanBlock), 0, st, in,
-                     out, n, sums);
+                     out, n, nb > 1 ? sums : nullptr);
   if (nb > 1) {
     hipError_t e = scan_exclusive(sums, offs, nb, offs + nb + 1, tmp_elems - (2 * nb + 1), st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(scan_add_kernel, dim3(static_cast<unsigned>(nb)), dim3(kScanBlock), 0, st,
                        out, n, offs);
   }
-  hipLaunchKernelGGL(scan_total_kernel, dim3(1), dim3(1), 0, st, out, n, in);
   return hipGetLastError();
 }
 

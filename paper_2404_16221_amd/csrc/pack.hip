@@ -13,16 +13,19 @@
 // interval holds s.  Boxes sharing a face get the same rounded parameter, so
 // the pieces of a sample tile it exactly.
 //
-// Three passes, one wave per ray and one lane per box:
-//   pack_count  each lane: its box's interval and, by two binary searches over
-//               the ray's sorted samples, the run of samples that meet it ->
-//               piece count at [b][r] (box-major, so an exclusive scan gives
-//               region-major slots) and a 0/1 segment flag;
+// Three passes:
+//   pack_count  one lane per (ray, box), 64 / K rays per wave: the box's
+//               interval and, by two binary searches over the ray's sorted
+//               samples, the run of samples that meet it -> piece count at
+//               [b][r] (box-major, so an exclusive scan gives region-major
+//               slots), a 0/1 segment flag, the run's first sample and the
+//               interval;
 //   scans       pieces and segment flags over [K][R], segments per ray;
-//   pack_fill   lanes rank their boxes front to back through LDS, write the
-//               segment lists, then stride over the ray's samples and write
-//               every piece to its slot (consecutive samples of one box go to
-//               consecutive slots).
+//   pack_fill   one wave per ray: lanes load their box's run, rank the boxes
+//               front to back through LDS and write the segment lists, then
+//               the wave strides over the ray's samples and writes every piece
+//               to its slot (consecutive samples of one box go to consecutive
+//               slots).
 // Every store index is bounded by the counts of the plan, so inputs that break
 // the sortedness contract give unspecified pieces but never out-of-range
 // stores.
@@ -55,6 +58,8 @@ struct PackDev {
 struct PackWs {
   int64_t* cnt;      // [K * R] pieces of ray r in box b, at b * R + r
   int64_t* has;      // [K * R] 1 when that count is positive
+  int32_t* first;    // [K * R] first sample of the run (index inside the ray)
+  float2* span;      // [K * R] the box's interval (t_in, t_out) on the ray
   int64_t* off;      // [K * R + 1] first slot of those pieces
   int64_t* sid;      // [K * R + 1] id of that segment
   int64_t* nseg;     // [R] segments of each ray
@@ -127,20 +132,27 @@ __device__ BoxSpan box_span(const PackDev& p, int64_t r, int b, int64_t s0, int6
   return sp;
 }
 
+// 64 / K rays per wave, K consecutive lanes per ray (K divides 64).
 __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(PackDev p, PackWs w) {
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  const int64_t r = static_cast<int64_t>(blockIdx.x) * kPackWaves + wave;
-  if (r >= p.R) return;
-  const int64_t s0 = p.ray_off[r], n = p.ray_off[r + 1] - s0;
+  const int per_wave = kWave / p.K;
+  const int sub = lane / p.K, b = lane % p.K;
+  const int64_t r = (static_cast<int64_t>(blockIdx.x) * kPackWaves + wave) * per_wave + sub;
+  const bool live = r < p.R;
   int64_t cnt = 0;
-  if (lane < p.K) {
-    cnt = box_span(p, r, lane, s0, n).count;
-    const int64_t at = static_cast<int64_t>(lane) * p.R + r;
+  if (live) {
+    const int64_t s0 = p.ray_off[r], n = p.ray_off[r + 1] - s0;
+    const BoxSpan sp = box_span(p, r, b, s0, n);
+    cnt = sp.count;
+    const int64_t at = static_cast<int64_t>(b) * p.R + r;
     w.cnt[at] = cnt;
     w.has[at] = cnt > 0 ? 1 : 0;
+    w.first[at] = static_cast<int32_t>(sp.first);
+    w.span[at] = make_float2(sp.tin, sp.tout);
   }
   const unsigned long long m = __ballot(cnt > 0);
-  if (lane == 0) w.nseg[r] = __popcll(m);
+  const unsigned long long group = p.K == kWave ? ~0ull : (((1ull << p.K) - 1) << (sub * p.K));
+  if (live && b == 0) w.nseg[r] = __popcll(m & group);
 }
 
 __global__ __launch_bounds__(kPackBlock) void pack_fill_kernel(PackDev p, PackWs w,
@@ -160,11 +172,21 @@ __global__ __launch_bounds__(kPackBlock) void pack_fill_kernel(PackDev p, PackWs
     s0 = p.ray_off[r];
     n = p.ray_off[r + 1] - s0;
   }
+  // this lane's box: the run and interval that the count pass found
   BoxSpan sp;
   sp.tin = INFINITY;
   sp.tout = -INFINITY;
   sp.first = sp.count = 0;
-  if (live && lane < p.K) sp = box_span(p, r, lane, s0, n);
+  const int64_t at = static_cast<int64_t>(lane) * p.R + r;
+  if (live && lane < p.K) {
+    sp.count = w.cnt[at];
+    if (sp.count > 0) {
+      const float2 ts = w.span[at];
+      sp.tin = ts.x;
+      sp.tout = ts.y;
+      sp.first = w.first[at];
+    }
+  }
   const bool valid = sp.count > 0;
   s_tin[wave][lane] = valid ? sp.tin : INFINITY;
   __syncthreads();
@@ -178,7 +200,6 @@ __global__ __launch_bounds__(kPackBlock) void pack_fill_kernel(PackDev p, PackWs
   s_cnt[wave][lane] = 0;  // entries no box fills take no pieces
   __syncthreads();
   if (valid) {
-    const int64_t at = static_cast<int64_t>(lane) * p.R + r;
     const int64_t base = w.off[at], id = w.sid[at];
     s_tin[wave][rank] = sp.tin;
     s_tout[wave][rank] = sp.tout;
@@ -192,8 +213,18 @@ __global__ __launch_bounds__(kPackBlock) void pack_fill_kernel(PackDev p, PackWs
   __syncthreads();
   if (!live) return;
   int k0 = 0;
+  // the next chunk's interval is loaded before this chunk's pieces are stored
+  float s_next = 0.f, e_next = 0.f;
+  if (lane < n) {
+    s_next = p.t0[s0 + lane];
+    e_next = p.t1[s0 + lane];
+  }
   for (int64_t j = lane; j < n; j += kWave) {
-    const float s = p.t0[s0 + j], e = p.t1[s0 + j];
+    const float s = s_next, e = e_next;
+    if (j + kWave < n) {
+      s_next = p.t0[s0 + j + kWave];
+      e_next = p.t1[s0 + j + kWave];
+    }
     while (k0 < nv && !(s_tout[wave][k0] > s)) ++k0;  // samples ascend: k0 only grows
     for (int k = k0; k < nv; ++k) {
       const float tin = s_tin[wave][k], tout = s_tout[wave][k];
@@ -226,7 +257,7 @@ __global__ __launch_bounds__(kPackBlock) void pack_fill_kernel(PackDev p, PackWs
 struct PackLayout {
   int64_t R, K, KR;
   size_t scan_elems;
-  size_t off[7];
+  size_t off[9];
   size_t bytes;
 };
 
@@ -239,6 +270,8 @@ PackLayout pack_layout(int64_t R, int levels) {
   const size_t sizes[] = {
       sizeof(int64_t) * L.KR,           // cnt
       sizeof(int64_t) * L.KR,           // has
+      sizeof(int32_t) * L.KR,           // first
+      sizeof(float2) * L.KR,            // span
       sizeof(int64_t) * (L.KR + 1),     // off
       sizeof(int64_t) * (L.KR + 1),     // sid
       sizeof(int64_t) * R,              // nseg
@@ -246,7 +279,7 @@ PackLayout pack_layout(int64_t R, int levels) {
       sizeof(int64_t) * L.scan_elems,   // scan_tmp
   };
   size_t o = 0;
-  for (int i = 0; i < 7; ++i) {
+  for (int i = 0; i < 9; ++i) {
     L.off[i] = o;
     o += (sizes[i] + 255) & ~static_cast<size_t>(255);
   }
@@ -259,11 +292,13 @@ PackWs pack_views(const PackLayout& L, void* ws) {
   PackWs w;
   w.cnt = reinterpret_cast<int64_t*>(b + L.off[0]);
   w.has = reinterpret_cast<int64_t*>(b + L.off[1]);
-  w.off = reinterpret_cast<int64_t*>(b + L.off[2]);
-  w.sid = reinterpret_cast<int64_t*>(b + L.off[3]);
-  w.nseg = reinterpret_cast<int64_t*>(b + L.off[4]);
-  w.ray_off = reinterpret_cast<int64_t*>(b + L.off[5]);
-  w.scan_tmp = reinterpret_cast<int64_t*>(b + L.off[6]);
+  w.first = reinterpret_cast<int32_t*>(b + L.off[2]);
+  w.span = reinterpret_cast<float2*>(b + L.off[3]);
+  w.off = reinterpret_cast<int64_t*>(b + L.off[4]);
+  w.sid = reinterpret_cast<int64_t*>(b + L.off[5]);
+  w.nseg = reinterpret_cast<int64_t*>(b + L.off[6]);
+  w.ray_off = reinterpret_cast<int64_t*>(b + L.off[7]);
+  w.scan_tmp = reinterpret_cast<int64_t*>(b + L.off[8]);
   return w;
 }
 
@@ -282,7 +317,10 @@ PackDev pack_dev(const xl_rays* rays, const int32_t* axis, const float* plane, i
   return p;
 }
 
-unsigned ray_blocks(int64_t R) { return static_cast<unsigned>((R + kPackWaves - 1) / kPackWaves); }
+unsigned ray_blocks(int64_t R, int per_wave = 1) {
+  const int64_t per_block = static_cast<int64_t>(kPackWaves) * per_wave;
+  return static_cast<unsigned>((R + per_block - 1) / per_block);
+}
 
 }  // namespace
 
@@ -294,7 +332,8 @@ hipError_t pack_plan(const xl_rays* rays, const int32_t* axis, const float* plan
   const PackWs w = pack_views(L, ws);
   const PackDev p = pack_dev(rays, axis, plane, levels);
   if (L.R > 0)
-    hipLaunchKernelGGL(pack_count_kernel, dim3(ray_blocks(L.R)), dim3(kPackBlock), 0, st, p, w);
+    hipLaunchKernelGGL(pack_count_kernel, dim3(ray_blocks(L.R, kWave / p.K)), dim3(kPackBlock), 0, st,
+                       p, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = scan_exclusive(w.cnt, w.off, L.KR, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
