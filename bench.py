@@ -305,6 +305,15 @@ def distribution(steps, warmup):
                      "samples_per_box_max_over_mean": float(per_box.max() / per_box.mean()),
                      "samples_per_box_min_over_mean": float(per_box.min() / per_box.mean()),
                      "samples_per_box_cv": float(per_box.std() / per_box.mean())}
+        del out
+        # the same pack without the optional source index of every piece
+        e0.record()
+        for _ in range(steps):
+            out = xl.xl_pack(o, d, g["t_start"], g["t_end"], g["seg_offsets"], axis, plane, 4,
+                             with_src=False)
+        e1.record()
+        torch.cuda.synchronize()
+        res[name]["ms_without_src"] = e0.elapsed_time(e1) / steps
         log("distribution", name, json.dumps(res[name]))
         del out
     return res
