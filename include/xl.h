@@ -264,6 +264,58 @@ int xl_pack_fill(const xl_rays* rays, const int32_t* axis, const float* plane, i
                  int64_t* seg_ids, int32_t* seg_box, void* stream);
 
 /*
+ * Feature channels (App. B.2: breakable integrals are closed under integration
+ * against a breakable factor, Property 2; with the transmittance as that
+ * factor every per-sample feature vector f_i rendered with the volume-rendering
+ * weights splits over regions like colour).  Per segment k, Phi_k =
+ * sum_i w_i f_i with the weights of the colour path (transmittance from 1 at
+ * the segment start); per ray, Phi = sum_k exp(-sum_{j<k} tau_j) Phi_k front
+ * to back.  Uses: semantic logits, normals, learned features, or the squared
+ * depth of a variance estimate.
+ */
+typedef struct xl_features {
+  int32_t dtype;        /* storage of sigma, feat and their gradients */
+  int32_t n_feat;       /* F: 4, 8, 16 or 32 channels */
+  const void* sigma;    /* device [n] */
+  const void* feat;     /* device [n][F], 16-byte aligned */
+  const float* t_start; /* device [n] */
+  const float* t_end;   /* device [n] */
+  int64_t n;
+} xl_features;
+
+/* Per segment: phi_seg float32 [F][n_seg] (written), and tau_seg float32
+ * [n_seg], the segment's optical depth (written; may be NULL).  Samples and
+ * seg_offsets as for xl_render_segments_fwd.  FP32 accumulation. */
+int xl_render_features_fwd(const xl_features* f, const int64_t* seg_offsets, int64_t n_seg,
+                           float* phi_seg, float* tau_seg, void* stream);
+
+/* Per ray: phi_ray float32 [F][n_rays] from tau_seg and phi_seg in the order
+ * of ray_offsets / seg_ids (as for xl_merge_fwd; a ray without segments gets
+ * zeros). */
+int xl_merge_features_fwd(const float* tau_seg, const float* phi_seg, int32_t n_feat, int64_t n_seg,
+                          const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                          float* phi_ray, void* stream);
+
+/* Backward of the merge: grad_ray = dl/dphi_ray [F][n_rays] -> grad_phi_seg
+ * [F][n_seg] = T_{<k} grad_ray and grad_tau_seg [n_seg] = -sum over later
+ * segments of T_{<k'} (grad_ray . phi_k'), for every listed segment (each
+ * listed by at most one ray; unlisted entries are left untouched). */
+int xl_merge_features_bwd(const float* tau_seg, const float* phi_seg, int32_t n_feat, int64_t n_seg,
+                          const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                          const float* grad_ray, float* grad_phi_seg, float* grad_tau_seg,
+                          void* stream);
+
+/* Backward per segment: dl/dsigma [n] and dl/dfeat [n][F] in the storage
+ * dtype.  grad_tau_seg may be NULL (no gradient through later segments).
+ * accumulate_sigma = 1 adds to grad_sigma (e.g. the colour path's), 0
+ * overwrites it; grad_feat is always overwritten.  Transmittance is
+ * recomputed; phi_seg is the forward's output for the same samples. */
+int xl_render_features_bwd(const xl_features* f, const int64_t* seg_offsets, int64_t n_seg,
+                           const float* phi_seg, const float* grad_phi_seg,
+                           const float* grad_tau_seg, void* grad_sigma, void* grad_feat,
+                           int32_t accumulate_sigma, void* stream);
+
+/*
  * Render server: continuous batching of novel-view requests (the inference
  * path of App. A.2: per-region composite, then the merge on one device).
  * Requests are generated on the device (stand-in for per-region NeRF

@@ -45,6 +45,11 @@ class XLRays(_c.Structure):
                 ("ray_offsets", _vp), ("n_rays", _i64)]
 
 
+class XLFeatures(_c.Structure):
+    _fields_ = [("dtype", _i32), ("n_feat", _i32), ("sigma", _vp), ("feat", _vp), ("t_start", _vp),
+                ("t_end", _vp), ("n", _i64)]
+
+
 class XLError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libxl error {code}: {msg}")
@@ -70,6 +75,11 @@ SIGNATURES = {
     "xl_gen_fill": (_c.c_int, [_c.POINTER(XLGenParams), _i32, _vp, _sz, _i64, _vp, _vp, _vp, _vp,
                                _vp, _vp, _vp, _vp]),
     "xl_partition_build": (_c.c_int, [_vp, _i64, _i32, _vp, _vp]),
+    "xl_render_features_fwd": (_c.c_int, [_c.POINTER(XLFeatures), _vp, _i64, _vp, _vp, _vp]),
+    "xl_merge_features_fwd": (_c.c_int, [_vp, _vp, _i32, _i64, _vp, _vp, _i64, _vp, _vp]),
+    "xl_merge_features_bwd": (_c.c_int, [_vp, _vp, _i32, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
+    "xl_render_features_bwd": (_c.c_int, [_c.POINTER(XLFeatures), _vp, _i64, _vp, _vp, _vp, _vp, _vp,
+                                          _i32, _vp]),
     "xl_pack_workspace_bytes": (_sz, [_i64, _i32]),
     "xl_pack_plan": (_c.c_int, [_c.POINTER(XLRays), _vp, _vp, _i32, _vp, _sz, _c.POINTER(_i64),
                                 _c.POINTER(_i64), _vp]),
@@ -315,3 +325,78 @@ def xl_pack(origins, dirs, t_start, t_end, ray_offsets, axis, plane, levels: int
                           _dev(out["ray_offsets"], "ray_offsets"), _dev(out["seg_ids"], "seg_ids"),
                           _dev(out["seg_box"], "seg_box"), _stream()))
     return out
+
+
+def features(sigma, feat, t_start, t_end) -> XLFeatures:
+    if sigma.dtype not in DTYPES or feat.dtype != sigma.dtype:
+        raise ValueError("sigma and feat must share a storage dtype (float32, bfloat16, float16)")
+    n = sigma.shape[0]
+    if feat.dim() != 2 or feat.shape[0] != n or t_start.shape != (n,) or t_end.shape != (n,):
+        raise ValueError("shapes must be sigma[n], feat[n, F], t_start[n], t_end[n]")
+    return XLFeatures(DTYPES[sigma.dtype], feat.shape[1], _dev(sigma, "sigma"), _dev(feat, "feat"),
+                      _dev(t_start, "t_start", torch.float32), _dev(t_end, "t_end", torch.float32), n)
+
+
+def xl_render_features_fwd(sigma, feat, t_start, t_end, seg_offsets, phi_seg=None, tau_seg=None):
+    """(phi_seg [F, n_seg], tau_seg [n_seg]) of every segment."""
+    f = features(sigma, feat, t_start, t_end)
+    n_seg = seg_offsets.shape[0] - 1
+    dev = sigma.device
+    if phi_seg is None:
+        phi_seg = torch.empty((f.n_feat, n_seg), dtype=torch.float32, device=dev)
+    if tau_seg is None:
+        tau_seg = torch.empty(n_seg, dtype=torch.float32, device=dev)
+    _check(lib().xl_render_features_fwd(ctypes.byref(f), _dev(seg_offsets, "seg_offsets", torch.int64),
+                                        n_seg, _dev(phi_seg, "phi_seg", torch.float32),
+                                        _dev(tau_seg, "tau_seg", torch.float32), _stream()))
+    return phi_seg, tau_seg
+
+
+def xl_merge_features_fwd(tau_seg, phi_seg, ray_offsets, seg_ids, phi_ray=None) -> torch.Tensor:
+    """phi_ray [F, n_rays]."""
+    F, n_seg = phi_seg.shape
+    n_rays = ray_offsets.shape[0] - 1
+    if phi_ray is None:
+        phi_ray = torch.empty((F, n_rays), dtype=torch.float32, device=phi_seg.device)
+    _check(lib().xl_merge_features_fwd(_dev(tau_seg, "tau_seg", torch.float32),
+                                       _dev(phi_seg, "phi_seg", torch.float32), F, n_seg,
+                                       _dev(ray_offsets, "ray_offsets", torch.int64),
+                                       _dev(seg_ids, "seg_ids", torch.int64), n_rays,
+                                       _dev(phi_ray, "phi_ray", torch.float32), _stream()))
+    return phi_ray
+
+
+def xl_merge_features_bwd(tau_seg, phi_seg, ray_offsets, seg_ids, grad_ray):
+    """(grad_phi_seg [F, n_seg], grad_tau_seg [n_seg]); unlisted segments get 0."""
+    F, n_seg = phi_seg.shape
+    n_rays = ray_offsets.shape[0] - 1
+    gphi = torch.zeros((F, n_seg), dtype=torch.float32, device=phi_seg.device)
+    gtau = torch.zeros(n_seg, dtype=torch.float32, device=phi_seg.device)
+    _check(lib().xl_merge_features_bwd(_dev(tau_seg, "tau_seg", torch.float32),
+                                       _dev(phi_seg, "phi_seg", torch.float32), F, n_seg,
+                                       _dev(ray_offsets, "ray_offsets", torch.int64),
+                                       _dev(seg_ids, "seg_ids", torch.int64), n_rays,
+                                       _dev(grad_ray, "grad_ray", torch.float32),
+                                       _dev(gphi, "grad_phi_seg"), _dev(gtau, "grad_tau_seg"), _stream()))
+    return gphi, gtau
+
+
+def xl_render_features_bwd(sigma, feat, t_start, t_end, seg_offsets, phi_seg, grad_phi_seg,
+                           grad_tau_seg=None, grad_sigma=None, grad_feat=None,
+                           accumulate_sigma: bool = False):
+    """(dl/dsigma [n], dl/dfeat [n, F]) in the storage dtype."""
+    f = features(sigma, feat, t_start, t_end)
+    n_seg = seg_offsets.shape[0] - 1
+    if grad_sigma is None:
+        if accumulate_sigma:
+            raise ValueError("accumulate_sigma needs grad_sigma")
+        grad_sigma = torch.empty_like(sigma)
+    if grad_feat is None:
+        grad_feat = torch.empty_like(feat)
+    _check(lib().xl_render_features_bwd(
+        ctypes.byref(f), _dev(seg_offsets, "seg_offsets", torch.int64), n_seg,
+        _dev(phi_seg, "phi_seg", torch.float32), _dev(grad_phi_seg, "grad_phi_seg", torch.float32),
+        None if grad_tau_seg is None else _dev(grad_tau_seg, "grad_tau_seg", torch.float32),
+        _dev(grad_sigma, "grad_sigma", sigma.dtype), _dev(grad_feat, "grad_feat", sigma.dtype),
+        1 if accumulate_sigma else 0, _stream()))
+    return grad_sigma, grad_feat

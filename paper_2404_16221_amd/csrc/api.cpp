@@ -303,4 +303,81 @@ int xl_pack_fill(const xl_rays* rays, const int32_t* axis, const float* plane, i
                     "xl_pack_fill");
 }
 
+static int check_features(const xl_features* f, const int64_t* seg_offsets, int64_t n_seg) {
+  if (f == nullptr) return fail(XL_EINVAL, "features descriptor is NULL");
+  if (f->dtype != XL_F32 && f->dtype != XL_BF16 && f->dtype != XL_F16)
+    return fail(XL_EINVAL, "unknown sample dtype %d", f->dtype);
+  if (f->n_feat != 4 && f->n_feat != 8 && f->n_feat != 16 && f->n_feat != 32)
+    return fail(XL_EINVAL, "n_feat must be 4, 8, 16 or 32, got %d", f->n_feat);
+  if (f->n < 0 || n_seg < 0) return fail(XL_EINVAL, "negative count");
+  if (f->n > 0 && (!f->sigma || !f->feat || !f->t_start || !f->t_end))
+    return fail(XL_EINVAL, "NULL sample array with n = %lld", (long long)f->n);
+  if (f->n > 0 && !aligned16(f->feat)) return fail(XL_EINVAL, "feat must be 16-byte aligned");
+  if (seg_offsets == nullptr) return fail(XL_EINVAL, "seg_offsets is NULL");
+  if (n_seg == 0 && f->n > 0) return fail(XL_EINVAL, "%lld samples but no segments", (long long)f->n);
+  return XL_OK;
+}
+
+int xl_render_features_fwd(const xl_features* f, const int64_t* seg_offsets, int64_t n_seg,
+                           float* phi_seg, float* tau_seg, void* stream) {
+  int rc = check_features(f, seg_offsets, n_seg);
+  if (rc) return rc;
+  if (n_seg > 0 && phi_seg == nullptr) return fail(XL_EINVAL, "phi_seg is NULL");
+  return hip_status(xl::launch_features_fwd(f, seg_offsets, n_seg, phi_seg, tau_seg,
+                                            static_cast<hipStream_t>(stream)),
+                    "xl_render_features_fwd launch");
+}
+
+int xl_render_features_bwd(const xl_features* f, const int64_t* seg_offsets, int64_t n_seg,
+                           const float* phi_seg, const float* grad_phi_seg,
+                           const float* grad_tau_seg, void* grad_sigma, void* grad_feat,
+                           int32_t accumulate_sigma, void* stream) {
+  int rc = check_features(f, seg_offsets, n_seg);
+  if (rc) return rc;
+  if (n_seg > 0 && (!phi_seg || !grad_phi_seg))
+    return fail(XL_EINVAL, "phi_seg or grad_phi_seg is NULL");
+  if (f->n > 0 && (!grad_sigma || !grad_feat)) return fail(XL_EINVAL, "NULL gradient array");
+  if (f->n > 0 && !aligned16(grad_feat)) return fail(XL_EINVAL, "grad_feat must be 16-byte aligned");
+  return hip_status(xl::launch_features_bwd(f, seg_offsets, n_seg, phi_seg, grad_phi_seg, grad_tau_seg,
+                                            grad_sigma, grad_feat, accumulate_sigma != 0,
+                                            static_cast<hipStream_t>(stream)),
+                    "xl_render_features_bwd launch");
+}
+
+static int check_feature_merge(const float* tau_seg, const float* phi_seg, int32_t n_feat, int64_t n_seg,
+                               const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays) {
+  if (n_feat != 4 && n_feat != 8 && n_feat != 16 && n_feat != 32)
+    return fail(XL_EINVAL, "n_feat must be 4, 8, 16 or 32, got %d", n_feat);
+  if (n_seg < 0 || n_rays < 0) return fail(XL_EINVAL, "negative count");
+  if (n_rays > 0 && ray_offsets == nullptr) return fail(XL_EINVAL, "ray_offsets is NULL");
+  if (n_seg > 0 && (!tau_seg || !phi_seg || !seg_ids))
+    return fail(XL_EINVAL, "tau_seg, phi_seg or seg_ids is NULL");
+  return XL_OK;
+}
+
+int xl_merge_features_fwd(const float* tau_seg, const float* phi_seg, int32_t n_feat, int64_t n_seg,
+                          const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                          float* phi_ray, void* stream) {
+  int rc = check_feature_merge(tau_seg, phi_seg, n_feat, n_seg, ray_offsets, seg_ids, n_rays);
+  if (rc) return rc;
+  if (n_rays > 0 && phi_ray == nullptr) return fail(XL_EINVAL, "phi_ray is NULL");
+  return hip_status(xl::launch_features_merge(tau_seg, phi_seg, n_feat, n_seg, ray_offsets, seg_ids,
+                                              n_rays, phi_ray, static_cast<hipStream_t>(stream)),
+                    "xl_merge_features_fwd launch");
+}
+
+int xl_merge_features_bwd(const float* tau_seg, const float* phi_seg, int32_t n_feat, int64_t n_seg,
+                          const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                          const float* grad_ray, float* grad_phi_seg, float* grad_tau_seg,
+                          void* stream) {
+  int rc = check_feature_merge(tau_seg, phi_seg, n_feat, n_seg, ray_offsets, seg_ids, n_rays);
+  if (rc) return rc;
+  if (n_rays > 0 && (!grad_ray || (n_seg > 0 && (!grad_phi_seg || !grad_tau_seg))))
+    return fail(XL_EINVAL, "grad_ray, grad_phi_seg or grad_tau_seg is NULL");
+  return hip_status(xl::launch_features_merge_bwd(tau_seg, phi_seg, n_feat, n_seg, ray_offsets, seg_ids,
+                                                  n_rays, grad_ray, grad_phi_seg, grad_tau_seg,
+                                                  static_cast<hipStream_t>(stream)),
+                    "xl_merge_features_bwd launch");
+}
+
 }  // extern "C"

@@ -67,4 +67,18 @@ hipError_t pack_fill(const xl_rays* rays, const int32_t* axis, const float* plan
                      int64_t* seg_offsets, int64_t* ray_offsets, int64_t* seg_ids, int32_t* seg_box,
                      hipStream_t st);
 
+// Feature channels (features.hip).
+hipError_t launch_features_fwd(const xl_features* f, const int64_t* seg_offsets, int64_t n_seg,
+                               float* phi_seg, float* tau_seg, hipStream_t st);
+hipError_t launch_features_bwd(const xl_features* f, const int64_t* seg_offsets, int64_t n_seg,
+                               const float* phi_seg, const float* grad_phi_seg, const float* grad_tau_seg,
+                               void* grad_sigma, void* grad_feat, int accumulate, hipStream_t st);
+hipError_t launch_features_merge(const float* tau_seg, const float* phi_seg, int F, int64_t n_seg,
+                                 const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                                 float* phi_ray, hipStream_t st);
+hipError_t launch_features_merge_bwd(const float* tau_seg, const float* phi_seg, int F, int64_t n_seg,
+                                     const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                                     const float* grad_ray, float* grad_phi_seg, float* grad_tau_seg,
+                                     hipStream_t st);
+
 }  // namespace xl
