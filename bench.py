@@ -319,6 +319,64 @@ def distribution(steps, warmup):
     return res
 
 
+def feature_channels(f, steps, warmup, F=16):
+    """F feature channels (App. B.2) over the samples of form f: segment
+    features, merge, merge backward and per-sample backward per step; the
+    features are a hash of the sample index in f's storage type."""
+    from paper_2404_16221_amd import _lib as xl
+    dev = f.sigma.device
+    idx = torch.arange(f.n, device=dev)
+    x = idx[:, None] * F + torch.arange(F, device=dev)[None, :]
+    x = (x * 2654435761) % 4294967296
+    feat = ((x.float() / 2147483648.0) - 1.0).to(f.sigma.dtype)
+    del idx, x
+    g = torch.from_numpy(np.random.default_rng(6).normal(size=(F, f.n_rays)).astype(np.float32)).to(dev)
+    phi = torch.empty((F, f.n_seg), dtype=torch.float32, device=dev)
+    tau = torch.empty(f.n_seg, dtype=torch.float32, device=dev)
+    out = torch.empty((F, f.n_rays), dtype=torch.float32, device=dev)
+    gs = torch.empty_like(f.sigma)
+    gf = torch.empty_like(feat)
+
+    def step(ev=None):
+        xl.xl_render_features_fwd(f.sigma, feat, f.t0, f.t1, f.seg_offsets, phi, tau)
+        xl.xl_merge_features_fwd(tau, phi, f.ray_offsets, f.seg_ids, out)
+        gphi, gtau = xl.xl_merge_features_bwd(tau, phi, f.ray_offsets, f.seg_ids, g)
+        if ev is not None:
+            ev[0].record()
+        xl.xl_render_features_bwd(f.sigma, feat, f.t0, f.t1, f.seg_offsets, phi, gphi, gtau, gs, gf)
+        if ev is not None:
+            ev[1].record()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    kern = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        step(kern[k])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    kms = float(np.mean([a.elapsed_time(b) for a, b in kern]))
+    es = f.sigma.element_size()
+    # algorithmic bytes: per sample sigma, t0, t1, features read twice, dsigma and
+    # dfeat written; per segment the features, depth and their gradients
+    per_sample = 2 * (es + 8 + F * es) + es + F * es
+    per_seg = (8 + 4 * F + 4) + (8 + 4 * F + 4) + (8 + 4 * F + 4 + 4 * F + 4) + (8 + 8 * F + 4)
+    per_ray = 16 + 4 * F + 16 + 4 * F
+    step_bytes = f.n * per_sample + f.n_seg * per_seg + f.n_rays * per_ray
+    bwd_bytes = f.n * (es + 8 + F * es + es + F * es) + f.n_seg * (8 + 8 * F + 4)
+    res = {"workload": f"{f.name} samples, {F} feature channels ({str(f.sigma.dtype)[6:]})",
+           "ms_per_step": ms, "samples_per_s": f.n / (ms * 1e-3),
+           "step_gbs": step_bytes / (ms * 1e-3) / 1e9, "bwd_ms": kms,
+           "bwd_gbs": bwd_bytes / (kms * 1e-3) / 1e9,
+           "bwd_frac_of_hbm_peak": bwd_bytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    log("features", json.dumps(res))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +384,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="bf16,fp32,plain,k64")
+    ap.add_argument("--no-features", action="store_true", help="skip the feature-channel timing")
     ap.add_argument("--no-distribution", action="store_true",
                     help="skip the tag/split/pack timing")
     ap.add_argument("--serve-requests", type=int, default=300,
@@ -415,6 +474,8 @@ def main():
                      "kernel": "seg_bwd_kernel", "step_achieved": hr["step_gbs"],
                      "step_frac": hr["step_gbs"] / HBM_PEAK_GBS},
     }
+    if not args.no_features and "bf16" in forms:
+        out["features"] = feature_channels(forms["bf16"], args.steps, args.warmup)
     if not args.no_distribution:
         out["distribution"] = distribution(max(args.steps // 2, 3), 2)
     if args.serve_requests > 0:
