@@ -1,10 +1,18 @@
-"""torch.autograd.Function over the C ABI: partitioned rendering, forward and backward.
+"""torch.autograd.Functions over the C ABI: partitioned rendering and feature
+channels, forward and backward.
 
-Forward: per-segment composite (xl_render_segments_fwd), then the merge in ray
-order (xl_merge_fwd).  Backward: merge backward (xl_merge_bwd) into each
-segment's tuple gradient, then the per-segment backward
-(xl_render_segments_bwd) into sigma and rgb.  Gradients flow to sigma and rgb
-only (interval ends are data, not parameters).
+XLRender -- forward: per-segment composite (xl_render_segments_fwd), then the
+merge in ray order (xl_merge_fwd).  Backward: merge backward (xl_merge_bwd)
+into each segment's tuple gradient, then the per-segment backward
+(xl_render_segments_bwd) into sigma and rgb.
+
+XLFeatures -- the same for F feature channels rendered with the
+volume-rendering weights (App. B.2): xl_render_features_fwd,
+xl_merge_features_fwd, and their backwards into sigma and the features.  When
+both are used on the same sigma, autograd adds the two density gradients.
+
+Gradients flow to sigma, rgb and the features only (interval ends are data,
+not parameters).
 """
 from __future__ import annotations
 
@@ -35,3 +43,26 @@ class XLRender(torch.autograd.Function):
 def render(sigma, rgb, t_start, t_end, seg_offsets, ray_offsets, seg_ids, fp64=False):
     """ray tuple [7, n_rays] = (T, r, g, b, A, D, L), differentiable in sigma and rgb."""
     return XLRender.apply(sigma, rgb, t_start, t_end, seg_offsets, ray_offsets, seg_ids, fp64)
+
+
+class XLFeatures(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, sigma, feat, t_start, t_end, seg_offsets, ray_offsets, seg_ids):
+        phi, tau = _lib.xl_render_features_fwd(sigma, feat, t_start, t_end, seg_offsets)
+        out = _lib.xl_merge_features_fwd(tau, phi, ray_offsets, seg_ids)
+        ctx.save_for_backward(sigma, feat, t_start, t_end, seg_offsets, ray_offsets, seg_ids, phi, tau)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        sigma, feat, t_start, t_end, seg_offsets, ray_offsets, seg_ids, phi, tau = ctx.saved_tensors
+        grad_out = grad_out.to(torch.float32).contiguous()
+        gphi, gtau = _lib.xl_merge_features_bwd(tau, phi, ray_offsets, seg_ids, grad_out)
+        gs, gf = _lib.xl_render_features_bwd(sigma, feat, t_start, t_end, seg_offsets, phi, gphi, gtau)
+        return gs, gf, None, None, None, None, None
+
+
+def render_features(sigma, feat, t_start, t_end, seg_offsets, ray_offsets, seg_ids):
+    """Per-ray features [F, n_rays] (F = feat.shape[1] in {4, 8, 16, 32}),
+    differentiable in sigma and feat."""
+    return XLFeatures.apply(sigma, feat, t_start, t_end, seg_offsets, ray_offsets, seg_ids)

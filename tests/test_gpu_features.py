@@ -175,3 +175,33 @@ def features_of(i, F):
     x = (x * 2654435761) % 4294967296
     x = (x ^ (x >> 13)) * 1274126177 % 4294967296
     return (x.float() / 2147483648.0) - 1.0
+
+
+def test_autograd_colour_and_features_share_sigma():
+    """render() and render_features() on the same sigma: autograd adds the two
+    density gradients; checked against the two oracles' gradients summed."""
+    from oracle import render as O
+    from paper_2404_16221_amd.autograd import render, render_features
+    b, feat = batch(rays=128, F=8, seed=21)
+    d = to_dev(b)
+    sig = d.sigma.clone().requires_grad_(True)
+    rgb = d.rgb.clone().requires_grad_(True)
+    f = torch.from_numpy(feat).cuda().requires_grad_(True)
+    rng = np.random.default_rng(22)
+    g_col = rng.normal(size=(7, b.n_rays))
+    g_ft = rng.normal(size=(8, b.n_rays))
+    ray = render(sig, rgb, d.t0, d.t1, d.seg_offsets, d.ray_offsets, d.seg_ids)
+    out = render_features(sig, f, d.t0, d.t1, d.seg_offsets, d.ray_offsets, d.seg_ids)
+    loss = (ray * torch.from_numpy(g_col).cuda().float()).sum() + \
+        (out * torch.from_numpy(g_ft).cuda().float()).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    _, _, idx, ds_col, _ = O.backward_partitioned(b.sigma, b.rgb, b.t_start, b.t_end, b.seg_offsets,
+                                                  b.ray_offsets, b.seg_ids, g_col)
+    ds_ft, df = Fo.grad_features(b.sigma, feat, b.t_start, b.t_end, b.seg_offsets, b.ray_offsets,
+                                 b.seg_ids, g_ft.T)
+    ds_ref = ds_ft.copy()
+    ds_ref[idx] += ds_col
+    assert_grads(sig.grad.cpu().numpy(), ds_ref, "dsigma, colour + features", rtol=1e-5, floor=1e-6,
+                 norm_tol=1e-5)
+    assert_grads(f.grad.cpu().numpy(), df, "dfeat", rtol=1e-5, floor=1e-6, norm_tol=1e-5)
