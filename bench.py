@@ -261,61 +261,71 @@ def serving(n_req, warmup, rate):
 
 
 def distribution(steps, warmup):
-    """Sample distribution (tag / split / pack) of all k16 rays (ray-major, 135M
-    samples) into 16 boxes, for the uniform 4x2x2 grid and for the CDF
-    partition built from the samples of every 64th ray; time per pack (plan,
-    whose size read-back synchronises, plus fill) and samples per box."""
+    """Sample distribution (tag / split / pack) of all rays of a workload
+    (ray-major) into its boxes, for the uniform grid and for the CDF partition
+    built from the samples of a subset of its rays; time per pack (plan, whose
+    size read-back synchronises, plus fill) and samples per box.  The k16
+    batch (16 boxes) and the k64 large partition (64 boxes)."""
     from paper_2404_16221_amd import _lib as xl
     from paper_2404_16221_amd import synth
-    w = synth.WORKLOADS[2]
-    g = xl.xl_gen(w.plain(), torch.float32)
-    o, d = synth.ray_geometry(w, np.arange(w.n_rays))
-    o = torch.from_numpy(o.astype(np.float32)).cuda()
-    d = torch.from_numpy(d.astype(np.float32)).cuda()
-    t = time.perf_counter()
-    pts = synth.sample_points(w, np.arange(0, w.n_rays, 64))
-    t_pts = time.perf_counter() - t
-    t = time.perf_counter()
-    cdf = xl.xl_partition_build(pts, 4)
-    t_build = time.perf_counter() - t
-    grid_axis, grid_plane, _ = synth.grid_tree(w.grid)
-    n_in = g["t_start"].shape[0]
-    res = {"workload": f"{w.name} rays, ray-major, {n_in} samples, 16 boxes",
-           "cdf_points": int(pts.shape[0]), "cdf_build_s": t_build, "cdf_points_s": t_pts}
-    for name, (axis, plane) in (("grid_4x2x2", (grid_axis, grid_plane)), ("cdf", cdf)):
-        def call():
-            return xl.xl_pack(o, d, g["t_start"], g["t_end"], g["seg_offsets"], axis, plane, 4)
-        for _ in range(warmup):
-            out = call()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            out = call()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        n, n_seg = out["t_start"].shape[0], out["seg_ids"].shape[0]
-        seg_len = (out["seg_offsets"][1:] - out["seg_offsets"][:-1]).double()
-        per_box = torch.zeros(16, dtype=torch.float64, device="cuda").index_add_(
-            0, out["seg_box"].long(), seg_len).cpu().numpy()
-        alg = n_in * 8 + w.n_rays * (24 + 8 + 8) + n * 16 + n_seg * 20
-        res[name] = {"ms": ms, "samples_per_s": n_in / (ms * 1e-3), "pieces": int(n),
-                     "segments": int(n_seg), "algorithmic_gbs": alg / (ms * 1e-3) / 1e9,
-                     "samples_per_box_max_over_mean": float(per_box.max() / per_box.mean()),
-                     "samples_per_box_min_over_mean": float(per_box.min() / per_box.mean()),
-                     "samples_per_box_cv": float(per_box.std() / per_box.mean())}
-        del out
-        # the same pack without the optional source index of every piece
-        e0.record()
-        for _ in range(steps):
-            out = xl.xl_pack(o, d, g["t_start"], g["t_end"], g["seg_offsets"], axis, plane, 4,
-                             with_src=False)
-        e1.record()
-        torch.cuda.synchronize()
-        res[name]["ms_without_src"] = e0.elapsed_time(e1) / steps
-        log("distribution", name, json.dumps(res[name]))
-        del out
+    res = {}
+    for w, every, dtype in ((synth.WORKLOADS[2], 64, torch.float32),
+                            (synth.WORKLOADS[4], 1024, torch.bfloat16)):
+        g = xl.xl_gen(w.plain(), dtype)
+        del g["sigma"], g["rgb"], g["seg_ids"]
+        o, d = synth.ray_geometry(w, np.arange(w.n_rays))
+        o = torch.from_numpy(o.astype(np.float32)).cuda()
+        d = torch.from_numpy(d.astype(np.float32)).cuda()
+        grid_axis, grid_plane, levels = synth.grid_tree(w.grid)
+        K = 1 << levels
+        t = time.perf_counter()
+        pts = synth.sample_points(w, np.arange(0, w.n_rays, every))
+        t_pts = time.perf_counter() - t
+        t = time.perf_counter()
+        cdf = xl.xl_partition_build(pts, levels)
+        t_build = time.perf_counter() - t
+        n_in = g["t_start"].shape[0]
+        r = {"workload": f"{w.name} rays, ray-major, {n_in} samples, {K} boxes",
+             "cdf_points": int(pts.shape[0]), "cdf_build_s": t_build, "cdf_points_s": t_pts}
+        gname = "grid_" + "x".join(str(v) for v in w.grid)
+        for name, (axis, plane) in ((gname, (grid_axis, grid_plane)), ("cdf", cdf)):
+            def call(src=True):
+                return xl.xl_pack(o, d, g["t_start"], g["t_end"], g["seg_offsets"], axis, plane,
+                                  levels, with_src=src)
+            for _ in range(warmup):
+                out = call()
+            del out
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                out = call()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            n, n_seg = out["t_start"].shape[0], out["seg_ids"].shape[0]
+            seg_len = (out["seg_offsets"][1:] - out["seg_offsets"][:-1]).double()
+            per_box = torch.zeros(K, dtype=torch.float64, device="cuda").index_add_(
+                0, out["seg_box"].long(), seg_len).cpu().numpy()
+            del out, seg_len
+            alg = n_in * 8 + w.n_rays * (24 + 8 + 8) + n * 16 + n_seg * 20
+            r[name] = {"ms": ms, "samples_per_s": n_in / (ms * 1e-3), "pieces": int(n),
+                       "segments": int(n_seg), "algorithmic_gbs": alg / (ms * 1e-3) / 1e9,
+                       "samples_per_box_max_over_mean": float(per_box.max() / per_box.mean()),
+                       "samples_per_box_min_over_mean": float(per_box.min() / per_box.mean()),
+                       "samples_per_box_cv": float(per_box.std() / per_box.mean())}
+            # the same pack without the optional source index of every piece
+            e0.record()
+            for _ in range(steps):
+                out = call(False)
+            e1.record()
+            torch.cuda.synchronize()
+            r[name]["ms_without_src"] = e0.elapsed_time(e1) / steps
+            del out
+            log("distribution", w.name, name, json.dumps(r[name]))
+        res[w.name] = r
+        del g, o, d
+        torch.cuda.empty_cache()
     return res
 
 

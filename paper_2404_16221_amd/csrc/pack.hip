@@ -13,19 +13,23 @@
 // interval holds s.  Boxes sharing a face get the same rounded parameter, so
 // the pieces of a sample tile it exactly.
 //
-// Three passes:
+// Passes:
 //   pack_count  one lane per (ray, box), 64 / K rays per wave: the box's
 //               interval and, by two binary searches over the ray's sorted
-//               samples, the run of samples that meet it -> piece count at
-//               [b][r] (box-major, so an exclusive scan gives region-major
-//               slots), a 0/1 segment flag, the run's first sample and the
-//               interval;
-//   scans       pieces and segment flags over [K][R], segments per ray;
-//   pack_fill   one wave per ray: lanes load their box's run, rank the boxes
-//               front to back through LDS and write the segment lists, then
-//               the wave strides over the ray's samples and writes every piece
-//               to its slot (consecutive samples of one box go to consecutive
-//               slots).
+//               samples, the run of samples that meet it -> its length and
+//               first sample, ray-major at [r][b] (a wave writes one
+//               contiguous block), and the ray's segment count;
+//   block sums  pieces and segments of every box in every block of rays,
+//               box-major at [b][block], so that an exclusive scan gives each
+//               (box, block) its first slot and first segment id in
+//               region-major order; a scan of the segments per ray gives the
+//               per-ray lists;
+//   pack_fill   one wave per block of rays, taken in order: lanes hold their
+//               box's running slot and segment id, rank the ray's boxes front
+//               to back and write the segment lists; then the wave strides
+//               over the ray's samples and writes every piece to its slot
+//               (consecutive samples of one box go to consecutive slots).
+// The workspace is 8 bytes per ray and box plus 16 per box and block of rays.
 // Every store index is bounded by the counts of the plan, so inputs that break
 // the sortedness contract give unspecified pieces but never out-of-range
 // stores.
@@ -42,6 +46,7 @@ namespace {
 
 constexpr int kPackWaves = 4;
 constexpr int kPackBlock = kPackWaves * kWave;
+constexpr int kRayBlock = 16;  // rays per fill wave and per block of the slot prefix
 
 struct PackDev {
   const float* o;        // [R][3]
@@ -51,29 +56,34 @@ struct PackDev {
   const int64_t* ray_off;  // [R + 1] samples of each ray
   const int32_t* axis;   // [K - 1]
   const float* plane;    // [K - 1]
-  int64_t R;
+  int64_t R, nblk;
   int32_t levels, K;
 };
 
 struct PackWs {
-  int64_t* cnt;      // [K * R] pieces of ray r in box b, at b * R + r
-  int64_t* has;      // [K * R] 1 when that count is positive
-  int32_t* first;    // [K * R] first sample of the run (index inside the ray)
-  float2* span;      // [K * R] the box's interval (t_in, t_out) on the ray
-  int64_t* off;      // [K * R + 1] first slot of those pieces
-  int64_t* sid;      // [K * R + 1] id of that segment
+  int32_t* cnt;      // [R][K] pieces of ray r in box b
+  int32_t* first;    // [R][K] first sample of that run (index inside the ray)
+  int64_t* bsum;     // [K][nblk] pieces of box b in block blk
+  int64_t* bseg;     // [K][nblk] rays of block blk with pieces in box b
+  int64_t* bpre;     // [K * nblk + 1] first slot of (b, blk)
+  int64_t* bsegpre;  // [K * nblk + 1] first segment id of (b, blk)
   int64_t* nseg;     // [R] segments of each ray
   int64_t* ray_off;  // [R + 1] first entry of each ray in seg_ids
   int64_t* scan_tmp;
 };
 
-struct BoxSpan {
-  float tin, tout;
-  int64_t first, count;  // samples [first, first + count) of the ray meet the box
+struct Box {
+  float lo[3], hi[3];
 };
 
-__device__ BoxSpan box_span(const PackDev& p, int64_t r, int b, int64_t s0, int64_t n) {
-  float lo[3] = {-INFINITY, -INFINITY, -INFINITY}, hi[3] = {INFINITY, INFINITY, INFINITY};
+// Leaf b of the tree as the intersection of the half-spaces on its path.
+__device__ Box leaf_box(const PackDev& p, int b) {
+  Box bx;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    bx.lo[c] = -INFINITY;
+    bx.hi[c] = INFINITY;
+  }
   int node = b + p.K - 1;
   for (int l = 0; l < p.levels; ++l) {
     const int parent = (node - 1) >> 1;
@@ -83,18 +93,24 @@ __device__ BoxSpan box_span(const PackDev& p, int64_t r, int b, int64_t s0, int6
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (a != c) continue;
-      if (high) lo[c] = pl > lo[c] ? pl : lo[c];
-      else hi[c] = pl < hi[c] ? pl : hi[c];
+      if (high) bx.lo[c] = pl > bx.lo[c] ? pl : bx.lo[c];
+      else bx.hi[c] = pl < bx.hi[c] ? pl : bx.hi[c];
     }
     node = parent;
   }
+  return bx;
+}
+
+// The box's parameter interval [t_in, t_out) on ray r: float64 slab test,
+// ends rounded to float32; an empty box gives (inf, -inf).
+__device__ float2 ray_span(const PackDev& p, int64_t r, const Box& bx) {
   double tin = -INFINITY, tout = INFINITY;
   bool empty = false;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const double oc = static_cast<double>(p.o[3 * r + c]);
     const double dc = static_cast<double>(p.d[3 * r + c]);
-    const double l = static_cast<double>(lo[c]), h = static_cast<double>(hi[c]);
+    const double l = static_cast<double>(bx.lo[c]), h = static_cast<double>(bx.hi[c]);
     if (dc == 0.0) {
       empty |= !(l <= oc && oc < h);
     } else {
@@ -104,35 +120,39 @@ __device__ BoxSpan box_span(const PackDev& p, int64_t r, int b, int64_t s0, int6
       tout = far < tout ? far : tout;
     }
   }
-  BoxSpan sp;
-  sp.tin = empty ? INFINITY : static_cast<float>(tin);
-  sp.tout = empty ? -INFINITY : static_cast<float>(tout);
-  sp.first = 0;
-  sp.count = 0;
-  if (!(sp.tin < sp.tout) || n <= 0) return sp;
+  return empty ? make_float2(INFINITY, -INFINITY)
+               : make_float2(static_cast<float>(tin), static_cast<float>(tout));
+}
+
+// Samples [first, first + count) of the ray (s0, n) that meet [tin, tout).
+__device__ void run_of(const PackDev& p, float tin, float tout, int64_t s0, int64_t n,
+                       int64_t& first, int64_t& count) {
+  first = 0;
+  count = 0;
+  if (!(tin < tout) || n <= 0) return;
   // first sample reaching into the box: it ends after t_in, or has zero
   // length at t_in
   int64_t a = 0, c = n;
   while (a < c) {
     const int64_t m = (a + c) >> 1;
     const float e = p.t1[s0 + m];
-    const bool in = e > sp.tin || (e == sp.tin && p.t0[s0 + m] == sp.tin);
+    const bool in = e > tin || (e == tin && p.t0[s0 + m] == tin);
     if (in) c = m;
     else a = m + 1;
   }
-  sp.first = a;
+  first = a;
   // first sample starting at or after t_out
   c = n;
   while (a < c) {
     const int64_t m = (a + c) >> 1;
-    if (p.t0[s0 + m] >= sp.tout) c = m;
+    if (p.t0[s0 + m] >= tout) c = m;
     else a = m + 1;
   }
-  sp.count = a - sp.first;
-  return sp;
+  count = a - first;
 }
 
-// 64 / K rays per wave, K consecutive lanes per ray (K divides 64).
+// 64 / K rays per wave, K consecutive lanes per ray (K divides 64); lane
+// (sub, b) writes entry (r, b) at r * K + b: one contiguous block per wave.
 __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(PackDev p, PackWs w) {
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int per_wave = kWave / p.K;
@@ -142,17 +162,34 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(PackDev p, PackW
   int64_t cnt = 0;
   if (live) {
     const int64_t s0 = p.ray_off[r], n = p.ray_off[r + 1] - s0;
-    const BoxSpan sp = box_span(p, r, b, s0, n);
-    cnt = sp.count;
-    const int64_t at = static_cast<int64_t>(b) * p.R + r;
-    w.cnt[at] = cnt;
-    w.has[at] = cnt > 0 ? 1 : 0;
-    w.first[at] = static_cast<int32_t>(sp.first);
-    w.span[at] = make_float2(sp.tin, sp.tout);
+    const float2 sp = ray_span(p, r, leaf_box(p, b));
+    int64_t first;
+    run_of(p, sp.x, sp.y, s0, n, first, cnt);
+    cnt = cnt < INT32_MAX ? cnt : INT32_MAX;  // (stored as int32; all passes agree on it)
+    w.cnt[r * p.K + b] = static_cast<int32_t>(cnt);
+    w.first[r * p.K + b] = static_cast<int32_t>(first);
   }
   const unsigned long long m = __ballot(cnt > 0);
   const unsigned long long group = p.K == kWave ? ~0ull : (((1ull << p.K) - 1) << (sub * p.K));
   if (live && b == 0) w.nseg[r] = __popcll(m & group);
+}
+
+// Pieces and segments of box b in block blk, one thread per (blk, b).
+__global__ void pack_block_sum_kernel(PackDev p, PackWs w) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= p.K * p.nblk) return;
+  const int64_t blk = t / p.K;
+  const int b = static_cast<int>(t % p.K);
+  int64_t pieces = 0, segs = 0;
+  for (int j = 0; j < kRayBlock; ++j) {
+    const int64_t r = blk * kRayBlock + j;
+    if (r >= p.R) break;
+    const int32_t c = w.cnt[r * p.K + b];
+    pieces += c > 0 ? c : 0;
+    segs += c > 0 ? 1 : 0;
+  }
+  w.bsum[b * p.nblk + blk] = pieces;
+  w.bseg[b * p.nblk + blk] = segs;
 }
 
 __global__ __launch_bounds__(kPackBlock) void pack_fill_kernel(PackDev p, PackWs w,
@@ -162,100 +199,111 @@ __global__ __launch_bounds__(kPackBlock) void pack_fill_kernel(PackDev p, PackWs
                                                                int64_t* __restrict__ seg_offsets,
                                                                int64_t* __restrict__ seg_ids,
                                                                int32_t* __restrict__ seg_box) {
-  __shared__ float s_tin[kPackWaves][kWave], s_tout[kPackWaves][kWave];
-  __shared__ int64_t s_first[kPackWaves][kWave], s_cnt[kPackWaves][kWave], s_base[kPackWaves][kWave];
+  // Each wave uses its own rows, and a wave's LDS operations execute in
+  // order, so between the steps only the compiler is held back (a signal
+  // fence emits no instruction and no wait on the pieces' stores).
+  __shared__ float s_key[kPackWaves][kWave], s_tout[kPackWaves][kWave];
+  __shared__ int32_t s_first[kPackWaves][kWave], s_cnt[kPackWaves][kWave];
+  __shared__ int64_t s_base[kPackWaves][kWave];
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  const int64_t r = static_cast<int64_t>(blockIdx.x) * kPackWaves + wave;
-  const bool live = r < p.R;
-  int64_t s0 = 0, n = 0;
-  if (live) {
-    s0 = p.ray_off[r];
-    n = p.ray_off[r + 1] - s0;
+  const int64_t blk = static_cast<int64_t>(blockIdx.x) * kPackWaves + wave;
+  if (blk >= p.nblk) return;
+  // this lane's box, and its running slot and segment id in region-major order
+  Box bx;
+  int64_t slot = 0, sid = 0;
+  if (lane < p.K) {
+    bx = leaf_box(p, lane);
+    slot = w.bpre[lane * p.nblk + blk];
+    sid = w.bsegpre[lane * p.nblk + blk];
   }
-  // this lane's box: the run and interval that the count pass found
-  BoxSpan sp;
-  sp.tin = INFINITY;
-  sp.tout = -INFINITY;
-  sp.first = sp.count = 0;
-  const int64_t at = static_cast<int64_t>(lane) * p.R + r;
-  if (live && lane < p.K) {
-    sp.count = w.cnt[at];
-    if (sp.count > 0) {
-      const float2 ts = w.span[at];
-      sp.tin = ts.x;
-      sp.tout = ts.y;
-      sp.first = w.first[at];
-    }
-  }
-  const bool valid = sp.count > 0;
-  s_tin[wave][lane] = valid ? sp.tin : INFINITY;
-  __syncthreads();
-  // front-to-back rank among the boxes with pieces (their t_in differ: the
-  // intervals of disjoint boxes on one ray do not overlap)
-  int rank = 0;
-  if (valid)
-    for (int k = 0; k < p.K; ++k) rank += s_tin[wave][k] < sp.tin ? 1 : 0;
-  const int nv = __popcll(__ballot(valid));
-  __syncthreads();
-  s_cnt[wave][lane] = 0;  // entries no box fills take no pieces
-  __syncthreads();
-  if (valid) {
-    const int64_t base = w.off[at], id = w.sid[at];
-    s_tin[wave][rank] = sp.tin;
-    s_tout[wave][rank] = sp.tout;
-    s_first[wave][rank] = sp.first;
-    s_cnt[wave][rank] = sp.count;
-    s_base[wave][rank] = base;
-    seg_offsets[id] = base;
-    if (seg_box) seg_box[id] = lane;
-    seg_ids[w.ray_off[r] + rank] = id;
-  }
-  __syncthreads();
-  if (!live) return;
-  int k0 = 0;
-  // the next chunk's interval is loaded before this chunk's pieces are stored
-  float s_next = 0.f, e_next = 0.f;
-  if (lane < n) {
-    s_next = p.t0[s0 + lane];
-    e_next = p.t1[s0 + lane];
-  }
-  for (int64_t j = lane; j < n; j += kWave) {
-    const float s = s_next, e = e_next;
-    if (j + kWave < n) {
-      s_next = p.t0[s0 + j + kWave];
-      e_next = p.t1[s0 + j + kWave];
-    }
-    while (k0 < nv && !(s_tout[wave][k0] > s)) ++k0;  // samples ascend: k0 only grows
-    for (int k = k0; k < nv; ++k) {
-      const float tin = s_tin[wave][k], tout = s_tout[wave][k];
-      const bool pos = s < e;
-      if (pos && !(tin < e)) break;
-      float a0, a1;
-      bool piece;
-      if (pos) {
-        a0 = s > tin ? s : tin;
-        a1 = e < tout ? e : tout;
-        piece = a0 < a1;
-      } else {
-        a0 = a1 = s;
-        piece = tin <= s && s < tout;
+  const int64_t r_end = (blk + 1) * kRayBlock < p.R ? (blk + 1) * kRayBlock : p.R;
+  for (int64_t r = blk * kRayBlock; r < r_end; ++r) {
+    const int64_t s0 = p.ray_off[r], n = p.ray_off[r + 1] - s0;
+    int32_t c = 0, f = 0;
+    float tin = INFINITY, tout = -INFINITY;
+    if (lane < p.K) {
+      c = w.cnt[r * p.K + lane];
+      f = w.first[r * p.K + lane];
+      if (c > 0) {
+        const float2 sp = ray_span(p, r, bx);
+        tin = sp.x;
+        tout = sp.y;
       }
-      if (piece) {
-        const int64_t q = j - s_first[wave][k];
-        if (q >= 0 && q < s_cnt[wave][k]) {
-          const int64_t slot = s_base[wave][k] + q;
-          out_t0[slot] = a0;
-          out_t1[slot] = a1;
-          if (out_src) out_src[slot] = s0 + j;
+    }
+    const bool valid = c > 0;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the previous ray's table reads come first
+    s_key[wave][lane] = valid ? tin : INFINITY;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    // front-to-back rank among the boxes with pieces (ties, which disjoint
+    // boxes cannot produce, broken by lane so that ranks stay distinct)
+    int rank = 0;
+    if (valid)
+      for (int k = 0; k < p.K; ++k) {
+        const float t = s_key[wave][k];
+        rank += (t < tin || (t == tin && k < lane)) ? 1 : 0;
+      }
+    const int nv = __popcll(__ballot(valid));
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (valid) {
+      s_key[wave][rank] = tin;
+      s_tout[wave][rank] = tout;
+      s_first[wave][rank] = f;
+      s_cnt[wave][rank] = c;
+      s_base[wave][rank] = slot;
+      seg_offsets[sid] = slot;
+      if (seg_box) seg_box[sid] = lane;
+      seg_ids[w.ray_off[r] + rank] = sid;
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (valid) {
+      slot += c;
+      sid += 1;
+    }
+    int k0 = 0;
+    // the next chunk's interval is loaded before this chunk's pieces are stored
+    float s_next = 0.f, e_next = 0.f;
+    if (lane < n) {
+      s_next = p.t0[s0 + lane];
+      e_next = p.t1[s0 + lane];
+    }
+    for (int64_t j = lane; j < n; j += kWave) {
+      const float s = s_next, e = e_next;
+      if (j + kWave < n) {
+        s_next = p.t0[s0 + j + kWave];
+        e_next = p.t1[s0 + j + kWave];
+      }
+      while (k0 < nv && !(s_tout[wave][k0] > s)) ++k0;  // samples ascend: k0 only grows
+      for (int k = k0; k < nv; ++k) {
+        const float ti = s_key[wave][k], to = s_tout[wave][k];
+        const bool pos = s < e;
+        if (pos && !(ti < e)) break;
+        float a0, a1;
+        bool piece;
+        if (pos) {
+          a0 = s > ti ? s : ti;
+          a1 = e < to ? e : to;
+          piece = a0 < a1;
+        } else {
+          a0 = a1 = s;
+          piece = ti <= s && s < to;
         }
+        if (piece) {
+          const int64_t q = j - s_first[wave][k];
+          if (q >= 0 && q < s_cnt[wave][k]) {
+            const int64_t at = s_base[wave][k] + q;
+            out_t0[at] = a0;
+            out_t1[at] = a1;
+            if (out_src) out_src[at] = s0 + j;
+          }
+        }
+        if (!pos) break;  // a zero-length sample has one piece
       }
-      if (!pos) break;  // a zero-length sample has one piece
     }
   }
 }
 
 struct PackLayout {
-  int64_t R, K, KR;
+  int64_t R, K, RK, nblk, KB;
   size_t scan_elems;
   size_t off[9];
   size_t bytes;
@@ -265,15 +313,17 @@ PackLayout pack_layout(int64_t R, int levels) {
   PackLayout L;
   L.R = R;
   L.K = int64_t{1} << levels;
-  L.KR = L.K * R;
-  L.scan_elems = scan_tmp_elems(L.KR > R ? L.KR : R);
+  L.RK = L.K * R;
+  L.nblk = (R + kRayBlock - 1) / kRayBlock;
+  L.KB = L.K * L.nblk;
+  L.scan_elems = scan_tmp_elems(L.KB > R ? L.KB : R);
   const size_t sizes[] = {
-      sizeof(int64_t) * L.KR,           // cnt
-      sizeof(int64_t) * L.KR,           // has
-      sizeof(int32_t) * L.KR,           // first
-      sizeof(float2) * L.KR,            // span
-      sizeof(int64_t) * (L.KR + 1),     // off
-      sizeof(int64_t) * (L.KR + 1),     // sid
+      sizeof(int32_t) * L.RK,           // cnt
+      sizeof(int32_t) * L.RK,           // first
+      sizeof(int64_t) * L.KB,           // bsum
+      sizeof(int64_t) * L.KB,           // bseg
+      sizeof(int64_t) * (L.KB + 1),     // bpre
+      sizeof(int64_t) * (L.KB + 1),     // bsegpre
       sizeof(int64_t) * R,              // nseg
       sizeof(int64_t) * (R + 1),        // ray_off
       sizeof(int64_t) * L.scan_elems,   // scan_tmp
@@ -290,12 +340,12 @@ PackLayout pack_layout(int64_t R, int levels) {
 PackWs pack_views(const PackLayout& L, void* ws) {
   char* b = static_cast<char*>(ws);
   PackWs w;
-  w.cnt = reinterpret_cast<int64_t*>(b + L.off[0]);
-  w.has = reinterpret_cast<int64_t*>(b + L.off[1]);
-  w.first = reinterpret_cast<int32_t*>(b + L.off[2]);
-  w.span = reinterpret_cast<float2*>(b + L.off[3]);
-  w.off = reinterpret_cast<int64_t*>(b + L.off[4]);
-  w.sid = reinterpret_cast<int64_t*>(b + L.off[5]);
+  w.cnt = reinterpret_cast<int32_t*>(b + L.off[0]);
+  w.first = reinterpret_cast<int32_t*>(b + L.off[1]);
+  w.bsum = reinterpret_cast<int64_t*>(b + L.off[2]);
+  w.bseg = reinterpret_cast<int64_t*>(b + L.off[3]);
+  w.bpre = reinterpret_cast<int64_t*>(b + L.off[4]);
+  w.bsegpre = reinterpret_cast<int64_t*>(b + L.off[5]);
   w.nseg = reinterpret_cast<int64_t*>(b + L.off[6]);
   w.ray_off = reinterpret_cast<int64_t*>(b + L.off[7]);
   w.scan_tmp = reinterpret_cast<int64_t*>(b + L.off[8]);
@@ -312,14 +362,14 @@ PackDev pack_dev(const xl_rays* rays, const int32_t* axis, const float* plane, i
   p.axis = axis;
   p.plane = plane;
   p.R = rays->n_rays;
+  p.nblk = (p.R + kRayBlock - 1) / kRayBlock;
   p.levels = levels;
   p.K = 1 << levels;
   return p;
 }
 
-unsigned ray_blocks(int64_t R, int per_wave = 1) {
-  const int64_t per_block = static_cast<int64_t>(kPackWaves) * per_wave;
-  return static_cast<unsigned>((R + per_block - 1) / per_block);
+unsigned grid_for(int64_t items, int64_t per_block) {
+  return static_cast<unsigned>((items + per_block - 1) / per_block);
 }
 
 }  // namespace
@@ -331,18 +381,20 @@ hipError_t pack_plan(const xl_rays* rays, const int32_t* axis, const float* plan
   const PackLayout L = pack_layout(rays->n_rays, levels);
   const PackWs w = pack_views(L, ws);
   const PackDev p = pack_dev(rays, axis, plane, levels);
-  if (L.R > 0)
-    hipLaunchKernelGGL(pack_count_kernel, dim3(ray_blocks(L.R, kWave / p.K)), dim3(kPackBlock), 0, st,
-                       p, w);
+  if (L.R > 0) {
+    hipLaunchKernelGGL(pack_count_kernel, dim3(grid_for(L.R, kPackWaves * (kWave / p.K))),
+                       dim3(kPackBlock), 0, st, p, w);
+    hipLaunchKernelGGL(pack_block_sum_kernel, dim3(grid_for(L.KB, 256)), dim3(256), 0, st, p, w);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = scan_exclusive(w.cnt, w.off, L.KR, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
-  if ((e = scan_exclusive(w.has, w.sid, L.KR, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
+  if ((e = scan_exclusive(w.bsum, w.bpre, L.KB, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
+  if ((e = scan_exclusive(w.bseg, w.bsegpre, L.KB, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
   if ((e = scan_exclusive(w.nseg, w.ray_off, L.R, w.scan_tmp, L.scan_elems, st)) != hipSuccess) return e;
   int64_t h[2] = {0, 0};
-  if ((e = hipMemcpyAsync(&h[0], w.off + L.KR, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+  if ((e = hipMemcpyAsync(&h[0], w.bpre + L.KB, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
     return e;
-  if ((e = hipMemcpyAsync(&h[1], w.sid + L.KR, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+  if ((e = hipMemcpyAsync(&h[1], w.bsegpre + L.KB, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
     return e;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
   *n_pieces = h[0];
@@ -358,11 +410,11 @@ hipError_t pack_fill(const xl_rays* rays, const int32_t* axis, const float* plan
   const PackWs w = pack_views(L, ws);
   const PackDev p = pack_dev(rays, axis, plane, levels);
   if (L.R > 0)
-    hipLaunchKernelGGL(pack_fill_kernel, dim3(ray_blocks(L.R)), dim3(kPackBlock), 0, st, p, w,
-                       t_start, t_end, src, seg_offsets, seg_ids, seg_box);
+    hipLaunchKernelGGL(pack_fill_kernel, dim3(grid_for(L.nblk, kPackWaves)), dim3(kPackBlock), 0, st, p,
+                       w, t_start, t_end, src, seg_offsets, seg_ids, seg_box);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = hipMemcpyAsync(seg_offsets + n_seg, w.off + L.KR, sizeof(int64_t),
+  if ((e = hipMemcpyAsync(seg_offsets + n_seg, w.bpre + L.KB, sizeof(int64_t),
                           hipMemcpyDeviceToDevice, st)) != hipSuccess)
     return e;
   return hipMemcpyAsync(ray_offsets, w.ray_off, sizeof(int64_t) * (L.R + 1), hipMemcpyDeviceToDevice,

@@ -111,17 +111,23 @@ def test_workload_rays_bit_exact_and_render():
     assert_tuples(ray_out.cpu().numpy(), want, "ray", "k16 cut samples rendered")
 
 
-def test_k16_all_rays_full_size():
-    """All 262,144 k16 rays (135M samples) in one pack, as the benchmark runs
-    it; sampled rays against the oracle run on those rays alone."""
-    w = synth.WORKLOADS[2]
-    g = xl.xl_gen(w.plain(), torch.float32)
+@pytest.mark.parametrize("wi,levels,every,n_check", [(2, 4, 64, 24), (4, 6, 1024, 16)],
+                         ids=["k16-16boxes", "k64-64boxes"])
+def test_all_rays_full_size(wi, levels, every, n_check):
+    """All rays of the k16 batch (262,144 rays, 135M samples, 16 boxes) or of
+    the k64 large partition (4,194,304 rays, 1.14G samples, 64 boxes) in one
+    pack, as the benchmark runs it; sampled rays against the oracle run on
+    those rays alone."""
+    w = synth.WORKLOADS[wi]
+    g = xl.xl_gen(w.plain(), torch.bfloat16)
+    del g["sigma"], g["rgb"]
     o, d = synth.ray_geometry(w, np.arange(w.n_rays))
-    axis, plane = xl.xl_partition_build(synth.sample_points(w, np.arange(0, w.n_rays, 64)), 4)
-    say(f"pack k16 full size: {g['t_start'].shape[0]} samples")
+    axis, plane = xl.xl_partition_build(synth.sample_points(w, np.arange(0, w.n_rays, every)),
+                                        levels)
+    say(f"pack {w.name} full size: {g['t_start'].shape[0]} samples, {1 << levels} boxes")
     out = xl.xl_pack(torch.from_numpy(o.astype(np.float32)).cuda(),
                      torch.from_numpy(d.astype(np.float32)).cuda(),
-                     g["t_start"], g["t_end"], g["seg_offsets"], axis, plane, 4)
+                     g["t_start"], g["t_end"], g["seg_offsets"], axis, plane, levels)
     torch.cuda.synchronize()
     n_in = g["t_start"].shape[0]
     n = out["t_start"].shape[0]
@@ -135,10 +141,10 @@ def test_k16_all_rays_full_size():
     full = (g["t_end"] - g["t_start"]).double()
     assert float((per_src - full).abs().max()) <= 1e-5
     # sampled rays, bit-exact against the oracle on those rays
-    rays = sample_rays(w.n_rays, 24, 77)
+    rays = sample_rays(w.n_rays, n_check, 77)
     h = synth.generate(w.plain(), rays=rays)
     ref = P.tag_split_pack(o[rays].astype(np.float32), d[rays].astype(np.float32), h.t_start,
-                           h.t_end, h.seg_offsets, axis, plane, 4)
+                           h.t_end, h.seg_offsets, axis, plane, levels)
     ro, so = out["ray_offsets"].cpu().numpy(), out["seg_offsets"]
     base_in = g["seg_offsets"].cpu().numpy()
     for k, r in enumerate(rays):
