@@ -227,7 +227,7 @@ typedef struct xl_rays {
 } xl_rays;
 
 /* Device workspace bytes for xl_pack_plan / xl_pack_fill: about
- * 44 * 2^levels + 16 bytes per ray. */
+ * 10 * 2^levels + 16 bytes per ray. */
 size_t xl_pack_workspace_bytes(int64_t n_rays, int32_t levels);
 
 /*
