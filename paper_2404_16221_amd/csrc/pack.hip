@@ -14,11 +14,12 @@
 // the pieces of a sample tile it exactly.
 //
 // Passes:
-//   pack_count  one lane per (ray, box), 64 / K rays per wave: the box's
-//               interval and, by two binary searches over the ray's sorted
-//               samples, the run of samples that meet it -> its length and
-//               first sample, ray-major at [r][b] (a wave writes one
-//               contiguous block), and the ray's segment count;
+//   pack_count  a wave examines 256 (ray, box) pairs: the box's interval on
+//               the ray; pairs that can meet the ray's samples are compacted
+//               and searched 64 at a time (two binary searches over the ray's
+//               sorted samples give the run of samples that meet the box) ->
+//               run length and first sample, ray-major at [r][b], and the
+//               ray's segment count;
 //   block sums  pieces and segments of every box in every block of rays,
 //               box-major at [b][block], so that an exclusive scan gives each
 //               (box, block) its first slot and first segment id in
@@ -47,6 +48,7 @@ namespace {
 constexpr int kPackWaves = 4;
 constexpr int kPackBlock = kPackWaves * kWave;
 constexpr int kRayBlock = 16;  // rays per fill wave and per block of the slot prefix
+constexpr int kPairs = 256;     // (ray, box) pairs a count wave examines
 
 struct PackDev {
   const float* o;        // [R][3]
@@ -151,27 +153,69 @@ __device__ void run_of(const PackDev& p, float tin, float tout, int64_t s0, int6
   count = a - first;
 }
 
-// 64 / K rays per wave, K consecutive lanes per ray (K divides 64); lane
-// (sub, b) writes entry (r, b) at r * K + b: one contiguous block per wave.
+// A wave examines kPairs (ray, box) pairs: kPairs / K consecutive rays.
+// Pairs whose box interval cannot meet the ray's samples (empty, or outside
+// [first start, last end]) get a zero count at once; the others are compacted
+// into LDS and searched 64 at a time, so one chain of dependent loads serves
+// many rays.  Counts and first samples are written ray-major at r * K + b.
 __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(PackDev p, PackWs w) {
+  __shared__ float c_tin[kPackWaves][kPairs], c_tout[kPackWaves][kPairs];
+  __shared__ int32_t c_pair[kPackWaves][kPairs], c_nseg[kPackWaves][kPairs];
+  __shared__ Box boxes[kWave];  // the K leaf boxes, built once per block
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  const int per_wave = kWave / p.K;
-  const int sub = lane / p.K, b = lane % p.K;
-  const int64_t r = (static_cast<int64_t>(blockIdx.x) * kPackWaves + wave) * per_wave + sub;
-  const bool live = r < p.R;
-  int64_t cnt = 0;
-  if (live) {
-    const int64_t s0 = p.ray_off[r], n = p.ray_off[r + 1] - s0;
-    const float2 sp = ray_span(p, r, leaf_box(p, b));
-    int64_t first;
-    run_of(p, sp.x, sp.y, s0, n, first, cnt);
-    cnt = cnt < INT32_MAX ? cnt : INT32_MAX;  // (stored as int32; all passes agree on it)
-    w.cnt[r * p.K + b] = static_cast<int32_t>(cnt);
-    w.first[r * p.K + b] = static_cast<int32_t>(first);
+  if (threadIdx.x < p.K) boxes[threadIdx.x] = leaf_box(p, threadIdx.x);
+  __syncthreads();
+  const int rays = kPairs / p.K;
+  const int64_t r0 = (static_cast<int64_t>(blockIdx.x) * kPackWaves + wave) * rays;
+  for (int i = lane; i < rays; i += kWave) c_nseg[wave][i] = 0;
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+  int ncand = 0;
+  for (int i0 = 0; i0 < kPairs; i0 += kWave) {
+    const int i = i0 + lane;
+    const int64_t r = r0 + i / p.K;
+    const int b = i % p.K;
+    bool cand = false;
+    float2 sp = make_float2(INFINITY, -INFINITY);
+    if (r < p.R) {
+      const int64_t s0 = p.ray_off[r], s1 = p.ray_off[r + 1];
+      sp = ray_span(p, r, boxes[b]);
+      if (s1 > s0 && sp.x < sp.y) {
+        // a piece needs t_in <= some sample's end and t_out > some start
+        cand = sp.x <= p.t1[s1 - 1] && sp.y > p.t0[s0];
+      }
+      if (!cand) {
+        w.cnt[r * p.K + b] = 0;
+        w.first[r * p.K + b] = 0;
+      }
+    }
+    const unsigned long long m = __ballot(cand);
+    if (cand) {
+      const int at = ncand + __popcll(m & below);
+      c_tin[wave][at] = sp.x;
+      c_tout[wave][at] = sp.y;
+      c_pair[wave][at] = i;
+    }
+    ncand += __popcll(m);
   }
-  const unsigned long long m = __ballot(cnt > 0);
-  const unsigned long long group = p.K == kWave ? ~0ull : (((1ull << p.K) - 1) << (sub * p.K));
-  if (live && b == 0) w.nseg[r] = __popcll(m & group);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);  // (a wave's LDS operations run in order)
+  for (int j0 = 0; j0 < ncand; j0 += kWave) {
+    const int j = j0 + lane;
+    if (j < ncand) {
+      const int i = c_pair[wave][j];
+      const int64_t r = r0 + i / p.K;
+      const int b = i % p.K;
+      const int64_t s0 = p.ray_off[r], n = p.ray_off[r + 1] - s0;
+      int64_t first, count;
+      run_of(p, c_tin[wave][j], c_tout[wave][j], s0, n, first, count);
+      count = count < INT32_MAX ? count : INT32_MAX;  // (stored as int32; all passes agree on it)
+      w.cnt[r * p.K + b] = static_cast<int32_t>(count);
+      w.first[r * p.K + b] = static_cast<int32_t>(first);
+      if (count > 0) atomicAdd(&c_nseg[wave][i / p.K], 1);
+    }
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  for (int i = lane; i < rays; i += kWave)
+    if (r0 + i < p.R) w.nseg[r0 + i] = c_nseg[wave][i];
 }
 
 // Pieces and segments of box b in block blk, one thread per (blk, b).
@@ -382,7 +426,7 @@ hipError_t pack_plan(const xl_rays* rays, const int32_t* axis, const float* plan
   const PackWs w = pack_views(L, ws);
   const PackDev p = pack_dev(rays, axis, plane, levels);
   if (L.R > 0) {
-    hipLaunchKernelGGL(pack_count_kernel, dim3(grid_for(L.R, kPackWaves * (kWave / p.K))),
+    hipLaunchKernelGGL(pack_count_kernel, dim3(grid_for(L.R, kPackWaves * (kPairs / p.K))),
                        dim3(kPackBlock), 0, st, p, w);
     hipLaunchKernelGGL(pack_block_sum_kernel, dim3(grid_for(L.KB, 256)), dim3(256), 0, st, p, w);
   }
