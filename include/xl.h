@@ -227,7 +227,9 @@ typedef struct xl_rays {
 } xl_rays;
 
 /* Device workspace bytes for xl_pack_plan / xl_pack_fill: about
- * 10 * 2^levels + 16 bytes per ray. */
+ * 18 * 2^levels + 16 bytes per ray (10 * 2^levels + 16 above 16 boxes).
+ * One ray's run of samples in one box is limited to 134,217,727 samples
+ * (2^31 / 16); a longer run keeps only its first that many. */
 size_t xl_pack_workspace_bytes(int64_t n_rays, int32_t levels);
 
 /*

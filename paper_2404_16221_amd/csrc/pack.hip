@@ -20,17 +20,23 @@
 //               sorted samples give the run of samples that meet the box) ->
 //               run length and first sample, ray-major at [r][b], and the
 //               ray's segment count;
-//   block sums  pieces and segments of every box in every block of rays,
+//   block sums  pieces and segments of every box in every block of 16 rays,
 //               box-major at [b][block], so that an exclusive scan gives each
 //               (box, block) its first slot and first segment id in
-//               region-major order; a scan of the segments per ray gives the
-//               per-ray lists;
-//   pack_fill   one wave per block of rays, taken in order: lanes hold their
-//               box's running slot and segment id, rank the ray's boxes front
-//               to back and write the segment lists; then the wave strides
-//               over the ray's samples and writes every piece to its slot
-//               (consecutive samples of one box go to consecutive slots).
-// The workspace is 8 bytes per ray and box plus 16 per box and block of rays.
+//               region-major order, and (up to 16 boxes), ray-major, each (ray,
+//               box)'s pieces and segments in the earlier rays of its block; a
+//               scan of the segments per ray gives the per-ray lists;
+//   pack_fill   up to 16 boxes one wave per ray: lanes take their box's
+//               slot and segment id from those two prefixes; above 16 boxes
+//               one wave per block of 16 rays taken in order, lanes carrying
+//               their box's running slot and segment id.  Lanes rank the
+//               ray's boxes front to back through LDS and write the segment
+//               lists; then the wave strides over the ray's samples and writes
+//               every piece to its slot (consecutive samples of one box go to
+//               consecutive slots).
+// The workspace is 16 bytes per ray and box (8 above 16 boxes) plus 32 per
+// box and block of rays.
+// A ray's run in one box is capped at 2^31 / 16 samples (int32 prefixes).
 // Every store index is bounded by the counts of the plan, so inputs that break
 // the sortedness contract give unspecified pieces but never out-of-range
 // stores.
@@ -47,8 +53,13 @@ namespace {
 
 constexpr int kPackWaves = 4;
 constexpr int kPackBlock = kPackWaves * kWave;
-constexpr int kRayBlock = 16;  // rays per fill wave and per block of the slot prefix
+constexpr int kRayBlock = 16;  // rays per block of the region-major slot prefix
 constexpr int kPairs = 256;     // (ray, box) pairs a count wave examines
+constexpr int64_t kMaxRun = INT32_MAX / kRayBlock;  // samples of one ray in one box
+// Up to this many boxes the fill takes one wave per ray (the block sums then
+// also write in-block prefixes); above it one wave per block of rays, whose
+// per-ray set-up is shared by fewer lanes' worth of samples.
+constexpr int kRayFillMaxK = 16;
 
 struct PackDev {
   const float* o;        // [R][3]
@@ -65,6 +76,8 @@ struct PackDev {
 struct PackWs {
   int32_t* cnt;      // [R][K] pieces of ray r in box b
   int32_t* first;    // [R][K] first sample of that run (index inside the ray)
+  int32_t* pre;      // [R][K] pieces of box b in the earlier rays of r's block
+  int32_t* presg;    // [R][K] segments of box b in the earlier rays of r's block
   int64_t* bsum;     // [K][nblk] pieces of box b in block blk
   int64_t* bseg;     // [K][nblk] rays of block blk with pieces in box b
   int64_t* bpre;     // [K * nblk + 1] first slot of (b, blk)
@@ -207,7 +220,8 @@ __global__ __launch_bounds__(kPackBlock) void pack_count_kernel(PackDev p, PackW
       const int64_t s0 = p.ray_off[r], n = p.ray_off[r + 1] - s0;
       int64_t first, count;
       run_of(p, c_tin[wave][j], c_tout[wave][j], s0, n, first, count);
-      count = count < INT32_MAX ? count : INT32_MAX;  // (stored as int32; all passes agree on it)
+      // int32 storage with room for a block's sum; all passes use this value
+      count = count < kMaxRun ? count : kMaxRun;
       w.cnt[r * p.K + b] = static_cast<int32_t>(count);
       w.first[r * p.K + b] = static_cast<int32_t>(first);
       if (count > 0) atomicAdd(&c_nseg[wave][i / p.K], 1);
@@ -229,6 +243,10 @@ __global__ void pack_block_sum_kernel(PackDev p, PackWs w) {
     const int64_t r = blk * kRayBlock + j;
     if (r >= p.R) break;
     const int32_t c = w.cnt[r * p.K + b];
+    if (p.K <= kRayFillMaxK) {
+      w.pre[r * p.K + b] = static_cast<int32_t>(pieces);
+      w.presg[r * p.K + b] = static_cast<int32_t>(segs);
+    }
     pieces += c > 0 ? c : 0;
     segs += c > 0 ? 1 : 0;
   }
@@ -236,7 +254,112 @@ __global__ void pack_block_sum_kernel(PackDev p, PackWs w) {
   w.bseg[b * p.nblk + blk] = segs;
 }
 
-__global__ __launch_bounds__(kPackBlock) void pack_fill_kernel(PackDev p, PackWs w,
+// Small K: one wave per ray.
+__global__ __launch_bounds__(kPackBlock) void pack_fill_ray_kernel(PackDev p, PackWs w,
+                                                               float* __restrict__ out_t0,
+                                                               float* __restrict__ out_t1,
+                                                               int64_t* __restrict__ out_src,
+                                                               int64_t* __restrict__ seg_offsets,
+                                                               int64_t* __restrict__ seg_ids,
+                                                               int32_t* __restrict__ seg_box) {
+  __shared__ float s_tin[kPackWaves][kWave], s_tout[kPackWaves][kWave];
+  __shared__ int32_t s_first[kPackWaves][kWave], s_cnt[kPackWaves][kWave];
+  __shared__ int64_t s_base[kPackWaves][kWave];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * kPackWaves + wave;
+  const bool live = r < p.R;
+  int64_t s0 = 0, n = 0;
+  if (live) {
+    s0 = p.ray_off[r];
+    n = p.ray_off[r + 1] - s0;
+  }
+  // this lane's box: its run on the ray, and its slot and segment id in
+  // region-major order ((box, block) start plus the block's earlier rays)
+  int32_t c = 0, f = 0;
+  int64_t slot = 0, sid = 0;
+  if (live && lane < p.K) {
+    const int64_t blk = r / kRayBlock, at = r * p.K + lane;
+    c = w.cnt[at];
+    f = w.first[at];
+    slot = w.bpre[lane * p.nblk + blk] + w.pre[at];
+    sid = w.bsegpre[lane * p.nblk + blk] + w.presg[at];
+  }
+  const bool valid = c > 0;
+  float tin = INFINITY, tout = -INFINITY;
+  if (valid) {
+    const float2 sp = ray_span(p, r, leaf_box(p, lane));
+    tin = sp.x;
+    tout = sp.y;
+  }
+  s_tin[wave][lane] = valid ? tin : INFINITY;
+  __syncthreads();
+  // front-to-back rank among the boxes with pieces (ties, which disjoint
+  // boxes cannot produce, broken by lane so that ranks stay distinct)
+  int rank = 0;
+  if (valid)
+    for (int k = 0; k < p.K; ++k) {
+      const float t = s_tin[wave][k];
+      rank += (t < tin || (t == tin && k < lane)) ? 1 : 0;
+    }
+  const int nv = __popcll(__ballot(valid));
+  __syncthreads();
+  if (valid) {
+    s_tin[wave][rank] = tin;
+    s_tout[wave][rank] = tout;
+    s_first[wave][rank] = f;
+    s_cnt[wave][rank] = c;
+    s_base[wave][rank] = slot;
+    seg_offsets[sid] = slot;
+    if (seg_box) seg_box[sid] = lane;
+    seg_ids[w.ray_off[r] + rank] = sid;
+  }
+  __syncthreads();
+  if (!live) return;
+  int k0 = 0;
+  // the next chunk's interval is loaded before this chunk's pieces are stored
+  float s_next = 0.f, e_next = 0.f;
+  if (lane < n) {
+    s_next = p.t0[s0 + lane];
+    e_next = p.t1[s0 + lane];
+  }
+  for (int64_t j = lane; j < n; j += kWave) {
+    const float s = s_next, e = e_next;
+    if (j + kWave < n) {
+      s_next = p.t0[s0 + j + kWave];
+      e_next = p.t1[s0 + j + kWave];
+    }
+    while (k0 < nv && !(s_tout[wave][k0] > s)) ++k0;  // samples ascend: k0 only grows
+    for (int k = k0; k < nv; ++k) {
+      const float ti = s_tin[wave][k], to = s_tout[wave][k];
+      const bool pos = s < e;
+      if (pos && !(ti < e)) break;
+      float a0, a1;
+      bool piece;
+      if (pos) {
+        a0 = s > ti ? s : ti;
+        a1 = e < to ? e : to;
+        piece = a0 < a1;
+      } else {
+        a0 = a1 = s;
+        piece = ti <= s && s < to;
+      }
+      if (piece) {
+        const int64_t q = j - s_first[wave][k];
+        if (q >= 0 && q < s_cnt[wave][k]) {
+          const int64_t at = s_base[wave][k] + q;
+          out_t0[at] = a0;
+          out_t1[at] = a1;
+          if (out_src) out_src[at] = s0 + j;
+        }
+      }
+      if (!pos) break;  // a zero-length sample has one piece
+    }
+  }
+}
+
+// Large K: one wave per block of 16 rays, taken in order; lanes carry their
+// box's running slot and segment id from ray to ray.
+__global__ __launch_bounds__(kPackBlock) void pack_fill_block_kernel(PackDev p, PackWs w,
                                                                float* __restrict__ out_t0,
                                                                float* __restrict__ out_t1,
                                                                int64_t* __restrict__ out_src,
@@ -349,7 +472,7 @@ __global__ __launch_bounds__(kPackBlock) void pack_fill_kernel(PackDev p, PackWs
 struct PackLayout {
   int64_t R, K, RK, nblk, KB;
   size_t scan_elems;
-  size_t off[9];
+  size_t off[11];
   size_t bytes;
 };
 
@@ -364,6 +487,8 @@ PackLayout pack_layout(int64_t R, int levels) {
   const size_t sizes[] = {
       sizeof(int32_t) * L.RK,           // cnt
       sizeof(int32_t) * L.RK,           // first
+      sizeof(int32_t) * (L.K <= kRayFillMaxK ? L.RK : 0),  // pre
+      sizeof(int32_t) * (L.K <= kRayFillMaxK ? L.RK : 0),  // presg
       sizeof(int64_t) * L.KB,           // bsum
       sizeof(int64_t) * L.KB,           // bseg
       sizeof(int64_t) * (L.KB + 1),     // bpre
@@ -373,7 +498,7 @@ PackLayout pack_layout(int64_t R, int levels) {
       sizeof(int64_t) * L.scan_elems,   // scan_tmp
   };
   size_t o = 0;
-  for (int i = 0; i < 9; ++i) {
+  for (int i = 0; i < 11; ++i) {
     L.off[i] = o;
     o += (sizes[i] + 255) & ~static_cast<size_t>(255);
   }
@@ -386,13 +511,15 @@ PackWs pack_views(const PackLayout& L, void* ws) {
   PackWs w;
   w.cnt = reinterpret_cast<int32_t*>(b + L.off[0]);
   w.first = reinterpret_cast<int32_t*>(b + L.off[1]);
-  w.bsum = reinterpret_cast<int64_t*>(b + L.off[2]);
-  w.bseg = reinterpret_cast<int64_t*>(b + L.off[3]);
-  w.bpre = reinterpret_cast<int64_t*>(b + L.off[4]);
-  w.bsegpre = reinterpret_cast<int64_t*>(b + L.off[5]);
-  w.nseg = reinterpret_cast<int64_t*>(b + L.off[6]);
-  w.ray_off = reinterpret_cast<int64_t*>(b + L.off[7]);
-  w.scan_tmp = reinterpret_cast<int64_t*>(b + L.off[8]);
+  w.pre = reinterpret_cast<int32_t*>(b + L.off[2]);
+  w.presg = reinterpret_cast<int32_t*>(b + L.off[3]);
+  w.bsum = reinterpret_cast<int64_t*>(b + L.off[4]);
+  w.bseg = reinterpret_cast<int64_t*>(b + L.off[5]);
+  w.bpre = reinterpret_cast<int64_t*>(b + L.off[6]);
+  w.bsegpre = reinterpret_cast<int64_t*>(b + L.off[7]);
+  w.nseg = reinterpret_cast<int64_t*>(b + L.off[8]);
+  w.ray_off = reinterpret_cast<int64_t*>(b + L.off[9]);
+  w.scan_tmp = reinterpret_cast<int64_t*>(b + L.off[10]);
   return w;
 }
 
@@ -454,8 +581,14 @@ hipError_t pack_fill(const xl_rays* rays, const int32_t* axis, const float* plan
   const PackWs w = pack_views(L, ws);
   const PackDev p = pack_dev(rays, axis, plane, levels);
   if (L.R > 0)
-    hipLaunchKernelGGL(pack_fill_kernel, dim3(grid_for(L.nblk, kPackWaves)), dim3(kPackBlock), 0, st, p,
-                       w, t_start, t_end, src, seg_offsets, seg_ids, seg_box);
+  {
+    if (p.K <= kRayFillMaxK)
+      hipLaunchKernelGGL(pack_fill_ray_kernel, dim3(grid_for(L.R, kPackWaves)), dim3(kPackBlock), 0, st, p,
+                         w, t_start, t_end, src, seg_offsets, seg_ids, seg_box);
+    else
+      hipLaunchKernelGGL(pack_fill_block_kernel, dim3(grid_for(L.nblk, kPackWaves)), dim3(kPackBlock), 0,
+                         st, p, w, t_start, t_end, src, seg_offsets, seg_ids, seg_box);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = hipMemcpyAsync(seg_offsets + n_seg, w.bpre + L.KB, sizeof(int64_t),
