@@ -84,3 +84,27 @@ def test_serve_argument_errors():
     r = serve.XLResult()
     assert L.xl_serve_poll(None, 1, ctypes.byref(r), 0) == xl.XL_EINVAL
     assert L.xl_serve_release(None, 1) == xl.XL_EINVAL
+
+
+def test_pack_and_feature_argument_errors():
+    L = xl.lib()
+    assert L.xl_pack_workspace_bytes(-1, 4) == 0 and L.xl_pack_workspace_bytes(10, 7) == 0
+    assert L.xl_pack_workspace_bytes(1000, 4) > 1000 * 16 * 8
+    n, ns = ctypes.c_int64(), ctypes.c_int64()
+    assert L.xl_pack_plan(None, 16, 16, 4, 16, 1 << 20, ctypes.byref(n), ctypes.byref(ns), None) == xl.XL_EINVAL
+    rays = xl.XLRays(16, 16, 16, 16, 16, 10)
+    assert L.xl_pack_plan(ctypes.byref(rays), 16, 16, 7, 16, 1 << 30, ctypes.byref(n), ctypes.byref(ns),
+                          None) == xl.XL_EINVAL
+    assert "levels" in L.xl_last_error().decode()
+    assert L.xl_pack_plan(ctypes.byref(rays), None, None, 2, 16, 1 << 30, ctypes.byref(n),
+                          ctypes.byref(ns), None) == xl.XL_EINVAL
+    assert L.xl_pack_plan(ctypes.byref(rays), 16, 16, 2, 16, 1, ctypes.byref(n), ctypes.byref(ns),
+                          None) == xl.XL_EINVAL and "too small" in L.xl_last_error().decode()
+    f = xl.XLFeatures(0, 5, 16, 16, 16, 16, 4)
+    assert L.xl_render_features_fwd(ctypes.byref(f), 16, 1, 16, 16, None) == xl.XL_EINVAL
+    assert "n_feat" in L.xl_last_error().decode()
+    f = xl.XLFeatures(0, 8, 16, 0x1008, 16, 16, 4)
+    assert L.xl_render_features_fwd(ctypes.byref(f), 16, 1, 16, 16, None) == xl.XL_EINVAL
+    assert "aligned" in L.xl_last_error().decode()
+    assert L.xl_merge_features_fwd(16, 16, 3, 1, 16, 16, 1, 16, None) == xl.XL_EINVAL
+    assert L.xl_merge_features_bwd(16, 16, 8, 1, 16, 16, 1, None, 16, 16, None) == xl.XL_EINVAL
