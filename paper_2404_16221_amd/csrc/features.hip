@@ -11,7 +11,8 @@
 //
 // One wave per segment walks its samples 64 at a time (one per lane) with a
 // wave scan of the optical depths; a lane loads its sample's feature row as
-// 16-byte vectors (rows are contiguous across the wave).  F is 4, 8, 16 or 32.
+// 16-byte vectors (rows are contiguous across the wave) and keeps partial
+// sums, reduced once per segment.  F is 4, 8, 16 or 32.
 #include <hip/hip_runtime.h>
 
 #include "../../include/xl.h"
@@ -30,12 +31,6 @@ __device__ __forceinline__ float wave_incl_sum(float v, int lane) {
     const float y = __shfl_up(v, d);
     if (lane >= d) v += y;
   }
-  return v;
-}
-
-__device__ __forceinline__ float wave_all_sum(float v) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d);
   return v;
 }
 
@@ -113,6 +108,7 @@ template <int DT, int F>
 __global__ __launch_bounds__(kFeatBlock) void feat_fwd_kernel(FeatDev s, const int64_t* __restrict__ seg_offsets,
                                                               int64_t n_seg, float* __restrict__ phi,
                                                               float* __restrict__ tau_seg) {
+  __shared__ float red[kFeatWaves][kWave * (F + 1)];
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int64_t k = static_cast<int64_t>(blockIdx.x) * kFeatWaves + wave;
   if (k >= n_seg) return;
@@ -140,13 +136,20 @@ __global__ __launch_bounds__(kFeatBlock) void feat_fwd_kernel(FeatDev s, const i
     for (int c = 0; c < F; ++c) acc[c] = fmaf(w, f[c], acc[c]);
     before += __shfl(incl, kWave - 1);
   }
+  // Channel sums through a transpose in the wave's own LDS rows (a wave's
+  // LDS operations run in order): lane (part, ch) adds F rows of channel ch,
+  // then log2(64 / F) shuffles join the parts -- instead of 6 F shuffles.
+  float* row = &red[wave][lane * (F + 1)];
 #pragma unroll
-  for (int c = 0; c < F; ++c) acc[c] = wave_all_sum(acc[c]);
-  float mine = 0.f;
+  for (int c = 0; c < F; ++c) row[c] = acc[c];
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const int ch = lane % F, part = lane / F;
+  float t = 0.f;
 #pragma unroll
-  for (int c = 0; c < F; ++c)
-    if (lane == c) mine = acc[c];
-  if (lane < F) phi[lane * n_seg + k] = mine;
+  for (int j = 0; j < F; ++j) t += red[wave][(part * F + j) * (F + 1) + ch];
+#pragma unroll
+  for (int d = F; d < kWave; d <<= 1) t += __shfl_xor(t, d);
+  if (lane < F) phi[lane * n_seg + k] = t;
   if (tau_seg && lane == 0) tau_seg[k] = before;
 }
 
