@@ -166,19 +166,6 @@ def render_segments(sigma, rgb, t0, t1, seg_offsets, segs=None) -> np.ndarray:
     return out
 
 
-def merge_rays(seg_out, ray_offsets, seg_ids, rays=None) -> np.ndarray:
-    """ray_out[7, R] (or for the listed rays) from a full seg_out[7, n_seg]."""
-    seg_out = np.asarray(seg_out, F64)
-    ray_offsets = np.asarray(ray_offsets, np.int64)
-    seg_ids = np.asarray(seg_ids, np.int64)
-    rays = np.arange(ray_offsets.shape[0] - 1) if rays is None else np.asarray(rays)
-    out = np.zeros((TUPLE, rays.shape[0]), F64)
-    for j, r in enumerate(rays):
-        ids = seg_ids[ray_offsets[r]:ray_offsets[r + 1]]
-        out[:, j] = merge([seg_out[:, s] for s in ids])
-    return out
-
-
 def ray_index(seg_offsets, ray_offsets, seg_ids, r) -> np.ndarray:
     """Sample indices of ray r, front to back (its segments in the order I)."""
     ids = seg_ids[ray_offsets[r]:ray_offsets[r + 1]]
@@ -292,11 +279,17 @@ def merge_bwd(seg_tuples, g_ray) -> np.ndarray:
 
 
 def backward_partitioned(sigma, rgb, t0, t1, seg_offsets, ray_offsets, seg_ids,
-                         grad_ray, rays=None):
+                         grad_ray, rays=None, autodiff: bool = True):
     """Per-ray gradients by the partitioned path: merge bwd, then each segment's bwd.
 
     Returns (grad_seg [7, n_listed_segs], segs, {sample index: (dsigma, drgb)} as
     arrays over the listed rays' samples: (idx, dsigma, drgb)).
+
+    autodiff=True differentiates the definitions (``merge_bwd``,
+    ``grad_composite``); autodiff=False evaluates the hand-derived closed forms
+    (``merge_bwd_formula``, ``grad_composite_formula``) with numpy alone, which
+    the tests pin against the autodiff and against finite differences.  Worker
+    processes that must not start PyTorch's autograd engine use the latter.
     """
     sigma, rgb, t0, t1 = _f64(sigma), _f64(rgb).reshape(-1, 3), _f64(t0), _f64(t1)
     seg_offsets = np.asarray(seg_offsets, np.int64)
@@ -304,6 +297,8 @@ def backward_partitioned(sigma, rgb, t0, t1, seg_offsets, ray_offsets, seg_ids,
     seg_ids = np.asarray(seg_ids, np.int64)
     grad_ray = np.asarray(grad_ray, F64)
     rays = np.arange(ray_offsets.shape[0] - 1) if rays is None else np.asarray(rays)
+    m_bwd = merge_bwd if autodiff else merge_bwd_formula
+    s_bwd = grad_composite if autodiff else grad_composite_formula
     g_segs, segs, idx_all, ds_all, dc_all = [], [], [], [], []
     for j, r in enumerate(rays):
         ids = seg_ids[ray_offsets[r]:ray_offsets[r + 1]]
@@ -311,10 +306,10 @@ def backward_partitioned(sigma, rgb, t0, t1, seg_offsets, ray_offsets, seg_ids,
         for s in ids:
             a, b = int(seg_offsets[s]), int(seg_offsets[s + 1])
             parts.append(composite(sigma[a:b], rgb[a:b], t0[a:b], t1[a:b]))
-        gk = merge_bwd(parts, grad_ray[:, j])
+        gk = m_bwd(parts, grad_ray[:, j])
         for q, s in enumerate(ids):
             a, b = int(seg_offsets[s]), int(seg_offsets[s + 1])
-            ds, dc = grad_composite(sigma[a:b], rgb[a:b], t0[a:b], t1[a:b], gk[q])
+            ds, dc = s_bwd(sigma[a:b], rgb[a:b], t0[a:b], t1[a:b], gk[q])
             g_segs.append(gk[q])
             segs.append(int(s))
             idx_all.append(np.arange(a, b))

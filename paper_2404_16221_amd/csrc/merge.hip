@@ -4,63 +4,65 @@
 // in front of segment k is the exclusive product of the segment
 // transmittances (Eq. 4), formed as exp(-sum_{j<k} tau_j); the distortion
 // loss gains 2 T_{<k} S_k + T_{<k}^2 L_k with S_k = D_k A_{<k} - A_k D_{<k}
-// (Eq. 7-8).  With XL_MERGE_FP64 the running sums and products are float64.
+// (Eq. 7-8).  Colour, opacity, depth and distortion are folded in float32.
+// The running optical depth is a compensated float32 pair, or a float64
+// (XL_MERGE_FP64), so that only the cross-segment transmittance product is
+// wider than float32.
 //
 // The backward gives each segment the gradient of the merged tuple with
 // respect to its own tuple only (the per-region differentiation rule of Sec.
 // 4.2 and App. A.2): for segment k with exclusive prefix fold P and suffix fold
 // S, the merged tuple is P (+) x_k (+) S, and the chain rule through the two
-// (+) operations gives the per-component gradients below.  Rays with up to
-// kCached segments hold their tuples and suffix folds in registers; longer rays
-// compute the suffix folds by a reverse sweep and park them in grad_seg, which
-// the forward sweep then overwrites with the gradients.
+// (+) operations needs only P's transmittance, opacity and depth and all of S.
+// A forward sweep records (P_T, P_A, P_D) of every segment; a reverse sweep
+// carries S and writes the gradients.  Rays with up to kCached segments keep
+// their tuples and prefixes in registers; longer rays park the prefixes in
+// their own grad_seg entries, which the reverse sweep then overwrites.
+//
+// Rays are taken 256 to a workgroup, and consecutive workgroups of rays run
+// on the same XCD: adjacent rays' segments are adjacent inside every region,
+// so a cache line of tuples serves several neighbouring workgroups, which
+// then find it in their XCD's L2.
 #include "internal.h"
 #include "xl_device.hpp"
 
 namespace xl {
 
-template <typename R>
-__device__ __forceinline__ R exp_neg_t(R x);
-template <>
-__device__ __forceinline__ float exp_neg_t<float>(float x) { return exp_neg(x); }  // as in the segment kernels
-template <>
-__device__ __forceinline__ double exp_neg_t<double>(double x) { return exp(-x); }
+constexpr int kMergeBlock = 256;
+constexpr int kXcds = 8;  // MI355X: 8 XCDs, workgroups dispatched to them round robin
 
+// Running optical depth of a fold: float32 with TwoSum compensation, or float64.
 template <typename R>
-struct Tup {
-  R tau, cr, cg, cb, A, D, L;
-  R tlo;  // compensation of tau (the exact optical depth is tau + tlo)
+struct Depth;
+
+template <>
+struct Depth<float> {
+  float hi = 0.f, lo = 0.f;
+  __device__ __forceinline__ void add(float x) {  // Knuth's TwoSum, error kept in lo
+    const float s = hi + x;
+    const float bb = s - hi;
+    lo += (hi - (s - bb)) + (x - bb);
+    hi = s;
+  }
+  __device__ __forceinline__ float trans() const { return exp_neg(hi + lo); }
 };
 
-// Compensated accumulation of optical depths (Knuth's TwoSum on the high parts).
-template <typename R>
-__device__ __forceinline__ void add_tau_t(R& tau, R& tlo, R hi, R lo) {
-  const R s = tau + hi;
-  const R bb = s - tau;
-  tlo += ((tau - (s - bb)) + (hi - bb)) + lo;
-  tau = s;
-}
+template <>
+struct Depth<double> {
+  double v = 0.0;
+  __device__ __forceinline__ void add(float x) { v += static_cast<double>(x); }
+  __device__ __forceinline__ float trans() const { return static_cast<float>(exp(-v)); }
+};
 
-template <typename R>
-__device__ __forceinline__ Tup<R> load_tup(const float* __restrict__ p, int64_t n_seg, int64_t s) {
-  Tup<R> x;
+struct Tup {
+  float tau, cr, cg, cb, A, D, L;
+};
+
+__device__ __forceinline__ Tup load_tup(const float* __restrict__ p, int64_t n_seg, int64_t s) {
+  Tup x;
   x.tau = p[s]; x.cr = p[n_seg + s]; x.cg = p[2 * n_seg + s]; x.cb = p[3 * n_seg + s];
   x.A = p[4 * n_seg + s]; x.D = p[5 * n_seg + s]; x.L = p[6 * n_seg + s];
-  x.tlo = 0;
   return x;
-}
-
-// x in front of y, with T_x = exp(-x.tau).
-template <typename R>
-__device__ __forceinline__ Tup<R> fold(const Tup<R>& x, R Tx, const Tup<R>& y) {
-  Tup<R> r;
-  r.tau = x.tau; r.tlo = x.tlo;
-  add_tau_t<R>(r.tau, r.tlo, y.tau, y.tlo);
-  r.cr = x.cr + Tx * y.cr; r.cg = x.cg + Tx * y.cg; r.cb = x.cb + Tx * y.cb;
-  r.A = x.A + Tx * y.A;
-  r.D = x.D + Tx * y.D;
-  r.L = x.L + Tx * Tx * y.L + R(2) * Tx * (y.D * x.A - y.A * x.D);
-  return r;
 }
 
 __device__ __forceinline__ void clamp_range(const int64_t* __restrict__ ro, int64_t r, int64_t n_seg,
@@ -71,36 +73,48 @@ __device__ __forceinline__ void clamp_range(const int64_t* __restrict__ ro, int6
   k1 = k1 < k0 ? k0 : (k1 > n_seg ? n_seg : k1);
 }
 
+// Ray of this thread: workgroup b of the launch takes ray block
+// (b % kXcds) * per + b / kXcds, so each XCD walks a contiguous run of blocks.
+__device__ __forceinline__ int64_t merge_ray(int64_t n_rays) {
+  const int64_t nblocks = (n_rays + kMergeBlock - 1) / kMergeBlock;
+  const int64_t per = (nblocks + kXcds - 1) / kXcds;
+  const int64_t b = blockIdx.x;
+  const int64_t lb = (b % kXcds) * per + b / kXcds;
+  return lb * kMergeBlock + threadIdx.x;
+}
+
 // Rays with up to kCached segments are handled with all their tuples in registers.
 constexpr int kCached = 8;
 
 template <typename R>
-__global__ __launch_bounds__(256) void merge_fwd_kernel(const float* __restrict__ seg_out,
-                                                        int64_t n_seg,
-                                                        const int64_t* __restrict__ ro,
-                                                        const int64_t* __restrict__ ids,
-                                                        int64_t n_rays, float* __restrict__ out) {
-  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kMergeBlock) void merge_fwd_kernel(const float* __restrict__ seg_out,
+                                                                int64_t n_seg,
+                                                                const int64_t* __restrict__ ro,
+                                                                const int64_t* __restrict__ ids,
+                                                                int64_t n_rays,
+                                                                float* __restrict__ out) {
+  const int64_t r = merge_ray(n_rays);
   if (r >= n_rays) return;
   int64_t k0, k1;
   clamp_range(ro, r, n_seg, k0, k1);
   // Alg. 1/2 state: T(t_1 -> t_k) and C, A, D, L accumulated so far.
-  R tau = 0, tlo = 0, Tpre = 1, cr = 0, cg = 0, cb = 0, A = 0, D = 0, L = 0;
-  auto step = [&](const Tup<R>& x) {
-    const R S = x.D * A - x.A * D;                    // Eq. 8
-    L += Tpre * Tpre * x.L + R(2) * Tpre * S;         // Eq. 7
+  Depth<R> tau;
+  float Tpre = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, A = 0.f, D = 0.f, L = 0.f;
+  auto step = [&](const Tup& x) {
+    const float S = x.D * A - x.A * D;                 // Eq. 8
+    L += Tpre * Tpre * x.L + 2.f * Tpre * S;           // Eq. 7
     cr += Tpre * x.cr; cg += Tpre * x.cg; cb += Tpre * x.cb;  // Eq. 3
-    A += Tpre * x.A;                                  // Eq. 5
-    D += Tpre * x.D;                                  // Eq. 6
-    add_tau_t<R>(tau, tlo, x.tau, R(0));
-    Tpre = exp_neg_t<R>(tau + tlo);                   // Eq. 4
+    A += Tpre * x.A;                                   // Eq. 5
+    D += Tpre * x.D;                                   // Eq. 6
+    tau.add(x.tau);
+    Tpre = tau.trans();                                // Eq. 4
   };
   const int64_t n = k1 - k0;
   if (n <= kCached) {
     // All of the ray's tuples are requested at once (two dependent loads in
     // flight per ray instead of two per segment).
     int64_t sid[kCached];
-    Tup<R> x[kCached];
+    Tup x[kCached];
 #pragma unroll
     for (int q = 0; q < kCached; ++q) {
       const int64_t s = q < n ? ids[k0 + q] : -1;
@@ -108,7 +122,7 @@ __global__ __launch_bounds__(256) void merge_fwd_kernel(const float* __restrict_
     }
 #pragma unroll
     for (int q = 0; q < kCached; ++q)
-      if (sid[q] >= 0) x[q] = load_tup<R>(seg_out, n_seg, sid[q]);
+      if (sid[q] >= 0) x[q] = load_tup(seg_out, n_seg, sid[q]);
 #pragma unroll
     for (int q = 0; q < kCached; ++q)
       if (sid[q] >= 0) step(x[q]);
@@ -116,119 +130,149 @@ __global__ __launch_bounds__(256) void merge_fwd_kernel(const float* __restrict_
     for (int64_t k = k0; k < k1; ++k) {
       const int64_t s = ids[k];
       if (s < 0 || s >= n_seg) continue;
-      step(load_tup<R>(seg_out, n_seg, s));
+      step(load_tup(seg_out, n_seg, s));
     }
   }
-  out[r] = static_cast<float>(Tpre);
-  out[n_rays + r] = static_cast<float>(cr);
-  out[2 * n_rays + r] = static_cast<float>(cg);
-  out[3 * n_rays + r] = static_cast<float>(cb);
-  out[4 * n_rays + r] = static_cast<float>(A);
-  out[5 * n_rays + r] = static_cast<float>(D);
-  out[6 * n_rays + r] = static_cast<float>(L);
+  out[r] = Tpre;
+  out[n_rays + r] = cr;
+  out[2 * n_rays + r] = cg;
+  out[3 * n_rays + r] = cb;
+  out[4 * n_rays + r] = A;
+  out[5 * n_rays + r] = D;
+  out[6 * n_rays + r] = L;
 }
 
-// Gradient of P (+) x (+) S with respect to x, written to gseg[:, s].
+// Exclusive suffix fold of a ray's segments (everything behind segment k).
+template <typename R>
+struct Suffix {
+  Depth<R> tau;
+  float cr = 0.f, cg = 0.f, cb = 0.f, A = 0.f, D = 0.f, L = 0.f;
+  // S <- x (+) S, x in front of S.
+  __device__ __forceinline__ void push_front(const Tup& x, float Tx) {
+    L = x.L + Tx * Tx * L + 2.f * Tx * (D * x.A - A * x.D);
+    cr = x.cr + Tx * cr; cg = x.cg + Tx * cg; cb = x.cb + Tx * cb;
+    A = x.A + Tx * A;
+    D = x.D + Tx * D;
+    tau.add(x.tau);
+  }
+};
+
+struct RayGrad {
+  float T, cr, cg, cb, A, D, L;
+};
+
+// Gradient of P (+) x (+) S with respect to x, written to gseg[:, s]; P enters
+// through its transmittance PT, opacity PA and depth PD only.
 template <typename R>
 __device__ __forceinline__ void write_seg_grad(float* __restrict__ gseg, int64_t n_seg, int64_t s,
-                                               const Tup<R>& P, R PT, const Tup<R>& x,
-                                               const Tup<R>& Sk, R gT, R gCr, R gCg, R gCb, R gA,
-                                               R gD, R gL) {
-  const R Tk = exp_neg_t<R>(x.tau);
-  const R ST = exp_neg_t<R>(Sk.tau + Sk.tlo);
-  const R gA_k = PT * (gA + R(2) * gL * (PT * Tk * Sk.D - P.D));
-  const R gD_k = PT * (gD + R(2) * gL * (P.A - PT * Tk * Sk.A));
-  const R gL_k = gL * PT * PT;
-  const R gT_k = PT * gT * ST + PT * (gCr * Sk.cr + gCg * Sk.cg + gCb * Sk.cb) +
-                 (PT * gA - R(2) * gL * PT * P.D) * Sk.A +
-                 (PT * gD + R(2) * gL * PT * P.A) * Sk.D +
-                 gL * PT * PT * (R(2) * Tk * Sk.L + R(2) * (Sk.D * x.A - Sk.A * x.D));
-  gseg[s] = static_cast<float>(-Tk * gT_k);
-  gseg[n_seg + s] = static_cast<float>(PT * gCr);
-  gseg[2 * n_seg + s] = static_cast<float>(PT * gCg);
-  gseg[3 * n_seg + s] = static_cast<float>(PT * gCb);
-  gseg[4 * n_seg + s] = static_cast<float>(gA_k);
-  gseg[5 * n_seg + s] = static_cast<float>(gD_k);
-  gseg[6 * n_seg + s] = static_cast<float>(gL_k);
+                                               float PT, float PA, float PD, const Tup& x,
+                                               const Suffix<R>& S, const RayGrad& g) {
+  const float Tk = exp_neg(x.tau);
+  const float ST = S.tau.trans();
+  const float gA_k = PT * (g.A + 2.f * g.L * (PT * Tk * S.D - PD));
+  const float gD_k = PT * (g.D + 2.f * g.L * (PA - PT * Tk * S.A));
+  const float gL_k = g.L * PT * PT;
+  const float gT_k = PT * g.T * ST + PT * (g.cr * S.cr + g.cg * S.cg + g.cb * S.cb) +
+                     (PT * g.A - 2.f * g.L * PT * PD) * S.A +
+                     (PT * g.D + 2.f * g.L * PT * PA) * S.D +
+                     g.L * PT * PT * (2.f * Tk * S.L + 2.f * (S.D * x.A - S.A * x.D));
+  gseg[s] = -Tk * gT_k;
+  gseg[n_seg + s] = PT * g.cr;
+  gseg[2 * n_seg + s] = PT * g.cg;
+  gseg[3 * n_seg + s] = PT * g.cb;
+  gseg[4 * n_seg + s] = gA_k;
+  gseg[5 * n_seg + s] = gD_k;
+  gseg[6 * n_seg + s] = gL_k;
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void merge_bwd_kernel(const float* __restrict__ seg_out,
-                                                        int64_t n_seg,
-                                                        const int64_t* __restrict__ ro,
-                                                        const int64_t* __restrict__ ids,
-                                                        int64_t n_rays,
-                                                        const float* __restrict__ gray,
-                                                        float* __restrict__ gseg) {
-  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kMergeBlock) void merge_bwd_kernel(const float* __restrict__ seg_out,
+                                                                int64_t n_seg,
+                                                                const int64_t* __restrict__ ro,
+                                                                const int64_t* __restrict__ ids,
+                                                                int64_t n_rays,
+                                                                const float* __restrict__ gray,
+                                                                float* __restrict__ gseg) {
+  const int64_t r = merge_ray(n_rays);
   if (r >= n_rays) return;
   int64_t k0, k1;
   clamp_range(ro, r, n_seg, k0, k1);
-  const R gT = gray[r], gCr = gray[n_rays + r], gCg = gray[2 * n_rays + r],
-          gCb = gray[3 * n_rays + r], gA = gray[4 * n_rays + r], gD = gray[5 * n_rays + r],
-          gL = gray[6 * n_rays + r];
-  if (k1 - k0 <= kCached) {
-    Tup<R> x[kCached];
+  const RayGrad g{gray[r], gray[n_rays + r], gray[2 * n_rays + r], gray[3 * n_rays + r],
+                  gray[4 * n_rays + r], gray[5 * n_rays + r], gray[6 * n_rays + r]};
+  const int64_t n = k1 - k0;
+  if (n <= kCached) {
+    Tup x[kCached];
     int64_t sid[kCached];
 #pragma unroll
     for (int q = 0; q < kCached; ++q) {
-      const int64_t k = k0 + q;
-      sid[q] = (k < k1) ? ids[k] : -1;
-      const bool ok = sid[q] >= 0 && sid[q] < n_seg;
-      if (!ok) sid[q] = -1;
-      x[q] = ok ? load_tup<R>(seg_out, n_seg, sid[q]) : Tup<R>{0, 0, 0, 0, 0, 0, 0};
+      const int64_t s = q < n ? ids[k0 + q] : -1;
+      sid[q] = (s >= 0 && s < n_seg) ? s : -1;
     }
-    // Slots past the ray's last segment are skipped (by the whole wave when
-    // no ray of it has that many); invalid ids inside it are identities.
-    const int64_t n = k1 - k0;
-    Tup<R> S[kCached];
-    Tup<R> acc{0, 0, 0, 0, 0, 0, 0};
+    // Invalid ids inside the ray are identities (zero tuples).
 #pragma unroll
-    for (int q = kCached - 1; q >= 0; --q) {
-      if (q < n) {
-        S[q] = acc;
-        acc = fold<R>(x[q], exp_neg_t<R>(x[q].tau), acc);
-      }
-    }
-    Tup<R> P{0, 0, 0, 0, 0, 0, 0};
-    R PT = 1;
+    for (int q = 0; q < kCached; ++q)
+      x[q] = sid[q] >= 0 ? load_tup(seg_out, n_seg, sid[q]) : Tup{0, 0, 0, 0, 0, 0, 0};
+    // Forward sweep: exclusive prefix transmittance, opacity and depth.  Slots
+    // past the ray's last segment are skipped (by the whole wave when no ray
+    // of it has that many).
+    float PT[kCached], PA[kCached], PD[kCached];
+    Depth<R> ptau;
+    float T = 1.f, A = 0.f, D = 0.f;
 #pragma unroll
     for (int q = 0; q < kCached; ++q) {
       if (q < n) {
-        if (sid[q] >= 0) write_seg_grad<R>(gseg, n_seg, sid[q], P, PT, x[q], S[q], gT, gCr, gCg, gCb, gA, gD, gL);
-        P = fold<R>(P, PT, x[q]);
-        PT = exp_neg_t<R>(P.tau + P.tlo);
+        PT[q] = T; PA[q] = A; PD[q] = D;
+        A += T * x[q].A;
+        D += T * x[q].D;
+        ptau.add(x[q].tau);
+        T = ptau.trans();
+      }
+    }
+    // Reverse sweep with the exclusive suffix fold.
+    Suffix<R> S;
+#pragma unroll
+    for (int q = kCached - 1; q >= 0; --q) {
+      if (q < n) {
+        if (sid[q] >= 0) write_seg_grad<R>(gseg, n_seg, sid[q], PT[q], PA[q], PD[q], x[q], S, g);
+        S.push_front(x[q], exp_neg(x[q].tau));
       }
     }
     return;
   }
-  // Reverse sweep: exclusive suffix fold of every segment, parked in gseg.
-  Tup<R> S{0, 0, 0, 0, 0, 0, 0};
+  // Forward sweep: the exclusive prefix (P_T, P_A, P_D) of every segment,
+  // parked in the segment's own tau, A and D gradient entries.
+  {
+    Depth<R> ptau;
+    float T = 1.f, A = 0.f, D = 0.f;
+    for (int64_t k = k0; k < k1; ++k) {
+      const int64_t s = ids[k];
+      if (s < 0 || s >= n_seg) continue;
+      const Tup x = load_tup(seg_out, n_seg, s);
+      gseg[s] = T;
+      gseg[4 * n_seg + s] = A;
+      gseg[5 * n_seg + s] = D;
+      A += T * x.A;
+      D += T * x.D;
+      ptau.add(x.tau);
+      T = ptau.trans();
+    }
+  }
+  // Reverse sweep: the suffix fold S, and every segment's gradient.
+  Suffix<R> S;
   for (int64_t k = k1 - 1; k >= k0; --k) {
     const int64_t s = ids[k];
     if (s < 0 || s >= n_seg) continue;
-    gseg[s] = static_cast<float>(S.tau + S.tlo);
-    gseg[n_seg + s] = static_cast<float>(S.cr);
-    gseg[2 * n_seg + s] = static_cast<float>(S.cg);
-    gseg[3 * n_seg + s] = static_cast<float>(S.cb);
-    gseg[4 * n_seg + s] = static_cast<float>(S.A);
-    gseg[5 * n_seg + s] = static_cast<float>(S.D);
-    gseg[6 * n_seg + s] = static_cast<float>(S.L);
-    const Tup<R> x = load_tup<R>(seg_out, n_seg, s);
-    S = fold<R>(x, exp_neg_t<R>(x.tau), S);
+    const Tup x = load_tup(seg_out, n_seg, s);
+    const float PT = gseg[s], PA = gseg[4 * n_seg + s], PD = gseg[5 * n_seg + s];
+    write_seg_grad<R>(gseg, n_seg, s, PT, PA, PD, x, S, g);
+    S.push_front(x, exp_neg(x.tau));
   }
-  // Forward sweep with the exclusive prefix fold P.
-  Tup<R> P{0, 0, 0, 0, 0, 0, 0};
-  R PT = 1;
-  for (int64_t k = k0; k < k1; ++k) {
-    const int64_t s = ids[k];
-    if (s < 0 || s >= n_seg) continue;
-    const Tup<R> x = load_tup<R>(seg_out, n_seg, s);
-    const Tup<R> Sk = load_tup<R>(gseg, n_seg, s);
-    write_seg_grad<R>(gseg, n_seg, s, P, PT, x, Sk, gT, gCr, gCg, gCb, gA, gD, gL);
-    P = fold<R>(P, PT, x);
-    PT = exp_neg_t<R>(P.tau + P.tlo);
-  }
+}
+
+static inline unsigned merge_grid(int64_t n_rays) {
+  const int64_t nblocks = (n_rays + kMergeBlock - 1) / kMergeBlock;
+  const int64_t per = (nblocks + kXcds - 1) / kXcds;
+  return static_cast<unsigned>(per * kXcds);
 }
 
 static inline unsigned grid_for(int64_t count, int block) {
@@ -240,11 +284,11 @@ hipError_t launch_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* 
                             hipStream_t stream) {
   if (n_rays == 0) return hipSuccess;
   if (fp64)
-    hipLaunchKernelGGL(merge_fwd_kernel<double>, dim3(grid_for(n_rays, 256)), dim3(256), 0, stream,
-                       seg_out, n_seg, ro, ids, n_rays, out);
+    hipLaunchKernelGGL(merge_fwd_kernel<double>, dim3(merge_grid(n_rays)), dim3(kMergeBlock), 0,
+                       stream, seg_out, n_seg, ro, ids, n_rays, out);
   else
-    hipLaunchKernelGGL(merge_fwd_kernel<float>, dim3(grid_for(n_rays, 256)), dim3(256), 0, stream,
-                       seg_out, n_seg, ro, ids, n_rays, out);
+    hipLaunchKernelGGL(merge_fwd_kernel<float>, dim3(merge_grid(n_rays)), dim3(kMergeBlock), 0,
+                       stream, seg_out, n_seg, ro, ids, n_rays, out);
   return hipGetLastError();
 }
 
@@ -253,11 +297,11 @@ hipError_t launch_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* 
                             bool fp64, hipStream_t stream) {
   if (n_rays == 0) return hipSuccess;
   if (fp64)
-    hipLaunchKernelGGL(merge_bwd_kernel<double>, dim3(grid_for(n_rays, 256)), dim3(256), 0, stream,
-                       seg_out, n_seg, ro, ids, n_rays, gray, gseg);
+    hipLaunchKernelGGL(merge_bwd_kernel<double>, dim3(merge_grid(n_rays)), dim3(kMergeBlock), 0,
+                       stream, seg_out, n_seg, ro, ids, n_rays, gray, gseg);
   else
-    hipLaunchKernelGGL(merge_bwd_kernel<float>, dim3(grid_for(n_rays, 256)), dim3(256), 0, stream,
-                       seg_out, n_seg, ro, ids, n_rays, gray, gseg);
+    hipLaunchKernelGGL(merge_bwd_kernel<float>, dim3(merge_grid(n_rays)), dim3(kMergeBlock), 0,
+                       stream, seg_out, n_seg, ro, ids, n_rays, gray, gseg);
   return hipGetLastError();
 }
 

@@ -14,7 +14,9 @@ Tolerances (FP32 path, the 1e-5 relative bar with explicit floors):
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -52,15 +54,25 @@ def quantize(b, dtype):
 
 
 def tuple_report(got, ref, kind: str, rtol=RTOL, atol=ATOL):
-    """Per-component worst normalised error (<= 1 passes) for [7, N] tuples.
+    """Per-component errors of [7, N] tuples.
 
-    kind = "seg": component 0 is tau; kind = "ray": component 0 is T.
+    kind = "seg": component 0 is tau; kind = "ray": component 0 is T, judged
+    through tau = -log T.  Returns worst normalised error (<= 1 passes), the
+    largest absolute error, the largest relative error over the elements the
+    relative bar governs (rtol |ref| >= floor), and how many elements the floor
+    governs instead.
     """
     got = np.asarray(got, np.float64)
     ref = np.asarray(ref, np.float64)
-    rep = {"norm": np.zeros(7), "rel": np.zeros(7), "floored": np.zeros(7, int), "n": ref.shape[1]}
+    rep = {"norm": np.zeros(7), "rel": np.zeros(7), "abs": np.zeros(7), "floored": np.zeros(7, int),
+           "n": ref.shape[1]}
     if ref.shape[1] == 0:
         return rep
+
+    def rel_governed(err, r, floor):
+        gov = rtol * np.abs(r) >= floor
+        return (float((err[gov] / np.abs(r[gov])).max()) if gov.any() else 0.0), int((~gov).sum())
+
     if kind == "ray":
         with np.errstate(divide="ignore"):
             tau_ref = -np.log(ref[0])
@@ -70,20 +82,20 @@ def tuple_report(got, ref, kind: str, rtol=RTOL, atol=ATOL):
         e = np.where(deep, 0.0, np.abs(tau_got - tau_ref) / np.where(deep, 1.0, lim))
         e = np.where(deep & (got[0] >= 1e-34), np.inf, e)
         rep["norm"][0] = e.max()
-        ok = ~deep & (tau_ref > 0)
-        rep["rel"][0] = (np.abs(tau_got - tau_ref)[ok] / tau_ref[ok]).max() if ok.any() else 0.0
+        ok = ~deep
+        rep["rel"][0], rep["floored"][0] = rel_governed(np.abs(tau_got - tau_ref)[ok], tau_ref[ok],
+                                                        TAU_ATOL)
+        rep["abs"][0] = np.abs(got[0] - ref[0]).max()
     else:
-        lim = rtol * np.abs(ref[0]) + TAU_ATOL
-        rep["norm"][0] = (np.abs(got[0] - ref[0]) / lim).max()
-        nz = ref[0] > 0
-        rep["rel"][0] = (np.abs(got[0] - ref[0])[nz] / ref[0][nz]).max() if nz.any() else 0.0
+        err = np.abs(got[0] - ref[0])
+        rep["norm"][0] = (err / (rtol * np.abs(ref[0]) + TAU_ATOL)).max()
+        rep["rel"][0], rep["floored"][0] = rel_governed(err, ref[0], TAU_ATOL)
+        rep["abs"][0] = err.max()
     for k in range(1, 7):
         err = np.abs(got[k] - ref[k])
-        lim = rtol * np.abs(ref[k]) + atol[k]
-        rep["norm"][k] = (err / lim).max()
-        nz = np.abs(ref[k]) > 0
-        rep["rel"][k] = (err[nz] / np.abs(ref[k][nz])).max() if nz.any() else err.max()
-        rep["floored"][k] = int((atol[k] > rtol * np.abs(ref[k])).sum())
+        rep["norm"][k] = (err / (rtol * np.abs(ref[k]) + atol[k])).max()
+        rep["rel"][k], rep["floored"][k] = rel_governed(err, ref[k], atol[k])
+        rep["abs"][k] = err.max()
     return rep
 
 
@@ -93,26 +105,56 @@ def assert_tuples(got, ref, kind, what="", **kw):
     msg = f"{what}: worst normalised error " + ", ".join(
         f"{n}={v:.3g}" for n, v in zip(names, rep["norm"])) + "; max rel " + ", ".join(
         f"{n}={v:.3g}" for n, v in zip(names, rep["rel"]))
+    record(what, {n: {"max_abs": float(a), "max_rel": float(r), "floored": int(f)}
+                  for n, a, r, f in zip(names, rep["abs"], rep["rel"], rep["floored"])},
+           n=int(rep["n"]), worst_normalised=float(rep["norm"].max()))
     assert np.all(rep["norm"] <= 1.0), msg
     return rep
 
 
 def grad_report(got, ref, rtol=RTOL, floor=1e-6):
+    """Worst normalised error (<= 1 passes), norm-wise relative error, and the
+    unfloored maxima: largest absolute error, largest relative error over the
+    elements the relative bar governs, and how many elements the floor governs
+    (floor * max|ref| > rtol * |ref|)."""
     got = np.asarray(got, np.float64).ravel()
     ref = np.asarray(ref, np.float64).ravel()
+    rep = {"norm": 0.0, "normwise": 0.0, "max_abs": 0.0, "max_rel": 0.0, "floored": 0,
+           "max_ref": 0.0, "n": int(ref.size)}
     if ref.size == 0:
-        return 0.0, 0.0
+        return rep
     s = np.abs(ref).max()
+    err = np.abs(got - ref)
     lim = rtol * np.abs(ref) + floor * s
-    norm = float((np.abs(got - ref) / np.where(lim > 0, lim, 1.0)).max()) if s > 0 else float(np.abs(got).max())
-    nrm = float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
-    return norm, nrm
+    rep["norm"] = float((err / np.where(lim > 0, lim, 1.0)).max()) if s > 0 else float(np.abs(got).max())
+    rep["normwise"] = float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+    rep["max_abs"] = float(err.max())
+    rep["max_ref"] = float(s)
+    rel_gov = rtol * np.abs(ref) >= floor * s
+    rep["floored"] = int((~rel_gov).sum())
+    if rel_gov.any():
+        rep["max_rel"] = float((err[rel_gov] / np.abs(ref[rel_gov])).max())
+    return rep
 
 
 def assert_grads(got, ref, what="", rtol=RTOL, floor=1e-6, norm_tol=1e-5):
-    norm, nrm = grad_report(got, ref, rtol, floor)
-    assert norm <= 1.0 and nrm <= norm_tol, f"{what}: worst normalised {norm:.3g}, norm-wise rel {nrm:.3g}"
-    return norm, nrm
+    rep = grad_report(got, ref, rtol, floor)
+    record(what, {k: rep[k] for k in ("max_abs", "max_rel", "floored", "normwise", "max_ref")},
+           n=rep["n"], worst_normalised=rep["norm"])
+    assert rep["norm"] <= 1.0 and rep["normwise"] <= norm_tol, \
+        f"{what}: worst normalised {rep['norm']:.3g}, norm-wise rel {rep['normwise']:.3g}"
+    return rep
+
+
+def record(what, errors, **extra):
+    """Append one comparison's measured errors to the JSON-lines file named by
+    XL_ERRORS_LOG (nothing is written when it is unset)."""
+    path = os.environ.get("XL_ERRORS_LOG")
+    if not path or not what:
+        return
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    with open(path, "a") as f:
+        f.write(json.dumps({"what": what, **extra, "errors": errors}) + "\n")
 
 
 def sample_rays(n_rays, k, seed):

@@ -342,3 +342,54 @@ def test_crowded_tiles(dtype):
                      norm_tol=ulp)
         assert_grads(gc.float().cpu().numpy()[idx], dc_ref, "crowded drgb", rtol=ulp, floor=1e-5,
                      norm_tol=ulp)
+
+
+# ------------------------------------------------------------------ long rays in the merge
+@pytest.mark.parametrize("fp64", [False, True])
+def test_merge_long_rays_empty_segments_and_invalid_ids(fp64):
+    """Rays of 1-40 segments in the same waves: the merge keeps up to eight of
+    a ray's tuples in registers and walks longer rays segment by segment.
+    Some segments are empty, and some listed ids lie outside [0, n_seg): the
+    merge skips those (their segments are listed by no ray)."""
+    rng = np.random.default_rng(51)
+    empty = (np.zeros(0), np.zeros((0, 3)), np.zeros(0), np.zeros(0))
+    rays = []
+    for r in range(400):
+        nseg = int(rng.integers(9, 41)) if r % 3 else int(rng.integers(1, 9))
+        ray, t = [], 0.05
+        for k in range(nseg):
+            if rng.random() < 0.15:
+                ray.append(empty)
+                continue
+            n = int(rng.integers(1, 6))
+            ray.append(_seg(rng, n, t))
+            t += 0.02 * n + 0.01
+        rays.append(ray)
+    b = _hand_batch(rays, shuffle_seed=3)
+    ids = b.seg_ids.copy()
+    bad = rng.random(ids.size) < 0.03
+    nb = int(bad.sum())
+    ids[bad] = np.where(rng.random(nb) < 0.5, -1 - rng.integers(0, 5, nb), b.n_seg + rng.integers(0, 5, nb))
+    # the oracle's batch: the same samples with the invalid entries dropped
+    counts = np.add.reduceat((~bad).astype(np.int64), b.ray_offsets[:-1]) if b.n_rays else np.zeros(0)
+    counts = np.where(np.diff(b.ray_offsets) > 0, counts, 0)
+    ro = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    ob = synth.Batch(b.sigma, b.rgb, b.t_start, b.t_end, b.seg_offsets, ro, b.seg_ids[~bad],
+                     b.seg_box, b.seg_ray, b.rays)
+    say("long rays: segments per ray up to", np.diff(b.ray_offsets).max(), "invalid ids", nb)
+    d = to_dev(b)
+    d.seg_ids = torch.from_numpy(ids).cuda()
+    seg_out, ws, ray_out = run_fwd(d, fp64=fp64)
+    rays_all = np.arange(b.n_rays)
+    assert_tuples(ray_out.cpu().numpy(), oracle_rays(ob, rays_all), "ray",
+                  f"long rays fp64={fp64} ray tuples")
+    grad_ray = np.random.default_rng(52).normal(size=(7, b.n_rays))
+    gseg, gs, gc = run_bwd(d, seg_out, ws, grad_ray, fp64=fp64)
+    g_seg_ref, segs, idx, ds_ref, dc_ref = O.backward_partitioned(
+        b.sigma, b.rgb, b.t_start, b.t_end, b.seg_offsets, ro, ob.seg_ids, grad_ray, rays_all)
+    g = gseg.cpu().numpy()
+    assert_grads(g[:, segs], g_seg_ref, f"long rays fp64={fp64} grad_seg")
+    unlisted = np.setdiff1d(np.arange(b.n_seg), segs)
+    assert unlisted.size > 0 and np.all(g[:, unlisted] == 0)
+    assert_grads(gs.cpu().numpy()[idx], ds_ref, f"long rays fp64={fp64} dsigma")
+    assert_grads(gc.cpu().numpy()[idx], dc_ref, f"long rays fp64={fp64} drgb")

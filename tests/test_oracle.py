@@ -323,3 +323,20 @@ def test_batch_partitioned_equals_single_on_generated_rays():
         single = O.render_rays_single(b.sigma, b.rgb, b.t_start, b.t_end, b.seg_offsets,
                                       b.ray_offsets, b.seg_ids)
         np.testing.assert_allclose(part, single, rtol=1e-11, atol=1e-14)
+
+
+def test_backward_closed_forms_equal_autodiff_on_generated_rays():
+    """The partitioned backward from the closed forms (what the oracle's worker
+    processes use) equals the autodiff of the definitions, ray by ray."""
+    for cfg in (1, 2, 4):
+        b = synth.generate(synth.WORKLOADS[cfg], rays=np.arange(25))
+        g = np.random.default_rng(20 + cfg).normal(size=(7, b.n_rays))
+        a = O.backward_partitioned(b.sigma, b.rgb, b.t_start, b.t_end, b.seg_offsets,
+                                   b.ray_offsets, b.seg_ids, g)
+        f = O.backward_partitioned(b.sigma, b.rgb, b.t_start, b.t_end, b.seg_offsets,
+                                   b.ray_offsets, b.seg_ids, g, autodiff=False)
+        np.testing.assert_array_equal(a[1], f[1])
+        np.testing.assert_array_equal(a[2], f[2])
+        np.testing.assert_allclose(f[0], a[0], rtol=1e-10, atol=1e-13)
+        np.testing.assert_allclose(f[3], a[3], rtol=1e-9, atol=1e-12 * np.abs(a[3]).max())
+        np.testing.assert_allclose(f[4], a[4], rtol=1e-12, atol=1e-15)
