@@ -85,10 +85,10 @@ def segment(sigma, ch, t0, t1, pairs) -> np.ndarray:
         out[1 + c] = (w * ch[:, c]).sum()
     for p, (a, b) in enumerate(pairs):
         s = 0.0
+        inner = 0.0  # sum_{j<i} w_j b_j
         for i in range(n):
-            for j in range(i):
-                s += w[i] * ch[i, a] * w[j] * ch[j, b]
-            s += 0.5 * w[i] * w[i] * ch[i, a] * ch[i, b]
+            s += w[i] * ch[i, a] * inner + 0.5 * w[i] * w[i] * ch[i, a] * ch[i, b]
+            inner += w[i] * ch[i, b]
         out[1 + F + p] = s
     return out
 
