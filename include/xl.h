@@ -103,6 +103,30 @@ int xl_render_segments_fwd(const xl_samples* s, const int64_t* seg_offsets, int6
                            void* stream);
 
 /*
+ * Per-segment composite, forward, allocating nothing and taking no workspace.
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, kernels and results as xl_render_segments_fwd, except that the
+ * tile records go to a static device array of XL_STATIC_SCRATCH_BYTES per GPU,
+ * held by the library until the process ends.  Hence:
+ *   - at most 162,070,528 samples per call (xl_segments_workspace_bytes(n)
+ *     <= XL_STATIC_SCRATCH_BYTES); larger calls fail with XL_EINVAL before
+ *     anything is launched;
+ *   - every call on one GPU shares that array: calls that overlap on one GPU
+ *     (concurrent streams or threads) race and give wrong tuples; serialise
+ *     them;
+ *   - no xl_render_segments_bwd can follow (it needs the workspace of
+ *     xl_render_segments_fwd), so this is a forward-only (inference) call.
+ * The current device must be the device of `stream` and of the arrays.  The
+ * first call on a device looks up the array's address (hipGetSymbolAddress);
+ * XL_EHIP if that fails.  Nothing is zeroed: every record is written before it
+ * is read within the call.
+ */
+#define XL_STATIC_SCRATCH_BYTES (64u << 20)
+int xl_render_segments_fwd_static(const xl_samples* s, const int64_t* seg_offsets,
+                                  int64_t n_seg, float* seg_out, void* stream);
+
+/*
  * Per-segment composite, backward.  Given grad_seg = dl/d(seg tuple) (device
  * float32 [7][n_seg], component 0 is dl/dtau), writes dl/dsigma (device [n])
  * and dl/drgb (device [n][3]) in the storage dtype of `s`, overwriting them.

@@ -64,6 +64,7 @@ SIGNATURES = {
     "xl_last_error": (_c.c_char_p, []),
     "xl_segments_workspace_bytes": (_sz, [_i64]),
     "xl_render_segments_fwd": (_c.c_int, [_c.POINTER(XLSamples), _vp, _i64, _vp, _vp, _sz, _vp]),
+    "xl_render_segments_fwd_static": (_c.c_int, [_c.POINTER(XLSamples), _vp, _i64, _vp, _vp]),
     "xl_render_segments_bwd": (_c.c_int, [_c.POINTER(XLSamples), _vp, _i64, _vp, _sz, _vp, _vp,
                                           _vp, _vp]),
     "xl_merge_fwd": (_c.c_int, [_vp, _i64, _vp, _vp, _i64, _vp, _i32, _vp]),
@@ -158,6 +159,20 @@ def xl_render_segments_fwd(sigma, rgb, t_start, t_end, seg_offsets, seg_out=None
                                         n_seg, _dev(seg_out, "seg_out", torch.float32),
                                         _dev(workspace, "workspace"), workspace.numel(), _stream()))
     return seg_out, workspace
+
+
+def xl_render_segments_fwd_static(sigma, rgb, t_start, t_end, seg_offsets,
+                                  seg_out=None) -> torch.Tensor:
+    """seg_out[7, n_seg] by the no-allocation entry point (tile records in the
+    library's static scratch; forward only)."""
+    s = samples(sigma, rgb, t_start, t_end)
+    n_seg = seg_offsets.shape[0] - 1
+    if seg_out is None:
+        seg_out = torch.empty((TUPLE, n_seg), dtype=torch.float32, device=sigma.device)
+    _check(lib().xl_render_segments_fwd_static(ctypes.byref(s),
+                                               _dev(seg_offsets, "seg_offsets", torch.int64), n_seg,
+                                               _dev(seg_out, "seg_out", torch.float32), _stream()))
+    return seg_out
 
 
 def xl_render_segments_bwd(sigma, rgb, t_start, t_end, seg_offsets, workspace, grad_seg,

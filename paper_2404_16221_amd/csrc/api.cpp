@@ -104,6 +104,29 @@ int xl_render_segments_fwd(const xl_samples* s, const int64_t* seg_offsets, int6
                     "xl_render_segments_fwd launch");
 }
 
+int xl_render_segments_fwd_static(const xl_samples* s, const int64_t* seg_offsets,
+                                  int64_t n_seg, float* seg_out, void* stream) {
+  xl::SamplesDev d;
+  int rc = check_samples(s, &d);
+  if (rc) return rc;
+  if ((rc = check_segments(d, seg_offsets, n_seg))) return rc;
+  if (n_seg > 0 && seg_out == nullptr) return fail(XL_EINVAL, "seg_out is NULL");
+  const size_t need = xl_segments_workspace_bytes(d.n);
+  if (need > static_cast<size_t>(XL_STATIC_SCRATCH_BYTES))
+    return fail(XL_EINVAL,
+                "%lld samples need %zu bytes of tile records, more than the static scratch "
+                "holds (%zu bytes); use xl_render_segments_fwd with a workspace",
+                static_cast<long long>(d.n), need, static_cast<size_t>(XL_STATIC_SCRATCH_BYTES));
+  void* ws = nullptr;
+  if (d.n > 0 && n_seg > 0) {
+    rc = hip_status(xl::static_scratch(&ws), "xl_render_segments_fwd_static scratch address");
+    if (rc) return rc;
+  }
+  return hip_status(xl::launch_segments_fwd(d, seg_offsets, n_seg, seg_out, ws,
+                                            static_cast<hipStream_t>(stream)),
+                    "xl_render_segments_fwd_static launch");
+}
+
 int xl_render_segments_bwd(const xl_samples* s, const int64_t* seg_offsets, int64_t n_seg,
                            const void* workspace, size_t workspace_bytes, const float* grad_seg,
                            void* grad_sigma, void* grad_rgb, void* stream) {

@@ -23,6 +23,9 @@ size_t segments_workspace_bytes(int64_t n);  // per-tile records
 
 hipError_t launch_segments_fwd(const SamplesDev& s, const int64_t* seg_offsets, int64_t n_seg,
                                float* seg_out, void* workspace, hipStream_t stream);
+// Device address of this GPU's static tile-record scratch
+// (XL_STATIC_SCRATCH_BYTES), looked up once per device.
+hipError_t static_scratch(void** ptr);
 hipError_t launch_segments_bwd(const SamplesDev& s, const int64_t* seg_offsets, int64_t n_seg,
                                const void* workspace, const float* grad_seg, void* grad_sigma,
                                void* grad_rgb, hipStream_t stream);

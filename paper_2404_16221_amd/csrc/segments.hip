@@ -19,6 +19,8 @@
 // The backward recomputes transmittance with the same forward scan, takes the
 // suffix with a reverse scan, and applies the exact per-sample Jacobian of the
 // merge operator, so nothing per sample is stored between the passes.
+#include <mutex>
+
 #include "internal.h"
 #include "xl_device.hpp"
 
@@ -809,6 +811,33 @@ hipError_t launch_segments_bwd(const SamplesDev& s, const int64_t* off, int64_t 
     default: launch_bwd_dt<kF16>(s, off, n_seg, nt, recs, grad_seg, grad_sigma, grad_rgb, stream); break;
   }
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- no-allocation forward
+// xl_render_segments_fwd_static keeps the tile records in this file-scope
+// device array instead of a caller workspace.  Every GPU the library runs on
+// holds its own copy until the process ends.  In host code `scratch` names a
+// host-side stand-in, not device memory: host code uses only the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[XL_STATIC_SCRATCH_BYTES];
+
+hipError_t static_scratch(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (addr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 }  // namespace xl
