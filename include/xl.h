@@ -348,13 +348,15 @@ int xl_render_features_bwd(const xl_features* f, const int64_t* seg_offsets, int
  * evaluation), rendered with xl_render_segments_fwd + xl_merge_fwd and kept
  * until released.  Up to max_slots requests run at once, each on its own HIP
  * stream.  The server allocates hbm_budget_bytes of device memory once, at
- * creation, and carves every request's buffers out of it: a request is
- * admitted when a slot is free and an upper bound of its footprint (every ray
- * at n_max samples, capped at the budget) fits next to the requests in
- * flight; generation planning then fixes the exact footprint and the rest is
- * returned at once.  A request larger than the budget fails with XL_ENOMEM.
- * A request's result does not depend on the others.  All functions are
- * thread-safe.
+ * creation, and carves every request's buffers out of it.  Requests are
+ * admitted in arrival order, one at a time, when a slot is free: generation
+ * planning fixes the exact footprint, and the request waits until that much
+ * memory is free next to the requests in flight and the results not yet
+ * released.  A request whose footprint exceeds the whole budget fails at once
+ * with XL_ENOMEM.  Results hold their memory until xl_serve_release: a client
+ * that keeps results while it waits for later requests must leave room for
+ * them.  A request's result does not depend on the others.  All functions
+ * are thread-safe.
  */
 typedef struct xl_server xl_server;
 
@@ -387,6 +389,8 @@ typedef struct xl_result {
   int64_t latency_us;        /* completion - arrival (host monotonic clock) */
   int64_t queue_us;          /* admission to a slot - arrival */
   int64_t device_us;         /* generation + composite + merge on the device */
+  int64_t device_start_us;   /* its device interval, from one origin per server */
+  int64_t device_end_us;     /* (-1 if unavailable): intervals of requests compare */
 } xl_result;
 
 typedef struct xl_serve_stats {
@@ -410,7 +414,9 @@ int xl_serve_copy_result(xl_server* s, uint64_t ticket, float* dst, void* stream
  * by xl_serve_copy_result have completed (ray_out becomes invalid). */
 int xl_serve_release(xl_server* s, uint64_t ticket);
 int xl_serve_stats_get(xl_server* s, xl_serve_stats* out);
-/* Finishes queued requests, then frees everything. */
+/* Stops the server: requests not yet admitted fail with XL_EAGAIN, requests
+ * already rendering complete; then every result and buffer is freed.  No other
+ * call on the server may overlap this one or follow it. */
 int xl_serve_destroy(xl_server* s);
 
 #ifdef __cplusplus

@@ -15,14 +15,19 @@
 //     or free happens per request, so the workers never serialise on the
 //     allocator.
 //   * max_slots worker threads, each owning one HIP stream (default priority),
-//     take requests in arrival order.  A worker reserves an upper bound of the
-//     request's footprint (every ray at n_max samples), waiting until it fits
-//     next to the requests in flight; runs the generator's plan phase, which
-//     fixes the exact footprint (samples, segment arrays, tuples, workspaces,
-//     result); gives the excess back; and launches generation, segment
-//     composite and merge.  Requests therefore join while others are on the
-//     GPU as soon as a slot and memory free up, and the kernels of different
-//     requests overlap on the device.
+//     take requests in arrival order.  Admission is one request at a time: the
+//     admitting worker reserves the request's head (result, generator
+//     workspace, ray offsets), runs the generator's plan phase on its own
+//     stream, which fixes the exact footprint (samples, segment arrays,
+//     tuples, tile records), and reserves that body, waiting for memory that
+//     running requests or released results give back.  A request whose
+//     footprint exceeds the whole budget fails at once with XL_ENOMEM.  The
+//     worker then launches generation, segment composite and merge.  Requests
+//     therefore join while others are on the GPU as soon as a slot and memory
+//     free up, and the kernels of different requests overlap on the device.
+//     Only the admitting worker waits for memory, and it holds nothing but its
+//     head while it does, so workers never wait on each other's partial
+//     reservations.
 //   * Each request has its own buffers and runs the same kernels, so its result
 //     does not depend on what else is in flight (bit for bit).
 //   * xl_serve_poll waits for a ticket (bounded by a timeout) and reports the
@@ -67,12 +72,15 @@ struct Job {
   int64_t n_rays = 0, n_samples = 0, n_seg = 0;
   uint64_t footprint = 0, result_bytes = 0;
   float device_ms = 0.f;
+  float device_start_ms = -1.f, device_end_ms = -1.f;  // since the server's origin event
   char msg[160] = "";
 };
 
 struct Server {
   xl_serve_config cfg{};
   std::mutex mu;
+  std::mutex admit_mu;          // one request in admission at a time
+  hipEvent_t origin = nullptr;  // device-time origin of the per-request intervals
   std::condition_variable cv_queue, cv_done, cv_budget;
   std::deque<std::shared_ptr<Job>> queue;
   std::unordered_map<uint64_t, std::shared_ptr<Job>> jobs;
@@ -143,7 +151,6 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int
     return round256(n * es) + round256(3 * n * es) + 2 * round256(4 * n) + round256(8 * (n_seg + 1)) +
            round256(8 * n_seg) + round256(4 * 7 * n_seg) + round256(xl_segments_workspace_bytes(n));
   };
-  const size_t bound = head + body(p.n_rays * static_cast<int64_t>(p.n_max), gen_max_segments(&p));
   char m[200];
   if (head > s->arena.size()) {
     std::snprintf(m, sizeof(m), "request needs more than %llu bytes, budget is %llu",
@@ -152,46 +159,58 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int
     finish(s, j, XL_ENOMEM, m);
     return;
   }
-  const size_t reserve = std::min(bound, s->arena.size());
-  size_t off = 0;
-  {
+  // Waits (under the server mutex) until `bytes` can be carved out or the
+  // server stops; false if it stopped.
+  auto reserve = [&](size_t bytes, size_t* at) {
     std::unique_lock<std::mutex> lk(s->mu);
     bool got = false;
-    s->cv_budget.wait(lk, [&] { return s->stop || (got = s->arena.alloc(reserve, &off)); });
-    if (!got) {
-      lk.unlock();
-      finish(s, j, XL_EAGAIN, "server stopped before the request was admitted");
-      return;
-    }
+    s->cv_budget.wait(lk, [&] { return s->stop || (got = s->arena.alloc(bytes, at)); });
+    return got;
+  };
+  std::unique_lock<std::mutex> admission(s->admit_mu);
+  size_t off = 0, off_b = 0;
+  if (!reserve(head, &off)) {
+    admission.unlock();
+    finish(s, j, XL_EAGAIN, "server stopped before the request was admitted");
+    return;
   }
   char* blk = s->base + off;
   float* out = reinterpret_cast<float*>(blk);
   void* ws = blk + b_out;
   int64_t* ro = reinterpret_cast<int64_t*>(blk + b_out + ws_b);
-  char* c = blk + head;
 
   int64_t n = 0, n_seg = 0;
   int overflow = 0;
   if (gen_plan(&p, ws, st, &n, &n_seg, &overflow, pinned) != hipSuccess || overflow) {
     (void)hipStreamSynchronize(st);  // cleanup on a path that already reports failure
-    release_block(s, off, reserve);
+    admission.unlock();
+    release_block(s, off, head);
     finish(s, j, XL_EHIP, "generator plan failed");
     return;
   }
   j->n_samples = n;
   j->n_seg = n_seg;
-  const size_t fp = head + body(n, n_seg);
+  const size_t bb = body(n, n_seg);
+  const size_t fp = head + bb;
   j->footprint = fp;
   j->result_bytes = b_out;
-  if (fp > reserve) {
-    release_block(s, off, reserve);
+  if (fp > s->arena.size()) {
+    admission.unlock();
+    release_block(s, off, head);
     std::snprintf(m, sizeof(m), "request needs %llu bytes, budget is %llu",
                   static_cast<unsigned long long>(fp),
                   static_cast<unsigned long long>(s->arena.size()));
     finish(s, j, XL_ENOMEM, m);
     return;
   }
-  if (fp < reserve) release_block(s, off + fp, reserve - fp);
+  if (!reserve(bb, &off_b)) {
+    admission.unlock();
+    release_block(s, off, head);
+    finish(s, j, XL_EAGAIN, "server stopped before the request was admitted");
+    return;
+  }
+  admission.unlock();
+  char* c = s->base + off_b;
 
   void* sigma = c; c += round256(n * es);
   void* rgb = c; c += round256(3 * n * es);
@@ -213,15 +232,29 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int
   float ms = 0.f;
   if (e == hipSuccess && es2 == hipSuccess && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 0.f;
   j->device_ms = ms;
+  if (e == hipSuccess && es2 == hipSuccess && s->origin) {
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, s->origin, e0) == hipSuccess &&
+        hipEventElapsedTime(&b, s->origin, e1) == hipSuccess) {
+      j->device_start_ms = a;
+      j->device_end_ms = b;
+    }
+  }
+  release_block(s, off_b, bb);
   if (e != hipSuccess || es2 != hipSuccess) {
-    release_block(s, off, fp);
+    release_block(s, off, head);
     finish(s, j, XL_EHIP, hipGetErrorString(e != hipSuccess ? e : es2));
     return;
   }
-  release_block(s, off + b_out, fp - b_out);  // the result stays until released
+  release_block(s, off + b_out, head - b_out);  // the result stays until released
   j->ray_out = out;
   j->arena_off = off;
   finish(s, j, XL_OK, nullptr);
+}
+
+static bool stopping(Server* s) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  return s->stop;
 }
 
 static void worker(Server* s) {
@@ -244,7 +277,9 @@ static void worker(Server* s) {
       s->queue.pop_front();
       j->t_admit = now_us();
     }
-    if (ready)
+    if (stopping(s))
+      finish(s, j, XL_EAGAIN, "server destroyed before the request started");
+    else if (ready)
       run_job(s, st, e0, e1, pinned, j);
     else
       finish(s, j, XL_EHIP, "serving slot has no stream or events");
@@ -278,6 +313,13 @@ int xl_serve_create(const xl_serve_config* cfg, xl_server** out) {
                          static_cast<unsigned long long>(cfg->hbm_budget_bytes), hipGetErrorString(e));
   }
   s->arena.reset(cfg->hbm_budget_bytes);
+  // Device-time origin of the per-request intervals (best effort: without it
+  // the intervals are reported as -1).
+  if (hipEventCreate(&s->origin) != hipSuccess || hipEventRecord(s->origin, nullptr) != hipSuccess ||
+      hipEventSynchronize(s->origin) != hipSuccess) {
+    if (s->origin) (void)hipEventDestroy(s->origin);
+    s->origin = nullptr;
+  }
   for (int i = 0; i < cfg->max_slots; ++i) s->workers.emplace_back(xl::worker, s);
   *out = reinterpret_cast<xl_server*>(s);
   return xl::clear_error();
@@ -333,6 +375,9 @@ int xl_serve_poll(xl_server* srv, uint64_t ticket, xl_result* out, int64_t timeo
   out->latency_us = j->t_done - j->t_arrival;
   out->queue_us = j->t_admit - j->t_arrival;
   out->device_us = static_cast<int64_t>(j->device_ms * 1000.0f);
+  out->device_start_us =
+      j->device_start_ms < 0 ? -1 : static_cast<int64_t>(j->device_start_ms * 1000.0);
+  out->device_end_us = j->device_end_ms < 0 ? -1 : static_cast<int64_t>(j->device_end_ms * 1000.0);
   if (j->status != XL_OK) return xl::set_error(j->status, "request %llu failed: %s",
                                                (unsigned long long)ticket, j->msg);
   return xl::clear_error();
@@ -425,6 +470,7 @@ int xl_serve_destroy(xl_server* srv) {
       (void)hipEventDestroy(kv.second->copied);
     }
   }
+  if (s->origin) (void)hipEventDestroy(s->origin);
   const hipError_t ef = hipFree(s->base);
   if (e == hipSuccess) e = ef;
   delete s;

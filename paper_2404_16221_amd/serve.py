@@ -27,7 +27,8 @@ class XLRequest(_c.Structure):
 class XLResult(_c.Structure):
     _fields_ = [("status", _i32), ("reserved", _i32), ("ray_out", _vp), ("n_rays", _i64),
                 ("n_samples", _i64), ("n_segments", _i64), ("footprint_bytes", _u64),
-                ("latency_us", _i64), ("queue_us", _i64), ("device_us", _i64)]
+                ("latency_us", _i64), ("queue_us", _i64), ("device_us", _i64),
+                ("device_start_us", _i64), ("device_end_us", _i64)]
 
 
 class XLServeStats(_c.Structure):

@@ -100,12 +100,39 @@ def test_budget_admission_and_injected_fault():
 
 
 def test_continuous_batching_overlaps_requests():
-    """Requests submitted while others run are admitted into free slots at once."""
+    """Requests submitted while others run are admitted into free slots at once,
+    and their device work overlaps (device intervals from one origin)."""
     with Server(max_slots=4, dtype=torch.float16) as srv:
         ts = [srv.submit(request(512, 512, seed=300 + k, **SCENE)) for k in range(4)]
         res = wait_all(srv, ts)
         assert all(v["rc"] == 0 for v in res.values())
         # all four were admitted without waiting for each other to finish
         assert max(v["queue_us"] for v in res.values()) < min(v["latency_us"] for v in res.values())
+        iv = sorted((v["device_start_us"], v["device_end_us"]) for v in res.values())
+        assert all(0 <= a < b for a, b in iv), iv
+        overlap = sum(max(0, min(b1, b2) - max(a1, a2))
+                      for i, (a1, b1) in enumerate(iv) for (a2, b2) in iv[i + 1:])
+        print("device intervals (us):", iv, "pairwise overlap", overlap, flush=True)
+        assert overlap > 0
         for t in ts:
             srv.release(t)
+
+
+def test_held_result_and_over_budget_request():
+    """A result the client still holds and a request larger than the whole
+    budget: the latter fails with XL_ENOMEM at once instead of waiting for
+    memory that could never suffice."""
+    with Server(hbm_budget_bytes=64 << 20, max_slots=2, dtype=torch.float16) as srv:
+        held = srv.submit(request(64, 64, seed=9, **SCENE))
+        assert srv.poll(held, timeout_us=60_000_000)["rc"] == 0
+        big = srv.submit(request(1280, 720, seed=10, **SCENE))
+        t0 = time.perf_counter()
+        r = srv.poll(big, timeout_us=60_000_000)
+        assert r["rc"] == -2 and "budget" in r["error"], r
+        assert time.perf_counter() - t0 < 30
+        # a request that fits next to the held result still runs
+        small = srv.submit(request(64, 64, seed=11, **SCENE))
+        assert srv.poll(small, timeout_us=60_000_000)["rc"] == 0
+        srv.release(small)
+        srv.release(held)
+        assert srv.stats()["budget_used_bytes"] == 0
