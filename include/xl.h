@@ -342,6 +342,75 @@ int xl_render_features_bwd(const xl_features* f, const int64_t* seg_offsets, int
                            int32_t accumulate_sigma, void* stream);
 
 /*
+ * Breakable integrals composited across regions (App. B.2): the family that
+ * Property 2 (integration against a breakable factor) and Property 1
+ * (products) generate from the transmittance, up to one level of nesting.
+ * With F per-sample channels f_c and P pairs (a_p, b_p) of them, and
+ * w = T sigma the volume-rendering weight:
+ *   first order   Phi_c = int w f_c  (colour, opacity, depth, features ...)
+ *   second order  Psi_p = int w(u) f_a(u) [int_{v<u} w(v) f_b(v) dv] du
+ *                 (the distortion loss of App. B.2's Examples is
+ *                 2 (Psi_(m,1) - Psi_(1,m)) plus its within-sample term).
+ * Quadrature as xl_render_segments_fwd's (piecewise-constant density and
+ * channels per sample interval): Phi_c = sum_i w_i f_ci, Psi_p = sum_i w_i a_i
+ * sum_{j<i} w_j b_j + 1/2 sum_i w_i^2 a_i b_i.
+ * Tuples are float32 structure of arrays with 1 + F + P rows: per segment
+ * (tau, Phi, Psi) with T from 1 inside the segment, per ray (T, Phi, Psi).
+ * A ray's segments fold front to back by
+ *   (x (+) y) = (tau_x + tau_y, Phi_x + T_x Phi_y,
+ *                Psi_x + T_x^2 Psi_y + T_x Phi_(a)y Phi_(b)x).
+ * Channel sources: XL_CH_LOADED reads ch [n][F] in the storage dtype;
+ * XL_CH_MIDPOINT_POWERS forms channel c of sample i as m_i^c (m the interval
+ * midpoint; channels 1, m, m^2 give the depth moments), with no channel
+ * gradient.  Samples, offsets and streams as for the colour path; errors:
+ * XL_EINVAL for NULL arrays, bad dtype or source, F outside 1..8, P outside
+ * 0..4 or a pair index outside [0, F); XL_EHIP if a launch fails.
+ */
+#define XL_CH_LOADED 0
+#define XL_CH_MIDPOINT_POWERS 1
+#define XL_BREAKABLE_MAX_CH 8
+#define XL_BREAKABLE_MAX_PAIRS 4
+
+typedef struct xl_breakable {
+  int32_t dtype;        /* storage of sigma, loaded channels and their gradients */
+  int32_t source;       /* XL_CH_LOADED or XL_CH_MIDPOINT_POWERS */
+  int32_t n_ch;         /* F, 1..XL_BREAKABLE_MAX_CH */
+  int32_t n_pairs;      /* P, 0..XL_BREAKABLE_MAX_PAIRS */
+  int32_t pair_a[XL_BREAKABLE_MAX_PAIRS]; /* channel a_p of second-order member p */
+  int32_t pair_b[XL_BREAKABLE_MAX_PAIRS]; /* channel b_p (the inner integral's) */
+  const void* sigma;    /* device [n] */
+  const void* ch;       /* device [n][F] (XL_CH_LOADED), else unused */
+  const float* t_start; /* device [n] */
+  const float* t_end;   /* device [n] */
+  int64_t n;
+} xl_breakable;
+
+/* Per segment: seg_out float32 [1+F+P][n_seg] = (tau, Phi, Psi), written. */
+int xl_render_breakable_fwd(const xl_breakable* b, const int64_t* seg_offsets, int64_t n_seg,
+                            float* seg_out, void* stream);
+/* Per ray: ray_out float32 [1+F+P][n_rays] = (T, Phi, Psi), folding the
+ * segments listed by ray_offsets / seg_ids front to back (a ray without
+ * segments gets (1, 0, ..., 0); ids outside [0, n_seg) are skipped).  Only the
+ * channel count, pairs and dtype of `b` are used. */
+int xl_merge_breakable_fwd(const xl_breakable* b, const float* seg_out, int64_t n_seg,
+                           const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                           float* ray_out, void* stream);
+/* Backward of the merge: grad_ray = dl/d(T, Phi, Psi) [1+F+P][n_rays] ->
+ * grad_seg = dl/d(tau, Phi, Psi) [1+F+P][n_seg] of every listed segment
+ * (overwritten there; each segment listed by at most one ray). */
+int xl_merge_breakable_bwd(const xl_breakable* b, const float* seg_out, int64_t n_seg,
+                           const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                           const float* grad_ray, float* grad_seg, void* stream);
+/* Backward of the segments: from seg_out (the forward's) and grad_seg, writes
+ * dl/dsigma [n] (added to grad_sigma's contents when accumulate_sigma != 0)
+ * and, for XL_CH_LOADED, dl/dch [n][F] (grad_ch may be NULL otherwise).
+ * Per-sample suffix sums are a forward total minus an inclusive prefix: their
+ * rounding error is absolute, about one float32 ulp of that total. */
+int xl_render_breakable_bwd(const xl_breakable* b, const int64_t* seg_offsets, int64_t n_seg,
+                            const float* seg_out, const float* grad_seg, void* grad_sigma,
+                            void* grad_ch, int32_t accumulate_sigma, void* stream);
+
+/*
  * Render server: continuous batching of novel-view requests (the inference
  * path of App. A.2: per-region composite, then the merge on one device).
  * Requests are generated on the device (stand-in for per-region NeRF

@@ -50,6 +50,16 @@ class XLFeatures(_c.Structure):
                 ("t_end", _vp), ("n", _i64)]
 
 
+class XLBreakable(_c.Structure):
+    _fields_ = [("dtype", _i32), ("source", _i32), ("n_ch", _i32), ("n_pairs", _i32),
+                ("pair_a", _i32 * 4), ("pair_b", _i32 * 4), ("sigma", _vp), ("ch", _vp),
+                ("t_start", _vp), ("t_end", _vp), ("n", _i64)]
+
+
+XL_CH_LOADED = 0
+XL_CH_MIDPOINT_POWERS = 1
+
+
 class XLError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libxl error {code}: {msg}")
@@ -81,6 +91,13 @@ SIGNATURES = {
     "xl_merge_features_bwd": (_c.c_int, [_vp, _vp, _i32, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
     "xl_render_features_bwd": (_c.c_int, [_c.POINTER(XLFeatures), _vp, _i64, _vp, _vp, _vp, _vp, _vp,
                                           _i32, _vp]),
+    "xl_render_breakable_fwd": (_c.c_int, [_c.POINTER(XLBreakable), _vp, _i64, _vp, _vp]),
+    "xl_merge_breakable_fwd": (_c.c_int, [_c.POINTER(XLBreakable), _vp, _i64, _vp, _vp, _i64, _vp,
+                                          _vp]),
+    "xl_merge_breakable_bwd": (_c.c_int, [_c.POINTER(XLBreakable), _vp, _i64, _vp, _vp, _i64, _vp,
+                                          _vp, _vp]),
+    "xl_render_breakable_bwd": (_c.c_int, [_c.POINTER(XLBreakable), _vp, _i64, _vp, _vp, _vp, _vp,
+                                           _i32, _vp]),
     "xl_pack_workspace_bytes": (_sz, [_i64, _i32]),
     "xl_pack_plan": (_c.c_int, [_c.POINTER(XLRays), _vp, _vp, _i32, _vp, _sz, _c.POINTER(_i64),
                                 _c.POINTER(_i64), _vp]),
@@ -415,3 +432,83 @@ def xl_render_features_bwd(sigma, feat, t_start, t_end, seg_offsets, phi_seg, gr
         _dev(grad_sigma, "grad_sigma", sigma.dtype), _dev(grad_feat, "grad_feat", sigma.dtype),
         1 if accumulate_sigma else 0, _stream()))
     return grad_sigma, grad_feat
+
+
+def breakable(sigma, t_start, t_end, pairs, ch=None, n_ch=None, dtype=None) -> XLBreakable:
+    """Descriptor of a breakable-integral member set: loaded channels ch [n, F]
+    (sigma's storage dtype), or with ch None the midpoint powers m^0..m^(n_ch-1)."""
+    dt = sigma.dtype if dtype is None else dtype
+    if dt not in DTYPES:
+        raise ValueError("storage dtype must be float32, bfloat16 or float16")
+    n = sigma.shape[0]
+    if t_start.shape != (n,) or t_end.shape != (n,):
+        raise ValueError("shapes must be sigma[n], t_start[n], t_end[n]")
+    if ch is not None:
+        if ch.dim() != 2 or ch.shape[0] != n or ch.dtype != sigma.dtype:
+            raise ValueError("ch must be [n, F] in sigma's dtype")
+        F, src, chp = ch.shape[1], XL_CH_LOADED, _dev(ch, "ch")
+    else:
+        F, src, chp = int(n_ch), XL_CH_MIDPOINT_POWERS, None
+    if len(pairs) > 4:
+        raise ValueError("at most 4 pairs")
+    pa = [a for a, _ in pairs] + [0] * (4 - len(pairs))
+    pb = [b for _, b in pairs] + [0] * (4 - len(pairs))
+    return XLBreakable(DTYPES[dt], src, F, len(pairs), (_i32 * 4)(*pa), (_i32 * 4)(*pb),
+                       _dev(sigma, "sigma"), chp, _dev(t_start, "t_start", torch.float32),
+                       _dev(t_end, "t_end", torch.float32), n)
+
+
+def _rows(d: XLBreakable) -> int:
+    return 1 + d.n_ch + d.n_pairs
+
+
+def xl_render_breakable_fwd(d: XLBreakable, seg_offsets, seg_out=None) -> torch.Tensor:
+    """seg_out [1+F+P, n_seg] = (tau, Phi, Psi) of every segment."""
+    n_seg = seg_offsets.shape[0] - 1
+    if seg_out is None:
+        seg_out = torch.empty((_rows(d), n_seg), dtype=torch.float32, device=seg_offsets.device)
+    _check(lib().xl_render_breakable_fwd(ctypes.byref(d), _dev(seg_offsets, "seg_offsets", torch.int64),
+                                         n_seg, _dev(seg_out, "seg_out", torch.float32), _stream()))
+    return seg_out
+
+
+def xl_merge_breakable_fwd(d: XLBreakable, seg_out, ray_offsets, seg_ids, ray_out=None) -> torch.Tensor:
+    """ray_out [1+F+P, n_rays] = (T, Phi, Psi) of every ray."""
+    n_seg = seg_out.shape[1]
+    n_rays = ray_offsets.shape[0] - 1
+    if ray_out is None:
+        ray_out = torch.empty((_rows(d), n_rays), dtype=torch.float32, device=seg_out.device)
+    _check(lib().xl_merge_breakable_fwd(ctypes.byref(d), _dev(seg_out, "seg_out", torch.float32), n_seg,
+                                        _dev(ray_offsets, "ray_offsets", torch.int64),
+                                        _dev(seg_ids, "seg_ids", torch.int64), n_rays,
+                                        _dev(ray_out, "ray_out", torch.float32), _stream()))
+    return ray_out
+
+
+def xl_merge_breakable_bwd(d: XLBreakable, seg_out, ray_offsets, seg_ids, grad_ray,
+                           grad_seg=None) -> torch.Tensor:
+    """grad_seg [1+F+P, n_seg] = dl/d(tau, Phi, Psi) of every listed segment."""
+    n_seg = seg_out.shape[1]
+    n_rays = ray_offsets.shape[0] - 1
+    if grad_seg is None:
+        grad_seg = torch.zeros((_rows(d), n_seg), dtype=torch.float32, device=seg_out.device)
+    _check(lib().xl_merge_breakable_bwd(ctypes.byref(d), _dev(seg_out, "seg_out", torch.float32), n_seg,
+                                        _dev(ray_offsets, "ray_offsets", torch.int64),
+                                        _dev(seg_ids, "seg_ids", torch.int64), n_rays,
+                                        _dev(grad_ray, "grad_ray", torch.float32),
+                                        _dev(grad_seg, "grad_seg", torch.float32), _stream()))
+    return grad_seg
+
+
+def xl_render_breakable_bwd(d: XLBreakable, seg_offsets, seg_out, grad_seg, grad_sigma,
+                            grad_ch=None, accumulate_sigma: bool = False):
+    """Writes dl/dsigma into grad_sigma [n] and, for loaded channels, dl/dch into
+    grad_ch [n, F] (storage dtype); returns (grad_sigma, grad_ch)."""
+    n_seg = seg_offsets.shape[0] - 1
+    _check(lib().xl_render_breakable_bwd(ctypes.byref(d), _dev(seg_offsets, "seg_offsets", torch.int64),
+                                         n_seg, _dev(seg_out, "seg_out", torch.float32),
+                                         _dev(grad_seg, "grad_seg", torch.float32),
+                                         _dev(grad_sigma, "grad_sigma"),
+                                         _dev(grad_ch, "grad_ch") if grad_ch is not None else None,
+                                         int(accumulate_sigma), _stream()))
+    return grad_sigma, grad_ch

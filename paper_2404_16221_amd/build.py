@@ -12,7 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxl.so")
-SOURCES = ["segments.hip", "merge.hip", "gen.hip", "pack.hip", "features.hip", "partition.cpp",
+SOURCES = ["segments.hip", "merge.hip", "gen.hip", "pack.hip", "features.hip", "breakable.hip",
+           "partition.cpp",
            "serve.cpp", "api.cpp"]
 ARCH = "gfx950"
 

@@ -403,4 +403,92 @@ int xl_merge_features_bwd(const float* tau_seg, const float* phi_seg, int32_t n_
                     "xl_merge_features_bwd launch");
 }
 
+// ---------------------------------------------------------------- breakable integrals
+static int check_breakable_shape(const xl_breakable* b) {
+  if (b == nullptr) return fail(XL_EINVAL, "breakable descriptor is NULL");
+  if (b->dtype != XL_F32 && b->dtype != XL_BF16 && b->dtype != XL_F16)
+    return fail(XL_EINVAL, "unknown sample dtype %d", b->dtype);
+  if (b->source != XL_CH_LOADED && b->source != XL_CH_MIDPOINT_POWERS)
+    return fail(XL_EINVAL, "unknown channel source %d", b->source);
+  if (b->n_ch < 1 || b->n_ch > XL_BREAKABLE_MAX_CH)
+    return fail(XL_EINVAL, "n_ch must be 1..%d, got %d", XL_BREAKABLE_MAX_CH, b->n_ch);
+  if (b->n_pairs < 0 || b->n_pairs > XL_BREAKABLE_MAX_PAIRS)
+    return fail(XL_EINVAL, "n_pairs must be 0..%d, got %d", XL_BREAKABLE_MAX_PAIRS, b->n_pairs);
+  for (int p = 0; p < b->n_pairs; ++p)
+    if (b->pair_a[p] < 0 || b->pair_a[p] >= b->n_ch || b->pair_b[p] < 0 || b->pair_b[p] >= b->n_ch)
+      return fail(XL_EINVAL, "pair %d (%d, %d) names a channel outside [0, %d)", p, b->pair_a[p],
+                  b->pair_b[p], b->n_ch);
+  return XL_OK;
+}
+
+static int check_breakable(const xl_breakable* b, const int64_t* seg_offsets, int64_t n_seg) {
+  int rc = check_breakable_shape(b);
+  if (rc) return rc;
+  if (b->n < 0 || n_seg < 0) return fail(XL_EINVAL, "negative count");
+  if (b->n > 0 && (!b->sigma || !b->t_start || !b->t_end))
+    return fail(XL_EINVAL, "NULL sample array with n = %lld", (long long)b->n);
+  if (b->n > 0 && b->source == XL_CH_LOADED && !b->ch) return fail(XL_EINVAL, "ch is NULL");
+  if (seg_offsets == nullptr) return fail(XL_EINVAL, "seg_offsets is NULL");
+  if (n_seg == 0 && b->n > 0) return fail(XL_EINVAL, "%lld samples but no segments", (long long)b->n);
+  return XL_OK;
+}
+
+int xl_render_breakable_fwd(const xl_breakable* b, const int64_t* seg_offsets, int64_t n_seg,
+                            float* seg_out, void* stream) {
+  int rc = check_breakable(b, seg_offsets, n_seg);
+  if (rc) return rc;
+  if (n_seg > 0 && seg_out == nullptr) return fail(XL_EINVAL, "seg_out is NULL");
+  return hip_status(xl::launch_breakable_fwd(b, seg_offsets, n_seg, seg_out,
+                                             static_cast<hipStream_t>(stream)),
+                    "xl_render_breakable_fwd launch");
+}
+
+int xl_render_breakable_bwd(const xl_breakable* b, const int64_t* seg_offsets, int64_t n_seg,
+                            const float* seg_out, const float* grad_seg, void* grad_sigma,
+                            void* grad_ch, int32_t accumulate_sigma, void* stream) {
+  int rc = check_breakable(b, seg_offsets, n_seg);
+  if (rc) return rc;
+  if (n_seg > 0 && (!seg_out || !grad_seg)) return fail(XL_EINVAL, "seg_out or grad_seg is NULL");
+  if (b->n > 0 && !grad_sigma) return fail(XL_EINVAL, "grad_sigma is NULL");
+  if (b->n > 0 && b->source == XL_CH_LOADED && !grad_ch) return fail(XL_EINVAL, "grad_ch is NULL");
+  return hip_status(xl::launch_breakable_bwd(b, seg_offsets, n_seg, seg_out, grad_seg, grad_sigma,
+                                             grad_ch, accumulate_sigma != 0,
+                                             static_cast<hipStream_t>(stream)),
+                    "xl_render_breakable_bwd launch");
+}
+
+static int check_breakable_merge(const xl_breakable* b, const float* seg_out, int64_t n_seg,
+                                 const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays) {
+  int rc = check_breakable_shape(b);
+  if (rc) return rc;
+  if (n_seg < 0 || n_rays < 0) return fail(XL_EINVAL, "negative count");
+  if (n_rays > 0 && ray_offsets == nullptr) return fail(XL_EINVAL, "ray_offsets is NULL");
+  if (n_seg > 0 && (!seg_out || !seg_ids)) return fail(XL_EINVAL, "seg_out or seg_ids is NULL");
+  return XL_OK;
+}
+
+int xl_merge_breakable_fwd(const xl_breakable* b, const float* seg_out, int64_t n_seg,
+                           const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                           float* ray_out, void* stream) {
+  int rc = check_breakable_merge(b, seg_out, n_seg, ray_offsets, seg_ids, n_rays);
+  if (rc) return rc;
+  if (n_rays > 0 && ray_out == nullptr) return fail(XL_EINVAL, "ray_out is NULL");
+  return hip_status(xl::launch_breakable_merge(b, seg_out, n_seg, ray_offsets, seg_ids, n_rays,
+                                               ray_out, static_cast<hipStream_t>(stream)),
+                    "xl_merge_breakable_fwd launch");
+}
+
+int xl_merge_breakable_bwd(const xl_breakable* b, const float* seg_out, int64_t n_seg,
+                           const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                           const float* grad_ray, float* grad_seg, void* stream) {
+  int rc = check_breakable_merge(b, seg_out, n_seg, ray_offsets, seg_ids, n_rays);
+  if (rc) return rc;
+  if (n_rays > 0 && (!grad_ray || (n_seg > 0 && !grad_seg)))
+    return fail(XL_EINVAL, "grad_ray or grad_seg is NULL");
+  return hip_status(xl::launch_breakable_merge_bwd(b, seg_out, n_seg, ray_offsets, seg_ids, n_rays,
+                                                   grad_ray, grad_seg,
+                                                   static_cast<hipStream_t>(stream)),
+                    "xl_merge_breakable_bwd launch");
+}
+
 }  // extern "C"

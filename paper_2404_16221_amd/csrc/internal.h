@@ -84,4 +84,18 @@ hipError_t launch_features_merge_bwd(const float* tau_seg, const float* phi_seg,
                                      const float* grad_ray, float* grad_phi_seg, float* grad_tau_seg,
                                      hipStream_t st);
 
+// Breakable integrals (breakable.hip).
+hipError_t launch_breakable_fwd(const xl_breakable* b, const int64_t* seg_offsets, int64_t n_seg,
+                                float* seg_out, hipStream_t st);
+hipError_t launch_breakable_bwd(const xl_breakable* b, const int64_t* seg_offsets, int64_t n_seg,
+                                const float* seg_out, const float* grad_seg, void* grad_sigma,
+                                void* grad_ch, int accumulate, hipStream_t st);
+hipError_t launch_breakable_merge(const xl_breakable* b, const float* seg_out, int64_t n_seg,
+                                  const int64_t* ray_offsets, const int64_t* seg_ids, int64_t n_rays,
+                                  float* ray_out, hipStream_t st);
+hipError_t launch_breakable_merge_bwd(const xl_breakable* b, const float* seg_out, int64_t n_seg,
+                                      const int64_t* ray_offsets, const int64_t* seg_ids,
+                                      int64_t n_rays, const float* grad_ray, float* grad_seg,
+                                      hipStream_t st);
+
 }  // namespace xl

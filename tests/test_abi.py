@@ -108,3 +108,29 @@ def test_pack_and_feature_argument_errors():
     assert "aligned" in L.xl_last_error().decode()
     assert L.xl_merge_features_fwd(16, 16, 3, 1, 16, 16, 1, 16, None) == xl.XL_EINVAL
     assert L.xl_merge_features_bwd(16, 16, 8, 1, 16, 16, 1, None, 16, 16, None) == xl.XL_EINVAL
+
+
+def test_breakable_argument_errors():
+    L = xl.lib()
+    B = xl.XLBreakable
+
+    def desc(dtype=0, source=0, F=3, pairs=((0, 1),), n=4):
+        pa = ([a for a, _ in pairs] + [0] * 4)[:4]
+        pb = ([b for _, b in pairs] + [0] * 4)[:4]
+        return B(dtype, source, F, len(pairs), (ctypes.c_int32 * 4)(*pa), (ctypes.c_int32 * 4)(*pb),
+                 16, 16, 16, 16, n)
+
+    def fwd(d):
+        return L.xl_render_breakable_fwd(ctypes.byref(d), 16, 1, 16, None)
+
+    assert L.xl_render_breakable_fwd(None, 16, 1, 16, None) == xl.XL_EINVAL
+    assert fwd(desc(dtype=9)) == xl.XL_EINVAL and "dtype" in L.xl_last_error().decode()
+    assert fwd(desc(source=5)) == xl.XL_EINVAL and "source" in L.xl_last_error().decode()
+    assert fwd(desc(F=0)) == xl.XL_EINVAL and "n_ch" in L.xl_last_error().decode()
+    assert fwd(desc(F=9)) == xl.XL_EINVAL
+    assert fwd(desc(pairs=((0, 3),))) == xl.XL_EINVAL and "outside" in L.xl_last_error().decode()
+    assert fwd(desc(pairs=((0, 0),) * 5)) == xl.XL_EINVAL
+    assert fwd(desc(n=-1)) == xl.XL_EINVAL
+    d = desc()
+    assert L.xl_merge_breakable_fwd(ctypes.byref(d), 16, 1, None, 16, 1, 16, None) == xl.XL_EINVAL
+    assert L.xl_render_breakable_bwd(ctypes.byref(d), 16, 1, 16, 16, 16, None, 0, None) == xl.XL_EINVAL
