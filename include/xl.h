@@ -146,9 +146,12 @@ int xl_render_segments_bwd(const xl_samples* s, const int64_t* seg_offsets, int6
  *   ray_offsets  device int64 [n_rays + 1]; ray r's segments are
  *                seg_ids[ray_offsets[r] .. ray_offsets[r+1]) front to back
  *                (the paper's ordered index list I)
- *   seg_ids      device int64, values in [0, n_seg)
+ *   seg_ids      device int64, values in [0, n_seg); ids outside are
+ *                skipped (identities); each segment is listed at most once
  *   ray_out      device float32 [7][n_rays], written
- *   flags        0 or XL_MERGE_FP64
+ *   flags        0 or XL_MERGE_FP64 (the running optical depth, i.e. the
+ *                cross-segment transmittance product, in float64; the other
+ *                fields fold in float32 either way)
  */
 int xl_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
                  const int64_t* seg_ids, int64_t n_rays, float* ray_out, int32_t flags,

@@ -22,7 +22,11 @@
 // Rays are taken 256 to a workgroup, and consecutive workgroups of rays run
 // on the same XCD: adjacent rays' segments are adjacent inside every region,
 // so a cache line of tuples serves several neighbouring workgroups, which
-// then find it in their XCD's L2.
+// then find it in their XCD's L2.  Every tuple field is a separate 4-byte
+// access (the tuples are region-major, a ray's segments in many regions), so
+// the rays in flight on an XCD decide how many partly used lines its L2 must
+// hold.  Each workgroup therefore reserves kMergeLds bytes of LDS it does not
+// use, which holds two workgroups (two waves per SIMD) on a CU.
 #include "internal.h"
 #include "xl_device.hpp"
 
@@ -30,6 +34,7 @@ namespace xl {
 
 constexpr int kMergeBlock = 256;
 constexpr int kXcds = 8;  // MI355X: 8 XCDs, workgroups dispatched to them round robin
+constexpr size_t kMergeLds = 64 * 1024;  // occupancy limit (see above)
 
 // Running optical depth of a fold: float32 with TwoSum compensation, or float64.
 template <typename R>
@@ -284,11 +289,11 @@ hipError_t launch_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* 
                             hipStream_t stream) {
   if (n_rays == 0) return hipSuccess;
   if (fp64)
-    hipLaunchKernelGGL(merge_fwd_kernel<double>, dim3(merge_grid(n_rays)), dim3(kMergeBlock), 0,
-                       stream, seg_out, n_seg, ro, ids, n_rays, out);
+    hipLaunchKernelGGL(merge_fwd_kernel<double>, dim3(merge_grid(n_rays)), dim3(kMergeBlock),
+                       kMergeLds, stream, seg_out, n_seg, ro, ids, n_rays, out);
   else
-    hipLaunchKernelGGL(merge_fwd_kernel<float>, dim3(merge_grid(n_rays)), dim3(kMergeBlock), 0,
-                       stream, seg_out, n_seg, ro, ids, n_rays, out);
+    hipLaunchKernelGGL(merge_fwd_kernel<float>, dim3(merge_grid(n_rays)), dim3(kMergeBlock),
+                       kMergeLds, stream, seg_out, n_seg, ro, ids, n_rays, out);
   return hipGetLastError();
 }
 
@@ -297,11 +302,11 @@ hipError_t launch_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* 
                             bool fp64, hipStream_t stream) {
   if (n_rays == 0) return hipSuccess;
   if (fp64)
-    hipLaunchKernelGGL(merge_bwd_kernel<double>, dim3(merge_grid(n_rays)), dim3(kMergeBlock), 0,
-                       stream, seg_out, n_seg, ro, ids, n_rays, gray, gseg);
+    hipLaunchKernelGGL(merge_bwd_kernel<double>, dim3(merge_grid(n_rays)), dim3(kMergeBlock),
+                       kMergeLds, stream, seg_out, n_seg, ro, ids, n_rays, gray, gseg);
   else
-    hipLaunchKernelGGL(merge_bwd_kernel<float>, dim3(merge_grid(n_rays)), dim3(kMergeBlock), 0,
-                       stream, seg_out, n_seg, ro, ids, n_rays, gray, gseg);
+    hipLaunchKernelGGL(merge_bwd_kernel<float>, dim3(merge_grid(n_rays)), dim3(kMergeBlock),
+                       kMergeLds, stream, seg_out, n_seg, ro, ids, n_rays, gray, gseg);
   return hipGetLastError();
 }
 
