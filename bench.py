@@ -127,6 +127,12 @@ class Form:
         if ev is not None:
             ev[1].record()
 
+    def forward(self):
+        xl = self.xl
+        xl.xl_render_segments_fwd(self.sigma, self.rgb, self.t0, self.t1, self.seg_offsets,
+                                  self.seg_out, self.ws)
+        xl.xl_merge_fwd(self.seg_out, self.ray_offsets, self.seg_ids, self.ray_out, fp64=self.fp64)
+
     def bytes_step(self):
         """Algorithmic HBM bytes of one step (fwd+bwd): per sample, segment and ray."""
         es = self.sigma.element_size()
@@ -161,30 +167,169 @@ def time_form(f: Form, steps: int, warmup: int):
     return ms, kms, wall
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The FP64 oracle, single thread, fwd+bwd on a bounded sample of rays."""
-    from oracle import render as O
+def ray_major(seg_offsets, ray_offsets, seg_ids, rays):
+    """(segment ids, sample indices) of the listed rays, ray by ray: a ray's
+    segments front to back, each segment's samples in t order."""
+    def ranges(starts, lens):
+        tot = int(lens.sum())
+        first = np.zeros(lens.shape[0], np.int64)
+        np.cumsum(lens[:-1], out=first[1:])
+        return np.repeat(starts - first, lens) + np.arange(tot, dtype=np.int64)
+    k0 = ray_offsets[rays]
+    segs = seg_ids[ranges(k0, ray_offsets[rays + 1] - k0)]
+    return segs, ranges(seg_offsets[segs], seg_offsets[segs + 1] - seg_offsets[segs])
+
+
+def gather_form(f: Form, rays, cfg, with_grads=True, grad_seed=None):
+    """Host copies of form f's results of its last step for `rays` of
+    workload `cfg`, ray-major."""
+    layout = [t.cpu().numpy() for t in (f.seg_offsets, f.ray_offsets, f.seg_ids)]
+    segs, samples = ray_major(*layout, rays)
+    dev = f.sigma.device
+    at_r = torch.from_numpy(rays).to(dev)
+    at_s = torch.from_numpy(segs).to(dev)
+    at = torch.from_numpy(samples).to(dev)
+    torch.cuda.synchronize()
+    return {"ray": f.ray_out[:, at_r].cpu().numpy(), "seg": f.seg_out[:, at_s].cpu().numpy(),
+            "grad_seg": f.grad_seg[:, at_s].cpu().numpy(), "dsigma": f.gs[at].float().cpu().numpy(),
+            "drgb": f.gc[at].float().cpu().numpy(), "rays": rays,
+            "grad_ray": f.grad_ray[:, at_r].cpu().numpy().astype(np.float64),
+            "storage": str(f.sigma.dtype).replace("torch.", ""), "regions": f.regions,
+            "cfg": cfg, "with_grads": with_grads, "grad_seed": grad_seed}
+
+
+def output_errors(got, ref, grads=True, segs=True):
+    """Error of every output against the FP64 oracle: the largest absolute
+    error, the largest relative error over the elements the relative bar
+    governs, and how many elements the absolute floor governs instead (the
+    floors of the parity tests: 1e-8 for colour and opacity, 3e-8 for depth
+    and distortion, 1e-7 for optical depths, 1e-6 of the largest reference
+    for gradients).  Transmittance is reported through tau = -log T (rays with
+    tau above 80 excluded: T is below float32's normal range there)."""
+    rtol = 1e-5
+    names = ["T", "r", "g", "b", "A", "D", "L"]
+    floors = [None, 1e-8, 1e-8, 1e-8, 1e-8, 3e-8, 3e-8]
+
+    def one(a, b, floor):
+        a = np.asarray(a, np.float64).ravel()
+        b = np.asarray(b, np.float64).ravel()
+        e = np.abs(a - b)
+        gov = rtol * np.abs(b) >= floor
+        return {"max_abs": float(e.max()) if e.size else 0.0,
+                "max_rel": float((e[gov] / np.abs(b[gov])).max()) if gov.any() else 0.0,
+                "floored": int((~gov).sum()), "n": int(e.size)}
+
+    out = {}
+    with np.errstate(divide="ignore"):
+        tr, tg = -np.log(ref["ray"][0]), -np.log(np.maximum(got["ray"][0], 1e-300))
+    ok = tr < 80
+    out["tau_of_T"] = one(tg[ok], tr[ok], 1e-7)
+    out["T_max_abs"] = float(np.abs(got["ray"][0] - ref["ray"][0]).max())
+    for k in range(1, 7):
+        out[names[k]] = one(got["ray"][k], ref["ray"][k], floors[k])
+    if segs:
+        out["segment_tuples"] = {n: one(got["seg"][k], ref["seg"][k], 1e-7 if k == 0 else floors[k])
+                                 for k, n in enumerate(["tau"] + names[1:])}
+    if grads:
+        def g1(a, b):
+            return one(a, b, 1e-6 * max(np.abs(np.asarray(b)).max(), 1e-300))
+        if segs:
+            out["grad_seg"] = {n: g1(got["grad_seg"][k], ref["grad_seg"][k])
+                               for k, n in enumerate(["tau"] + names[1:])}
+        for n in ("dsigma", "drgb"):
+            e = g1(got[n], ref[n])
+            g, r = np.asarray(got[n], np.float64).ravel(), np.asarray(ref[n], np.float64).ravel()
+            e["normwise_rel"] = float(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-300))
+            out[n] = e
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_leg(opool, gathered, workloads):
+    """The FP64 oracle on the host cores: its throughput (one thread, and all
+    pool workers), and the error of every timed GPU form against it on the
+    same rays.  gathered: form key -> gather_form output (same rays for the
+    k16 forms)."""
+    from oracle import pool as OP
     from paper_2404_16221_amd import synth
-    torch.set_num_threads(1)
-    rng = np.random.default_rng(7)
+    res = {"errors": {}, "configs": {}}
+    hosts, cache = {}, {}
 
-    def run(k):
-        rays = np.sort(rng.choice(w.n_rays, size=k, replace=False))
-        b = synth.generate(w, rays=rays)
-        g = rng.normal(size=(7, b.n_rays))
+    def host(cfg, rays):
+        key = (cfg, len(rays), int(rays[0]) if len(rays) else -1)
+        if key not in hosts:
+            hosts[key] = synth.generate(workloads[cfg], rays=rays)
+        return hosts[key]
+
+    def oracle(h, storage, grad, pool, key=None):
+        """Oracle results (cached by key) and the seconds they took."""
+        if key is not None and key in cache:
+            return cache[key]
+        if storage == "float32":
+            s_in, c_in = h.sigma, h.rgb
+        else:  # the stored 16-bit values (round to nearest even), de-quantised
+            dt = getattr(torch, storage)
+            s_in = torch.from_numpy(h.sigma).to(dt).float().numpy()
+            c_in = torch.from_numpy(h.rgb).to(dt).float().numpy()
         t = time.perf_counter()
-        O.render_rays_partitioned(b.sigma, b.rgb, b.t_start, b.t_end, b.seg_offsets, b.ray_offsets,
-                                  b.seg_ids)
-        O.backward_partitioned(b.sigma, b.rgb, b.t_start, b.t_end, b.seg_offsets, b.ray_offsets,
-                               b.seg_ids, g)
-        return time.perf_counter() - t, b.n
+        o = OP.run(pool, s_in, c_in, h.t_start, h.t_end, h.seg_offsets, h.ray_offsets,
+                   h.seg_ids, np.arange(h.n_rays), grad)
+        out = (o, time.perf_counter() - t)
+        if key is not None:
+            cache[key] = out
+        return out
 
-    dt, n = run(4)
-    k = int(max(4, min(16384, 4 * budget_s / max(dt, 1e-3))))
-    dt, n = run(k)
-    return {"value": n / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"{k} random rays of the {w.name} workload ({n} samples), FP64 oracle, "
-                      f"segment composite + merge + merge backward + segment backward, {dt:.1f} s"}
+    cores = opool._processes if opool is not None else 1
+    # single thread: 1,024 rays of the k16 batch, forward and backward
+    rng = np.random.default_rng(7)
+    w2 = workloads[2]
+    r1 = np.sort(rng.choice(w2.n_rays, 1024, replace=False))
+    h1 = host(2, r1)
+    _, dt1 = oracle(h1, "float32", rng.normal(size=(7, r1.size)), None)
+    single = h1.n / dt1
+    log(f"oracle, one thread: {h1.n} samples in {dt1:.1f} s")
+    for key, g in gathered.items():
+        cfg = g["cfg"]
+        h = host(cfg, g["rays"])
+        grads = g["with_grads"]
+        rkey = (cfg, len(g["rays"]), int(g["rays"][0]))
+        o, dt = oracle(h, g["storage"], g["grad_ray"] if grads else None, opool,
+                       rkey + (g["storage"], grads, g["grad_seed"]))
+        plain = g["regions"] == 1 and workloads[cfg].k > 1
+        e = output_errors(g, o, grads=grads, segs=not plain)
+        e["rays"] = int(len(g["rays"]))
+        e["samples"] = int(h.n)
+        if g["storage"] != "float32":
+            orig, _ = oracle(h, "float32", None, opool, rkey + ("float32", False, None))
+            e["rgb_vs_original_fp32_inputs_max_abs"] = float(
+                np.abs(g["ray"][1:4] - orig["ray"][1:4]).max())
+        res["errors"][key] = e
+        res["configs"].setdefault(workloads[cfg].name, {"samples_per_s": h.n / dt, "samples": int(h.n),
+                                                        "rays": int(len(g["rays"])),
+                                                        "passes": "fwd+bwd" if grads else "fwd"})
+        log(f"oracle, {cores} workers, {key}: {h.n} samples in {dt:.1f} s")
+    head = res["configs"].get(w2.name)
+    res["baseline"] = {
+        "value": head["samples_per_s"] if head else single, "unit": "samples/s", "cores": cores,
+        "kind": "oracle",
+        "sample": (f"{head['rays'] if head else 1024} random rays of the {w2.name} workload "
+                   f"({head['samples'] if head else h1.n} samples), FP64 oracle (segment "
+                   "composite, merge, single pass, merge backward, segment backward) in "
+                   f"{cores} worker processes on {cpu_model()}; one thread: {single:.4g} "
+                   f"samples/s on {r1.size} rays"),
+        "single_thread_samples_per_s": single, "cpu_model": cpu_model(),
+        "host_cpu_count": os.cpu_count(), "per_workload": res["configs"]}
+    return res
 
 
 def serve_stream(n_req, warmup, rate, dtype, slots, seed=2404_16221 + 103):
@@ -218,7 +363,7 @@ def serve_stream(n_req, warmup, rate, dtype, slots, seed=2404_16221 + 103):
 
     th = threading.Thread(target=producer)
     th.start()
-    res = []
+    res, done_at = [], []
     for i in range(total):
         while tickets[i] is None:
             time.sleep(0.0005)
@@ -232,31 +377,46 @@ def serve_stream(n_req, warmup, rate, dtype, slots, seed=2404_16221 + 103):
     m = res[warmup:]
     lat = np.array([r["latency_us"] for r in m]) / 1e3
     sub = np.array(submitted[warmup:])
-    span = float((sub + lat / 1e3).max() - sub.min())
+    done = sub + lat / 1e3
+    span = float(done.max() - sub.min())
     samples = sum(r["n_samples"] for r in m)
-    return {"requests": n_req, "warmup": warmup, "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
-            "device_ms_mean": float(np.mean([r["device_us"] for r in m]) / 1e3),
-            "requests_per_s": n_req / span, "samples_per_s": samples / span}
+    # requests submitted but not completed when the last one arrived: bounded
+    # (about the slot count) when the server keeps up, growing with the run
+    # length when it does not
+    backlog = int((done > sub.max()).sum())
+    sustained = n_req / span
+    dev = np.array([r["device_us"] for r in m]) / 1e3
+    return {"requests": n_req, "warmup": warmup, "offered_rate_per_s": rate,
+            "sustained_rate_per_s": sustained, "stable": bool(sustained >= 0.97 * rate),
+            "backlog_at_last_arrival": backlog,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "device_ms_mean": float(dev.mean()),
+            "device_ms_by_size": {f"{w}x{h}": float(dev[sizes[warmup:] == k].mean())
+                                  for k, (w, h) in enumerate(synth.SERVE_SIZES)
+                                  if (sizes[warmup:] == k).any()},
+            "requests_per_s": sustained, "samples_per_s": samples / span}
 
 
 def serving(n_req, warmup, rate):
-    """Continuous batching (FP16, 4 slots) and the FIFO single-request FP32 baseline
-    at the offered rate; then continuous batching again at 70 % of the rate it
-    sustained, where latency is service time rather than queueing."""
+    """Continuous batching (FP16, 4 slots) and the FIFO single-request FP32
+    baseline on the same arrivals (same seed, same count) at the offered rate;
+    then both again at 70 % of the lower of the two sustained rates, where
+    neither queue grows and latency is service time rather than queueing."""
     cb = serve_stream(n_req, warmup, rate, torch.float16, slots=4)
     log("serving fp16 x4 slots:", json.dumps(cb))
-    fifo = serve_stream(max(n_req // 3, 20), max(warmup // 3, 5), rate, torch.float32, slots=1)
+    fifo = serve_stream(n_req, warmup, rate, torch.float32, slots=1)
     log("serving fifo fp32:", json.dumps(fifo))
     out = {"workload": "k32 scene, Poisson %.0f/s, sizes 256^2/512^2/1280x720/1920x1080" % rate,
            "continuous_batching_fp16": cb, "fifo_fp32_baseline": fifo}
-    sustained = min(rate, cb["requests_per_s"])
-    if sustained < rate:
-        light = 0.7 * sustained
-        lt = serve_stream(max(n_req // 2, 20), max(warmup // 2, 5), light, torch.float16, slots=4)
-        lt["rate_per_s"] = light
-        log("serving fp16 x4 slots below capacity:", json.dumps(lt))
-        out["continuous_batching_fp16_at_70pct_capacity"] = lt
+    light = 0.7 * min(rate, cb["sustained_rate_per_s"], fifo["sustained_rate_per_s"])
+    if light < 0.97 * rate:
+        lt = serve_stream(n_req, warmup, light, torch.float16, slots=4)
+        log("serving fp16 x4 slots, light load:", json.dumps(lt))
+        lf = serve_stream(n_req, warmup, light, torch.float32, slots=1)
+        log("serving fifo fp32, light load:", json.dumps(lf))
+        out["light_load_rate_per_s"] = light
+        out["continuous_batching_fp16_light_load"] = lt
+        out["fifo_fp32_baseline_light_load"] = lf
     return out
 
 
@@ -387,19 +547,141 @@ def feature_channels(f, steps, warmup, F=16):
     return res
 
 
+def breakable_integrals(f, steps, warmup):
+    """The breakable-integral operator (App. B.2) over the samples of form f:
+    channels 1, m, m^2 formed in the kernel (depth moments: opacity, depth and
+    the second moment, from which a ray's depth variance follows) and the two
+    second-order members of the distortion loss, Psi_(m,1) and Psi_(1,m);
+    segment forward, merge, merge backward and segment backward per step."""
+    from paper_2404_16221_amd import _lib as xl
+    pairs = [(1, 0), (0, 1)]
+    d = xl.breakable(f.sigma, f.t0, f.t1, pairs, n_ch=3)
+    rows = 1 + 3 + len(pairs)
+    dev = f.sigma.device
+    seg = torch.empty((rows, f.n_seg), dtype=torch.float32, device=dev)
+    ray = torch.empty((rows, f.n_rays), dtype=torch.float32, device=dev)
+    gseg = torch.zeros((rows, f.n_seg), dtype=torch.float32, device=dev)
+    g = torch.from_numpy(np.random.default_rng(12).normal(size=(rows, f.n_rays)).astype(np.float32)).to(dev)
+    gs = torch.empty_like(f.sigma)
+
+    def step(ev=None):
+        xl.xl_render_breakable_fwd(d, f.seg_offsets, seg)
+        xl.xl_merge_breakable_fwd(d, seg, f.ray_offsets, f.seg_ids, ray)
+        xl.xl_merge_breakable_bwd(d, seg, f.ray_offsets, f.seg_ids, g, gseg)
+        if ev is not None:
+            ev[0].record()
+        xl.xl_render_breakable_bwd(d, f.seg_offsets, seg, gseg, gs)
+        if ev is not None:
+            ev[1].record()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    kern = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        step(kern[k])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    kms = float(np.mean([a.elapsed_time(b) for a, b in kern]))
+    es = f.sigma.element_size()
+    tb = 4 * rows
+    per_sample = 2 * (es + 8) + es                 # sigma, t0, t1 read twice; dsigma written
+    per_seg = (8 + tb) + (8 + tb) + (8 + 2 * tb + tb) + (8 + 2 * tb)
+    per_ray = (16 + tb) + (16 + tb)
+    step_bytes = f.n * per_sample + f.n_seg * per_seg + f.n_rays * per_ray
+    bwd_bytes = f.n * (es + 8 + es) + f.n_seg * (8 + 2 * tb)
+    res = {"workload": f"{f.name} samples, channels 1, m, m^2 formed in the kernel, "
+                       "pairs (m, 1) and (1, m)",
+           "ms_per_step": ms, "samples_per_s": f.n / (ms * 1e-3),
+           "step_gbs": step_bytes / (ms * 1e-3) / 1e9, "bwd_ms": kms,
+           "bwd_gbs": bwd_bytes / (kms * 1e-3) / 1e9,
+           "bwd_frac_of_hbm_peak": bwd_bytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    log("breakable", json.dumps(res))
+    return res
+
+
+def small_workloads(steps, warmup, gathered):
+    """The two parity workloads: K=1 forward over 4,096 rays (its inputs fit
+    in the L2 caches: launch and latency bound, reported in microseconds) and
+    K=8 forward and backward over 65,536 rays (202 MB of inputs: they fit the
+    256 MB last-level cache, so it is timed both back to back and with a
+    1 GiB write between steps that evicts them)."""
+    from paper_2404_16221_amd import _lib as xl
+    from paper_2404_16221_amd import synth
+    res = {}
+    w0, w1 = synth.WORKLOADS[0], synth.WORKLOADS[1]
+    g = xl.xl_gen(w0, torch.float32)
+    z = torch.zeros((7, w0.n_rays), device="cuda")
+    f0 = Form(w0.name, g["sigma"], g["rgb"], g["t_start"], g["t_end"], g["seg_offsets"],
+              g["ray_offsets"], g["seg_ids"], z, 1)
+    reps = 200
+    for _ in range(20):
+        f0.forward()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        f0.forward()
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / reps * 1e3
+    res[w0.name] = {"form": "plain FP32, K=1, forward (segment composite + merge)",
+                    "us_per_forward": us, "samples": f0.n, "samples_per_s": f0.n / (us * 1e-6),
+                    "note": "inputs (6.6 MB) stay in the caches between repetitions"}
+    gathered["k1_fp32_fwd"] = gather_form(f0, np.arange(w0.n_rays), 0, with_grads=False)
+    log("small", w0.name, json.dumps(res[w0.name]))
+    f0.release()
+    g = xl.xl_gen(w1, torch.float32)
+    gr = torch.from_numpy(np.random.default_rng(5).normal(size=(7, w1.n_rays)).astype(np.float32)).cuda()
+    f1 = Form(w1.name, g["sigma"], g["rgb"], g["t_start"], g["t_end"], g["seg_offsets"],
+              g["ray_offsets"], g["seg_ids"], gr, 8)
+    ms_res, _, _ = time_form(f1, max(steps, 20), warmup)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(max(steps, 20))]
+    for a, b in ev:
+        flush.fill_(1.0)
+        a.record()
+        f1.step()
+        b.record()
+    torch.cuda.synchronize()
+    ms_flush = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    del flush
+    res[w1.name] = {"form": "FP32, K=8, segment composite + merge + merge backward + segment backward",
+                    "ms_per_step_cache_resident": ms_res, "ms_per_step_flushed": ms_flush,
+                    "samples": f1.n, "segments": f1.n_seg,
+                    "samples_per_s_cache_resident": f1.n / (ms_res * 1e-3),
+                    "samples_per_s_flushed": f1.n / (ms_flush * 1e-3),
+                    "step_gbs_flushed": f1.bytes_step() / (ms_flush * 1e-3) / 1e9}
+    gathered["k8_fp32"] = gather_form(f1, np.arange(w1.n_rays), 1, grad_seed=5)
+    log("small", w1.name, json.dumps(res[w1.name]))
+    f1.release()
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the FP64 oracle (its timing and the errors against it)")
     ap.add_argument("--forms", default="bf16,fp32,plain,k64")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the K=1 (4,096 rays) and K=8 (65,536 rays) workloads")
     ap.add_argument("--no-features", action="store_true", help="skip the feature-channel timing")
     ap.add_argument("--no-distribution", action="store_true",
                     help="skip the tag/split/pack timing")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="measured serving requests (0 skips the serving run)")
     ap.add_argument("--serve-warmup", type=int, default=30)
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving measurement and print its JSON")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrivals per second")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB device to device (scales HBM byte counters)")
@@ -417,6 +699,16 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the exchange of segment "
               "tuples between GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
+    if args.serving_only:
+        import paper_2404_16221_amd  # noqa: F401
+        print(json.dumps({"serving": serving(args.serve_requests, args.serve_warmup,
+                                             args.serve_rate)}), flush=True)
+        return
+    opool = None
+    if not args.no_cpu_baseline:
+        # the oracle's worker processes are forked before anything touches the GPU
+        from oracle import pool as OP
+        opool = OP.Pool()
     import paper_2404_16221_amd  # noqa: F401  (fails loudly without libxl.so)
     from paper_2404_16221_amd import _lib as xl
     from paper_2404_16221_amd import synth
@@ -424,9 +716,12 @@ def main():
     dev = torch.device("cuda:0")
     w = synth.WORKLOADS[2]
     want = args.forms.split(",")
-    forms, results = {}, {}
+    forms, results, gathered = {}, {}, {}
     grad_ray = torch.from_numpy(
         np.random.default_rng(3).normal(size=(7, w.n_rays)).astype(np.float32)).to(dev)
+    # rays compared with the oracle: 16,384 seeded rays of the k16 batch, and of
+    # the k64 batch 16,384 seeded rays plus up to 1,024 with more than 8 segments
+    err_rays = np.sort(np.random.default_rng(8).choice(w.n_rays, 16384, replace=False))
 
     def make(name, workload, dtype, regions, fp64=False, grad=None):
         t = time.perf_counter()
@@ -437,7 +732,6 @@ def main():
         return Form(name, g["sigma"], g["rgb"], g["t_start"], g["t_end"], g["seg_offsets"],
                     g["ray_offsets"], g["seg_ids"], grad_ray if grad is None else grad, regions,
                     fp64=fp64)
-
     if "bf16" in want:
         forms["bf16"] = make("k16-bf16", w, torch.bfloat16, 16)
     if "fp32" in want:
@@ -464,6 +758,17 @@ def main():
         results[key]["exchange_sample_mb"] = xb["sample_based"] / 1e6
         results[key]["exchange_tuple_mb"] = xb["segment_based"] / 1e6
         log(key, json.dumps(results[key]))
+        if opool is not None:
+            if key == "k64":
+                spr = np.diff(f.ray_offsets.cpu().numpy())
+                long_rays = np.flatnonzero(spr > 8)
+                long_rays = long_rays[np.random.default_rng(9).choice(
+                    long_rays.size, min(1024, long_rays.size), replace=False)]
+                rays64 = np.union1d(np.random.default_rng(10).choice(f.n_rays, 16384, replace=False),
+                                    long_rays)
+                gathered[key] = gather_form(f, rays64, 4, grad_seed=4)
+            else:
+                gathered[key] = gather_form(f, err_rays, 2, grad_seed=3)
     head = "bf16" if "bf16" in results else next(iter(results))
     hf, hr = forms[head], results[head]
     out = {
@@ -484,8 +789,16 @@ def main():
                      "kernel": "seg_bwd_kernel", "step_achieved": hr["step_gbs"],
                      "step_frac": hr["step_gbs"] / HBM_PEAK_GBS},
     }
+    prof_us = profile_number("seg_bwd_avg_us") if head == "bf16" else None
+    if prof_us:
+        # the same kernel's average from the committed kernel trace
+        out["roofline"]["profile_avg_us"] = prof_us
+        out["roofline"]["frac_profile"] = hf.bytes_seg_bwd() / (prof_us * 1e-6) / 1e9 / HBM_PEAK_GBS
+    if not args.no_small:
+        out["small_workloads"] = small_workloads(args.steps, args.warmup, gathered)
     if not args.no_features and "bf16" in forms:
         out["features"] = feature_channels(forms["bf16"], args.steps, args.warmup)
+        out["breakable_integrals"] = breakable_integrals(forms["bf16"], args.steps, args.warmup)
     if not args.no_distribution:
         out["distribution"] = distribution(max(args.steps // 2, 3), 2)
     if args.serve_requests > 0:
@@ -494,8 +807,11 @@ def main():
         forms.clear()
         torch.cuda.empty_cache()
         out["serving"] = serving(args.serve_requests, args.serve_warmup, args.serve_rate)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+    if opool is not None:
+        leg = oracle_leg(opool, gathered, synth.WORKLOADS)
+        opool.terminate()
+        out["cpu_baseline"] = leg["baseline"]
+        out["errors"] = leg["errors"]
     print(json.dumps(out), flush=True)
 
 
