@@ -4,9 +4,11 @@
 Metric: composited samples/s for one training step (per-segment composite,
 merge, merge backward, per-segment backward) over the K=16 training batch
 (262,144 rays, 8..1024 samples per ray, about 135M samples, density
-lognormal(0, 2) with 30% empty samples), BF16 sample storage.  The same step
-is also timed with FP32 storage and in the plain form (FP32, the same samples
-as one K=1 segment per ray).  Inputs are resident in HBM before timing starts.
+lognormal(0, 2) with 30% empty samples), 16-bit sample storage: densities in
+BF16 and colours in FP16.  The same step is also timed with BF16 for both,
+with FP32 storage and in the plain form (FP32, the same samples as one K=1
+segment per ray), and on the K=64 large partition.  Inputs are resident in
+HBM before timing starts.
 
 Prints one JSON line.  Options: --steps K --warmup W --gpus 1 [--no-cpu-baseline].
 """
@@ -60,9 +62,13 @@ def profile_fields():
     return fields
 
 
-def profile_number(key):
+def profile_number(key, form):
+    """A number of the committed counter summary, if it was taken on `form`."""
+    f = profile_fields()
+    if f.get("form") != form:
+        return None
     try:
-        return float(profile_fields()[key])
+        return float(f[key])
     except (KeyError, ValueError):
         return None
 
@@ -180,6 +186,13 @@ def ray_major(seg_offsets, ray_offsets, seg_ids, rays):
     return segs, ranges(seg_offsets[segs], seg_offsets[segs + 1] - seg_offsets[segs])
 
 
+def storage_of(f: Form) -> str:
+    """Storage name of a form: one dtype, or "<sigma dtype>/<rgb dtype>"."""
+    s = str(f.sigma.dtype).replace("torch.", "")
+    c = str(f.rgb.dtype).replace("torch.", "")
+    return s if s == c else f"{s}/{c}"
+
+
 def gather_form(f: Form, rays, cfg, with_grads=True, grad_seed=None):
     """Host copies of form f's results of its last step for `rays` of
     workload `cfg`, ray-major."""
@@ -194,7 +207,7 @@ def gather_form(f: Form, rays, cfg, with_grads=True, grad_seed=None):
             "grad_seg": f.grad_seg[:, at_s].cpu().numpy(), "dsigma": f.gs[at].float().cpu().numpy(),
             "drgb": f.gc[at].float().cpu().numpy(), "rays": rays,
             "grad_ray": f.grad_ray[:, at_r].cpu().numpy().astype(np.float64),
-            "storage": str(f.sigma.dtype).replace("torch.", ""), "regions": f.regions,
+            "storage": storage_of(f), "regions": f.regions,
             "cfg": cfg, "with_grads": with_grads, "grad_seed": grad_seed}
 
 
@@ -278,9 +291,9 @@ def oracle_leg(opool, gathered, workloads):
         if storage == "float32":
             s_in, c_in = h.sigma, h.rgb
         else:  # the stored 16-bit values (round to nearest even), de-quantised
-            dt = getattr(torch, storage)
-            s_in = torch.from_numpy(h.sigma).to(dt).float().numpy()
-            c_in = torch.from_numpy(h.rgb).to(dt).float().numpy()
+            sn, _, cn = storage.partition("/")
+            s_in = torch.from_numpy(h.sigma).to(getattr(torch, sn)).float().numpy()
+            c_in = torch.from_numpy(h.rgb).to(getattr(torch, cn or sn)).float().numpy()
         t = time.perf_counter()
         o = OP.run(pool, s_in, c_in, h.t_start, h.t_end, h.seg_offsets, h.ray_offsets,
                    h.seg_ids, np.arange(h.n_rays), grad)
@@ -671,7 +684,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the FP64 oracle (its timing and the errors against it)")
-    ap.add_argument("--forms", default="bf16,fp32,plain,k64")
+    ap.add_argument("--forms", default="bf16f16,bf16,fp32,plain,k64",
+                    help="bf16f16: densities in BF16 and colours in FP16 (the headline form)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the K=1 (4,096 rays) and K=8 (65,536 rays) workloads")
     ap.add_argument("--no-features", action="store_true", help="skip the feature-channel timing")
@@ -732,6 +746,10 @@ def main():
         return Form(name, g["sigma"], g["rgb"], g["t_start"], g["t_end"], g["seg_offsets"],
                     g["ray_offsets"], g["seg_ids"], grad_ray if grad is None else grad, regions,
                     fp64=fp64)
+    if "bf16f16" in want:
+        # densities in BF16, colours in FP16: the same bytes as BF16, with the
+        # colour rounding (2^-11) far inside the 2e-3 colour bar
+        forms["bf16f16"] = make("k16-bf16sigma-f16rgb", w, xl.BF16_F16, 16)
     if "bf16" in want:
         forms["bf16"] = make("k16-bf16", w, torch.bfloat16, 16)
     if "fp32" in want:
@@ -744,7 +762,8 @@ def main():
         w64 = synth.WORKLOADS[4]
         g64 = torch.from_numpy(
             np.random.default_rng(4).normal(size=(7, w64.n_rays)).astype(np.float32)).to(dev)
-        forms["k64"] = make("k64-bf16-fp64merge", w64, torch.bfloat16, 64, fp64=True, grad=g64)
+        forms["k64"] = make("k64-bf16sigma-f16rgb-fp64merge", w64, xl.BF16_F16, 64, fp64=True,
+                            grad=g64)
     for key, f in forms.items():
         ms, kms, wall = time_form(f, args.steps, args.warmup)
         results[key] = dict(name=f.name, ms_per_step=ms, samples_per_s=f.n / (ms * 1e-3),
@@ -769,7 +788,7 @@ def main():
                 gathered[key] = gather_form(f, rays64, 4, grad_seed=4)
             else:
                 gathered[key] = gather_form(f, err_rays, 2, grad_seed=3)
-    head = "bf16" if "bf16" in results else next(iter(results))
+    head = next((k for k in ("bf16f16", "bf16") if k in results), next(iter(results)))
     hf, hr = forms[head], results[head]
     out = {
         "metric": METRIC, "value": hr["samples_per_s"], "unit": "samples/s", "n_gpus": 1,
@@ -777,19 +796,19 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "rays": hf.n_rays, "samples": hf.n, "segments": hf.n_seg,
-                   "regions": hf.regions, "storage": str(hf.sigma.dtype).replace("torch.", ""),
+                   "regions": hf.regions, "storage": storage_of(hf),
                    "passes": "segment fwd + merge fwd + merge bwd + segment bwd"},
         "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in results.items()},
         "roofline": {"bound": "hbm", "achieved": hr["seg_bwd_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": hr["seg_bwd_gbs"] / HBM_PEAK_GBS,
-                     "traffic": profile_number("hbm_bytes_per_launch") if head == "bf16" else None,
-                     "valu_busy": profile_number("valu_busy") if head == "bf16" else None,
+                     "traffic": profile_number("hbm_bytes_per_launch", head),
+                     "valu_busy": profile_number("valu_busy", head),
                      "algorithmic_bytes": hf.bytes_seg_bwd(),
                      "kernel": "seg_bwd_kernel", "step_achieved": hr["step_gbs"],
                      "step_frac": hr["step_gbs"] / HBM_PEAK_GBS},
     }
-    prof_us = profile_number("seg_bwd_avg_us") if head == "bf16" else None
+    prof_us = profile_number("seg_bwd_avg_us", head)
     if prof_us:
         # the same kernel's average from the committed kernel trace
         out["roofline"]["profile_avg_us"] = prof_us

@@ -58,10 +58,15 @@ extern "C" {
 #define XL_EFAULT (-5)
 
 /* Storage type of sigma and rgb (and of their gradients).  t_start/t_end are
- * always float32; accumulation is always float32 or wider. */
+ * always float32; accumulation is always float32 or wider.  XL_BF16_F16 keeps
+ * sigma (and dl/dsigma) in bfloat16 and rgb (and dl/drgb) in float16: the
+ * same two bytes per value, with colour rounded to 2^-11 relative instead of
+ * bfloat16's 2^-8 (accepted by the segment and generator entry points and the
+ * server; the feature and breakable entry points take one storage type). */
 #define XL_F32 0
 #define XL_BF16 1
 #define XL_F16 2
+#define XL_BF16_F16 3
 
 /* xl_merge_* flags. */
 #define XL_MERGE_FP64 1 /* cross-segment prefix sums and products in float64 */

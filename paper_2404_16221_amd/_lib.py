@@ -21,6 +21,24 @@ XL_EINVAL, XL_ENOMEM, XL_EHIP, XL_EAGAIN, XL_EFAULT = -1, -2, -3, -4, -5
 XL_F32, XL_BF16, XL_F16 = 0, 1, 2
 XL_MERGE_FP64 = 1
 DTYPES = {torch.float32: XL_F32, torch.bfloat16: XL_BF16, torch.float16: XL_F16}
+XL_BF16_F16 = 3
+# Mixed 16-bit storage: sigma in bfloat16, rgb in float16.
+BF16_F16 = (torch.bfloat16, torch.float16)
+
+
+def storage_code(sigma_dtype, rgb_dtype=None) -> int:
+    """The XL_* storage code of (sigma, rgb) dtypes (one dtype: both alike)."""
+    rgb_dtype = sigma_dtype if rgb_dtype is None else rgb_dtype
+    if (sigma_dtype, rgb_dtype) == BF16_F16:
+        return XL_BF16_F16
+    if sigma_dtype != rgb_dtype or sigma_dtype not in DTYPES:
+        raise ValueError(f"unsupported storage: sigma {sigma_dtype}, rgb {rgb_dtype}")
+    return DTYPES[sigma_dtype]
+
+
+def storage_dtypes(dtype):
+    """(sigma dtype, rgb dtype) of a storage given as a torch dtype or a pair."""
+    return tuple(dtype) if isinstance(dtype, (tuple, list)) else (dtype, dtype)
 TORCH_DTYPES = {v: k for k, v in DTYPES.items()}
 TUPLE = 7
 
@@ -142,14 +160,11 @@ def _dev(t: torch.Tensor, name: str, dtype=None) -> int:
 
 
 def samples(sigma, rgb, t_start, t_end) -> XLSamples:
-    if sigma.dtype not in DTYPES:
-        raise ValueError(f"unsupported storage dtype {sigma.dtype}")
-    if rgb.dtype != sigma.dtype:
-        raise ValueError("sigma and rgb must share the storage dtype")
+    code = storage_code(sigma.dtype, rgb.dtype)
     n = sigma.shape[0]
     if rgb.shape != (n, 3) or t_start.shape != (n,) or t_end.shape != (n,):
         raise ValueError("shapes must be sigma[n], rgb[n,3], t_start[n], t_end[n]")
-    return XLSamples(DTYPES[sigma.dtype], _dev(sigma, "sigma"), _dev(rgb, "rgb"),
+    return XLSamples(code, _dev(sigma, "sigma"), _dev(rgb, "rgb"),
                      _dev(t_start, "t_start", torch.float32), _dev(t_end, "t_end", torch.float32), n)
 
 
@@ -205,7 +220,7 @@ def xl_render_segments_bwd(sigma, rgb, t_start, t_end, seg_offsets, workspace, g
                                         n_seg, _dev(workspace, "workspace"), workspace.numel(),
                                         _dev(grad_seg, "grad_seg", torch.float32),
                                         _dev(grad_sigma, "grad_sigma", sigma.dtype),
-                                        _dev(grad_rgb, "grad_rgb", sigma.dtype), _stream()))
+                                        _dev(grad_rgb, "grad_rgb", rgb.dtype), _stream()))
     return grad_sigma, grad_rgb
 
 
@@ -269,7 +284,8 @@ def xl_gen(w, dtype=torch.float32, ray0: int = 0, n_rays: Optional[int] = None,
            device="cuda") -> dict:
     """Generate rays of workload `w` on the device, packed region-major.
 
-    Returns device tensors sigma, rgb (storage dtype), t_start, t_end,
+    dtype: a torch dtype for both sigma and rgb, or the pair BF16_F16.
+    Returns device tensors sigma, rgb (storage dtypes), t_start, t_end,
     seg_offsets, ray_offsets, seg_ids."""
     p = gen_params(w, ray0, n_rays)
     L = lib()
@@ -279,14 +295,15 @@ def xl_gen(w, dtype=torch.float32, ray0: int = 0, n_rays: Optional[int] = None,
     _check(L.xl_gen_plan(ctypes.byref(p), ws.data_ptr(), wsb, ctypes.byref(ns), ctypes.byref(nseg),
                          _stream()))
     n, n_seg = ns.value, nseg.value
-    out = dict(sigma=torch.empty(n, dtype=dtype, device=device),
-               rgb=torch.empty((n, 3), dtype=dtype, device=device),
+    sdt, cdt = storage_dtypes(dtype)
+    out = dict(sigma=torch.empty(n, dtype=sdt, device=device),
+               rgb=torch.empty((n, 3), dtype=cdt, device=device),
                t_start=torch.empty(n, dtype=torch.float32, device=device),
                t_end=torch.empty(n, dtype=torch.float32, device=device),
                seg_offsets=torch.empty(n_seg + 1, dtype=torch.int64, device=device),
                ray_offsets=torch.empty(p.n_rays + 1, dtype=torch.int64, device=device),
                seg_ids=torch.empty(n_seg, dtype=torch.int64, device=device))
-    _check(L.xl_gen_fill(ctypes.byref(p), DTYPES[dtype], ws.data_ptr(), wsb, n_seg,
+    _check(L.xl_gen_fill(ctypes.byref(p), storage_code(sdt, cdt), ws.data_ptr(), wsb, n_seg,
                          _dev(out["sigma"], "sigma"), _dev(out["rgb"], "rgb"),
                          _dev(out["t_start"], "t_start"), _dev(out["t_end"], "t_end"),
                          _dev(out["seg_offsets"], "seg_offsets"), _dev(out["ray_offsets"], "ray_offsets"),

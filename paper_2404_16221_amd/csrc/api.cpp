@@ -34,7 +34,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 int check_samples(const xl_samples* s, xl::SamplesDev* out) {
   if (s == nullptr) return fail(XL_EINVAL, "samples descriptor is NULL");
-  if (s->dtype != XL_F32 && s->dtype != XL_BF16 && s->dtype != XL_F16)
+  if (s->dtype != XL_F32 && s->dtype != XL_BF16 && s->dtype != XL_F16 && s->dtype != XL_BF16_F16)
     return fail(XL_EINVAL, "unknown sample dtype %d", s->dtype);
   if (s->n < 0) return fail(XL_EINVAL, "negative sample count %lld", (long long)s->n);
   if (s->n > 0) {
@@ -255,7 +255,7 @@ int xl_gen_fill(const xl_gen_params* p, int32_t dtype, void* workspace, size_t w
                 int64_t* seg_offsets, int64_t* ray_offsets, int64_t* seg_ids, void* stream) {
   int rc = check_gen(p);
   if (rc) return rc;
-  if (dtype != XL_F32 && dtype != XL_BF16 && dtype != XL_F16)
+  if (dtype != XL_F32 && dtype != XL_BF16 && dtype != XL_F16 && dtype != XL_BF16_F16)
     return fail(XL_EINVAL, "unknown sample dtype %d", dtype);
   if (!workspace || workspace_bytes < xl::gen_workspace_bytes(p))
     return fail(XL_EINVAL, "workspace missing or too small");

@@ -335,9 +335,9 @@ __device__ __forceinline__ void put_sample(void* sigma, void* rgb, int64_t i, fl
     float* C = static_cast<float*>(rgb) + 3 * i;
     C[0] = c0; C[1] = c1; C[2] = c2;
   } else {
-    static_cast<uint16_t*>(sigma)[i] = from_f32<DT>(sg);
+    static_cast<uint16_t*>(sigma)[i] = from_f32<sig_dt(DT)>(sg);
     uint16_t* C = static_cast<uint16_t*>(rgb) + 3 * i;
-    C[0] = from_f32<DT>(c0); C[1] = from_f32<DT>(c1); C[2] = from_f32<DT>(c2);
+    C[0] = from_f32<rgb_dt(DT)>(c0); C[1] = from_f32<rgb_dt(DT)>(c1); C[2] = from_f32<rgb_dt(DT)>(c2);
   }
 }
 
@@ -364,12 +364,14 @@ __device__ __forceinline__ void store_group(void* sigma, void* rgb, float* t_sta
   } else {
     uint4* S = reinterpret_cast<uint4*>(static_cast<uint16_t*>(sigma) + g0);
     uint4* C = reinterpret_cast<uint4*>(static_cast<uint16_t*>(rgb) + 3 * g0);
-    *S = make_uint4(pack2<DT>(sg[0], sg[1]), pack2<DT>(sg[2], sg[3]), pack2<DT>(sg[4], sg[5]),
-                    pack2<DT>(sg[6], sg[7]));
+    *S = make_uint4(pack2<sig_dt(DT)>(sg[0], sg[1]), pack2<sig_dt(DT)>(sg[2], sg[3]),
+                    pack2<sig_dt(DT)>(sg[4], sg[5]), pack2<sig_dt(DT)>(sg[6], sg[7]));
 #pragma unroll
     for (int q = 0; q < 3; ++q)
-      C[q] = make_uint4(pack2<DT>(c[8 * q], c[8 * q + 1]), pack2<DT>(c[8 * q + 2], c[8 * q + 3]),
-                        pack2<DT>(c[8 * q + 4], c[8 * q + 5]), pack2<DT>(c[8 * q + 6], c[8 * q + 7]));
+      C[q] = make_uint4(pack2<rgb_dt(DT)>(c[8 * q], c[8 * q + 1]),
+                        pack2<rgb_dt(DT)>(c[8 * q + 2], c[8 * q + 3]),
+                        pack2<rgb_dt(DT)>(c[8 * q + 4], c[8 * q + 5]),
+                        pack2<rgb_dt(DT)>(c[8 * q + 6], c[8 * q + 7]));
   }
   float4* A = reinterpret_cast<float4*>(t_start + g0);
   float4* B = reinterpret_cast<float4*>(t_end + g0);
@@ -692,6 +694,10 @@ hipError_t gen_fill(const xl_gen_params* p, int dtype, void* ws, int64_t n_seg, 
       break;
     case kBF16:
       hipLaunchKernelGGL(gen_fill_kernel<kBF16>, grid, dim3(128), 0, st, g, w, sigma, rgb, t_start, t_end);
+      break;
+    case kBF16F16:
+      hipLaunchKernelGGL(gen_fill_kernel<kBF16F16>, grid, dim3(128), 0, st, g, w, sigma, rgb, t_start,
+                         t_end);
       break;
     default:
       hipLaunchKernelGGL(gen_fill_kernel<kF16>, grid, dim3(128), 0, st, g, w, sigma, rgb, t_start, t_end);

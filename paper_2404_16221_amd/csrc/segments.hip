@@ -602,10 +602,11 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
       } else {
         if ((j & 1) == 0) {  // pairs of 16-bit values
           uint32_t* img = reinterpret_cast<uint32_t*>(park);
-          img[(lane * kRun + j) / 2] = pack2<DT>(dsg[j], dsg[j + 1]);
+          img[(lane * kRun + j) / 2] = pack2<sig_dt(DT)>(dsg[j], dsg[j + 1]);
 #pragma unroll
           for (int v = 0; v < 3; ++v)
-            img[kTile / 2 + (3 * (lane * kRun + j)) / 2 + v] = pack2<DT>(dc[3 * j + 2 * v], dc[3 * j + 2 * v + 1]);
+            img[kTile / 2 + (3 * (lane * kRun + j)) / 2 + v] =
+                pack2<rgb_dt(DT)>(dc[3 * j + 2 * v], dc[3 * j + 2 * v + 1]);
         }
       }
     }
@@ -656,14 +657,14 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
       for (int q = 0; q < kRun / 8; ++q) {
         uint32_t w[4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) w[h] = pack2<DT>(dsg[8 * q + 2 * h], dsg[8 * q + 2 * h + 1]);
+        for (int h = 0; h < 4; ++h) w[h] = pack2<sig_dt(DT)>(dsg[8 * q + 2 * h], dsg[8 * q + 2 * h + 1]);
         GS[q] = make_uint4(w[0], w[1], w[2], w[3]);
       }
 #pragma unroll
       for (int q = 0; q < 3 * kRun / 8; ++q) {
         uint32_t w[4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) w[h] = pack2<DT>(dc[8 * q + 2 * h], dc[8 * q + 2 * h + 1]);
+        for (int h = 0; h < 4; ++h) w[h] = pack2<rgb_dt(DT)>(dc[8 * q + 2 * h], dc[8 * q + 2 * h + 1]);
         GC[q] = make_uint4(w[0], w[1], w[2], w[3]);
       }
     }
@@ -677,11 +678,11 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
           float* GC = static_cast<float*>(grgb_p);
           GC[3 * i] = dc[3 * j]; GC[3 * i + 1] = dc[3 * j + 1]; GC[3 * i + 2] = dc[3 * j + 2];
         } else {
-          static_cast<uint16_t*>(gsig_p)[i] = from_f32<DT>(dsg[j]);
+          static_cast<uint16_t*>(gsig_p)[i] = from_f32<sig_dt(DT)>(dsg[j]);
           uint16_t* GC = static_cast<uint16_t*>(grgb_p);
-          GC[3 * i] = from_f32<DT>(dc[3 * j]);
-          GC[3 * i + 1] = from_f32<DT>(dc[3 * j + 1]);
-          GC[3 * i + 2] = from_f32<DT>(dc[3 * j + 2]);
+          GC[3 * i] = from_f32<rgb_dt(DT)>(dc[3 * j]);
+          GC[3 * i + 1] = from_f32<rgb_dt(DT)>(dc[3 * j + 1]);
+          GC[3 * i + 2] = from_f32<rgb_dt(DT)>(dc[3 * j + 2]);
         }
       }
     }
@@ -792,6 +793,7 @@ hipError_t launch_segments_fwd(const SamplesDev& s, const int64_t* off, int64_t 
   switch (s.dtype) {
     case kF32: launch_fwd_dt<kF32>(s, off, n_seg, nt, seg_out, recs, stream); break;
     case kBF16: launch_fwd_dt<kBF16>(s, off, n_seg, nt, seg_out, recs, stream); break;
+    case kBF16F16: launch_fwd_dt<kBF16F16>(s, off, n_seg, nt, seg_out, recs, stream); break;
     default: launch_fwd_dt<kF16>(s, off, n_seg, nt, seg_out, recs, stream); break;
   }
   hipLaunchKernelGGL(seg_fixup_kernel, dim3(grid_for(nt, 256)), dim3(256), 0, stream, nt, n_seg,
@@ -808,6 +810,7 @@ hipError_t launch_segments_bwd(const SamplesDev& s, const int64_t* off, int64_t 
   switch (s.dtype) {
     case kF32: launch_bwd_dt<kF32>(s, off, n_seg, nt, recs, grad_seg, grad_sigma, grad_rgb, stream); break;
     case kBF16: launch_bwd_dt<kBF16>(s, off, n_seg, nt, recs, grad_seg, grad_sigma, grad_rgb, stream); break;
+    case kBF16F16: launch_bwd_dt<kBF16F16>(s, off, n_seg, nt, recs, grad_seg, grad_sigma, grad_rgb, stream); break;
     default: launch_bwd_dt<kF16>(s, off, n_seg, nt, recs, grad_seg, grad_sigma, grad_rgb, stream); break;
   }
   return hipGetLastError();

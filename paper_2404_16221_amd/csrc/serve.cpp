@@ -298,7 +298,8 @@ int xl_serve_create(const xl_serve_config* cfg, xl_server** out) {
   if (!cfg || !out) return xl::set_error(XL_EINVAL, "NULL config or output");
   if (cfg->max_slots < 1 || cfg->max_queue < 1)
     return xl::set_error(XL_EINVAL, "max_slots and max_queue must be >= 1");
-  if (cfg->dtype != XL_F32 && cfg->dtype != XL_BF16 && cfg->dtype != XL_F16)
+  if (cfg->dtype != XL_F32 && cfg->dtype != XL_BF16 && cfg->dtype != XL_F16 &&
+      cfg->dtype != XL_BF16_F16)
     return xl::set_error(XL_EINVAL, "unknown sample dtype %d", cfg->dtype);
   if (cfg->hbm_budget_bytes < xl::Arena::kAlign)
     return xl::set_error(XL_EINVAL, "hbm_budget_bytes must be at least %zu", xl::Arena::kAlign);

@@ -12,6 +12,8 @@
 // which equals D_y A_x - A_y D_x of Eq. 8 without its cancellation.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -23,7 +25,11 @@ constexpr int kTile = kWave * kRun;       // samples per wave tile
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 
-enum Dtype : int { kF32 = 0, kBF16 = 1, kF16 = 2 };
+enum Dtype : int { kF32 = 0, kBF16 = 1, kF16 = 2, kBF16F16 = 3 };
+// Storage type of the densities and of the colours (and of their gradients):
+// kBF16F16 keeps densities in bfloat16 and colours in float16.
+constexpr int sig_dt(int dt) { return dt == kBF16F16 ? kBF16 : dt; }
+constexpr int rgb_dt(int dt) { return dt == kBF16F16 ? kF16 : dt; }
 
 struct Range {
   float tau;        // sum of optical depths sigma * delta; transmittance is exp(-tau)
@@ -260,8 +266,8 @@ __device__ __forceinline__ void load_run(const void* __restrict__ sigma_p,
         const uint32_t w[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
-          sg[8 * q + 2 * h] = to_f32<DT>(static_cast<uint16_t>(w[h] & 0xffffu));
-          sg[8 * q + 2 * h + 1] = to_f32<DT>(static_cast<uint16_t>(w[h] >> 16));
+          sg[8 * q + 2 * h] = to_f32<sig_dt(DT)>(static_cast<uint16_t>(w[h] & 0xffffu));
+          sg[8 * q + 2 * h + 1] = to_f32<sig_dt(DT)>(static_cast<uint16_t>(w[h] >> 16));
         }
       }
 #pragma unroll
@@ -270,8 +276,8 @@ __device__ __forceinline__ void load_run(const void* __restrict__ sigma_p,
         const uint32_t w[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
-          c[8 * q + 2 * h] = to_f32<DT>(static_cast<uint16_t>(w[h] & 0xffffu));
-          c[8 * q + 2 * h + 1] = to_f32<DT>(static_cast<uint16_t>(w[h] >> 16));
+          c[8 * q + 2 * h] = to_f32<rgb_dt(DT)>(static_cast<uint16_t>(w[h] & 0xffffu));
+          c[8 * q + 2 * h + 1] = to_f32<rgb_dt(DT)>(static_cast<uint16_t>(w[h] >> 16));
         }
       }
     }
@@ -291,10 +297,10 @@ __device__ __forceinline__ void load_run(const void* __restrict__ sigma_p,
       } else {
         const uint16_t* S = static_cast<const uint16_t*>(sigma_p);
         const uint16_t* C = static_cast<const uint16_t*>(rgb_p);
-        sg[j] = ok ? to_f32<DT>(S[i + j]) : 0.f;
-        c[3 * j] = ok ? to_f32<DT>(C[3 * (i + j)]) : 0.f;
-        c[3 * j + 1] = ok ? to_f32<DT>(C[3 * (i + j) + 1]) : 0.f;
-        c[3 * j + 2] = ok ? to_f32<DT>(C[3 * (i + j) + 2]) : 0.f;
+        sg[j] = ok ? to_f32<sig_dt(DT)>(S[i + j]) : 0.f;
+        c[3 * j] = ok ? to_f32<rgb_dt(DT)>(C[3 * (i + j)]) : 0.f;
+        c[3 * j + 1] = ok ? to_f32<rgb_dt(DT)>(C[3 * (i + j) + 1]) : 0.f;
+        c[3 * j + 2] = ok ? to_f32<rgb_dt(DT)>(C[3 * (i + j) + 2]) : 0.f;
       }
     }
   }
@@ -330,23 +336,24 @@ struct RawRun {
 
   __device__ __forceinline__ void decode(float (&sgf)[kRun], float (&c)[3 * kRun], float (&a)[kRun],
                                          float (&b)[kRun]) const {
-    auto unpack = [](const uint4* v, int nvec, float* out) {
+    auto unpack = [](const uint4* v, int nvec, float* out, auto kind) {
+      constexpr int K = decltype(kind)::value;
 #pragma unroll
       for (int q = 0; q < nvec; ++q) {
         const uint32_t w[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
-          if (DT == kF32) {
+          if (K == kF32) {
             out[4 * q + h] = __uint_as_float(w[h]);
           } else {
-            out[8 * q + 2 * h] = to_f32<DT>(static_cast<uint16_t>(w[h] & 0xffffu));
-            out[8 * q + 2 * h + 1] = to_f32<DT>(static_cast<uint16_t>(w[h] >> 16));
+            out[8 * q + 2 * h] = to_f32<K>(static_cast<uint16_t>(w[h] & 0xffffu));
+            out[8 * q + 2 * h + 1] = to_f32<K>(static_cast<uint16_t>(w[h] >> 16));
           }
         }
       }
     };
-    unpack(sg, kSigmaVec, sgf);
-    unpack(rgb, kRgbVec, c);
+    unpack(sg, kSigmaVec, sgf, std::integral_constant<int, sig_dt(DT)>{});
+    unpack(rgb, kRgbVec, c, std::integral_constant<int, rgb_dt(DT)>{});
 #pragma unroll
     for (int q = 0; q < kRun / 4; ++q) {
       a[4 * q] = t0[q].x; a[4 * q + 1] = t0[q].y; a[4 * q + 2] = t0[q].z; a[4 * q + 3] = t0[q].w;

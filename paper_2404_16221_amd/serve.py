@@ -77,7 +77,7 @@ class Server:
                  device: int = 0, dtype=torch.float16, merge_fp64: bool = False):
         L = _bind()
         self.cfg = XLServeConfig(hbm_budget_bytes, max_slots, max_queue, device,
-                                 _lib.DTYPES[dtype], int(merge_fp64), 0)
+                                 _lib.storage_code(*_lib.storage_dtypes(dtype)), int(merge_fp64), 0)
         h = _vp()
         _check(L.xl_serve_create(ctypes.byref(self.cfg), ctypes.byref(h)))
         self.h = h

@@ -38,18 +38,43 @@ class Dev:
     seg_ids: torch.Tensor
 
 
+# Mixed 16-bit storage: densities in bfloat16, colours in float16.
+BF16_F16 = (torch.bfloat16, torch.float16)
+
+
+def dtypes_of(dtype):
+    """(sigma dtype, rgb dtype) of a storage given as one dtype or a pair."""
+    return tuple(dtype) if isinstance(dtype, (tuple, list)) else (dtype, dtype)
+
+
+def storage_name(dtype):
+    s, c = dtypes_of(dtype)
+    return str(s)[6:] if s == c else f"{str(s)[6:]}-sigma/{str(c)[6:]}-rgb"
+
+
+def grad_ulps(dtype):
+    """Unit roundoff of the stored dsigma and drgb (None for float32)."""
+    u = {torch.bfloat16: 2.0 ** -8, torch.float16: 2.0 ** -11, torch.float32: None}
+    s, c = dtypes_of(dtype)
+    return u[s], u[c]
+
+
 def to_dev(b, dtype=torch.float32, device="cuda") -> Dev:
+    sdt, cdt = dtypes_of(dtype)
+
     def T(a, dt=None):
         t = torch.from_numpy(np.ascontiguousarray(a))
         return t.to(device=device, dtype=dt) if dt is not None else t.to(device)
-    return Dev(T(b.sigma, dtype), T(b.rgb, dtype), T(b.t_start), T(b.t_end), T(b.seg_offsets),
+    return Dev(T(b.sigma, sdt), T(b.rgb, cdt), T(b.t_start), T(b.t_end), T(b.seg_offsets),
                T(b.ray_offsets), T(b.seg_ids))
 
 
 def quantize(b, dtype):
-    """Host copies of sigma, rgb rounded to `dtype` (round to nearest even) and back."""
-    s = torch.from_numpy(b.sigma).to(dtype).to(torch.float32).numpy()
-    c = torch.from_numpy(b.rgb).to(dtype).to(torch.float32).numpy()
+    """Host copies of sigma, rgb rounded to their storage types (round to
+    nearest even) and back."""
+    sdt, cdt = dtypes_of(dtype)
+    s = torch.from_numpy(b.sigma).to(sdt).to(torch.float32).numpy()
+    c = torch.from_numpy(b.rgb).to(cdt).to(torch.float32).numpy()
     return s, c
 
 

@@ -23,7 +23,8 @@ from oracle import pool as OP
 from paper_2404_16221_amd import _lib as xl
 from paper_2404_16221_amd import synth
 from paper_2404_16221_amd.serve import Server, request
-from tests.parity import assert_grads, assert_tuples, quantize, sample_rays
+from tests.parity import (BF16_F16, assert_grads, assert_tuples, grad_ulps, quantize, sample_rays,
+                          storage_name)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.oracle_pool]
 
@@ -92,13 +93,13 @@ def compare(pool, w, got, rays, dtype, grad, what, host=None):
         return
     assert_grads(got["grad_seg"], ref["grad_seg"], label + " grad_seg")
     if dtype == torch.float32:
-        rtol, floor, nt = 1e-5, 1e-6, 1e-5
+        assert_grads(got["dsigma"], ref["dsigma"], label + " dsigma", 1e-5, 1e-6, 1e-5)
+        assert_grads(got["drgb"], ref["drgb"], label + " drgb", 1e-5, 1e-6, 1e-5)
     else:
-        # stored in the 16-bit type: judged against its rounding
-        rtol = 2.0 ** -8 if dtype == torch.bfloat16 else 2.0 ** -11
-        floor, nt = 1e-5, rtol
-    assert_grads(got["dsigma"], ref["dsigma"], label + " dsigma", rtol, floor, nt)
-    assert_grads(got["drgb"], ref["drgb"], label + " drgb", rtol, floor, nt)
+        # stored in the 16-bit types: judged against their rounding
+        us, uc = grad_ulps(dtype)
+        assert_grads(got["dsigma"], ref["dsigma"], label + " dsigma", us, 1e-5, us)
+        assert_grads(got["drgb"], ref["drgb"], label + " drgb", uc, 1e-5, uc)
 
 
 def test_k8_all_rays(oracle_pool):
@@ -113,7 +114,7 @@ def test_k8_all_rays(oracle_pool):
     compare(oracle_pool, w, got, rays, torch.float32, grad.astype(np.float64), "k8 FP32")
 
 
-@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16, BF16_F16], ids=storage_name)
 def test_k16_training_batch_full_size(oracle_pool, dtype):
     """All 262,144 rays launched at once; 16,384 seeded rays against the oracle."""
     w = synth.WORKLOADS[2]
@@ -125,7 +126,7 @@ def test_k16_training_batch_full_size(oracle_pool, dtype):
     got = gather(res, device_layout(g), rays)
     del res, g
     compare(oracle_pool, w, got, rays, dtype, grad[:, rays].astype(np.float64),
-            f"k16 {str(dtype)[6:]}")
+            f"k16 {storage_name(dtype)}")
 
 
 def test_k16_partitioned_equals_plain_full_size():
@@ -157,12 +158,13 @@ def test_k64_chunk_bf16_fp64_merge(oracle_pool, chunk):
             f"k64 chunk {chunk} bf16 fp64-merge")
 
 
-def test_k64_all_rays_one_launch_bf16_fp64_merge(oracle_pool):
+@pytest.mark.parametrize("dtype", [torch.bfloat16, BF16_F16], ids=storage_name)
+def test_k64_all_rays_one_launch_fp64_merge(oracle_pool, dtype):
     """The large partition as the benchmark runs it: all 4,194,304 rays in one
     launch of each kernel (about 1.1G samples).  Compared: 16,384 seeded rays
     and up to 2,048 rays with more than eight segments."""
     w = synth.WORKLOADS[4]
-    g = xl.xl_gen(w, torch.bfloat16)
+    g = xl.xl_gen(w, dtype)
     say(f"k64 all rays: {g['sigma'].shape[0]} samples, {g['seg_ids'].shape[0]} segments")
     grad = np.random.default_rng(44).normal(size=(7, w.n_rays)).astype(np.float32)
     res = run(g, torch.from_numpy(grad).cuda(), fp64=True)
@@ -176,8 +178,8 @@ def test_k64_all_rays_one_launch_bf16_fp64_merge(oracle_pool):
     rays = np.union1d(sample_rays(w.n_rays, 16384, 45), long_rays)
     got = gather(res, layout, rays)
     del res, g
-    compare(oracle_pool, w, got, rays, torch.bfloat16, grad[:, rays].astype(np.float64),
-            "k64 all rays bf16 fp64-merge")
+    compare(oracle_pool, w, got, rays, dtype, grad[:, rays].astype(np.float64),
+            f"k64 all rays {storage_name(dtype)} fp64-merge")
 
 
 def test_k32_served_view_1280x720(oracle_pool):

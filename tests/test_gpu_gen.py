@@ -21,11 +21,12 @@ def test_device_generator_matches_host(cfg, ray0, n_rays):
         assert np.array_equal(d[k], a), k
 
 
-@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16])
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16, xl.BF16_F16], ids=str)
 def test_device_generator_storage_rounding(dtype):
     w = synth.WORKLOADS[1]
     h = synth.generate(w, rays=np.arange(500))
     d = xl.xl_gen(w, dtype, 0, 500)
-    ref_rgb = torch.from_numpy(h.rgb).to(dtype)
-    assert torch.equal(d["rgb"].cpu(), ref_rgb)
-    assert torch.equal(d["sigma"].cpu(), torch.from_numpy(h.sigma).to(dtype))
+    sdt, cdt = xl.storage_dtypes(dtype)
+    assert d["sigma"].dtype == sdt and d["rgb"].dtype == cdt
+    assert torch.equal(d["rgb"].cpu(), torch.from_numpy(h.rgb).to(cdt))
+    assert torch.equal(d["sigma"].cpu(), torch.from_numpy(h.sigma).to(sdt))

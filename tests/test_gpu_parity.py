@@ -10,8 +10,8 @@ from oracle import render as O
 from paper_2404_16221_amd import _lib as xl
 from paper_2404_16221_amd import synth
 from paper_2404_16221_amd.autograd import render
-from tests.parity import (Dev, assert_grads, assert_tuples, quantize, sample_rays, to_dev,
-                          tuple_report)
+from tests.parity import (BF16_F16, Dev, assert_grads, assert_tuples, grad_ulps, quantize,
+                          sample_rays, storage_name, to_dev, tuple_report)
 
 pytestmark = pytest.mark.gpu
 
@@ -134,7 +134,7 @@ def test_k16_forward_backward_medium():
 
 
 # ------------------------------------------------------------------ 16-bit storage
-@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16])
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16, BF16_F16], ids=storage_name)
 def test_16bit_storage(dtype):
     b = gen(2, n_rays=16384)
     d = to_dev(b, dtype)
@@ -155,12 +155,12 @@ def test_16bit_storage(dtype):
         dq[0], dq[1], b.t_start, b.t_end, b.seg_offsets, b.ray_offsets, b.seg_ids,
         grad_ray[:, rays[:200]], rays[:200])
     assert_grads(gseg.cpu().numpy()[:, segs], g_seg_ref, "16-bit grad_seg")
-    # gradients are stored in the 16-bit type: judge them against its rounding
-    ulp = 2.0 ** -8 if dtype == torch.bfloat16 else 2.0 ** -11
-    assert_grads(gs.float().cpu().numpy()[idx], ds_ref, "16-bit dsigma", rtol=ulp, floor=1e-5,
-                 norm_tol=ulp)
-    assert_grads(gc.float().cpu().numpy()[idx], dc_ref, "16-bit drgb", rtol=ulp, floor=1e-5,
-                 norm_tol=ulp)
+    # gradients are stored in the 16-bit types: judge them against their rounding
+    us, uc = grad_ulps(dtype)
+    assert_grads(gs.float().cpu().numpy()[idx], ds_ref, "16-bit dsigma", rtol=us, floor=1e-5,
+                 norm_tol=us)
+    assert_grads(gc.float().cpu().numpy()[idx], dc_ref, "16-bit drgb", rtol=uc, floor=1e-5,
+                 norm_tol=uc)
 
 
 # ------------------------------------------------------------------ edge cases
