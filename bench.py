@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # Sources that define the segment kernels; HBM traffic measured with rocprofv3
 # counters is reported only while these are unchanged.
 KERNEL_SOURCES = ("paper_2404_16221_amd/csrc/segments.hip", "paper_2404_16221_amd/csrc/xl_device.hpp")
-TRAFFIC_PROFILE = "profiles/seg_bwd_kernel_k16-262144r_bf16_traffic.md"
+TRAFFIC_PROFILE = "profiles/seg_bwd_kernel_k16-262144r_bf16f16_traffic.md"
 
 
 def kernel_source_hash() -> str:
