@@ -69,10 +69,11 @@ extern "C" {
 #define XL_BF16_F16 3
 
 /* xl_merge_* flags. */
-#define XL_MERGE_FP64 1 /* cross-segment prefix sums and products in float64 */
+#define XL_MERGE_FP64 1   /* the running optical depth in float64 */
+#define XL_MERGE_STAGED 2 /* with region_offsets: the LDS-staged form at any size */
 
 typedef struct xl_samples {
-  int32_t dtype;        /* XL_F32, XL_BF16 or XL_F16 */
+  int32_t dtype;        /* XL_F32, XL_BF16, XL_F16 or XL_BF16_F16 */
   const void* sigma;    /* device [n] densities */
   const void* rgb;      /* device [n][3] colours */
   const float* t_start; /* device [n] interval starts */
@@ -147,20 +148,40 @@ int xl_render_segments_bwd(const xl_samples* s, const int64_t* seg_offsets, int6
 /*
  * Merge of segment tuples in ray order (Eq. 3-8; Alg. 1 and 2 of App. A.2
  * with Eq. 7's factor 2 and each segment's own A, D in the cross term).
- *   seg_out      device float32 [7][n_seg] from xl_render_segments_fwd
- *   ray_offsets  device int64 [n_rays + 1]; ray r's segments are
- *                seg_ids[ray_offsets[r] .. ray_offsets[r+1]) front to back
- *                (the paper's ordered index list I)
- *   seg_ids      device int64, values in [0, n_seg); ids outside are
- *                skipped (identities); each segment is listed at most once
- *   ray_out      device float32 [7][n_rays], written
- *   flags        0 or XL_MERGE_FP64 (the running optical depth, i.e. the
- *                cross-segment transmittance product, in float64; the other
- *                fields fold in float32 either way)
+ *   seg_out         device float32 [7][n_seg] from xl_render_segments_fwd
+ *   region_offsets  device int64 [n_regions + 1] or NULL: region k's tuples
+ *                   are seg_out[:, region_offsets[k] .. region_offsets[k+1])
+ *                   (the sample layout packs each region's segments in ray
+ *                   order, so consecutive rays list consecutive tuples of
+ *                   each region).  Given (1 <= n_regions <= 256) and from
+ *                   4,194,304 segments up (at any size with
+ *                   XL_MERGE_STAGED), each workgroup of 256 rays moves its
+ *                   rays' tuples into LDS run by run with contiguous loads
+ *                   (and the gradients back with contiguous stores) before
+ *                   folding.  Otherwise, and for a workgroup whose ids do not
+ *                   form one contiguous run per region (or that lists more
+ *                   than 1,280 ids, or, backward, has a ray of more than 64
+ *                   segments), every ray gathers its own tuples: below that
+ *                   size the tuples stay in the caches and gathering is
+ *                   faster.  The result is the same either way.
+ *   n_regions       entries of region_offsets minus one (ignored if NULL)
+ *   ray_offsets     device int64 [n_rays + 1]; ray r's segments are
+ *                   seg_ids[ray_offsets[r] .. ray_offsets[r+1]) front to back
+ *                   (the paper's ordered index list I)
+ *   seg_ids         device int64 [n_seg], values in [0, n_seg); ids outside
+ *                   are skipped (identities); each segment is listed at most
+ *                   once
+ *   ray_out         device float32 [7][n_rays], written
+ *   flags           XL_MERGE_FP64 (the running optical depth, i.e. the
+ *                   cross-segment transmittance product, in float64; the
+ *                   other fields fold in float32 either way) and/or
+ *                   XL_MERGE_STAGED
+ * Errors: XL_EINVAL for negative counts, unknown flags, NULL arrays, or
+ * region_offsets given with n_regions < 1.
  */
-int xl_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
-                 const int64_t* seg_ids, int64_t n_rays, float* ray_out, int32_t flags,
-                 void* stream);
+int xl_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* region_offsets,
+                 int32_t n_regions, const int64_t* ray_offsets, const int64_t* seg_ids,
+                 int64_t n_rays, float* ray_out, int32_t flags, void* stream);
 
 /*
  * Merge, backward: grad_ray = dl/d(T, r, g, b, A, D, L) (device float32
@@ -169,11 +190,13 @@ int xl_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets
  * segments that no ray lists are left untouched).  Each segment is listed by
  * at most one ray.  Exclusive prefix and suffix folds per ray; the paper's
  * rule that each region differentiates only through its own tuple (Sec. 4.2,
- * App. A.2) is exactly this per-segment Jacobian.
+ * App. A.2) is exactly this per-segment Jacobian.  Arguments as for the
+ * forward.
  */
-int xl_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
-                 const int64_t* seg_ids, int64_t n_rays, const float* grad_ray,
-                 float* grad_seg, int32_t flags, void* stream);
+int xl_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* region_offsets,
+                 int32_t n_regions, const int64_t* ray_offsets, const int64_t* seg_ids,
+                 int64_t n_rays, const float* grad_ray, float* grad_seg, int32_t flags,
+                 void* stream);
 
 /*
  * Input validation (synchronous; for debugging and tests).  Checks on the
@@ -218,12 +241,15 @@ int xl_gen_plan(const xl_gen_params* p, void* workspace, size_t workspace_bytes,
                 int64_t* n_samples, int64_t* n_seg, void* stream);
 
 /* Phase 2 (asynchronous): samples in storage type `dtype` and the CSR arrays
- * (seg_offsets [n_seg+1], ray_offsets [n_rays+1], seg_ids [n_seg]; any of the
- * three may be NULL) from the workspace filled by xl_gen_plan with the same
+ * (seg_offsets [n_seg+1], ray_offsets [n_rays+1], seg_ids [n_seg]) and
+ * region_offsets [K+1] (K = grid[0]*grid[1]*grid[2]: the first segment of
+ * each region, then n_seg; the merge's region boundaries), any of the four
+ * may be NULL, from the workspace filled by xl_gen_plan with the same
  * parameters. */
 int xl_gen_fill(const xl_gen_params* p, int32_t dtype, void* workspace, size_t workspace_bytes,
                 int64_t n_seg, void* sigma, void* rgb, float* t_start, float* t_end,
-                int64_t* seg_offsets, int64_t* ray_offsets, int64_t* seg_ids, void* stream);
+                int64_t* seg_offsets, int64_t* ray_offsets, int64_t* seg_ids,
+                int64_t* region_offsets, void* stream);
 
 /*
  * Spatial partitioning (Sec. 4.4, App. A.3), on the host.  Splits space
@@ -442,7 +468,7 @@ typedef struct xl_serve_config {
   int32_t max_slots;         /* requests processed concurrently (>= 1) */
   int32_t max_queue;         /* requests waiting for a slot; XL_EAGAIN beyond */
   int32_t device;            /* HIP device ordinal */
-  int32_t dtype;             /* sample storage: XL_F32, XL_BF16, XL_F16 */
+  int32_t dtype;             /* sample storage: XL_F32, XL_BF16, XL_F16, XL_BF16_F16 */
   int32_t merge_fp64;        /* 1: merge with XL_MERGE_FP64 */
   int32_t reserved;
 } xl_serve_config;

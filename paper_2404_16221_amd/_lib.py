@@ -20,6 +20,7 @@ XL_OK, XL_PENDING = 0, 1
 XL_EINVAL, XL_ENOMEM, XL_EHIP, XL_EAGAIN, XL_EFAULT = -1, -2, -3, -4, -5
 XL_F32, XL_BF16, XL_F16 = 0, 1, 2
 XL_MERGE_FP64 = 1
+XL_MERGE_STAGED = 2
 DTYPES = {torch.float32: XL_F32, torch.bfloat16: XL_BF16, torch.float16: XL_F16}
 XL_BF16_F16 = 3
 # Mixed 16-bit storage: sigma in bfloat16, rgb in float16.
@@ -95,14 +96,14 @@ SIGNATURES = {
     "xl_render_segments_fwd_static": (_c.c_int, [_c.POINTER(XLSamples), _vp, _i64, _vp, _vp]),
     "xl_render_segments_bwd": (_c.c_int, [_c.POINTER(XLSamples), _vp, _i64, _vp, _sz, _vp, _vp,
                                           _vp, _vp]),
-    "xl_merge_fwd": (_c.c_int, [_vp, _i64, _vp, _vp, _i64, _vp, _i32, _vp]),
-    "xl_merge_bwd": (_c.c_int, [_vp, _i64, _vp, _vp, _i64, _vp, _vp, _i32, _vp]),
+    "xl_merge_fwd": (_c.c_int, [_vp, _i64, _vp, _i32, _vp, _vp, _i64, _vp, _i32, _vp]),
+    "xl_merge_bwd": (_c.c_int, [_vp, _i64, _vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _vp]),
     "xl_check_inputs": (_c.c_int, [_c.POINTER(XLSamples), _vp, _i64, _vp, _vp, _i64, _vp]),
     "xl_gen_workspace_bytes": (_sz, [_c.POINTER(XLGenParams)]),
     "xl_gen_plan": (_c.c_int, [_c.POINTER(XLGenParams), _vp, _sz, _c.POINTER(_i64),
                                _c.POINTER(_i64), _vp]),
     "xl_gen_fill": (_c.c_int, [_c.POINTER(XLGenParams), _i32, _vp, _sz, _i64, _vp, _vp, _vp, _vp,
-                               _vp, _vp, _vp, _vp]),
+                               _vp, _vp, _vp, _vp, _vp]),
     "xl_partition_build": (_c.c_int, [_vp, _i64, _i32, _vp, _vp]),
     "xl_render_features_fwd": (_c.c_int, [_c.POINTER(XLFeatures), _vp, _i64, _vp, _vp, _vp]),
     "xl_merge_features_fwd": (_c.c_int, [_vp, _vp, _i32, _i64, _vp, _vp, _i64, _vp, _vp]),
@@ -229,23 +230,38 @@ def _check_ids(seg_out, seg_ids):
         raise ValueError("seg_ids must list every segment once: shape (n_seg,)")
 
 
-def xl_merge_fwd(seg_out, ray_offsets, seg_ids, ray_out=None, fp64: bool = False) -> torch.Tensor:
-    """ray_out[7, n_rays] = (T, r, g, b, A, D, L)."""
+def _regions(region_offsets):
+    """(pointer, n_regions) of optional region boundaries [K + 1]."""
+    if region_offsets is None:
+        return None, 0
+    return _dev(region_offsets, "region_offsets", torch.int64), region_offsets.shape[0] - 1
+
+
+def _merge_flags(fp64, staged):
+    return (XL_MERGE_FP64 if fp64 else 0) | (XL_MERGE_STAGED if staged else 0)
+
+
+def xl_merge_fwd(seg_out, ray_offsets, seg_ids, ray_out=None, fp64: bool = False,
+                 region_offsets=None, staged: bool = False) -> torch.Tensor:
+    """ray_out[7, n_rays] = (T, r, g, b, A, D, L).  region_offsets [K + 1]
+    (optional): the tuples' region boundaries, for the LDS-staged form (used
+    from 4M segments up, or at any size with staged=True)."""
     _check_ids(seg_out, seg_ids)
     n_seg = seg_out.shape[1]
     n_rays = ray_offsets.shape[0] - 1
     if ray_out is None:
         ray_out = torch.empty((TUPLE, n_rays), dtype=torch.float32, device=seg_out.device)
     _check(lib().xl_merge_fwd(_dev(seg_out, "seg_out", torch.float32), n_seg,
+                              *_regions(region_offsets),
                               _dev(ray_offsets, "ray_offsets", torch.int64),
                               _dev(seg_ids, "seg_ids", torch.int64), n_rays,
                               _dev(ray_out, "ray_out", torch.float32),
-                              XL_MERGE_FP64 if fp64 else 0, _stream()))
+                              _merge_flags(fp64, staged), _stream()))
     return ray_out
 
 
 def xl_merge_bwd(seg_out, ray_offsets, seg_ids, grad_ray, grad_seg=None,
-                 fp64: bool = False) -> torch.Tensor:
+                 fp64: bool = False, region_offsets=None, staged: bool = False) -> torch.Tensor:
     """grad_seg[7, n_seg] = dl/d(tau, r, g, b, A, D, L) of each listed segment."""
     _check_ids(seg_out, seg_ids)
     n_seg = seg_out.shape[1]
@@ -253,11 +269,12 @@ def xl_merge_bwd(seg_out, ray_offsets, seg_ids, grad_ray, grad_seg=None,
     if grad_seg is None:
         grad_seg = torch.zeros((TUPLE, n_seg), dtype=torch.float32, device=seg_out.device)
     _check(lib().xl_merge_bwd(_dev(seg_out, "seg_out", torch.float32), n_seg,
+                              *_regions(region_offsets),
                               _dev(ray_offsets, "ray_offsets", torch.int64),
                               _dev(seg_ids, "seg_ids", torch.int64), n_rays,
                               _dev(grad_ray, "grad_ray", torch.float32),
                               _dev(grad_seg, "grad_seg", torch.float32),
-                              XL_MERGE_FP64 if fp64 else 0, _stream()))
+                              _merge_flags(fp64, staged), _stream()))
     return grad_seg
 
 
@@ -286,7 +303,7 @@ def xl_gen(w, dtype=torch.float32, ray0: int = 0, n_rays: Optional[int] = None,
 
     dtype: a torch dtype for both sigma and rgb, or the pair BF16_F16.
     Returns device tensors sigma, rgb (storage dtypes), t_start, t_end,
-    seg_offsets, ray_offsets, seg_ids."""
+    seg_offsets, ray_offsets, seg_ids, region_offsets."""
     p = gen_params(w, ray0, n_rays)
     L = lib()
     wsb = L.xl_gen_workspace_bytes(ctypes.byref(p))
@@ -302,12 +319,15 @@ def xl_gen(w, dtype=torch.float32, ray0: int = 0, n_rays: Optional[int] = None,
                t_end=torch.empty(n, dtype=torch.float32, device=device),
                seg_offsets=torch.empty(n_seg + 1, dtype=torch.int64, device=device),
                ray_offsets=torch.empty(p.n_rays + 1, dtype=torch.int64, device=device),
-               seg_ids=torch.empty(n_seg, dtype=torch.int64, device=device))
+               seg_ids=torch.empty(n_seg, dtype=torch.int64, device=device),
+               region_offsets=torch.empty(w.grid[0] * w.grid[1] * w.grid[2] + 1, dtype=torch.int64,
+                                          device=device))
     _check(L.xl_gen_fill(ctypes.byref(p), storage_code(sdt, cdt), ws.data_ptr(), wsb, n_seg,
                          _dev(out["sigma"], "sigma"), _dev(out["rgb"], "rgb"),
                          _dev(out["t_start"], "t_start"), _dev(out["t_end"], "t_end"),
                          _dev(out["seg_offsets"], "seg_offsets"), _dev(out["ray_offsets"], "ray_offsets"),
-                         _dev(out["seg_ids"], "seg_ids"), _stream()))
+                         _dev(out["seg_ids"], "seg_ids"),
+                         _dev(out["region_offsets"], "region_offsets"), _stream()))
     return out
 
 

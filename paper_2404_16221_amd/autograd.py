@@ -23,26 +23,34 @@ from . import _lib
 
 class XLRender(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, sigma, rgb, t_start, t_end, seg_offsets, ray_offsets, seg_ids, fp64=False):
+    def forward(ctx, sigma, rgb, t_start, t_end, seg_offsets, ray_offsets, seg_ids, fp64=False,
+                region_offsets=None):
         seg_out, ws = _lib.xl_render_segments_fwd(sigma, rgb, t_start, t_end, seg_offsets)
-        ray_out = _lib.xl_merge_fwd(seg_out, ray_offsets, seg_ids, fp64=fp64)
+        ray_out = _lib.xl_merge_fwd(seg_out, ray_offsets, seg_ids, fp64=fp64,
+                                    region_offsets=region_offsets)
         ctx.save_for_backward(sigma, rgb, t_start, t_end, seg_offsets, ray_offsets, seg_ids,
                               seg_out, ws)
         ctx.fp64 = fp64
+        ctx.region_offsets = region_offsets
         return ray_out
 
     @staticmethod
     def backward(ctx, grad_ray):
         sigma, rgb, t_start, t_end, seg_offsets, ray_offsets, seg_ids, seg_out, ws = ctx.saved_tensors
         grad_ray = grad_ray.to(torch.float32).contiguous()
-        grad_seg = _lib.xl_merge_bwd(seg_out, ray_offsets, seg_ids, grad_ray, fp64=ctx.fp64)
+        grad_seg = _lib.xl_merge_bwd(seg_out, ray_offsets, seg_ids, grad_ray, fp64=ctx.fp64,
+                                     region_offsets=ctx.region_offsets)
         gs, gc = _lib.xl_render_segments_bwd(sigma, rgb, t_start, t_end, seg_offsets, ws, grad_seg)
-        return gs, gc, None, None, None, None, None, None
+        return gs, gc, None, None, None, None, None, None, None
 
 
-def render(sigma, rgb, t_start, t_end, seg_offsets, ray_offsets, seg_ids, fp64=False):
-    """ray tuple [7, n_rays] = (T, r, g, b, A, D, L), differentiable in sigma and rgb."""
-    return XLRender.apply(sigma, rgb, t_start, t_end, seg_offsets, ray_offsets, seg_ids, fp64)
+def render(sigma, rgb, t_start, t_end, seg_offsets, ray_offsets, seg_ids, fp64=False,
+           region_offsets=None):
+    """ray tuple [7, n_rays] = (T, r, g, b, A, D, L), differentiable in sigma and rgb.
+    region_offsets [K + 1] (optional): the segments' region boundaries, which
+    let the merge stage each workgroup's tuples through LDS."""
+    return XLRender.apply(sigma, rgb, t_start, t_end, seg_offsets, ray_offsets, seg_ids, fp64,
+                          region_offsets)
 
 
 class XLFeatures(torch.autograd.Function):

@@ -149,37 +149,47 @@ int xl_render_segments_bwd(const xl_samples* s, const int64_t* seg_offsets, int6
                     "xl_render_segments_bwd launch");
 }
 
-static int check_merge_args(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
-                            const int64_t* seg_ids, int64_t n_rays, int32_t flags) {
+static int check_merge_args(const float* seg_out, int64_t n_seg, const int64_t* region_offsets,
+                            int32_t n_regions, const int64_t* ray_offsets, const int64_t* seg_ids,
+                            int64_t n_rays, int32_t flags) {
   if (n_seg < 0 || n_rays < 0) return fail(XL_EINVAL, "negative count");
-  if (flags & ~XL_MERGE_FP64) return fail(XL_EINVAL, "unknown merge flags 0x%x", flags);
+  if (flags & ~(XL_MERGE_FP64 | XL_MERGE_STAGED))
+    return fail(XL_EINVAL, "unknown merge flags 0x%x", flags);
   if (n_rays > 0 && ray_offsets == nullptr) return fail(XL_EINVAL, "ray_offsets is NULL");
   if (n_seg > 0 && (seg_out == nullptr || seg_ids == nullptr))
     return fail(XL_EINVAL, "seg_out or seg_ids is NULL");
+  if (region_offsets != nullptr && n_regions < 1)
+    return fail(XL_EINVAL, "n_regions %d with region_offsets given", n_regions);
   return XL_OK;
 }
 
-int xl_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
-                 const int64_t* seg_ids, int64_t n_rays, float* ray_out, int32_t flags,
-                 void* stream) {
-  int rc = check_merge_args(seg_out, n_seg, ray_offsets, seg_ids, n_rays, flags);
+int xl_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* region_offsets,
+                 int32_t n_regions, const int64_t* ray_offsets, const int64_t* seg_ids,
+                 int64_t n_rays, float* ray_out, int32_t flags, void* stream) {
+  int rc = check_merge_args(seg_out, n_seg, region_offsets, n_regions, ray_offsets, seg_ids,
+                            n_rays, flags);
   if (rc) return rc;
   if (n_rays > 0 && ray_out == nullptr) return fail(XL_EINVAL, "ray_out is NULL");
-  return hip_status(xl::launch_merge_fwd(seg_out, n_seg, ray_offsets, seg_ids, n_rays, ray_out,
-                                         (flags & XL_MERGE_FP64) != 0,
+  return hip_status(xl::launch_merge_fwd(seg_out, n_seg, region_offsets, n_regions, ray_offsets,
+                                         seg_ids, n_rays, ray_out, (flags & XL_MERGE_FP64) != 0,
+                                         (flags & XL_MERGE_STAGED) != 0,
                                          static_cast<hipStream_t>(stream)),
                     "xl_merge_fwd launch");
 }
 
-int xl_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
-                 const int64_t* seg_ids, int64_t n_rays, const float* grad_ray, float* grad_seg,
-                 int32_t flags, void* stream) {
-  int rc = check_merge_args(seg_out, n_seg, ray_offsets, seg_ids, n_rays, flags);
+int xl_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* region_offsets,
+                 int32_t n_regions, const int64_t* ray_offsets, const int64_t* seg_ids,
+                 int64_t n_rays, const float* grad_ray, float* grad_seg, int32_t flags,
+                 void* stream) {
+  int rc = check_merge_args(seg_out, n_seg, region_offsets, n_regions, ray_offsets, seg_ids,
+                            n_rays, flags);
   if (rc) return rc;
   if (n_rays > 0 && (grad_ray == nullptr || (n_seg > 0 && grad_seg == nullptr)))
     return fail(XL_EINVAL, "grad_ray or grad_seg is NULL");
-  return hip_status(xl::launch_merge_bwd(seg_out, n_seg, ray_offsets, seg_ids, n_rays, grad_ray,
-                                         grad_seg, (flags & XL_MERGE_FP64) != 0,
+  return hip_status(xl::launch_merge_bwd(seg_out, n_seg, region_offsets, n_regions, ray_offsets,
+                                         seg_ids, n_rays, grad_ray, grad_seg,
+                                         (flags & XL_MERGE_FP64) != 0,
+                                         (flags & XL_MERGE_STAGED) != 0,
                                          static_cast<hipStream_t>(stream)),
                     "xl_merge_bwd launch");
 }
@@ -252,7 +262,8 @@ int xl_gen_plan(const xl_gen_params* p, void* workspace, size_t workspace_bytes,
 
 int xl_gen_fill(const xl_gen_params* p, int32_t dtype, void* workspace, size_t workspace_bytes,
                 int64_t n_seg, void* sigma, void* rgb, float* t_start, float* t_end,
-                int64_t* seg_offsets, int64_t* ray_offsets, int64_t* seg_ids, void* stream) {
+                int64_t* seg_offsets, int64_t* ray_offsets, int64_t* seg_ids,
+                int64_t* region_offsets, void* stream) {
   int rc = check_gen(p);
   if (rc) return rc;
   if (dtype != XL_F32 && dtype != XL_BF16 && dtype != XL_F16 && dtype != XL_BF16_F16)
@@ -263,7 +274,8 @@ int xl_gen_fill(const xl_gen_params* p, int32_t dtype, void* workspace, size_t w
   if (p->n_rays > 0 && (!sigma || !rgb || !t_start || !t_end))
     return fail(XL_EINVAL, "NULL sample array");
   return hip_status(xl::gen_fill(p, dtype, workspace, n_seg, sigma, rgb, t_start, t_end, seg_offsets,
-                                 ray_offsets, seg_ids, static_cast<hipStream_t>(stream)),
+                                 ray_offsets, seg_ids, region_offsets,
+                                 static_cast<hipStream_t>(stream)),
                     "xl_gen_fill");
 }
 

@@ -153,6 +153,29 @@ __global__ __launch_bounds__(kFeatBlock) void feat_fwd_kernel(FeatDev s, const i
   if (tau_seg && lane == 0) tau_seg[k] = before;
 }
 
+// A ray's id range, clamped to the id array [0, n_seg) (a malformed offset
+// array gives empty or shortened rays, never reads outside it).
+__device__ __forceinline__ void ray_range(const int64_t* __restrict__ ro, int64_t r, int64_t n_seg,
+                                          int64_t& q0, int64_t& q1) {
+  q0 = ro[r];
+  q1 = ro[r + 1];
+  q0 = q0 < 0 ? 0 : (q0 > n_seg ? n_seg : q0);
+  q1 = q1 < q0 ? q0 : (q1 > n_seg ? n_seg : q1);
+}
+
+// Running optical depth in front of a segment as a compensated pair (TwoSum),
+// so that a ray's log-transmittance keeps its relative accuracy however many
+// segments it crosses.
+struct DepthSum {
+  float hi = 0.f, lo = 0.f;
+  __device__ __forceinline__ void add(float x) {
+    float e;
+    hi = two_sum(hi, x, e);
+    lo += e;
+  }
+  __device__ __forceinline__ float value() const { return hi + lo; }
+};
+
 template <int F>
 __global__ void feat_merge_fwd_kernel(const float* __restrict__ tau_seg, const float* __restrict__ phi,
                                       int64_t n_seg, const int64_t* __restrict__ ray_offsets,
@@ -163,13 +186,16 @@ __global__ void feat_merge_fwd_kernel(const float* __restrict__ tau_seg, const f
   float acc[F];
 #pragma unroll
   for (int c = 0; c < F; ++c) acc[c] = 0.f;
-  float before = 0.f;
-  for (int64_t q = ray_offsets[r]; q < ray_offsets[r + 1]; ++q) {
+  int64_t q0, q1;
+  ray_range(ray_offsets, r, n_seg, q0, q1);
+  DepthSum before;
+  for (int64_t q = q0; q < q1; ++q) {
     const int64_t sg = seg_ids[q];
-    const float T = exp_neg(before);
+    if (sg < 0 || sg >= n_seg) continue;  // invalid ids are identities
+    const float T = exp_neg(before.value());
 #pragma unroll
     for (int c = 0; c < F; ++c) acc[c] = fmaf(T, phi[c * n_seg + sg], acc[c]);
-    before += tau_seg[sg];
+    before.add(tau_seg[sg]);
   }
 #pragma unroll
   for (int c = 0; c < F; ++c) out[c * n_rays + r] = acc[c];
@@ -189,19 +215,23 @@ __global__ void feat_merge_bwd_kernel(const float* __restrict__ tau_seg, const f
   float g[F];
 #pragma unroll
   for (int c = 0; c < F; ++c) g[c] = grad_ray[c * n_rays + r];
-  const int64_t q0 = ray_offsets[r], q1 = ray_offsets[r + 1];
-  float before = 0.f;
+  int64_t q0, q1;
+  ray_range(ray_offsets, r, n_seg, q0, q1);
+  DepthSum before;
   for (int64_t q = q0; q < q1; ++q) {
     const int64_t sg = seg_ids[q];
-    const float T = exp_neg(before);
+    if (sg < 0 || sg >= n_seg) continue;
+    const float d = before.value();
+    const float T = exp_neg(d);
 #pragma unroll
     for (int c = 0; c < F; ++c) gphi[c * n_seg + sg] = T * g[c];
-    gtau[sg] = before;
-    before += tau_seg[sg];
+    gtau[sg] = d;
+    before.add(tau_seg[sg]);
   }
   float later = 0.f;  // sum over later segments of T_{<k'} (g . Phi_k')
   for (int64_t q = q1 - 1; q >= q0; --q) {
     const int64_t sg = seg_ids[q];
+    if (sg < 0 || sg >= n_seg) continue;
     const float T = exp_neg(gtau[sg]);
     float dot = 0.f;
 #pragma unroll

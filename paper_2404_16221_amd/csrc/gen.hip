@@ -681,9 +681,21 @@ hipError_t gen_plan(const xl_gen_params* p, void* ws, hipStream_t st, int64_t* n
   return hipSuccess;
 }
 
+__global__ void fill_zero_i64_kernel(int64_t* __restrict__ p, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// First segment of every region (box-major block bases of block 0), and n_seg.
+__global__ void region_offsets_kernel(const int64_t* __restrict__ blk_base, int64_t nblk, int K,
+                                      int64_t* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b <= K) out[b] = blk_base[b * nblk];
+}
+
 hipError_t gen_fill(const xl_gen_params* p, int dtype, void* ws, int64_t n_seg, void* sigma, void* rgb,
                     float* t_start, float* t_end, int64_t* seg_offsets, int64_t* ray_offsets,
-                    int64_t* seg_ids, hipStream_t st) {
+                    int64_t* seg_ids, int64_t* region_offsets, hipStream_t st) {
   const GenLayout L = layout(p);
   const GenWs w = views(L, ws);
   const GenDev g = dev_params(p, L);
@@ -714,6 +726,18 @@ hipError_t gen_fill(const xl_gen_params* p, int dtype, void* ws, int64_t n_seg, 
   if (seg_ids && (e = hipMemcpyAsync(seg_ids, w.seg_ids, sizeof(int64_t) * n_seg,
                                      hipMemcpyDeviceToDevice, st)) != hipSuccess)
     return e;
+  if (region_offsets) {
+    if (L.nblk > 0) {
+      hipLaunchKernelGGL(region_offsets_kernel, dim3(blocks(L.K + 1, 256)), dim3(256), 0, st,
+                         w.blk_base, L.nblk, static_cast<int>(L.K), region_offsets);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+      // no rays: every region is empty (a small fill kernel, no memset node)
+      hipLaunchKernelGGL(fill_zero_i64_kernel, dim3(blocks(L.K + 1, 256)), dim3(256), 0, st,
+                         region_offsets, L.K + 1);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
   return hipSuccess;
 }
 

@@ -29,12 +29,17 @@ hipError_t static_scratch(void** ptr);
 hipError_t launch_segments_bwd(const SamplesDev& s, const int64_t* seg_offsets, int64_t n_seg,
                                const void* workspace, const float* grad_seg, void* grad_sigma,
                                void* grad_rgb, hipStream_t stream);
-hipError_t launch_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
-                            const int64_t* seg_ids, int64_t n_rays, float* ray_out, bool fp64,
+// region_offsets (n_regions + 1 entries) may be NULL: then the tuples are
+// gathered per ray; otherwise staged per workgroup through LDS from 4M
+// segments up, or at any size with `staged` (merge.hip).
+hipError_t launch_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* region_offsets,
+                            int n_regions, const int64_t* ray_offsets, const int64_t* seg_ids,
+                            int64_t n_rays, float* ray_out, bool fp64, bool staged,
                             hipStream_t stream);
-hipError_t launch_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* ray_offsets,
-                            const int64_t* seg_ids, int64_t n_rays, const float* grad_ray,
-                            float* grad_seg, bool fp64, hipStream_t stream);
+hipError_t launch_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* region_offsets,
+                            int n_regions, const int64_t* ray_offsets, const int64_t* seg_ids,
+                            int64_t n_rays, const float* grad_ray, float* grad_seg, bool fp64,
+                            bool staged, hipStream_t stream);
 // Device-side input checks; writes the number of the first failed check (0 =
 // none) to *code_dev.
 hipError_t launch_check(const SamplesDev& s, const int64_t* seg_offsets, int64_t n_seg,
@@ -52,7 +57,8 @@ hipError_t gen_plan(const xl_gen_params* p, void* ws, hipStream_t st, int64_t* n
                     int64_t* n_seg, int* overflow, int64_t* pinned = nullptr);
 hipError_t gen_fill(const xl_gen_params* p, int dtype, void* ws, int64_t n_seg, void* sigma,
                     void* rgb, float* t_start, float* t_end, int64_t* seg_offsets,
-                    int64_t* ray_offsets, int64_t* seg_ids, hipStream_t st);
+                    int64_t* ray_offsets, int64_t* seg_ids, int64_t* region_offsets,
+                    hipStream_t st);
 
 // Exclusive scan of int64 (gen.hip): out[0..n] with out[n] = total; tmp holds
 // scan_tmp_elems(n) entries.

@@ -27,8 +27,18 @@
 // the rays in flight on an XCD decide how many partly used lines its L2 must
 // hold.  Each workgroup therefore reserves kMergeLds bytes of LDS it does not
 // use, which holds two workgroups (two waves per SIMD) on a CU.
+//
+// When the caller gives the region boundaries of the tuple array, each
+// workgroup first moves its rays' tuples into LDS with contiguous loads and
+// folds from there (the region-aware form below); the gathering form above is
+// the fallback for any layout.
 #include "internal.h"
 #include "xl_device.hpp"
+
+// Multiply-adds are fused per source expression only (not across
+// statements), so that the folds, inlined into the gathering and the
+// region-aware kernels, round identically in both.
+#pragma clang fp contract(on)
 
 namespace xl {
 
@@ -91,21 +101,13 @@ __device__ __forceinline__ int64_t merge_ray(int64_t n_rays) {
 // Rays with up to kCached segments are handled with all their tuples in registers.
 constexpr int kCached = 8;
 
+// Front-to-back fold of a ray's segment tuples (Alg. 1/2 state: T(t_1 -> t_k)
+// and C, A, D, L accumulated so far).
 template <typename R>
-__global__ __launch_bounds__(kMergeBlock) void merge_fwd_kernel(const float* __restrict__ seg_out,
-                                                                int64_t n_seg,
-                                                                const int64_t* __restrict__ ro,
-                                                                const int64_t* __restrict__ ids,
-                                                                int64_t n_rays,
-                                                                float* __restrict__ out) {
-  const int64_t r = merge_ray(n_rays);
-  if (r >= n_rays) return;
-  int64_t k0, k1;
-  clamp_range(ro, r, n_seg, k0, k1);
-  // Alg. 1/2 state: T(t_1 -> t_k) and C, A, D, L accumulated so far.
+struct Fold {
   Depth<R> tau;
   float Tpre = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, A = 0.f, D = 0.f, L = 0.f;
-  auto step = [&](const Tup& x) {
+  __device__ __forceinline__ void step(const Tup& x) {
     const float S = x.D * A - x.A * D;                 // Eq. 8
     L += Tpre * Tpre * x.L + 2.f * Tpre * S;           // Eq. 7
     cr += Tpre * x.cr; cg += Tpre * x.cg; cb += Tpre * x.cb;  // Eq. 3
@@ -113,7 +115,27 @@ __global__ __launch_bounds__(kMergeBlock) void merge_fwd_kernel(const float* __r
     D += Tpre * x.D;                                   // Eq. 6
     tau.add(x.tau);
     Tpre = tau.trans();                                // Eq. 4
-  };
+  }
+  __device__ __forceinline__ void store(float* __restrict__ out, int64_t n_rays, int64_t r) const {
+    out[r] = Tpre;
+    out[n_rays + r] = cr;
+    out[2 * n_rays + r] = cg;
+    out[3 * n_rays + r] = cb;
+    out[4 * n_rays + r] = A;
+    out[5 * n_rays + r] = D;
+    out[6 * n_rays + r] = L;
+  }
+};
+
+// Forward merge of ray r, tuples gathered from seg_out.
+template <typename R>
+__device__ __forceinline__ void fwd_gather_ray(const float* __restrict__ seg_out, int64_t n_seg,
+                                               const int64_t* __restrict__ ro,
+                                               const int64_t* __restrict__ ids, int64_t n_rays,
+                                               float* __restrict__ out, int64_t r) {
+  int64_t k0, k1;
+  clamp_range(ro, r, n_seg, k0, k1);
+  Fold<R> f;
   const int64_t n = k1 - k0;
   if (n <= kCached) {
     // All of the ray's tuples are requested at once (two dependent loads in
@@ -130,21 +152,27 @@ __global__ __launch_bounds__(kMergeBlock) void merge_fwd_kernel(const float* __r
       if (sid[q] >= 0) x[q] = load_tup(seg_out, n_seg, sid[q]);
 #pragma unroll
     for (int q = 0; q < kCached; ++q)
-      if (sid[q] >= 0) step(x[q]);
+      if (sid[q] >= 0) f.step(x[q]);
   } else {
     for (int64_t k = k0; k < k1; ++k) {
       const int64_t s = ids[k];
       if (s < 0 || s >= n_seg) continue;
-      step(load_tup(seg_out, n_seg, s));
+      f.step(load_tup(seg_out, n_seg, s));
     }
   }
-  out[r] = Tpre;
-  out[n_rays + r] = cr;
-  out[2 * n_rays + r] = cg;
-  out[3 * n_rays + r] = cb;
-  out[4 * n_rays + r] = A;
-  out[5 * n_rays + r] = D;
-  out[6 * n_rays + r] = L;
+  f.store(out, n_rays, r);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kMergeBlock) void merge_fwd_kernel(const float* __restrict__ seg_out,
+                                                                int64_t n_seg,
+                                                                const int64_t* __restrict__ ro,
+                                                                const int64_t* __restrict__ ids,
+                                                                int64_t n_rays,
+                                                                float* __restrict__ out) {
+  const int64_t r = merge_ray(n_rays);
+  if (r >= n_rays) return;
+  fwd_gather_ray<R>(seg_out, n_seg, ro, ids, n_rays, out, r);
 }
 
 // Exclusive suffix fold of a ray's segments (everything behind segment k).
@@ -169,9 +197,8 @@ struct RayGrad {
 // Gradient of P (+) x (+) S with respect to x, written to gseg[:, s]; P enters
 // through its transmittance PT, opacity PA and depth PD only.
 template <typename R>
-__device__ __forceinline__ void write_seg_grad(float* __restrict__ gseg, int64_t n_seg, int64_t s,
-                                               float PT, float PA, float PD, const Tup& x,
-                                               const Suffix<R>& S, const RayGrad& g) {
+__device__ __forceinline__ Tup seg_grad(float PT, float PA, float PD, const Tup& x,
+                                        const Suffix<R>& S, const RayGrad& g) {
   const float Tk = exp_neg(x.tau);
   const float ST = S.tau.trans();
   const float gA_k = PT * (g.A + 2.f * g.L * (PT * Tk * S.D - PD));
@@ -181,25 +208,30 @@ __device__ __forceinline__ void write_seg_grad(float* __restrict__ gseg, int64_t
                      (PT * g.A - 2.f * g.L * PT * PD) * S.A +
                      (PT * g.D + 2.f * g.L * PT * PA) * S.D +
                      g.L * PT * PT * (2.f * Tk * S.L + 2.f * (S.D * x.A - S.A * x.D));
-  gseg[s] = -Tk * gT_k;
-  gseg[n_seg + s] = PT * g.cr;
-  gseg[2 * n_seg + s] = PT * g.cg;
-  gseg[3 * n_seg + s] = PT * g.cb;
-  gseg[4 * n_seg + s] = gA_k;
-  gseg[5 * n_seg + s] = gD_k;
-  gseg[6 * n_seg + s] = gL_k;
+  return Tup{-Tk * gT_k, PT * g.cr, PT * g.cg, PT * g.cb, gA_k, gD_k, gL_k};
 }
 
 template <typename R>
-__global__ __launch_bounds__(kMergeBlock) void merge_bwd_kernel(const float* __restrict__ seg_out,
-                                                                int64_t n_seg,
-                                                                const int64_t* __restrict__ ro,
-                                                                const int64_t* __restrict__ ids,
-                                                                int64_t n_rays,
-                                                                const float* __restrict__ gray,
-                                                                float* __restrict__ gseg) {
-  const int64_t r = merge_ray(n_rays);
-  if (r >= n_rays) return;
+__device__ __forceinline__ void write_seg_grad(float* __restrict__ gseg, int64_t n_seg, int64_t s,
+                                               float PT, float PA, float PD, const Tup& x,
+                                               const Suffix<R>& S, const RayGrad& g) {
+  const Tup d = seg_grad<R>(PT, PA, PD, x, S, g);
+  gseg[s] = d.tau;
+  gseg[n_seg + s] = d.cr;
+  gseg[2 * n_seg + s] = d.cg;
+  gseg[3 * n_seg + s] = d.cb;
+  gseg[4 * n_seg + s] = d.A;
+  gseg[5 * n_seg + s] = d.D;
+  gseg[6 * n_seg + s] = d.L;
+}
+
+// Backward merge of ray r, tuples gathered from seg_out.
+template <typename R>
+__device__ __forceinline__ void bwd_gather_ray(const float* __restrict__ seg_out, int64_t n_seg,
+                                               const int64_t* __restrict__ ro,
+                                               const int64_t* __restrict__ ids, int64_t n_rays,
+                                               const float* __restrict__ gray,
+                                               float* __restrict__ gseg, int64_t r) {
   int64_t k0, k1;
   clamp_range(ro, r, n_seg, k0, k1);
   const RayGrad g{gray[r], gray[n_rays + r], gray[2 * n_rays + r], gray[3 * n_rays + r],
@@ -274,6 +306,329 @@ __global__ __launch_bounds__(kMergeBlock) void merge_bwd_kernel(const float* __r
   }
 }
 
+
+template <typename R>
+__global__ __launch_bounds__(kMergeBlock) void merge_bwd_kernel(const float* __restrict__ seg_out,
+                                                                int64_t n_seg,
+                                                                const int64_t* __restrict__ ro,
+                                                                const int64_t* __restrict__ ids,
+                                                                int64_t n_rays,
+                                                                const float* __restrict__ gray,
+                                                                float* __restrict__ gseg) {
+  const int64_t r = merge_ray(n_rays);
+  if (r >= n_rays) return;
+  bwd_gather_ray<R>(seg_out, n_seg, ro, ids, n_rays, gray, gseg, r);
+}
+
+// ---------------------------------------------------------------- region-aware form
+// Region k's tuples are seg_out[:, roff[k] .. roff[k+1]) and, inside a region,
+// the segments of consecutive rays are consecutive (the sample layout packs
+// each region's segments in ray order).  The ids that a workgroup's
+// kMergeBlock consecutive rays list therefore form one contiguous run per
+// region.  The workgroup finds the runs (each id's region by binary search
+// over the boundaries, then the lowest and highest id and the count per
+// region), gives every listed tuple a slot in LDS, run after run, and moves
+// the runs with contiguous loads (and, in the backward, the gradients back
+// with contiguous stores).  Each lane then folds its ray from LDS.  A block
+// whose ids break the assumption (a region's ids not contiguous, ids outside
+// the boundaries, more listed ids than slots, decreasing ray offsets) merges
+// its rays with the gathering form instead, so any layout gives the same
+// result.
+constexpr int kMaxRegions = 256;
+constexpr int kCoopSlots = 1280;  // listed ids per workgroup (K=64 averages ~1,100)
+
+struct CoopStage {
+  int64_t roff[kMaxRegions + 1];
+  int lo[kMaxRegions], hi[kMaxRegions], cnt[kMaxRegions];
+  int base[kMaxRegions + 1];
+  int wsum[kMergeBlock / kWave];
+  int slot[kCoopSlots];      // id - roff[region], then the id's slot
+  float tup[7][kCoopSlots];
+  int16_t kid[kCoopSlots];   // region of the listed id (-1: invalid id, skipped)
+  uint8_t wrote[kCoopSlots]; // backward: the slot holds a gradient
+  int fail;
+};
+
+// Largest k in [0, n) with a[k] <= v, for a[0] <= v (a non-decreasing).
+template <typename T>
+__device__ __forceinline__ int last_not_above(const T* a, int n, T v) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Fills st.tup with the tuples of the ids that the workgroup's rays list (ids
+// [q0, q1) of the id array) and st.slot with each listed id's slot.  Returns
+// false (for the whole workgroup) if the block must take the gathering form.
+// Every thread handles the positions tid + i * kMergeBlock (i < kPerThread)
+// and issues all of its global loads before it uses any, so that a workgroup
+// waits for one round trip per phase, not one per position.
+constexpr int kPerThread = (kCoopSlots + kMergeBlock - 1) / kMergeBlock;
+static_assert(kMaxRegions <= kMergeBlock, "one thread per region in the count scan");
+
+__device__ __forceinline__ bool coop_stage(CoopStage& st, const float* __restrict__ seg_out,
+                                           int64_t n_seg, const int64_t* __restrict__ roff,
+                                           int n_regions, const int64_t* __restrict__ ids,
+                                           int64_t q0, int64_t q1, int64_t k0, int64_t k1,
+                                           bool own, int64_t max_segs) {
+  const int tid = threadIdx.x;
+  const int n = static_cast<int>(q1 < q0 ? 0 : (q1 - q0 < kCoopSlots ? q1 - q0 : kCoopSlots));
+  int64_t idv[kPerThread];
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const int p = tid + i * kMergeBlock;
+    idv[i] = p < n ? ids[q0 + p] : -1;
+  }
+  if (tid <= n_regions) st.roff[tid] = roff[tid];
+  if (tid < n_regions) {
+    st.lo[tid] = INT32_MAX;
+    st.hi[tid] = -1;
+    st.cnt[tid] = 0;
+  }
+  if (tid == 0) st.fail = (q1 < q0 || q1 - q0 > kCoopSlots) ? 1 : 0;
+  __syncthreads();
+  // Every ray's range must lie inside the block's (ray offsets increasing).
+  if (own && (k0 < q0 || k1 > q1 || k1 - k0 > max_segs)) st.fail = 1;
+  const int64_t first = st.roff[0], last = st.roff[n_regions];
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const int p = tid + i * kMergeBlock;
+    if (p < n) {
+      const int64_t id = idv[i];
+      int k = -1;
+      if (id >= 0 && id < n_seg) {
+        if (id < first || id >= last) {
+          st.fail = 1;
+        } else {
+          k = last_not_above(st.roff, n_regions, id);
+          const int64_t rel = id - st.roff[k];
+          if (rel < 0 || rel > INT32_MAX - kCoopSlots) {  // (boundaries not increasing)
+            st.fail = 1;
+            k = -1;
+          } else {
+            st.slot[p] = static_cast<int>(rel);
+            atomicMin(&st.lo[k], static_cast<int>(rel));
+            atomicMax(&st.hi[k], static_cast<int>(rel));
+            atomicAdd(&st.cnt[k], 1);
+          }
+        }
+      }
+      st.kid[p] = static_cast<int16_t>(k);
+    }
+  }
+  __syncthreads();
+  // Contiguity per region, and the scan of the counts (run bases).
+  {
+    const int lane = tid % kWave, wave = tid / kWave;
+    int c = 0;
+    if (tid < n_regions) {
+      c = st.cnt[tid];
+      if (c > 0 && st.hi[tid] - st.lo[tid] + 1 != c) st.fail = 1;
+    }
+    int incl = c;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int y = __shfl_up(incl, d);
+      if (lane >= d) incl += y;
+    }
+    if (lane == kWave - 1) st.wsum[wave] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += st.wsum[w];
+    if (tid < n_regions) st.base[tid + 1] = before + incl;
+    if (tid == 0) st.base[0] = 0;
+  }
+  __syncthreads();
+  if (st.fail) return false;
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const int p = tid + i * kMergeBlock;
+    if (p < n) {
+      const int k = st.kid[p];
+      if (k >= 0) st.slot[p] = st.base[k] + st.slot[p] - st.lo[k];
+    }
+  }
+  // Contiguous loads, run after run: every load of the thread first, then
+  // the LDS stores.
+  const int used = st.base[n_regions];
+  int64_t src[kPerThread];
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const int q = tid + i * kMergeBlock;
+    src[i] = -1;
+    if (q < used) {
+      const int k = last_not_above(st.base, n_regions, q);
+      src[i] = st.roff[k] + st.lo[k] + (q - st.base[k]);
+    }
+  }
+  float v[kPerThread][7];
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i)
+#pragma unroll
+    for (int f = 0; f < 7; ++f) v[i][f] = src[i] >= 0 ? seg_out[f * n_seg + src[i]] : 0.f;
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const int q = tid + i * kMergeBlock;
+    if (q < used) {
+#pragma unroll
+      for (int f = 0; f < 7; ++f) st.tup[f][q] = v[i][f];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+__device__ __forceinline__ Tup lds_tup(const CoopStage& st, int q) {
+  return Tup{st.tup[0][q], st.tup[1][q], st.tup[2][q], st.tup[3][q],
+             st.tup[4][q], st.tup[5][q], st.tup[6][q]};
+}
+
+// Rays of this workgroup: [r0, r1), the XCD-grouped block of merge_ray.
+__device__ __forceinline__ void coop_rays(int64_t n_rays, int64_t& r0, int64_t& r1) {
+  const int64_t nblocks = (n_rays + kMergeBlock - 1) / kMergeBlock;
+  const int64_t per = (nblocks + kXcds - 1) / kXcds;
+  const int64_t b = blockIdx.x;
+  r0 = ((b % kXcds) * per + b / kXcds) * kMergeBlock;
+  r1 = r0 + kMergeBlock < n_rays ? r0 + kMergeBlock : n_rays;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kMergeBlock) void merge_fwd_regions_kernel(
+    const float* __restrict__ seg_out, int64_t n_seg, const int64_t* __restrict__ roff,
+    int n_regions, const int64_t* __restrict__ ro, const int64_t* __restrict__ ids,
+    int64_t n_rays, float* __restrict__ out) {
+  __shared__ CoopStage st;
+  int64_t r0, r1;
+  coop_rays(n_rays, r0, r1);
+  if (r0 >= n_rays) return;  // the whole workgroup
+  const int64_t r = r0 + threadIdx.x;
+  const bool own = r < r1;
+  int64_t q0, q1, k0 = 0, k1 = 0, t;
+  clamp_range(ro, r0, n_seg, q0, t);
+  clamp_range(ro, r1 - 1, n_seg, t, q1);
+  if (own) clamp_range(ro, r, n_seg, k0, k1);
+  if (!coop_stage(st, seg_out, n_seg, roff, n_regions, ids, q0, q1, k0, k1, own, INT64_MAX)) {
+    if (own) fwd_gather_ray<R>(seg_out, n_seg, ro, ids, n_rays, out, r);
+    return;
+  }
+  if (!own) return;
+  Fold<R> f;
+  for (int64_t q = k0; q < k1; ++q) {
+    const int p = static_cast<int>(q - q0);
+    if (st.kid[p] >= 0) f.step(lds_tup(st, st.slot[p]));
+  }
+  f.store(out, n_rays, r);
+}
+
+// Backward of one ray from the staged tuples: the ray's positions are taken
+// kCached at a time, last group first; for each group the prefix fold up to
+// it is recomputed from LDS and the group's prefixes kept in registers, then
+// the group is swept in reverse with the suffix fold, every gradient
+// replacing its tuple.  Earlier groups are read before any of their slots is
+// overwritten.  The arithmetic is that of the gathering form, step for step.
+template <typename R>
+__device__ __forceinline__ void bwd_staged_ray(CoopStage& st, int64_t q0, int64_t k0, int64_t k1,
+                                               const RayGrad& g) {
+  Suffix<R> S;
+  const int64_t n = k1 - k0;
+  if (n <= 0) return;
+  for (int64_t c0 = k0 + (n - 1) / kCached * kCached; c0 >= k0; c0 -= kCached) {
+    Depth<R> ptau;
+    float T = 1.f, A = 0.f, D = 0.f;
+    for (int64_t q = k0; q < c0; ++q) {
+      const int p = static_cast<int>(q - q0);
+      if (st.kid[p] < 0) continue;
+      const int s = st.slot[p];
+      A += T * st.tup[4][s];
+      D += T * st.tup[5][s];
+      ptau.add(st.tup[0][s]);
+      T = ptau.trans();
+    }
+    float PT[kCached], PA[kCached], PD[kCached];
+    int sl[kCached];
+    Tup x[kCached];
+#pragma unroll
+    for (int i = 0; i < kCached; ++i) {
+      const int64_t q = c0 + i;
+      sl[i] = -1;
+      if (q < k1) {
+        const int p = static_cast<int>(q - q0);
+        if (st.kid[p] >= 0) {
+          sl[i] = st.slot[p];
+          x[i] = lds_tup(st, sl[i]);
+          PT[i] = T; PA[i] = A; PD[i] = D;
+          A += T * x[i].A;
+          D += T * x[i].D;
+          ptau.add(x[i].tau);
+          T = ptau.trans();
+        }
+      }
+    }
+#pragma unroll
+    for (int i = kCached - 1; i >= 0; --i) {
+      if (sl[i] >= 0) {
+        const Tup d = seg_grad<R>(PT[i], PA[i], PD[i], x[i], S, g);
+        const int s = sl[i];
+        st.tup[0][s] = d.tau; st.tup[1][s] = d.cr; st.tup[2][s] = d.cg; st.tup[3][s] = d.cb;
+        st.tup[4][s] = d.A; st.tup[5][s] = d.D; st.tup[6][s] = d.L;
+        st.wrote[s] = 1;
+        S.push_front(x[i], exp_neg(x[i].tau));
+      }
+    }
+  }
+}
+
+// Longest ray the staged backward takes (its regrouped prefixes cost
+// O(n^2 / kCached)); a block with a longer ray gathers.
+constexpr int64_t kStagedMaxSegs = 64;
+
+template <typename R>
+__global__ __launch_bounds__(kMergeBlock) void merge_bwd_regions_kernel(
+    const float* __restrict__ seg_out, int64_t n_seg, const int64_t* __restrict__ roff,
+    int n_regions, const int64_t* __restrict__ ro, const int64_t* __restrict__ ids,
+    int64_t n_rays, const float* __restrict__ gray, float* __restrict__ gseg) {
+  __shared__ CoopStage st;
+  int64_t r0, r1;
+  coop_rays(n_rays, r0, r1);
+  if (r0 >= n_rays) return;
+  const int64_t r = r0 + threadIdx.x;
+  const bool own = r < r1;
+  int64_t q0, q1, k0 = 0, k1 = 0, t;
+  clamp_range(ro, r0, n_seg, q0, t);
+  clamp_range(ro, r1 - 1, n_seg, t, q1);
+  if (own) clamp_range(ro, r, n_seg, k0, k1);
+  // Slots that no ray of the block writes (only if an id is listed twice,
+  // outside the contract) are not stored.
+  for (int q = threadIdx.x; q < kCoopSlots; q += kMergeBlock) st.wrote[q] = 0;
+  // The ray's gradient is requested before the staging (its loads wait there).
+  RayGrad g{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (own)
+    g = RayGrad{gray[r], gray[n_rays + r], gray[2 * n_rays + r], gray[3 * n_rays + r],
+                gray[4 * n_rays + r], gray[5 * n_rays + r], gray[6 * n_rays + r]};
+  if (!coop_stage(st, seg_out, n_seg, roff, n_regions, ids, q0, q1, k0, k1, own, kStagedMaxSegs)) {
+    if (own) bwd_gather_ray<R>(seg_out, n_seg, ro, ids, n_rays, gray, gseg, r);
+    return;
+  }
+  if (own) bwd_staged_ray<R>(st, q0, k0, k1, g);
+  __syncthreads();
+  // Contiguous stores, run after run.
+  const int used = st.base[n_regions];
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const int q = threadIdx.x + i * kMergeBlock;
+    if (q < used && st.wrote[q]) {
+      const int k = last_not_above(st.base, n_regions, q);
+      const int64_t id = st.roff[k] + st.lo[k] + (q - st.base[k]);
+#pragma unroll
+      for (int f = 0; f < 7; ++f) gseg[f * n_seg + id] = st.tup[f][q];
+    }
+  }
+}
+
 static inline unsigned merge_grid(int64_t n_rays) {
   const int64_t nblocks = (n_rays + kMergeBlock - 1) / kMergeBlock;
   const int64_t per = (nblocks + kXcds - 1) / kXcds;
@@ -284,29 +639,61 @@ static inline unsigned grid_for(int64_t count, int block) {
   return static_cast<unsigned>((count + block - 1) / block);
 }
 
-hipError_t launch_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* ro,
-                            const int64_t* ids, int64_t n_rays, float* out, bool fp64,
-                            hipStream_t stream) {
+// The staged form needs the boundaries; by default it is taken from
+// kStagedMinSegs segments up, where the tuples no longer stay in the caches
+// and the gathering form is bound by its scattered 4-byte accesses (measured
+// at 17.7M segments: forward 506 -> 362 us, backward 1163 -> 672 us).  Below
+// that the gathering form is faster (at 0.76M segments 12 against 19 us
+// forward): a workgroup's staging phases cost more latency than the gather.
+constexpr int64_t kStagedMinSegs = int64_t(1) << 22;
+
+static inline bool use_regions(const int64_t* roff, int n_regions, int64_t n_seg, bool force) {
+  if (roff == nullptr || n_regions < 1 || n_regions > kMaxRegions) return false;
+  return force || n_seg >= kStagedMinSegs;
+}
+
+hipError_t launch_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* roff,
+                            int n_regions, const int64_t* ro, const int64_t* ids, int64_t n_rays,
+                            float* out, bool fp64, bool staged, hipStream_t stream) {
   if (n_rays == 0) return hipSuccess;
-  if (fp64)
-    hipLaunchKernelGGL(merge_fwd_kernel<double>, dim3(merge_grid(n_rays)), dim3(kMergeBlock),
-                       kMergeLds, stream, seg_out, n_seg, ro, ids, n_rays, out);
-  else
-    hipLaunchKernelGGL(merge_fwd_kernel<float>, dim3(merge_grid(n_rays)), dim3(kMergeBlock),
-                       kMergeLds, stream, seg_out, n_seg, ro, ids, n_rays, out);
+  const dim3 grid(merge_grid(n_rays)), block(kMergeBlock);
+  if (use_regions(roff, n_regions, n_seg, staged)) {
+    if (fp64)
+      hipLaunchKernelGGL(merge_fwd_regions_kernel<double>, grid, block, 0, stream, seg_out, n_seg,
+                         roff, n_regions, ro, ids, n_rays, out);
+    else
+      hipLaunchKernelGGL(merge_fwd_regions_kernel<float>, grid, block, 0, stream, seg_out, n_seg,
+                         roff, n_regions, ro, ids, n_rays, out);
+  } else if (fp64) {
+    hipLaunchKernelGGL(merge_fwd_kernel<double>, grid, block, kMergeLds, stream, seg_out, n_seg,
+                       ro, ids, n_rays, out);
+  } else {
+    hipLaunchKernelGGL(merge_fwd_kernel<float>, grid, block, kMergeLds, stream, seg_out, n_seg,
+                       ro, ids, n_rays, out);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* ro,
-                            const int64_t* ids, int64_t n_rays, const float* gray, float* gseg,
-                            bool fp64, hipStream_t stream) {
+hipError_t launch_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* roff,
+                            int n_regions, const int64_t* ro, const int64_t* ids, int64_t n_rays,
+                            const float* gray, float* gseg, bool fp64, bool staged,
+                            hipStream_t stream) {
   if (n_rays == 0) return hipSuccess;
-  if (fp64)
-    hipLaunchKernelGGL(merge_bwd_kernel<double>, dim3(merge_grid(n_rays)), dim3(kMergeBlock),
-                       kMergeLds, stream, seg_out, n_seg, ro, ids, n_rays, gray, gseg);
-  else
-    hipLaunchKernelGGL(merge_bwd_kernel<float>, dim3(merge_grid(n_rays)), dim3(kMergeBlock),
-                       kMergeLds, stream, seg_out, n_seg, ro, ids, n_rays, gray, gseg);
+  const dim3 grid(merge_grid(n_rays)), block(kMergeBlock);
+  if (use_regions(roff, n_regions, n_seg, staged)) {
+    if (fp64)
+      hipLaunchKernelGGL(merge_bwd_regions_kernel<double>, grid, block, 0, stream, seg_out, n_seg,
+                         roff, n_regions, ro, ids, n_rays, gray, gseg);
+    else
+      hipLaunchKernelGGL(merge_bwd_regions_kernel<float>, grid, block, 0, stream, seg_out, n_seg,
+                         roff, n_regions, ro, ids, n_rays, gray, gseg);
+  } else if (fp64) {
+    hipLaunchKernelGGL(merge_bwd_kernel<double>, grid, block, kMergeLds, stream, seg_out, n_seg,
+                       ro, ids, n_rays, gray, gseg);
+  } else {
+    hipLaunchKernelGGL(merge_bwd_kernel<float>, grid, block, kMergeLds, stream, seg_out, n_seg,
+                       ro, ids, n_rays, gray, gseg);
+  }
   return hipGetLastError();
 }
 

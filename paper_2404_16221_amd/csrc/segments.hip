@@ -302,54 +302,72 @@ __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
 }
 
 // Completes segments that cross tile boundaries and leaves, in every tile
-// such a segment passes through, the carries the backward needs.  One thread
-// per tile, reading only its neighbours' records:
-//   pre: the part of the tile's first segment that lies before the tile (walk
-//        back over tiles without a head, then the open tail of the tile where
-//        the segment starts);
-//   suf: the part of the tile's last segment that lies after it (walk forward
-//        over tiles without an end, then the head of the tile where it ends);
+// such a segment passes through, the carries the backward needs:
+//   pre: the part of the tile's first segment that lies before the tile (the
+//        open tail of the tile where the segment starts, then the tiles
+//        without a head in between);
+//   suf: the part of the tile's last segment that lies after it (the tiles
+//        without an end up to the tile where it ends, then that tile's head);
 //   the tile in which a crossing segment ends writes its tuple, pre (+) head.
-// Segments are shorter than a tile on average, so a walk is one step.
+// One thread per tile; the thread of the tile where a segment starts folds
+// forward along that segment's tiles, the thread of the tile where it ends
+// folds backward, so a segment spanning M tiles costs O(M) record reads.
 __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restrict__ seg_out,
                                  TileRecs recs) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n_tiles) return;
   const int fl = recs.flags[t];
-  // (The empty range is not an identity of combine in the positive form, whose
-  // depths are relative to the ranges' end midpoints, so each walk starts from
-  // its first part.)
-  if (!(fl & kStartHead)) {
-    Part acc;
-    bool have = false, found = false;
-    for (int64_t u = t - 1; u >= 0; --u) {
-      const bool h = (recs.flags[u] & kHasHead) != 0;
-      const Part part = recs.get(h ? recs.tail : recs.head, u);
-      acc = have ? combine(part, acc) : part;
-      have = true;
-      if (h) {
-        found = true;
-        break;
+  // Carries into the tiles after t.  A tile where a segment starts (kHasHead)
+  // opens the chain of its last segment: the tiles that follow it, up to the
+  // next such tile, receive the running fold of that segment's parts (this
+  // tile's tail, then whole tiles) as their prefix, and the tile where the
+  // segment ends also completes its tuple.  Each tile is visited by one chain,
+  // so the work is linear in the tile count.  (The empty range is not an
+  // identity of combine in the positive form, whose depths are relative to the
+  // ranges' end midpoints, so each fold starts from its first part.)
+  if ((fl & kHasHead) && (fl & kTailOpen)) {
+    Part acc = recs.get(recs.tail, t);
+    for (int64_t u = t + 1; u < n_tiles; ++u) {
+      const int fu = recs.flags[u];
+      if (!(fu & kStartHead)) {
+        recs.put(recs.pre, u, acc);
+        if (fu & kHasEnd) {
+          const int64_t sgi = recs.first_seg[u];
+          if (sgi >= 0 && sgi < n_seg) write_tuple(seg_out, n_seg, sgi, combine(acc, recs.get(recs.head, u)));
+        }
       }
-    }
-    if (found) {
-      recs.put(recs.pre, t, acc);
-      if (fl & kHasEnd) {
-        const int64_t sgi = recs.first_seg[t];
-        if (sgi >= 0 && sgi < n_seg) write_tuple(seg_out, n_seg, sgi, combine(acc, recs.get(recs.head, t)));
-      }
+      if (fu & kHasHead) break;
+      acc = combine(acc, recs.get(recs.head, u));
     }
   }
-  if (fl & kTailOpen) {
+  // Carries out of the tiles before t.  A tile where a segment ends (kHasEnd),
+  // and a virtual one past the last tile, closes the chain of the tiles before
+  // it whose last segment is still open: walking down, each such tile receives
+  // the fold of the following tiles' parts up to the end as its suffix.
+  const bool anchor = (fl & kHasEnd) != 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    int64_t e;
+    if (pass == 0) {
+      if (!anchor) continue;
+      e = t;
+    } else {
+      if (t != n_tiles - 1) continue;
+      e = n_tiles;  // the virtual end
+    }
     Part acc;
     bool have = false;
-    for (int64_t u = t + 1; u < n_tiles; ++u) {
-      const Part part = recs.get(recs.head, u);
-      acc = have ? combine(acc, part) : part;
+    if (e < n_tiles) {
+      acc = recs.get(recs.head, e);
       have = true;
-      if (recs.flags[u] & kHasEnd) break;
     }
-    if (have) recs.put(recs.suf, t, acc);
+    for (int64_t u = e - 1; u >= 0; --u) {
+      const int fu = recs.flags[u];
+      if (have && (fu & kTailOpen)) recs.put(recs.suf, u, acc);
+      if (fu & kHasEnd) break;
+      const Part part = recs.get(recs.head, u);
+      acc = have ? combine(part, acc) : part;
+      have = true;
+    }
   }
 }
 

@@ -143,13 +143,15 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int
   const size_t es = dtype == XL_F32 ? 4 : 2;
 
   // Block layout: [result | generator workspace | ray offsets | samples, segment
-  // arrays, tuples, tile records].
+  // arrays, region offsets, tuples, tile records].
+  const int n_regions = p.grid[0] * p.grid[1] * p.grid[2];
   const size_t b_out = round256(4 * 7 * p.n_rays), b_ro = round256(8 * (p.n_rays + 1));
   const size_t ws_b = round256(gen_workspace_bytes(&p));
   const size_t head = b_out + ws_b + b_ro;
   auto body = [&](int64_t n, int64_t n_seg) -> size_t {
     return round256(n * es) + round256(3 * n * es) + 2 * round256(4 * n) + round256(8 * (n_seg + 1)) +
-           round256(8 * n_seg) + round256(4 * 7 * n_seg) + round256(xl_segments_workspace_bytes(n));
+           round256(8 * n_seg) + round256(8 * (n_regions + 1)) + round256(4 * 7 * n_seg) +
+           round256(xl_segments_workspace_bytes(n));
   };
   char m[200];
   if (head > s->arena.size()) {
@@ -218,15 +220,17 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int
   float* t1 = reinterpret_cast<float*>(c); c += round256(4 * n);
   int64_t* so = reinterpret_cast<int64_t*>(c); c += round256(8 * (n_seg + 1));
   int64_t* ids = reinterpret_cast<int64_t*>(c); c += round256(8 * n_seg);
+  int64_t* roff = reinterpret_cast<int64_t*>(c); c += round256(8 * (n_regions + 1));
   float* seg_out = reinterpret_cast<float*>(c); c += round256(4 * 7 * n_seg);
   void* recs = c;  // per-tile records of the segment composite
 
   hipError_t e = hipEventRecord(e0, st);
-  if (e == hipSuccess) e = gen_fill(&p, dtype, ws, n_seg, sigma, rgb, t0, t1, so, ro, ids, st);
+  if (e == hipSuccess) e = gen_fill(&p, dtype, ws, n_seg, sigma, rgb, t0, t1, so, ro, ids, roff, st);
   SamplesDev sd{dtype, sigma, rgb, t0, t1, n};
   if (e == hipSuccess) e = launch_segments_fwd(sd, so, n_seg, seg_out, recs, st);
   if (e == hipSuccess)
-    e = launch_merge_fwd(seg_out, n_seg, ro, ids, p.n_rays, out, s->cfg.merge_fp64 != 0, st);
+    e = launch_merge_fwd(seg_out, n_seg, roff, n_regions, ro, ids, p.n_rays, out,
+                         s->cfg.merge_fp64 != 0, false, st);
   if (e == hipSuccess) e = hipEventRecord(e1, st);
   const hipError_t es2 = hipStreamSynchronize(st);
   float ms = 0.f;

@@ -258,6 +258,17 @@ class Batch:
     def n_rays(self) -> int:
         return int(self.ray_offsets.shape[0] - 1)
 
+    def region_offsets(self, n_regions: Optional[int] = None) -> np.ndarray:
+        """First segment of each region, then n_seg: int64 [K + 1] (K defaults
+        to the workload's box count, else one more than the largest box)."""
+        if n_regions is None:
+            if self.workload is not None:
+                g = self.workload.grid
+                n_regions = int(g[0] * g[1] * g[2])
+            else:
+                n_regions = int(self.seg_box.max()) + 1 if self.seg_box.size else 1
+        return np.searchsorted(self.seg_box, np.arange(n_regions + 1), side="left").astype(np.int64)
+
     def ray_sample_index(self, r: int) -> np.ndarray:
         """Indices of ray r's samples in t order (its segments front to back)."""
         parts = [np.arange(self.seg_offsets[s], self.seg_offsets[s + 1])

@@ -47,8 +47,12 @@ def test_host_side_argument_errors():
     s = xl.XLSamples(0, 16, 16, 16, 16, 4)
     assert _fwd(s, 16, 0) == xl.XL_EINVAL and "no segments" in L.xl_last_error().decode()
     assert _fwd(s, 16, 1, 16, 16, 1) == xl.XL_EINVAL and "too small" in L.xl_last_error().decode()
-    assert L.xl_merge_fwd(16, 1, 16, 16, 1, 16, 4, None) == xl.XL_EINVAL
-    assert L.xl_merge_bwd(16, -1, 16, 16, 1, 16, 16, 0, None) == xl.XL_EINVAL
+    assert L.xl_merge_fwd(16, 1, None, 0, 16, 16, 1, 16, 4, None) == xl.XL_EINVAL
+    assert "flags" in L.xl_last_error().decode()
+    assert L.xl_merge_bwd(16, -1, None, 0, 16, 16, 1, 16, 16, 0, None) == xl.XL_EINVAL
+    assert L.xl_merge_fwd(16, 1, 16, 0, 16, 16, 1, 16, 0, None) == xl.XL_EINVAL
+    assert "n_regions" in L.xl_last_error().decode()
+    assert L.xl_merge_bwd(16, 1, 16, -2, 16, 16, 1, 16, 16, 0, None) == xl.XL_EINVAL
     assert L.xl_render_segments_bwd(ctypes.byref(s), 16, 1, None, 0, 16, 16, 16, None) == xl.XL_EINVAL
 
 

@@ -36,8 +36,11 @@ def say(*a):
 def run(g, grad_ray, fp64=False):
     seg_out, ws = xl.xl_render_segments_fwd(g["sigma"], g["rgb"], g["t_start"], g["t_end"],
                                             g["seg_offsets"])
-    ray_out = xl.xl_merge_fwd(seg_out, g["ray_offsets"], g["seg_ids"], fp64=fp64)
-    gseg = xl.xl_merge_bwd(seg_out, g["ray_offsets"], g["seg_ids"], grad_ray, fp64=fp64)
+    # the region-aware merge, as the bench times it
+    roff = g.get("region_offsets")
+    ray_out = xl.xl_merge_fwd(seg_out, g["ray_offsets"], g["seg_ids"], fp64=fp64, region_offsets=roff)
+    gseg = xl.xl_merge_bwd(seg_out, g["ray_offsets"], g["seg_ids"], grad_ray, fp64=fp64,
+                           region_offsets=roff)
     gs, gc = xl.xl_render_segments_bwd(g["sigma"], g["rgb"], g["t_start"], g["t_end"],
                                        g["seg_offsets"], ws, gseg)
     torch.cuda.synchronize()

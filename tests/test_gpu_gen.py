@@ -17,6 +17,7 @@ def test_device_generator_matches_host(cfg, ray0, n_rays):
     d = {k: v.cpu().numpy() for k, v in xl.xl_gen(w, torch.float32, ray0, n_rays).items()}
     print(f"cfg {cfg}: {h.n} samples, {h.n_seg} segments", flush=True)
     for k, a in (("seg_offsets", h.seg_offsets), ("ray_offsets", h.ray_offsets), ("seg_ids", h.seg_ids),
+                 ("region_offsets", h.region_offsets()),
                  ("t_start", h.t_start), ("t_end", h.t_end), ("rgb", h.rgb), ("sigma", h.sigma)):
         assert np.array_equal(d[k], a), k
 

@@ -253,6 +253,27 @@ def test_tiny_and_ragged_sizes(n_samples):
     _check_backward(b, d, np.arange(2), gseg, gs, gc, grad_ray, f"n={n_samples}")
 
 
+def test_segments_spanning_many_tiles():
+    """Segments of 9,000 and 7,000 samples (18 and 14 tiles of 512), placed
+    so that neither starts on a tile boundary, with short segments around:
+    the fixup's carries along long chains of tiles."""
+    rng = np.random.default_rng(77)
+    w = 2.9 / 16000
+    a = _seg(rng, 9000, 0.0, sigma=np.exp(rng.normal(0, 1.0, 9000)) * 4.0, width=np.full(9000, w))
+    b_ = _seg(rng, 7000, 9000 * w, sigma=np.exp(rng.normal(0, 1.0, 7000)) * 4.0, width=np.full(7000, w))
+    batch = _hand_batch([[_seg(rng, 37, 0.2)], [a, b_], [_seg(rng, 300, 0.1), _seg(rng, 5, 2.0)]],
+                        shuffle_seed=4)
+    d = to_dev(batch)
+    seg_out, ws, ray_out = run_fwd(d)
+    assert_tuples(seg_out.cpu().numpy(), O.render_segments(batch.sigma, batch.rgb, batch.t_start,
+                                                           batch.t_end, batch.seg_offsets), "seg",
+                  "long segments")
+    assert_tuples(ray_out.cpu().numpy(), oracle_rays(batch, np.arange(3)), "ray", "long segments")
+    grad_ray = np.random.default_rng(78).normal(size=(7, 3))
+    gseg, gs, gc = run_bwd(d, seg_out, ws, grad_ray)
+    _check_backward(batch, d, np.arange(3), gseg, gs, gc, grad_ray, "long segments")
+
+
 def test_no_samples():
     b = _hand_batch([[], [(np.zeros(0), np.zeros((0, 3)), np.zeros(0), np.zeros(0))]])
     d = to_dev(b)

@@ -48,6 +48,23 @@ def test_packing_invariants_all_workloads():
             assert abs((b.sigma == 0).mean() - w.zero_frac) < 0.02
 
 
+def test_region_offsets_bound_each_region_in_ray_order():
+    for cfg in (1, 2, 4):
+        w = synth.WORKLOADS[cfg]
+        b = synth.generate(w, rays=np.arange(300))
+        roff = b.region_offsets()
+        assert roff.shape == (w.k + 1,) and roff[0] == 0 and roff[-1] == b.n_seg
+        assert np.all(np.diff(roff) >= 0)
+        seg_ray = np.empty(b.n_seg, np.int64)
+        for r in range(b.n_rays):
+            seg_ray[b.seg_ids[b.ray_offsets[r]:b.ray_offsets[r + 1]]] = r
+        for k in range(w.k):
+            a, e = roff[k], roff[k + 1]
+            assert np.all(b.seg_box[a:e] == k)
+            # inside a region, consecutive rays own consecutive segments
+            assert np.all(np.diff(seg_ray[a:e]) > 0)
+
+
 def test_plain_form_has_one_segment_per_ray():
     w = synth.WORKLOADS[2]
     p = synth.generate(w.plain(), rays=np.arange(100))
