@@ -23,7 +23,7 @@
 // the segment's own gradient entries, then carries the suffix fold S in a
 // reverse sweep and takes the Jacobian of P (+) x (+) S with respect to x.
 //
-// Segment kernels: one wave per segment, 64 samples per step, shuffle scans
+// Segment kernels: one wave per segment, 64 samples per step, DPP scans
 // for the optical depth, the prefix sums of w b_p (forward) and the prefix
 // sums of w a_p and of w v (backward).  Per-sample suffix sums in the backward
 // are a segment total from the forward tuple minus the inclusive prefix (Phi_a
@@ -59,20 +59,28 @@ struct BrDev {
   int pa[kMaxPairs], pb[kMaxPairs];
 };
 
-__device__ __forceinline__ float incl_sum(float v, int lane) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const float y = __shfl_up(v, d);
-    if (lane >= d) v += y;
-  }
+// Wave scans on DPP (no LDS round trip): row shifts by 1, 2, 4, 8 inside each
+// row of 16 lanes, then rows 1 and 3 add the last lane of the row below and
+// rows 2-3 lane 31.  Lanes without a source, and disabled rows, read 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp0(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                               ROW_MASK, 0xF, true));
+}
+__device__ __forceinline__ float incl_sum(float v) {
+  v += dpp0<kRowShr1, 0xF>(v);
+  v += dpp0<kRowShr2, 0xF>(v);
+  v += dpp0<kRowShr4, 0xF>(v);
+  v += dpp0<kRowShr8, 0xF>(v);
+  v += dpp0<kRowBcast15, 0xA>(v);
+  v += dpp0<kRowBcast31, 0xC>(v);
   return v;
 }
 // Exclusive prefix from an inclusive one (lane 0 gets 0).
-__device__ __forceinline__ float excl_of(float incl, int lane) {
-  const float y = __shfl_up(incl, 1);
-  return lane == 0 ? 0.f : y;
+__device__ __forceinline__ float excl_of(float incl) { return dpp0<kWaveShr1, 0xF>(incl); }
+__device__ __forceinline__ float wave_total(float incl) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, incl), kWave - 1));
 }
-__device__ __forceinline__ float wave_total(float incl) { return __shfl(incl, kWave - 1); }
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d);
@@ -80,10 +88,11 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 // f[idx] for a wave-uniform runtime index, without dynamic register indexing.
-__device__ __forceinline__ float pick(const float (&f)[kMaxCh], int idx) {
+template <int FB>
+__device__ __forceinline__ float pick(const float (&f)[FB], int idx) {
   float r = f[0];
 #pragma unroll
-  for (int c = 1; c < kMaxCh; ++c) r = idx == c ? f[c] : r;
+  for (int c = 1; c < FB; ++c) r = idx == c ? f[c] : r;
   return r;
 }
 
@@ -98,19 +107,19 @@ __device__ __forceinline__ void store_one(void* p, int64_t i, float v) {
   else static_cast<uint16_t*>(p)[i] = from_f32<DT>(v);
 }
 
-// Channels of sample i (zero past F).
-template <int DT, int SRC>
-__device__ __forceinline__ void channels(const BrDev& s, int64_t i, float m, float (&f)[kMaxCh]) {
+// Channels of sample i (zero past F; FB >= F is the kernel's channel bound).
+template <int DT, int SRC, int FB>
+__device__ __forceinline__ void channels(const BrDev& s, int64_t i, float m, float (&f)[FB]) {
   if (SRC == XL_CH_MIDPOINT_POWERS) {
     float p = 1.f;
 #pragma unroll
-    for (int c = 0; c < kMaxCh; ++c) {
+    for (int c = 0; c < FB; ++c) {
       f[c] = c < s.F ? p : 0.f;
       p *= m;
     }
   } else {
 #pragma unroll
-    for (int c = 0; c < kMaxCh; ++c) f[c] = c < s.F ? load_one<DT>(s.ch, i * s.F + c) : 0.f;
+    for (int c = 0; c < FB; ++c) f[c] = c < s.F ? load_one<DT>(s.ch, i * s.F + c) : 0.f;
   }
 }
 
@@ -133,7 +142,7 @@ struct BrSample {
 
 template <int DT>
 __device__ __forceinline__ BrSample br_sample(const BrDev& s, int64_t i, bool in, float before,
-                                              int lane, float& step_depth) {
+                                              float& step_depth) {
   BrSample q;
   q.in = in;
   q.delta = 0.f;
@@ -145,7 +154,7 @@ __device__ __forceinline__ BrSample br_sample(const BrDev& s, int64_t i, bool in
     q.m = 0.5f * (t0 + t1);
     q.od = load_one<DT>(s.sigma, i) * q.delta;
   }
-  const float incl = incl_sum(q.od, lane);
+  const float incl = incl_sum(q.od);
   q.e = exp_neg(q.od);
   q.T = exp_neg(before + (incl - q.od));
   q.w = q.T * one_minus_exp_neg(q.od, q.e);
@@ -153,39 +162,39 @@ __device__ __forceinline__ BrSample br_sample(const BrDev& s, int64_t i, bool in
   return q;
 }
 
-template <int DT, int SRC>
+template <int DT, int SRC, int FB>
 __global__ __launch_bounds__(kBrBlock) void br_fwd_kernel(BrDev s, const int64_t* __restrict__ so,
                                                           int64_t n_seg, float* __restrict__ out) {
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int64_t k = static_cast<int64_t>(blockIdx.x) * kBrWaves + wave;
   if (k >= n_seg) return;
   const int64_t a = so[k], b = so[k + 1];
-  float phi[kMaxCh], psi[kMaxPairs], wb_before[kMaxPairs];
+  float phi[FB], psi[kMaxPairs], wb_before[kMaxPairs];
 #pragma unroll
-  for (int c = 0; c < kMaxCh; ++c) phi[c] = 0.f;
+  for (int c = 0; c < FB; ++c) phi[c] = 0.f;
 #pragma unroll
   for (int p = 0; p < kMaxPairs; ++p) psi[p] = wb_before[p] = 0.f;
   DepthSum before;
   for (int64_t base = a; base < b; base += kWave) {
     const int64_t i = base + lane;
     float step;
-    const BrSample q = br_sample<DT>(s, i, i < b, before.value(), lane, step);
-    float f[kMaxCh];
-    if (q.in) channels<DT, SRC>(s, i, q.m, f);
+    const BrSample q = br_sample<DT>(s, i, i < b, before.value(), step);
+    float f[FB];
+    if (q.in) channels<DT, SRC, FB>(s, i, q.m, f);
     else {
 #pragma unroll
-      for (int c = 0; c < kMaxCh; ++c) f[c] = 0.f;
+      for (int c = 0; c < FB; ++c) f[c] = 0.f;
     }
 #pragma unroll
-    for (int c = 0; c < kMaxCh; ++c) phi[c] = fmaf(q.w, f[c], phi[c]);
+    for (int c = 0; c < FB; ++c) phi[c] = fmaf(q.w, f[c], phi[c]);
 #pragma unroll
     for (int p = 0; p < kMaxPairs; ++p) {
       if (p < s.P) {
         const float av = pick(f, s.pa[p]), bv = pick(f, s.pb[p]);
         const float wb = q.w * bv;
-        const float ib = incl_sum(wb, lane);
+        const float ib = incl_sum(wb);
         const float wa = q.w * av;
-        psi[p] = fmaf(wa, wb_before[p] + excl_of(ib, lane) + 0.5f * wb, psi[p]);
+        psi[p] = fmaf(wa, wb_before[p] + excl_of(ib) + 0.5f * wb, psi[p]);
         wb_before[p] += wave_total(ib);
       }
     }
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(kBrBlock) void br_fwd_kernel(BrDev s, const int64_t
   const int F = s.F, P = s.P;
   float mine = 0.f;  // lane c of the output row gets channel c's total
 #pragma unroll
-  for (int c = 0; c < kMaxCh; ++c) {
+  for (int c = 0; c < FB; ++c) {
     if (c < F) {
       const float t = wave_sum(phi[c]);
       mine = lane == 1 + c ? t : mine;
@@ -211,7 +220,7 @@ __global__ __launch_bounds__(kBrBlock) void br_fwd_kernel(BrDev s, const int64_t
   if (lane < 1 + F + P) out[lane * n_seg + k] = mine;
 }
 
-template <int DT, int SRC>
+template <int DT, int SRC, int FB>
 __global__ __launch_bounds__(kBrBlock) void br_bwd_kernel(BrDev s, const int64_t* __restrict__ so,
                                                           int64_t n_seg,
                                                           const float* __restrict__ seg_out,
@@ -224,10 +233,10 @@ __global__ __launch_bounds__(kBrBlock) void br_bwd_kernel(BrDev s, const int64_t
   const int64_t a = so[k], b = so[k + 1];
   const int F = s.F, P = s.P;
   const float g_tau = gseg[k];
-  float g[kMaxCh], h[kMaxPairs], phi_a[kMaxPairs];
+  float g[FB], h[kMaxPairs], phi_a[kMaxPairs];
   float vtot = 0.f;  // sum over the segment of w_i v_i
 #pragma unroll
-  for (int c = 0; c < kMaxCh; ++c) {
+  for (int c = 0; c < FB; ++c) {
     g[c] = c < F ? gseg[(1 + c) * n_seg + k] : 0.f;
     if (c < F) vtot = fmaf(g[c], seg_out[(1 + c) * n_seg + k], vtot);
   }
@@ -245,16 +254,16 @@ __global__ __launch_bounds__(kBrBlock) void br_bwd_kernel(BrDev s, const int64_t
   for (int64_t base = a; base < b; base += kWave) {
     const int64_t i = base + lane;
     float step;
-    const BrSample q = br_sample<DT>(s, i, i < b, before.value(), lane, step);
-    float f[kMaxCh];
-    if (q.in) channels<DT, SRC>(s, i, q.m, f);
+    const BrSample q = br_sample<DT>(s, i, i < b, before.value(), step);
+    float f[FB];
+    if (q.in) channels<DT, SRC, FB>(s, i, q.m, f);
     else {
 #pragma unroll
-      for (int c = 0; c < kMaxCh; ++c) f[c] = 0.f;
+      for (int c = 0; c < FB; ++c) f[c] = 0.f;
     }
     float v = 0.f;
 #pragma unroll
-    for (int c = 0; c < kMaxCh; ++c) v = fmaf(g[c], f[c], v);
+    for (int c = 0; c < FB; ++c) v = fmaf(g[c], f[c], v);
     float wb_lt[kMaxPairs], wa_gt[kMaxPairs], av[kMaxPairs], bv[kMaxPairs];
 #pragma unroll
     for (int p = 0; p < kMaxPairs; ++p) {
@@ -262,9 +271,9 @@ __global__ __launch_bounds__(kBrBlock) void br_bwd_kernel(BrDev s, const int64_t
       if (p < P) {
         av[p] = pick(f, s.pa[p]);
         bv[p] = pick(f, s.pb[p]);
-        const float ib = incl_sum(q.w * bv[p], lane);
-        const float ia = incl_sum(q.w * av[p], lane);
-        wb_lt[p] = wb_before[p] + excl_of(ib, lane);          // sum_{j<i} w_j b_j
+        const float ib = incl_sum(q.w * bv[p]);
+        const float ia = incl_sum(q.w * av[p]);
+        wb_lt[p] = wb_before[p] + excl_of(ib);          // sum_{j<i} w_j b_j
         wa_gt[p] = phi_a[p] - (wa_before[p] + ia);            // sum_{j>i} w_j a_j
         wb_before[p] += wave_total(ib);
         wa_before[p] += wave_total(ia);
@@ -273,7 +282,7 @@ __global__ __launch_bounds__(kBrBlock) void br_bwd_kernel(BrDev s, const int64_t
         v = fmaf(h[p], U, v);
       }
     }
-    const float iu = incl_sum(q.w * v, lane);
+    const float iu = incl_sum(q.w * v);
     const float v_gt = vtot - (vpre + iu);  // sum_{j>i} w_j v_j
     const float dtau = g_tau + q.T * q.e * v - v_gt;
     vpre += wave_total(iu);
@@ -284,7 +293,7 @@ __global__ __launch_bounds__(kBrBlock) void br_bwd_kernel(BrDev s, const int64_t
       store_one<DT>(grad_sigma, i, ds);
       if (SRC == XL_CH_LOADED) {
 #pragma unroll
-        for (int c = 0; c < kMaxCh; ++c) {
+        for (int c = 0; c < FB; ++c) {
           if (c < F) {
             float df = q.w * g[c];
 #pragma unroll
@@ -483,18 +492,26 @@ BrDev br_dev(const xl_breakable* d) {
   return s;
 }
 
+// Channel loops run to 4 for up to four channels, else to kMaxCh.
 template <int DT, int SRC>
 void fwd_launch(const BrDev& s, const int64_t* so, int64_t n_seg, float* out, hipStream_t st) {
   const dim3 grid(static_cast<unsigned>((n_seg + kBrWaves - 1) / kBrWaves)), block(kBrBlock);
-  hipLaunchKernelGGL((br_fwd_kernel<DT, SRC>), grid, block, 0, st, s, so, n_seg, out);
+  if (s.F <= 4)
+    hipLaunchKernelGGL((br_fwd_kernel<DT, SRC, 4>), grid, block, 0, st, s, so, n_seg, out);
+  else
+    hipLaunchKernelGGL((br_fwd_kernel<DT, SRC, kMaxCh>), grid, block, 0, st, s, so, n_seg, out);
 }
 
 template <int DT, int SRC>
 void bwd_launch(const BrDev& s, const int64_t* so, int64_t n_seg, const float* seg_out,
                 const float* gseg, void* gs, void* gc, int acc, hipStream_t st) {
   const dim3 grid(static_cast<unsigned>((n_seg + kBrWaves - 1) / kBrWaves)), block(kBrBlock);
-  hipLaunchKernelGGL((br_bwd_kernel<DT, SRC>), grid, block, 0, st, s, so, n_seg, seg_out, gseg, gs,
-                     gc, acc);
+  if (s.F <= 4)
+    hipLaunchKernelGGL((br_bwd_kernel<DT, SRC, 4>), grid, block, 0, st, s, so, n_seg, seg_out, gseg,
+                       gs, gc, acc);
+  else
+    hipLaunchKernelGGL((br_bwd_kernel<DT, SRC, kMaxCh>), grid, block, 0, st, s, so, n_seg, seg_out,
+                       gseg, gs, gc, acc);
 }
 
 unsigned br_merge_grid(int64_t n_rays) {
