@@ -130,14 +130,16 @@ struct Smp {
   float tau, e, alpha, m, delta, c0, c1, c2;  // e = exp(-tau)
 };
 
-// 1 - exp(-tau) without cancellation: for tau < 1/4 the Taylor polynomial to
-// tau^6 (truncation below tau^6/5040 relative), else 1 - exp(-tau).
+// 1 - exp(-tau) without cancellation: for tau < 1/4, tau times a degree-4
+// polynomial fitted to (1 - exp(-tau)) / tau on [0, 1/4] (relative error of
+// the fit 2.5e-9; evaluated in float32 with fused multiply-adds the result is
+// within 9.6e-8 relative of the exact value), else 1 - exp(-tau), where the
+// subtraction is exact and only e's rounding remains.
 __device__ __forceinline__ float one_minus_exp_neg(float tau, float e) {
-  float q = fmaf(-tau, 1.f / 720.f, 1.f / 120.f);
-  q = fmaf(-tau, q, 1.f / 24.f);
-  q = fmaf(-tau, q, 1.f / 6.f);
-  q = fmaf(-tau, q, 0.5f);
-  q = fmaf(-tau, q, 1.f);
+  float q = fmaf(0.0075102211f, tau, -0.041488953f);
+  q = fmaf(q, tau, 0.16665082f);
+  q = fmaf(q, tau, -0.49999949f);
+  q = fmaf(q, tau, 1.f);
   return tau < 0.25f ? tau * q : 1.f - e;
 }
 
