@@ -384,32 +384,43 @@ __global__ __launch_bounds__(kPackBlock) void pack_fill_block_kernel(PackDev p, 
     sid = w.bsegpre[lane * p.nblk + blk];
   }
   const int64_t r_end = (blk + 1) * kRayBlock < p.R ? (blk + 1) * kRayBlock : p.R;
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+  // the first ray's table entries; each ray requests the next ray's before
+  // it works on its own samples
+  int32_t c_next = 0, f_next = 0;
+  if (lane < p.K && blk * kRayBlock < r_end) {
+    c_next = w.cnt[blk * kRayBlock * p.K + lane];
+    f_next = w.first[blk * kRayBlock * p.K + lane];
+  }
   for (int64_t r = blk * kRayBlock; r < r_end; ++r) {
     const int64_t s0 = p.ray_off[r], n = p.ray_off[r + 1] - s0;
-    int32_t c = 0, f = 0;
+    const int32_t c = c_next, f = f_next;
+    if (lane < p.K && r + 1 < r_end) {
+      c_next = w.cnt[(r + 1) * p.K + lane];
+      f_next = w.first[(r + 1) * p.K + lane];
+    }
     float tin = INFINITY, tout = -INFINITY;
-    if (lane < p.K) {
-      c = w.cnt[r * p.K + lane];
-      f = w.first[r * p.K + lane];
-      if (c > 0) {
-        const float2 sp = ray_span(p, r, bx);
-        tin = sp.x;
-        tout = sp.y;
-      }
+    if (lane < p.K && c > 0) {
+      const float2 sp = ray_span(p, r, bx);
+      tin = sp.x;
+      tout = sp.y;
     }
     const bool valid = c > 0;
+    // front-to-back rank among the boxes with pieces: the few such boxes are
+    // compacted first (ties, which disjoint boxes cannot produce, broken by
+    // compacted position so that ranks stay distinct)
+    const unsigned long long vm = __ballot(valid);
+    const int nv = __popcll(vm);
+    const int pos = __popcll(vm & below);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the previous ray's table reads come first
-    s_key[wave][lane] = valid ? tin : INFINITY;
+    if (valid) s_key[wave][pos] = tin;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    // front-to-back rank among the boxes with pieces (ties, which disjoint
-    // boxes cannot produce, broken by lane so that ranks stay distinct)
     int rank = 0;
     if (valid)
-      for (int k = 0; k < p.K; ++k) {
+      for (int k = 0; k < nv; ++k) {
         const float t = s_key[wave][k];
-        rank += (t < tin || (t == tin && k < lane)) ? 1 : 0;
+        rank += (t < tin || (t == tin && k < pos)) ? 1 : 0;
       }
-    const int nv = __popcll(__ballot(valid));
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if (valid) {
       s_key[wave][rank] = tin;
