@@ -314,14 +314,16 @@ int xl_pack_plan(const xl_rays* rays, const int32_t* axis, const float* plane, i
  * segments (rays in order) before box b+1's -- plus ray_offsets [n_rays + 1]
  * and seg_ids [n_seg] listing each ray's segments front to back.  Optional
  * (may be NULL): src [n_pieces] int64, the input sample each piece comes from
- * (for evaluating the owning region's field there), and seg_box [n_seg]
- * int32.  n_seg must be the plan's.  Samples that break the sortedness
- * contract give unspecified pieces, never stores outside these arrays.
+ * (for evaluating the owning region's field there), seg_box [n_seg] int32,
+ * and region_offsets [2^levels + 1] int64 (box b's segments are
+ * [region_offsets[b], region_offsets[b+1]); the merge's region boundaries).
+ * n_seg must be the plan's.  Samples that break the sortedness contract give
+ * unspecified pieces, never stores outside these arrays.
  */
 int xl_pack_fill(const xl_rays* rays, const int32_t* axis, const float* plane, int32_t levels,
                  void* workspace, size_t workspace_bytes, int64_t n_seg, float* t_start,
                  float* t_end, int64_t* src, int64_t* seg_offsets, int64_t* ray_offsets,
-                 int64_t* seg_ids, int32_t* seg_box, void* stream);
+                 int64_t* seg_ids, int32_t* seg_box, int64_t* region_offsets, void* stream);
 
 /*
  * Feature channels (App. B.2: breakable integrals are closed under integration

@@ -121,7 +121,7 @@ SIGNATURES = {
     "xl_pack_plan": (_c.c_int, [_c.POINTER(XLRays), _vp, _vp, _i32, _vp, _sz, _c.POINTER(_i64),
                                 _c.POINTER(_i64), _vp]),
     "xl_pack_fill": (_c.c_int, [_c.POINTER(XLRays), _vp, _vp, _i32, _vp, _sz, _i64, _vp, _vp, _vp,
-                                _vp, _vp, _vp, _vp, _vp]),
+                                _vp, _vp, _vp, _vp, _vp, _vp]),
 }
 
 
@@ -360,7 +360,7 @@ def xl_pack(origins, dirs, t_start, t_end, ray_offsets, axis, plane, levels: int
     origins, dirs: device float32 [R, 3]; t_start, t_end: device float32 [n];
     ray_offsets: device int64 [R + 1]; axis, plane: the partition tree (host or
     device).  Returns device tensors t_start, t_end, src (or None),
-    seg_offsets, ray_offsets, seg_ids, seg_box."""
+    seg_offsets, ray_offsets, seg_ids, seg_box, region_offsets."""
     dev = origins.device
     R = origins.shape[0]
     if origins.shape != (R, 3) or dirs.shape != (R, 3) or ray_offsets.shape != (R + 1,):
@@ -386,13 +386,15 @@ def xl_pack(origins, dirs, t_start, t_end, ray_offsets, axis, plane, levels: int
                seg_offsets=torch.empty(n_seg + 1, dtype=torch.int64, device=dev),
                ray_offsets=torch.empty(R + 1, dtype=torch.int64, device=dev),
                seg_ids=torch.empty(n_seg, dtype=torch.int64, device=dev),
-               seg_box=torch.empty(n_seg, dtype=torch.int32, device=dev))
+               seg_box=torch.empty(n_seg, dtype=torch.int32, device=dev),
+               region_offsets=torch.empty((1 << levels) + 1, dtype=torch.int64, device=dev))
     _check(L.xl_pack_fill(ctypes.byref(rays), a.data_ptr(), p.data_ptr(), levels, ws.data_ptr(), wsb,
                           n_seg, _dev(out["t_start"], "t_start"), _dev(out["t_end"], "t_end"),
                           _dev(out["src"], "src") if with_src else None,
                           _dev(out["seg_offsets"], "seg_offsets"),
                           _dev(out["ray_offsets"], "ray_offsets"), _dev(out["seg_ids"], "seg_ids"),
-                          _dev(out["seg_box"], "seg_box"), _stream()))
+                          _dev(out["seg_box"], "seg_box"),
+                          _dev(out["region_offsets"], "region_offsets"), _stream()))
     return out
 
 

@@ -326,14 +326,14 @@ int xl_pack_plan(const xl_rays* rays, const int32_t* axis, const float* plane, i
 int xl_pack_fill(const xl_rays* rays, const int32_t* axis, const float* plane, int32_t levels,
                  void* workspace, size_t workspace_bytes, int64_t n_seg, float* t_start,
                  float* t_end, int64_t* src, int64_t* seg_offsets, int64_t* ray_offsets,
-                 int64_t* seg_ids, int32_t* seg_box, void* stream) {
+                 int64_t* seg_ids, int32_t* seg_box, int64_t* region_offsets, void* stream) {
   int rc = check_pack(rays, axis, plane, levels, workspace, workspace_bytes);
   if (rc) return rc;
   if (n_seg < 0) return fail(XL_EINVAL, "negative segment count");
   if (!seg_offsets || !ray_offsets || (n_seg > 0 && (!t_start || !t_end || !seg_ids)))
     return fail(XL_EINVAL, "NULL output array");
   return hip_status(xl::pack_fill(rays, axis, plane, levels, workspace, n_seg, t_start, t_end, src,
-                                  seg_offsets, ray_offsets, seg_ids, seg_box,
+                                  seg_offsets, ray_offsets, seg_ids, seg_box, region_offsets,
                                   static_cast<hipStream_t>(stream)),
                     "xl_pack_fill");
 }

@@ -74,7 +74,7 @@ hipError_t pack_plan(const xl_rays* rays, const int32_t* axis, const float* plan
 hipError_t pack_fill(const xl_rays* rays, const int32_t* axis, const float* plane, int levels,
                      void* ws, int64_t n_seg, float* t_start, float* t_end, int64_t* src,
                      int64_t* seg_offsets, int64_t* ray_offsets, int64_t* seg_ids, int32_t* seg_box,
-                     hipStream_t st);
+                     int64_t* region_offsets, hipStream_t st);
 
 // Feature channels (features.hip).
 hipError_t launch_features_fwd(const xl_features* f, const int64_t* seg_offsets, int64_t n_seg,

@@ -584,10 +584,17 @@ hipError_t pack_plan(const xl_rays* rays, const int32_t* axis, const float* plan
   return hipSuccess;
 }
 
+// First segment of every box (the (box, block 0) segment prefix), and n_seg.
+__global__ void pack_region_offsets_kernel(const int64_t* __restrict__ bsegpre, int64_t nblk, int K,
+                                           int64_t* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b <= K) out[b] = bsegpre[b * nblk];
+}
+
 hipError_t pack_fill(const xl_rays* rays, const int32_t* axis, const float* plane, int levels,
                      void* ws, int64_t n_seg, float* t_start, float* t_end, int64_t* src,
                      int64_t* seg_offsets, int64_t* ray_offsets, int64_t* seg_ids, int32_t* seg_box,
-                     hipStream_t st) {
+                     int64_t* region_offsets, hipStream_t st) {
   const PackLayout L = pack_layout(rays->n_rays, levels);
   const PackWs w = pack_views(L, ws);
   const PackDev p = pack_dev(rays, axis, plane, levels);
@@ -605,8 +612,17 @@ hipError_t pack_fill(const xl_rays* rays, const int32_t* axis, const float* plan
   if ((e = hipMemcpyAsync(seg_offsets + n_seg, w.bpre + L.KB, sizeof(int64_t),
                           hipMemcpyDeviceToDevice, st)) != hipSuccess)
     return e;
-  return hipMemcpyAsync(ray_offsets, w.ray_off, sizeof(int64_t) * (L.R + 1), hipMemcpyDeviceToDevice,
-                        st);
+  if ((e = hipMemcpyAsync(ray_offsets, w.ray_off, sizeof(int64_t) * (L.R + 1),
+                          hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return e;
+  if (region_offsets) {
+    // (with no rays every block prefix is the single total 0 at bsegpre[0])
+    const int64_t nblk = L.nblk > 0 ? L.nblk : 0;
+    hipLaunchKernelGGL(pack_region_offsets_kernel, dim3(grid_for(L.K + 1, 256)), dim3(256), 0, st,
+                       w.bsegpre, nblk, static_cast<int>(L.K), region_offsets);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace xl

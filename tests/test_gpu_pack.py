@@ -24,7 +24,7 @@ def dev_pack(o, d, ts, te, ro, axis, plane, levels):
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     out = xl.xl_pack(T(o), T(d), T(ts), T(te), T(ro), axis, plane, levels)
     torch.cuda.synchronize()
-    return {k: out[k].cpu().numpy() for k in KEYS}
+    return {k: out[k].cpu().numpy() for k in KEYS + ("region_offsets",)}
 
 
 def assert_same_pack(got, ref, what):
@@ -105,6 +105,14 @@ def test_workload_rays_bit_exact_and_render():
     seg_out, _ = xl.xl_render_segments_fwd(sig, rgb, T(got["t_start"]), T(got["t_end"]),
                                            T(got["seg_offsets"]))
     ray_out = xl.xl_merge_fwd(seg_out, T(got["ray_offsets"]), T(got["seg_ids"]))
+    # the pack's region boundaries bound each box's segments and drive the
+    # staged merge to the same bits
+    roff = got["region_offsets"]
+    assert roff[0] == 0 and roff[-1] == got["seg_box"].size
+    assert np.array_equal(roff, np.searchsorted(got["seg_box"], np.arange(17), side="left"))
+    staged = xl.xl_merge_fwd(seg_out, T(got["ray_offsets"]), T(got["seg_ids"]),
+                             region_offsets=T(roff), staged=True)
+    assert torch.equal(staged, ray_out)
     want = O.render_rays_single(b.sigma[ref["src"]], b.rgb[ref["src"]], ref["t_start"],
                                 ref["t_end"], ref["seg_offsets"], ref["ray_offsets"],
                                 ref["seg_ids"])
