@@ -225,8 +225,11 @@ __device__ __forceinline__ void write_seg_grad(float* __restrict__ gseg, int64_t
   gseg[6 * n_seg + s] = d.L;
 }
 
-// Backward merge of ray r, tuples gathered from seg_out.
-template <typename R>
+// Backward merge of ray r, tuples gathered from seg_out.  CACHED: rays of up
+// to kCached segments keep their tuples and prefixes in registers (the
+// same values as the parked form below, which the staged kernel's fallback
+// uses alone to stay within its register budget).
+template <typename R, bool CACHED = true>
 __device__ __forceinline__ void bwd_gather_ray(const float* __restrict__ seg_out, int64_t n_seg,
                                                const int64_t* __restrict__ ro,
                                                const int64_t* __restrict__ ids, int64_t n_rays,
@@ -237,7 +240,7 @@ __device__ __forceinline__ void bwd_gather_ray(const float* __restrict__ seg_out
   const RayGrad g{gray[r], gray[n_rays + r], gray[2 * n_rays + r], gray[3 * n_rays + r],
                   gray[4 * n_rays + r], gray[5 * n_rays + r], gray[6 * n_rays + r]};
   const int64_t n = k1 - k0;
-  if (n <= kCached) {
+  if (CACHED && n <= kCached) {
     Tup x[kCached];
     int64_t sid[kCached];
 #pragma unroll
@@ -334,18 +337,24 @@ __global__ __launch_bounds__(kMergeBlock) void merge_bwd_kernel(const float* __r
 // the boundaries, more listed ids than slots, decreasing ray offsets) merges
 // its rays with the gathering form instead, so any layout gives the same
 // result.
+// LDS: the tuples of up to kCoopSlots listed ids (28 B each) plus 5 B of
+// bookkeeping per slot and the region table, 39.6 KB with up to 64 regions:
+// four workgroups per CU.  (256 consecutive rays of the K=64 workload list
+// 1,079 ids on average, at most 1,168 in a sample of 256 blocks; a block
+// over the slots gathers.)
 constexpr int kMaxRegions = 256;
-constexpr int kCoopSlots = 1280;  // listed ids per workgroup (K=64 averages ~1,100)
+constexpr int kCoopSlots = 1152;
 
+template <int RMAX>
 struct CoopStage {
-  int64_t roff[kMaxRegions + 1];
-  int lo[kMaxRegions], hi[kMaxRegions], cnt[kMaxRegions];
-  int base[kMaxRegions + 1];
+  int64_t roff[RMAX + 1];
+  int lo[RMAX], hi[RMAX], cnt[RMAX];
+  int base[RMAX + 1];
   int wsum[kMergeBlock / kWave];
-  int slot[kCoopSlots];      // id - roff[region], then the id's slot
   float tup[7][kCoopSlots];
-  int16_t kid[kCoopSlots];   // region of the listed id (-1: invalid id, skipped)
-  uint8_t wrote[kCoopSlots]; // backward: the slot holds a gradient
+  uint16_t slot[kCoopSlots];  // the listed id's slot
+  int16_t kid[kCoopSlots];    // region of the listed id (-1: invalid id, skipped)
+  uint8_t wrote[kCoopSlots];  // backward: the slot holds a gradient
   int fail;
 };
 
@@ -369,8 +378,10 @@ __device__ __forceinline__ int last_not_above(const T* a, int n, T v) {
 // waits for one round trip per phase, not one per position.
 constexpr int kPerThread = (kCoopSlots + kMergeBlock - 1) / kMergeBlock;
 static_assert(kMaxRegions <= kMergeBlock, "one thread per region in the count scan");
+static_assert(kCoopSlots <= 65535, "16-bit slots");
 
-__device__ __forceinline__ bool coop_stage(CoopStage& st, const float* __restrict__ seg_out,
+template <int RMAX>
+__device__ __forceinline__ bool coop_stage(CoopStage<RMAX>& st, const float* __restrict__ seg_out,
                                            int64_t n_seg, const int64_t* __restrict__ roff,
                                            int n_regions, const int64_t* __restrict__ ids,
                                            int64_t q0, int64_t q1, int64_t k0, int64_t k1,
@@ -410,7 +421,6 @@ __device__ __forceinline__ bool coop_stage(CoopStage& st, const float* __restric
             st.fail = 1;
             k = -1;
           } else {
-            st.slot[p] = static_cast<int>(rel);
             atomicMin(&st.lo[k], static_cast<int>(rel));
             atomicMax(&st.hi[k], static_cast<int>(rel));
             atomicAdd(&st.cnt[k], 1);
@@ -449,7 +459,8 @@ __device__ __forceinline__ bool coop_stage(CoopStage& st, const float* __restric
     const int p = tid + i * kMergeBlock;
     if (p < n) {
       const int k = st.kid[p];
-      if (k >= 0) st.slot[p] = st.base[k] + st.slot[p] - st.lo[k];
+      if (k >= 0)
+        st.slot[p] = static_cast<uint16_t>(st.base[k] + static_cast<int>(idv[i] - st.roff[k]) - st.lo[k]);
     }
   }
   // Contiguous loads, run after run: every load of the thread first, then
@@ -482,7 +493,8 @@ __device__ __forceinline__ bool coop_stage(CoopStage& st, const float* __restric
   return true;
 }
 
-__device__ __forceinline__ Tup lds_tup(const CoopStage& st, int q) {
+template <int RMAX>
+__device__ __forceinline__ Tup lds_tup(const CoopStage<RMAX>& st, int q) {
   return Tup{st.tup[0][q], st.tup[1][q], st.tup[2][q], st.tup[3][q],
              st.tup[4][q], st.tup[5][q], st.tup[6][q]};
 }
@@ -496,12 +508,12 @@ __device__ __forceinline__ void coop_rays(int64_t n_rays, int64_t& r0, int64_t& 
   r1 = r0 + kMergeBlock < n_rays ? r0 + kMergeBlock : n_rays;
 }
 
-template <typename R>
+template <typename R, int RMAX>
 __global__ __launch_bounds__(kMergeBlock) void merge_fwd_regions_kernel(
     const float* __restrict__ seg_out, int64_t n_seg, const int64_t* __restrict__ roff,
     int n_regions, const int64_t* __restrict__ ro, const int64_t* __restrict__ ids,
     int64_t n_rays, float* __restrict__ out) {
-  __shared__ CoopStage st;
+  __shared__ CoopStage<RMAX> st;
   int64_t r0, r1;
   coop_rays(n_rays, r0, r1);
   if (r0 >= n_rays) return;  // the whole workgroup
@@ -525,18 +537,20 @@ __global__ __launch_bounds__(kMergeBlock) void merge_fwd_regions_kernel(
 }
 
 // Backward of one ray from the staged tuples: the ray's positions are taken
-// kCached at a time, last group first; for each group the prefix fold up to
+// kStagedGroup at a time, last group first; for each group the prefix fold up to
 // it is recomputed from LDS and the group's prefixes kept in registers, then
 // the group is swept in reverse with the suffix fold, every gradient
 // replacing its tuple.  Earlier groups are read before any of their slots is
 // overwritten.  The arithmetic is that of the gathering form, step for step.
-template <typename R>
-__device__ __forceinline__ void bwd_staged_ray(CoopStage& st, int64_t q0, int64_t k0, int64_t k1,
-                                               const RayGrad& g) {
+constexpr int kStagedGroup = 4;  // (keeps the backward within 128 VGPRs: four waves per SIMD)
+
+template <typename R, int RMAX>
+__device__ __forceinline__ void bwd_staged_ray(CoopStage<RMAX>& st, int64_t q0, int64_t k0,
+                                               int64_t k1, const RayGrad& g) {
   Suffix<R> S;
   const int64_t n = k1 - k0;
   if (n <= 0) return;
-  for (int64_t c0 = k0 + (n - 1) / kCached * kCached; c0 >= k0; c0 -= kCached) {
+  for (int64_t c0 = k0 + (n - 1) / kStagedGroup * kStagedGroup; c0 >= k0; c0 -= kStagedGroup) {
     Depth<R> ptau;
     float T = 1.f, A = 0.f, D = 0.f;
     for (int64_t q = k0; q < c0; ++q) {
@@ -548,11 +562,11 @@ __device__ __forceinline__ void bwd_staged_ray(CoopStage& st, int64_t q0, int64_
       ptau.add(st.tup[0][s]);
       T = ptau.trans();
     }
-    float PT[kCached], PA[kCached], PD[kCached];
-    int sl[kCached];
-    Tup x[kCached];
+    float PT[kStagedGroup], PA[kStagedGroup], PD[kStagedGroup];
+    int sl[kStagedGroup];
+    Tup x[kStagedGroup];
 #pragma unroll
-    for (int i = 0; i < kCached; ++i) {
+    for (int i = 0; i < kStagedGroup; ++i) {
       const int64_t q = c0 + i;
       sl[i] = -1;
       if (q < k1) {
@@ -569,7 +583,7 @@ __device__ __forceinline__ void bwd_staged_ray(CoopStage& st, int64_t q0, int64_
       }
     }
 #pragma unroll
-    for (int i = kCached - 1; i >= 0; --i) {
+    for (int i = kStagedGroup - 1; i >= 0; --i) {
       if (sl[i] >= 0) {
         const Tup d = seg_grad<R>(PT[i], PA[i], PD[i], x[i], S, g);
         const int s = sl[i];
@@ -583,15 +597,15 @@ __device__ __forceinline__ void bwd_staged_ray(CoopStage& st, int64_t q0, int64_
 }
 
 // Longest ray the staged backward takes (its regrouped prefixes cost
-// O(n^2 / kCached)); a block with a longer ray gathers.
+// O(n^2 / kStagedGroup)); a block with a longer ray gathers.
 constexpr int64_t kStagedMaxSegs = 64;
 
-template <typename R>
+template <typename R, int RMAX>
 __global__ __launch_bounds__(kMergeBlock) void merge_bwd_regions_kernel(
     const float* __restrict__ seg_out, int64_t n_seg, const int64_t* __restrict__ roff,
     int n_regions, const int64_t* __restrict__ ro, const int64_t* __restrict__ ids,
     int64_t n_rays, const float* __restrict__ gray, float* __restrict__ gseg) {
-  __shared__ CoopStage st;
+  __shared__ CoopStage<RMAX> st;
   int64_t r0, r1;
   coop_rays(n_rays, r0, r1);
   if (r0 >= n_rays) return;
@@ -610,10 +624,10 @@ __global__ __launch_bounds__(kMergeBlock) void merge_bwd_regions_kernel(
     g = RayGrad{gray[r], gray[n_rays + r], gray[2 * n_rays + r], gray[3 * n_rays + r],
                 gray[4 * n_rays + r], gray[5 * n_rays + r], gray[6 * n_rays + r]};
   if (!coop_stage(st, seg_out, n_seg, roff, n_regions, ids, q0, q1, k0, k1, own, kStagedMaxSegs)) {
-    if (own) bwd_gather_ray<R>(seg_out, n_seg, ro, ids, n_rays, gray, gseg, r);
+    if (own) bwd_gather_ray<R, false>(seg_out, n_seg, ro, ids, n_rays, gray, gseg, r);
     return;
   }
-  if (own) bwd_staged_ray<R>(st, q0, k0, k1, g);
+  if (own) bwd_staged_ray<R, RMAX>(st, q0, k0, k1, g);
   __syncthreads();
   // Contiguous stores, run after run.
   const int used = st.base[n_regions];
@@ -652,6 +666,30 @@ static inline bool use_regions(const int64_t* roff, int n_regions, int64_t n_seg
   return force || n_seg >= kStagedMinSegs;
 }
 
+template <typename R>
+static void launch_fwd_regions(dim3 grid, const float* seg_out, int64_t n_seg, const int64_t* roff,
+                               int n_regions, const int64_t* ro, const int64_t* ids, int64_t n_rays,
+                               float* out, hipStream_t stream) {
+  if (n_regions <= 64)
+    hipLaunchKernelGGL((merge_fwd_regions_kernel<R, 64>), grid, dim3(kMergeBlock), 0, stream, seg_out,
+                       n_seg, roff, n_regions, ro, ids, n_rays, out);
+  else
+    hipLaunchKernelGGL((merge_fwd_regions_kernel<R, kMaxRegions>), grid, dim3(kMergeBlock), 0, stream,
+                       seg_out, n_seg, roff, n_regions, ro, ids, n_rays, out);
+}
+
+template <typename R>
+static void launch_bwd_regions(dim3 grid, const float* seg_out, int64_t n_seg, const int64_t* roff,
+                               int n_regions, const int64_t* ro, const int64_t* ids, int64_t n_rays,
+                               const float* gray, float* gseg, hipStream_t stream) {
+  if (n_regions <= 64)
+    hipLaunchKernelGGL((merge_bwd_regions_kernel<R, 64>), grid, dim3(kMergeBlock), 0, stream, seg_out,
+                       n_seg, roff, n_regions, ro, ids, n_rays, gray, gseg);
+  else
+    hipLaunchKernelGGL((merge_bwd_regions_kernel<R, kMaxRegions>), grid, dim3(kMergeBlock), 0, stream,
+                       seg_out, n_seg, roff, n_regions, ro, ids, n_rays, gray, gseg);
+}
+
 hipError_t launch_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* roff,
                             int n_regions, const int64_t* ro, const int64_t* ids, int64_t n_rays,
                             float* out, bool fp64, bool staged, hipStream_t stream) {
@@ -659,11 +697,9 @@ hipError_t launch_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* 
   const dim3 grid(merge_grid(n_rays)), block(kMergeBlock);
   if (use_regions(roff, n_regions, n_seg, staged)) {
     if (fp64)
-      hipLaunchKernelGGL(merge_fwd_regions_kernel<double>, grid, block, 0, stream, seg_out, n_seg,
-                         roff, n_regions, ro, ids, n_rays, out);
+      launch_fwd_regions<double>(grid, seg_out, n_seg, roff, n_regions, ro, ids, n_rays, out, stream);
     else
-      hipLaunchKernelGGL(merge_fwd_regions_kernel<float>, grid, block, 0, stream, seg_out, n_seg,
-                         roff, n_regions, ro, ids, n_rays, out);
+      launch_fwd_regions<float>(grid, seg_out, n_seg, roff, n_regions, ro, ids, n_rays, out, stream);
   } else if (fp64) {
     hipLaunchKernelGGL(merge_fwd_kernel<double>, grid, block, kMergeLds, stream, seg_out, n_seg,
                        ro, ids, n_rays, out);
@@ -682,11 +718,11 @@ hipError_t launch_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* 
   const dim3 grid(merge_grid(n_rays)), block(kMergeBlock);
   if (use_regions(roff, n_regions, n_seg, staged)) {
     if (fp64)
-      hipLaunchKernelGGL(merge_bwd_regions_kernel<double>, grid, block, 0, stream, seg_out, n_seg,
-                         roff, n_regions, ro, ids, n_rays, gray, gseg);
+      launch_bwd_regions<double>(grid, seg_out, n_seg, roff, n_regions, ro, ids, n_rays, gray, gseg,
+                                 stream);
     else
-      hipLaunchKernelGGL(merge_bwd_regions_kernel<float>, grid, block, 0, stream, seg_out, n_seg,
-                         roff, n_regions, ro, ids, n_rays, gray, gseg);
+      launch_bwd_regions<float>(grid, seg_out, n_seg, roff, n_regions, ro, ids, n_rays, gray, gseg,
+                                stream);
   } else if (fp64) {
     hipLaunchKernelGGL(merge_bwd_kernel<double>, grid, block, kMergeLds, stream, seg_out, n_seg,
                        ro, ids, n_rays, gray, gseg);
