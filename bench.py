@@ -107,11 +107,11 @@ class Form:
         self.region_offsets = region_offsets
         self.n, self.n_seg, self.n_rays = sigma.shape[0], seg_offsets.shape[0] - 1, ray_offsets.shape[0] - 1
         dev = sigma.device
-        self.seg_out = torch.empty((7, self.n_seg), dtype=torch.float32, device=dev)
+        self.seg_out = xl.tuple_buffer(self.n_seg, dev)
         self.ws = torch.empty(xl.xl_segments_workspace_bytes(self.n), dtype=torch.uint8, device=dev)
         self.ray_out = torch.empty((7, self.n_rays), dtype=torch.float32, device=dev)
         self.grad_ray = grad_ray
-        self.grad_seg = torch.zeros((7, self.n_seg), dtype=torch.float32, device=dev)
+        self.grad_seg = xl.tuple_buffer(self.n_seg, dev, zero=True)
         self.gs = torch.empty_like(sigma)
         self.gc = torch.empty_like(rgb)
 

@@ -27,10 +27,13 @@
  *     colour and interval ends in any finite range.
  *   - Segment tuple (what each region reduces its samples to before any
  *     exchange, App. A.2):
- *     seg_out is structure-of-arrays float32 [7][n_seg]:
+ *     seg_out is float32 [n_seg][XL_TUPLE_STRIDE]: one 32-byte record per
+ *     segment (array 16-byte aligned), words
  *       0 tau = sum sigma_i delta_i  (segment transmittance is exp(-tau))
  *       1-3 C = sum w_i c_i, 4 A = sum w_i, 5 D = sum w_i m_i (unnormalised),
  *       6 L = sum_ij w_i w_j |m_i - m_j| + 1/3 sum_i w_i^2 delta_i,
+ *       7 zero (written as 0, ignored when read);
+ *     gradients with respect to the tuples (grad_seg) use the same records.
  *     with delta_i = t_end - t_start, m_i the interval midpoint, alpha_i =
  *     1 - exp(-sigma_i delta_i), w_i = alpha_i prod_{j<i} (1 - alpha_j) taken
  *     inside the segment (transmittance starts at 1).  An empty segment has
@@ -40,6 +43,9 @@
  */
 #ifndef XL_H
 #define XL_H
+
+/* Words per segment tuple record (seg_out, grad_seg); see the conventions. */
+#define XL_TUPLE_STRIDE 8
 
 #include <stddef.h>
 #include <stdint.h>
@@ -98,11 +104,13 @@ size_t xl_segments_workspace_bytes(int64_t n);
  *   s            samples (device arrays, see conventions)
  *   seg_offsets  device int64 [n_seg + 1], non-decreasing, seg_offsets[0] = 0,
  *                seg_offsets[n_seg] = s->n
- *   seg_out      device float32 [7][n_seg], written (every segment)
+ *   seg_out      device float32 [n_seg][XL_TUPLE_STRIDE], 16-byte aligned,
+ *                written (every segment)
  *   workspace    device, >= xl_segments_workspace_bytes(s->n) bytes, written;
  *                keep it unchanged for the matching backward call
  * Errors: XL_EINVAL for null pointers, bad dtype, negative sizes, misaligned
- * sample arrays or a workspace that is too small; XL_EHIP if a launch fails.
+ * sample arrays or seg_out, or a workspace that is too small; XL_EHIP if a
+ * launch fails.
  */
 int xl_render_segments_fwd(const xl_samples* s, const int64_t* seg_offsets, int64_t n_seg,
                            float* seg_out, void* workspace, size_t workspace_bytes,
@@ -134,7 +142,8 @@ int xl_render_segments_fwd_static(const xl_samples* s, const int64_t* seg_offset
 
 /*
  * Per-segment composite, backward.  Given grad_seg = dl/d(seg tuple) (device
- * float32 [7][n_seg], component 0 is dl/dtau), writes dl/dsigma (device [n])
+ * float32 [n_seg][XL_TUPLE_STRIDE], 16-byte aligned, word 0 is dl/dtau, word 7
+ * ignored), writes dl/dsigma (device [n])
  * and dl/drgb (device [n][3]) in the storage dtype of `s`, overwriting them.
  * Transmittance is recomputed (forward and reverse wave scans); nothing per
  * sample is kept from the forward.  `workspace` must hold what the forward
@@ -148,9 +157,10 @@ int xl_render_segments_bwd(const xl_samples* s, const int64_t* seg_offsets, int6
 /*
  * Merge of segment tuples in ray order (Eq. 3-8; Alg. 1 and 2 of App. A.2
  * with Eq. 7's factor 2 and each segment's own A, D in the cross term).
- *   seg_out         device float32 [7][n_seg] from xl_render_segments_fwd
+ *   seg_out         device float32 [n_seg][XL_TUPLE_STRIDE] from
+ *                   xl_render_segments_fwd (16-byte aligned)
  *   region_offsets  device int64 [n_regions + 1] or NULL: region k's tuples
- *                   are seg_out[:, region_offsets[k] .. region_offsets[k+1])
+ *                   are records region_offsets[k] .. region_offsets[k+1] - 1
  *                   (the sample layout packs each region's segments in ray
  *                   order, so consecutive rays list consecutive tuples of
  *                   each region).  Given (1 <= n_regions <= 256) and from
@@ -186,8 +196,9 @@ int xl_merge_fwd(const float* seg_out, int64_t n_seg, const int64_t* region_offs
 /*
  * Merge, backward: grad_ray = dl/d(T, r, g, b, A, D, L) (device float32
  * [7][n_rays]) -> grad_seg = dl/d(tau, r, g, b, A, D, L) of every segment
- * listed in seg_ids (device float32 [7][n_seg], overwritten there; entries of
- * segments that no ray lists are left untouched).  Each segment is listed by
+ * listed in seg_ids (device float32 [n_seg][XL_TUPLE_STRIDE], 16-byte aligned;
+ * the records of listed segments are overwritten, word 7 with 0, and the
+ * records of segments that no ray lists are left untouched).  Each segment is listed by
  * at most one ray.  Exclusive prefix and suffix folds per ray; the paper's
  * rule that each region differentiates only through its own tuple (Sec. 4.2,
  * App. A.2) is exactly this per-segment Jacobian.  Arguments as for the

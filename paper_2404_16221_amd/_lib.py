@@ -42,6 +42,7 @@ def storage_dtypes(dtype):
     return tuple(dtype) if isinstance(dtype, (tuple, list)) else (dtype, dtype)
 TORCH_DTYPES = {v: k for k, v in DTYPES.items()}
 TUPLE = 7
+TUPLE_STRIDE = 8  # XL_TUPLE_STRIDE: words per segment tuple record
 
 _c = ctypes
 _vp, _i64, _i32, _sz = _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_size_t
@@ -160,6 +161,39 @@ def _dev(t: torch.Tensor, name: str, dtype=None) -> int:
     return t.data_ptr() if t.numel() else 0
 
 
+def tuple_buffer(n_seg: int, device, zero: bool = False) -> torch.Tensor:
+    """Segment tuples (or their gradients) as the library stores them, one
+    record of TUPLE_STRIDE floats per segment, seen as the [7, n_seg] tensor of
+    components (a strided view; the pad word stays out of it)."""
+    alloc = torch.zeros if zero else torch.empty
+    return alloc((n_seg, TUPLE_STRIDE), dtype=torch.float32, device=device)[:, :TUPLE].t()
+
+
+def as_tuples(x: torch.Tensor) -> torch.Tensor:
+    """A copy of [7, n_seg] components in tuple records (see tuple_buffer)."""
+    if x.dim() != 2 or x.shape[0] != TUPLE:
+        raise ValueError("expected [7, n_seg] tuple components")
+    out = tuple_buffer(x.shape[1], x.device, zero=True)
+    out.copy_(x)
+    return out
+
+
+def _tup(t: torch.Tensor, name: str) -> int:
+    """Pointer of a tuple array: a [7, n_seg] view made by tuple_buffer (or
+    any [7, n_seg] float32 view with strides (1, TUPLE_STRIDE) over
+    16-byte-aligned records)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+        raise ValueError(f"{name} must be a float32 CUDA tensor")
+    if t.dim() != 2 or t.shape[0] != TUPLE:
+        raise ValueError(f"{name} must be [7, n_seg] (see tuple_buffer)")
+    if t.shape[1] == 0:
+        return 0
+    if t.stride(0) != 1 or (t.shape[1] > 1 and t.stride(1) != TUPLE_STRIDE):
+        raise ValueError(f"{name} must be tuple records: a [7, n_seg] view with strides "
+                         f"(1, {TUPLE_STRIDE}) from tuple_buffer or as_tuples")
+    return t.data_ptr()
+
+
 def samples(sigma, rgb, t_start, t_end) -> XLSamples:
     code = storage_code(sigma.dtype, rgb.dtype)
     n = sigma.shape[0]
@@ -179,17 +213,18 @@ def xl_segments_workspace_bytes(n: int) -> int:
 
 def xl_render_segments_fwd(sigma, rgb, t_start, t_end, seg_offsets, seg_out=None,
                            workspace=None) -> Tuple[torch.Tensor, torch.Tensor]:
-    """seg_out[7, n_seg] and the workspace the backward needs."""
+    """seg_out[7, n_seg] (a view of the tuple records, see tuple_buffer) and
+    the workspace the backward needs."""
     s = samples(sigma, rgb, t_start, t_end)
     n_seg = seg_offsets.shape[0] - 1
     dev = sigma.device
     if seg_out is None:
-        seg_out = torch.empty((TUPLE, n_seg), dtype=torch.float32, device=dev)
+        seg_out = tuple_buffer(n_seg, dev)
     wsb = xl_segments_workspace_bytes(s.n)
     if workspace is None:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
     _check(lib().xl_render_segments_fwd(ctypes.byref(s), _dev(seg_offsets, "seg_offsets", torch.int64),
-                                        n_seg, _dev(seg_out, "seg_out", torch.float32),
+                                        n_seg, _tup(seg_out, "seg_out"),
                                         _dev(workspace, "workspace"), workspace.numel(), _stream()))
     return seg_out, workspace
 
@@ -201,10 +236,10 @@ def xl_render_segments_fwd_static(sigma, rgb, t_start, t_end, seg_offsets,
     s = samples(sigma, rgb, t_start, t_end)
     n_seg = seg_offsets.shape[0] - 1
     if seg_out is None:
-        seg_out = torch.empty((TUPLE, n_seg), dtype=torch.float32, device=sigma.device)
+        seg_out = tuple_buffer(n_seg, sigma.device)
     _check(lib().xl_render_segments_fwd_static(ctypes.byref(s),
                                                _dev(seg_offsets, "seg_offsets", torch.int64), n_seg,
-                                               _dev(seg_out, "seg_out", torch.float32), _stream()))
+                                               _tup(seg_out, "seg_out"), _stream()))
     return seg_out
 
 
@@ -219,7 +254,7 @@ def xl_render_segments_bwd(sigma, rgb, t_start, t_end, seg_offsets, workspace, g
         grad_rgb = torch.empty_like(rgb)
     _check(lib().xl_render_segments_bwd(ctypes.byref(s), _dev(seg_offsets, "seg_offsets", torch.int64),
                                         n_seg, _dev(workspace, "workspace"), workspace.numel(),
-                                        _dev(grad_seg, "grad_seg", torch.float32),
+                                        _tup(grad_seg, "grad_seg"),
                                         _dev(grad_sigma, "grad_sigma", sigma.dtype),
                                         _dev(grad_rgb, "grad_rgb", rgb.dtype), _stream()))
     return grad_sigma, grad_rgb
@@ -251,7 +286,7 @@ def xl_merge_fwd(seg_out, ray_offsets, seg_ids, ray_out=None, fp64: bool = False
     n_rays = ray_offsets.shape[0] - 1
     if ray_out is None:
         ray_out = torch.empty((TUPLE, n_rays), dtype=torch.float32, device=seg_out.device)
-    _check(lib().xl_merge_fwd(_dev(seg_out, "seg_out", torch.float32), n_seg,
+    _check(lib().xl_merge_fwd(_tup(seg_out, "seg_out"), n_seg,
                               *_regions(region_offsets),
                               _dev(ray_offsets, "ray_offsets", torch.int64),
                               _dev(seg_ids, "seg_ids", torch.int64), n_rays,
@@ -262,18 +297,19 @@ def xl_merge_fwd(seg_out, ray_offsets, seg_ids, ray_out=None, fp64: bool = False
 
 def xl_merge_bwd(seg_out, ray_offsets, seg_ids, grad_ray, grad_seg=None,
                  fp64: bool = False, region_offsets=None, staged: bool = False) -> torch.Tensor:
-    """grad_seg[7, n_seg] = dl/d(tau, r, g, b, A, D, L) of each listed segment."""
+    """grad_seg[7, n_seg] = dl/d(tau, r, g, b, A, D, L) of each listed segment
+    (tuple records, see tuple_buffer)."""
     _check_ids(seg_out, seg_ids)
     n_seg = seg_out.shape[1]
     n_rays = ray_offsets.shape[0] - 1
     if grad_seg is None:
-        grad_seg = torch.zeros((TUPLE, n_seg), dtype=torch.float32, device=seg_out.device)
-    _check(lib().xl_merge_bwd(_dev(seg_out, "seg_out", torch.float32), n_seg,
+        grad_seg = tuple_buffer(n_seg, seg_out.device, zero=True)
+    _check(lib().xl_merge_bwd(_tup(seg_out, "seg_out"), n_seg,
                               *_regions(region_offsets),
                               _dev(ray_offsets, "ray_offsets", torch.int64),
                               _dev(seg_ids, "seg_ids", torch.int64), n_rays,
                               _dev(grad_ray, "grad_ray", torch.float32),
-                              _dev(grad_seg, "grad_seg", torch.float32),
+                              _tup(grad_seg, "grad_seg"),
                               _merge_flags(fp64, staged), _stream()))
     return grad_seg
 

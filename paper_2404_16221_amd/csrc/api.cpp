@@ -91,6 +91,7 @@ int xl_render_segments_fwd(const xl_samples* s, const int64_t* seg_offsets, int6
   if (rc) return rc;
   if ((rc = check_segments(d, seg_offsets, n_seg))) return rc;
   if (n_seg > 0 && seg_out == nullptr) return fail(XL_EINVAL, "seg_out is NULL");
+  if (!aligned16(seg_out)) return fail(XL_EINVAL, "seg_out must be 16-byte aligned");
   if (d.n > 0) {
     if (workspace == nullptr) return fail(XL_EINVAL, "workspace is NULL");
     if (!aligned16(workspace)) return fail(XL_EINVAL, "workspace must be 16-byte aligned");
@@ -111,6 +112,7 @@ int xl_render_segments_fwd_static(const xl_samples* s, const int64_t* seg_offset
   if (rc) return rc;
   if ((rc = check_segments(d, seg_offsets, n_seg))) return rc;
   if (n_seg > 0 && seg_out == nullptr) return fail(XL_EINVAL, "seg_out is NULL");
+  if (!aligned16(seg_out)) return fail(XL_EINVAL, "seg_out must be 16-byte aligned");
   const size_t need = xl_segments_workspace_bytes(d.n);
   if (need > static_cast<size_t>(XL_STATIC_SCRATCH_BYTES))
     return fail(XL_EINVAL,
@@ -137,7 +139,7 @@ int xl_render_segments_bwd(const xl_samples* s, const int64_t* seg_offsets, int6
   if (d.n > 0) {
     if (workspace == nullptr || grad_seg == nullptr || grad_sigma == nullptr || grad_rgb == nullptr)
       return fail(XL_EINVAL, "NULL workspace or gradient array");
-    if (!aligned16(workspace) || !aligned16(grad_sigma) || !aligned16(grad_rgb))
+    if (!aligned16(workspace) || !aligned16(grad_seg) || !aligned16(grad_sigma) || !aligned16(grad_rgb))
       return fail(XL_EINVAL, "workspace and gradient arrays must be 16-byte aligned");
     if (workspace_bytes < xl_segments_workspace_bytes(d.n))
       return fail(XL_EINVAL, "workspace too small: %zu < %zu bytes", workspace_bytes,
@@ -158,6 +160,7 @@ static int check_merge_args(const float* seg_out, int64_t n_seg, const int64_t* 
   if (n_rays > 0 && ray_offsets == nullptr) return fail(XL_EINVAL, "ray_offsets is NULL");
   if (n_seg > 0 && (seg_out == nullptr || seg_ids == nullptr))
     return fail(XL_EINVAL, "seg_out or seg_ids is NULL");
+  if (!aligned16(seg_out)) return fail(XL_EINVAL, "seg_out must be 16-byte aligned");
   if (region_offsets != nullptr && n_regions < 1)
     return fail(XL_EINVAL, "n_regions %d with region_offsets given", n_regions);
   return XL_OK;
@@ -186,6 +189,7 @@ int xl_merge_bwd(const float* seg_out, int64_t n_seg, const int64_t* region_offs
   if (rc) return rc;
   if (n_rays > 0 && (grad_ray == nullptr || (n_seg > 0 && grad_seg == nullptr)))
     return fail(XL_EINVAL, "grad_ray or grad_seg is NULL");
+  if (!aligned16(grad_seg)) return fail(XL_EINVAL, "grad_seg must be 16-byte aligned");
   return hip_status(xl::launch_merge_bwd(seg_out, n_seg, region_offsets, n_regions, ray_offsets,
                                          seg_ids, n_rays, grad_ray, grad_seg,
                                          (flags & XL_MERGE_FP64) != 0,

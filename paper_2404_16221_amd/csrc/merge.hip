@@ -73,11 +73,9 @@ struct Tup {
   float tau, cr, cg, cb, A, D, L;
 };
 
-__device__ __forceinline__ Tup load_tup(const float* __restrict__ p, int64_t n_seg, int64_t s) {
-  Tup x;
-  x.tau = p[s]; x.cr = p[n_seg + s]; x.cg = p[2 * n_seg + s]; x.cb = p[3 * n_seg + s];
-  x.A = p[4 * n_seg + s]; x.D = p[5 * n_seg + s]; x.L = p[6 * n_seg + s];
-  return x;
+__device__ __forceinline__ Tup load_tup(const float* __restrict__ p, int64_t s) {
+  const Tup7 t = load_tup7(p, s);
+  return Tup{t.v[0], t.v[1], t.v[2], t.v[3], t.v[4], t.v[5], t.v[6]};
 }
 
 __device__ __forceinline__ void clamp_range(const int64_t* __restrict__ ro, int64_t r, int64_t n_seg,
@@ -149,7 +147,7 @@ __device__ __forceinline__ void fwd_gather_ray(const float* __restrict__ seg_out
     }
 #pragma unroll
     for (int q = 0; q < kCached; ++q)
-      if (sid[q] >= 0) x[q] = load_tup(seg_out, n_seg, sid[q]);
+      if (sid[q] >= 0) x[q] = load_tup(seg_out, sid[q]);
 #pragma unroll
     for (int q = 0; q < kCached; ++q)
       if (sid[q] >= 0) f.step(x[q]);
@@ -157,7 +155,7 @@ __device__ __forceinline__ void fwd_gather_ray(const float* __restrict__ seg_out
     for (int64_t k = k0; k < k1; ++k) {
       const int64_t s = ids[k];
       if (s < 0 || s >= n_seg) continue;
-      f.step(load_tup(seg_out, n_seg, s));
+      f.step(load_tup(seg_out, s));
     }
   }
   f.store(out, n_rays, r);
@@ -216,13 +214,7 @@ __device__ __forceinline__ void write_seg_grad(float* __restrict__ gseg, int64_t
                                                float PT, float PA, float PD, const Tup& x,
                                                const Suffix<R>& S, const RayGrad& g) {
   const Tup d = seg_grad<R>(PT, PA, PD, x, S, g);
-  gseg[s] = d.tau;
-  gseg[n_seg + s] = d.cr;
-  gseg[2 * n_seg + s] = d.cg;
-  gseg[3 * n_seg + s] = d.cb;
-  gseg[4 * n_seg + s] = d.A;
-  gseg[5 * n_seg + s] = d.D;
-  gseg[6 * n_seg + s] = d.L;
+  store_tup7(gseg, s, d.tau, d.cr, d.cg, d.cb, d.A, d.D, d.L);
 }
 
 // Backward merge of ray r, tuples gathered from seg_out.  CACHED: rays of up
@@ -251,7 +243,7 @@ __device__ __forceinline__ void bwd_gather_ray(const float* __restrict__ seg_out
     // Invalid ids inside the ray are identities (zero tuples).
 #pragma unroll
     for (int q = 0; q < kCached; ++q)
-      x[q] = sid[q] >= 0 ? load_tup(seg_out, n_seg, sid[q]) : Tup{0, 0, 0, 0, 0, 0, 0};
+      x[q] = sid[q] >= 0 ? load_tup(seg_out, sid[q]) : Tup{0, 0, 0, 0, 0, 0, 0};
     // Forward sweep: exclusive prefix transmittance, opacity and depth.  Slots
     // past the ray's last segment are skipped (by the whole wave when no ray
     // of it has that many).
@@ -280,17 +272,17 @@ __device__ __forceinline__ void bwd_gather_ray(const float* __restrict__ seg_out
     return;
   }
   // Forward sweep: the exclusive prefix (P_T, P_A, P_D) of every segment,
-  // parked in the segment's own tau, A and D gradient entries.
+  // parked in the first three words of the segment's own gradient record.
   {
     Depth<R> ptau;
     float T = 1.f, A = 0.f, D = 0.f;
     for (int64_t k = k0; k < k1; ++k) {
       const int64_t s = ids[k];
       if (s < 0 || s >= n_seg) continue;
-      const Tup x = load_tup(seg_out, n_seg, s);
-      gseg[s] = T;
-      gseg[4 * n_seg + s] = A;
-      gseg[5 * n_seg + s] = D;
+      const Tup x = load_tup(seg_out, s);
+      gseg[kTupStride * s] = T;
+      gseg[kTupStride * s + 1] = A;
+      gseg[kTupStride * s + 2] = D;
       A += T * x.A;
       D += T * x.D;
       ptau.add(x.tau);
@@ -302,8 +294,8 @@ __device__ __forceinline__ void bwd_gather_ray(const float* __restrict__ seg_out
   for (int64_t k = k1 - 1; k >= k0; --k) {
     const int64_t s = ids[k];
     if (s < 0 || s >= n_seg) continue;
-    const Tup x = load_tup(seg_out, n_seg, s);
-    const float PT = gseg[s], PA = gseg[4 * n_seg + s], PD = gseg[5 * n_seg + s];
+    const Tup x = load_tup(seg_out, s);
+    const float PT = gseg[kTupStride * s], PA = gseg[kTupStride * s + 1], PD = gseg[kTupStride * s + 2];
     write_seg_grad<R>(gseg, n_seg, s, PT, PA, PD, x, S, g);
     S.push_front(x, exp_neg(x.tau));
   }
@@ -476,17 +468,15 @@ __device__ __forceinline__ bool coop_stage(CoopStage<RMAX>& st, const float* __r
       src[i] = st.roff[k] + st.lo[k] + (q - st.base[k]);
     }
   }
-  float v[kPerThread][7];
+  Tup7 v[kPerThread];
 #pragma unroll
-  for (int i = 0; i < kPerThread; ++i)
-#pragma unroll
-    for (int f = 0; f < 7; ++f) v[i][f] = src[i] >= 0 ? seg_out[f * n_seg + src[i]] : 0.f;
+  for (int i = 0; i < kPerThread; ++i) v[i] = src[i] >= 0 ? load_tup7(seg_out, src[i]) : Tup7{};
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) {
     const int q = tid + i * kMergeBlock;
     if (q < used) {
 #pragma unroll
-      for (int f = 0; f < 7; ++f) st.tup[f][q] = v[i][f];
+      for (int f = 0; f < 7; ++f) st.tup[f][q] = v[i].v[f];
     }
   }
   __syncthreads();
@@ -637,8 +627,8 @@ __global__ __launch_bounds__(kMergeBlock) void merge_bwd_regions_kernel(
     if (q < used && st.wrote[q]) {
       const int k = last_not_above(st.base, n_regions, q);
       const int64_t id = st.roff[k] + st.lo[k] + (q - st.base[k]);
-#pragma unroll
-      for (int f = 0; f < 7; ++f) gseg[f * n_seg + id] = st.tup[f][q];
+      store_tup7(gseg, id, st.tup[0][q], st.tup[1][q], st.tup[2][q], st.tup[3][q], st.tup[4][q],
+                 st.tup[5][q], st.tup[6][q]);
     }
   }
 }

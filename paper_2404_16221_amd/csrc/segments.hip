@@ -50,19 +50,12 @@ __global__ void fill_zero_kernel(float* __restrict__ p, int64_t count) {
   if (i < count) p[i] = 0.f;
 }
 
-__device__ __forceinline__ void write_tuple(float* __restrict__ out, int64_t n_seg, int64_t s,
-                                            const Range& r, float tlo = 0.f) {
-  out[s] = r.tau + tlo;
-  out[n_seg + s] = r.cr;
-  out[2 * n_seg + s] = r.cg;
-  out[3 * n_seg + s] = r.cb;
-  out[4 * n_seg + s] = r.A;
-  out[5 * n_seg + s] = fmaf(r.A, r.m0, r.F);  // D = sum w m
-  out[6 * n_seg + s] = r.L;
+__device__ __forceinline__ void write_tuple(float* __restrict__ out, int64_t s, const Range& r,
+                                            float tlo = 0.f) {
+  store_tup7(out, s, r.tau + tlo, r.cr, r.cg, r.cb, r.A, fmaf(r.A, r.m0, r.F) /* D = sum w m */, r.L);
 }
-__device__ __forceinline__ void write_tuple(float* __restrict__ out, int64_t n_seg, int64_t s,
-                                            const Part& p) {
-  write_tuple(out, n_seg, s, p.r, p.tlo);
+__device__ __forceinline__ void write_tuple(float* __restrict__ out, int64_t s, const Part& p) {
+  write_tuple(out, s, p.r, p.tlo);
 }
 
 // Stage the segment ends of tile t in LDS and return how many segments the
@@ -92,7 +85,7 @@ __device__ __forceinline__ int64_t stage_ends(const int64_t* __restrict__ off, i
       if (in) {
         if (a >= e1) {
           if (WRITE_EMPTY && a >= base) {
-            write_tuple(seg_out, n_seg, sg, range_identity());
+            write_tuple(seg_out, sg, range_identity());
           }
         } else {
           const int64_t e = e1 - 1;
@@ -100,9 +93,10 @@ __device__ __forceinline__ int64_t stage_ends(const int64_t* __restrict__ off, i
             const int loc = static_cast<int>(sg - s_lo);
             endloc[e - base] = loc;
             if (gl != nullptr && loc < kStagedSegs) {
+              const Tup7 g = load_tup7(gseg, sg);
 #pragma unroll
-              for (int k = 0; k < 6; ++k) gl[k * kStagedSegs + loc] = gseg[k * n_seg + sg];
-              gl[6 * kStagedSegs + loc] = 2.f * gseg[6 * n_seg + sg];  // the sweep uses 2 g_L
+              for (int k = 0; k < 6; ++k) gl[k * kStagedSegs + loc] = g.v[k];
+              gl[6 * kStagedSegs + loc] = 2.f * g.v[6];  // the sweep uses 2 g_L
             }
           }
           if (a <= last && last <= e) *tailseg = sg;
@@ -170,26 +164,22 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
   R.load(s, endloc, lane, start_head, t * kTile, raw);
 
   // The segment ends are in registers now; their LDS space stages the tuples of
-  // segments that end in this tile (slot = local segment id), which are
-  // written to seg_out at the end with one coalesced store per component.
-  static_assert(7 * kStagedSegs + kStagedSegs <= kTile, "staging must fit the end table");
+  // segments that end in this tile as kTupStride-word records (slot = local
+  // segment id; the last word marks a slot written), which go to seg_out at
+  // the end as 16-byte stores of consecutive records.
+  static_assert(kTupStride * kStagedSegs <= kTile, "staging must fit the end table");
   // (kept as int so the compiler orders it with the end table's reads)
-  int* obuf = endloc;                      // [7][kStagedSegs] float bits
-  int* ovalid = endloc + 7 * kStagedSegs;  // [kStagedSegs]
+  int* obuf = endloc;  // [kStagedSegs][kTupStride] float bits
   const bool staged = n_win <= kStagedSegs;  // uniform: no divergence on the path
-  if (lane < kStagedSegs) ovalid[lane] = 0;
+  if (lane < kStagedSegs) obuf[lane * kTupStride + 7] = 0;
   auto emit = [&](int loc, const Range& r) {
     if (staged) {
-      obuf[0 * kStagedSegs + loc] = __float_as_int(r.tau);
-      obuf[1 * kStagedSegs + loc] = __float_as_int(r.cr);
-      obuf[2 * kStagedSegs + loc] = __float_as_int(r.cg);
-      obuf[3 * kStagedSegs + loc] = __float_as_int(r.cb);
-      obuf[4 * kStagedSegs + loc] = __float_as_int(r.A);
-      obuf[5 * kStagedSegs + loc] = __float_as_int(fmaf(r.A, r.m0, r.F));
-      obuf[6 * kStagedSegs + loc] = __float_as_int(r.L);
-      ovalid[loc] = 1;
+      int4* o = reinterpret_cast<int4*>(obuf + loc * kTupStride);
+      o[0] = make_int4(__float_as_int(r.tau), __float_as_int(r.cr), __float_as_int(r.cg),
+                       __float_as_int(r.cb));
+      o[1] = make_int4(__float_as_int(r.A), __float_as_int(fmaf(r.A, r.m0, r.F)), __float_as_int(r.L), 1);
     } else {
-      write_tuple(seg_out, n_seg, s_lo + loc, r);
+      write_tuple(seg_out, s_lo + loc, r);
     }
   };
 
@@ -242,12 +232,19 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
       recs.put(recs.head, t, lane > 0 ? combine(ex, pend) : pend);
     }
   }
-  // Staged tuples out (LDS operations of one wave complete in order).
+  // Staged tuples out (LDS operations of one wave complete in order): lane q
+  // stores half q % 2 of slot q / 2, the pad word as zero.
   wave_lds_fence();
-  if (staged && lane < kStagedSegs && ovalid[lane]) {
-    const int64_t sg = s_lo + lane;
-#pragma unroll
-    for (int k = 0; k < 7; ++k) seg_out[k * n_seg + sg] = __int_as_float(obuf[k * kStagedSegs + lane]);
+  if (staged) {
+    for (int q = lane; q < 2 * static_cast<int>(n_win); q += kWave) {
+      const int slot = q >> 1;
+      const int4 w = reinterpret_cast<const int4*>(obuf + slot * kTupStride)[q & 1];
+      if (obuf[slot * kTupStride + 7]) {
+        float4* o = reinterpret_cast<float4*>(seg_out + kTupStride * (s_lo + slot)) + (q & 1);
+        *o = make_float4(__int_as_float(w.x), __int_as_float(w.y), __int_as_float(w.z),
+                         (q & 1) ? 0.f : __int_as_float(w.w));
+      }
+    }
   }
   const unsigned long long end_mask = __ballot(any_end);
   const unsigned long long head_mask = __ballot(any_head);
@@ -272,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
                                                          int64_t t_first, int64_t t_end,
                                                          float* __restrict__ seg_out,
                                                          TileRecs recs) {
-  __shared__ int endloc_all[kWavesPerBlock][kTile];
+  __shared__ __align__(16) int endloc_all[kWavesPerBlock][kTile];
   __shared__ float park_all[kWavesPerBlock][kRangeFields * kWave];
   __shared__ int64_t tailseg_all[kWavesPerBlock];
   // wave index made provably uniform, so per-tile loads go through the scalar unit
@@ -333,7 +330,7 @@ __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restri
         recs.put(recs.pre, u, acc);
         if (fu & kHasEnd) {
           const int64_t sgi = recs.first_seg[u];
-          if (sgi >= 0 && sgi < n_seg) write_tuple(seg_out, n_seg, sgi, combine(acc, recs.get(recs.head, u)));
+          if (sgi >= 0 && sgi < n_seg) write_tuple(seg_out, sgi, combine(acc, recs.get(recs.head, u)));
         }
       }
       if (fu & kHasHead) break;
@@ -400,10 +397,10 @@ __device__ __forceinline__ void reverse_step(const Smp& q, float PTj, float PZj,
 #pragma unroll
         for (int k = 0; k < 7; ++k) g[k] = gl[k * kStagedSegs + endloc_j];
       } else {
-        const int64_t sgi = s_lo + endloc_j;
+        const Tup7 t = load_tup7(gseg, s_lo + endloc_j);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) g[k] = gseg[k * n_seg + sgi];
-        g[6] = 2.f * gseg[6 * n_seg + sgi];
+        for (int k = 0; k < 6; ++k) g[k] = t.v[k];
+        g[6] = 2.f * t.v[6];
       }
     }
   }
@@ -453,8 +450,9 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
     if (tail_open) {
       suf_t = recs.get(recs.suf, t);
       if (ts >= 0 && ts < n_seg) {
+        const Tup7 t = load_tup7(gseg, ts);
 #pragma unroll
-        for (int k = 0; k < 7; ++k) gt[k] = gseg[k * n_seg + ts];
+        for (int k = 0; k < 7; ++k) gt[k] = t.v[k];
         gt[6] *= 2.f;
       }
     }
@@ -555,9 +553,9 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
 #pragma unroll
         for (int k = 0; k < 7; ++k) g[k] = gl[k * kStagedSegs + sxseg];
       } else {
-        const int64_t cseg = s_lo + sxseg;
+        const Tup7 t = load_tup7(gseg, s_lo + sxseg);
 #pragma unroll
-        for (int k = 0; k < 7; ++k) g[k] = gseg[k * n_seg + cseg];
+        for (int k = 0; k < 7; ++k) g[k] = t.v[k];
         g[6] *= 2.f;
       }
     } else if (tail_open) {
@@ -712,7 +710,7 @@ __device__ __forceinline__ void seg_bwd_body(
     const SamplesDev& s, const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
     int64_t t_first, int64_t t_end, const TileRecs& recs,
     const float* __restrict__ gseg, void* __restrict__ gsig_p, void* __restrict__ grgb_p) {
-  __shared__ int endloc_all[kWavesPerBlock][kTile];
+  __shared__ __align__(16) int endloc_all[kWavesPerBlock][kTile];
   __shared__ float gl_all[kWavesPerBlock][7 * kStagedSegs];
   // Parked ranges during the scans; afterwards the image of the tile's
   // gradients (8 or 16 bytes per sample).
@@ -800,8 +798,8 @@ hipError_t launch_segments_fwd(const SamplesDev& s, const int64_t* off, int64_t 
                                float* seg_out, void* workspace, hipStream_t stream) {
   if (n_seg == 0) return hipSuccess;
   if (s.n == 0) {
-    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(7 * n_seg, 256)), dim3(256), 0, stream,
-                       seg_out, 7 * n_seg);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(kTupStride * n_seg, 256)), dim3(256), 0, stream,
+                       seg_out, kTupStride * n_seg);
     return hipGetLastError();
   }
   const int64_t nt = num_tiles(s.n);

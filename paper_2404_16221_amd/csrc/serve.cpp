@@ -150,7 +150,7 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int
   const size_t head = b_out + ws_b + b_ro;
   auto body = [&](int64_t n, int64_t n_seg) -> size_t {
     return round256(n * es) + round256(3 * n * es) + 2 * round256(4 * n) + round256(8 * (n_seg + 1)) +
-           round256(8 * n_seg) + round256(8 * (n_regions + 1)) + round256(4 * 7 * n_seg) +
+           round256(8 * n_seg) + round256(8 * (n_regions + 1)) + round256(4 * XL_TUPLE_STRIDE * n_seg) +
            round256(xl_segments_workspace_bytes(n));
   };
   char m[200];
@@ -221,7 +221,7 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int
   int64_t* so = reinterpret_cast<int64_t*>(c); c += round256(8 * (n_seg + 1));
   int64_t* ids = reinterpret_cast<int64_t*>(c); c += round256(8 * n_seg);
   int64_t* roff = reinterpret_cast<int64_t*>(c); c += round256(8 * (n_regions + 1));
-  float* seg_out = reinterpret_cast<float*>(c); c += round256(4 * 7 * n_seg);
+  float* seg_out = reinterpret_cast<float*>(c); c += round256(4 * XL_TUPLE_STRIDE * n_seg);
   void* recs = c;  // per-tile records of the segment composite
 
   hipError_t e = hipEventRecord(e0, st);

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/xl.h"
+
 namespace xl {
 
 constexpr int kWave = 64;                 // CDNA wavefront
@@ -24,6 +26,27 @@ constexpr int kRun = 8;                   // consecutive samples per lane
 constexpr int kTile = kWave * kRun;       // samples per wave tile
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
+
+// Segment tuples, and their gradients, are records of kTupStride floats, one
+// per segment: tau, r, g, b, A, D, L and a pad that is written as zero.  A
+// record is 32 bytes (the arrays are 32-byte aligned), so a tuple is two
+// 16-byte accesses and the records of consecutive segments are one stream.
+constexpr int kTupStride = XL_TUPLE_STRIDE;
+
+struct Tup7 {
+  float v[7];
+};
+__device__ __forceinline__ Tup7 load_tup7(const float* __restrict__ p, int64_t s) {
+  const float4* q = reinterpret_cast<const float4*>(p + kTupStride * s);
+  const float4 a = q[0], b = q[1];
+  return Tup7{{a.x, a.y, a.z, a.w, b.x, b.y, b.z}};
+}
+__device__ __forceinline__ void store_tup7(float* __restrict__ p, int64_t s, float tau, float cr,
+                                           float cg, float cb, float A, float D, float L) {
+  float4* q = reinterpret_cast<float4*>(p + kTupStride * s);
+  q[0] = make_float4(tau, cr, cg, cb);
+  q[1] = make_float4(A, D, L, 0.f);
+}
 
 enum Dtype : int { kF32 = 0, kBF16 = 1, kF16 = 2, kBF16F16 = 3 };
 // Storage type of the densities and of the colours (and of their gradients):

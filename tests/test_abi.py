@@ -49,6 +49,11 @@ def test_host_side_argument_errors():
     assert _fwd(s, 16, 1, 16, 16, 1) == xl.XL_EINVAL and "too small" in L.xl_last_error().decode()
     assert L.xl_merge_fwd(16, 1, None, 0, 16, 16, 1, 16, 4, None) == xl.XL_EINVAL
     assert "flags" in L.xl_last_error().decode()
+    # tuple records must be 16-byte aligned
+    assert L.xl_merge_fwd(8, 1, None, 0, 16, 16, 1, 16, 0, None) == xl.XL_EINVAL
+    assert "aligned" in L.xl_last_error().decode()
+    assert L.xl_merge_bwd(16, 1, None, 0, 16, 16, 1, 16, 8, 0, None) == xl.XL_EINVAL
+    assert "aligned" in L.xl_last_error().decode()
     assert L.xl_merge_bwd(16, -1, None, 0, 16, 16, 1, 16, 16, 0, None) == xl.XL_EINVAL
     assert L.xl_merge_fwd(16, 1, 16, 0, 16, 16, 1, 16, 0, None) == xl.XL_EINVAL
     assert "n_regions" in L.xl_last_error().decode()

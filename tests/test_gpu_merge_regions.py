@@ -28,7 +28,7 @@ def both(seg_out, ro, ids, roff, grad_ray, fp64):
     for r in (None, roff):
         f = xl.xl_merge_fwd(seg_out, ro, ids, fp64=fp64, region_offsets=r, staged=True)
         # every entry first holds a mark, so that untouched entries are seen
-        g = torch.full_like(seg_out, 7.0)
+        g = xl.tuple_buffer(seg_out.shape[1], seg_out.device).fill_(7.0)
         g = xl.xl_merge_bwd(seg_out, ro, ids, grad_ray, g, fp64=fp64, region_offsets=r, staged=True)
         out.append((f, g))
     torch.cuda.synchronize()
@@ -51,7 +51,7 @@ def tuples(n_seg, seed):
     t[4] = a                                    # opacity
     t[5] = a * rng.uniform(0.5, 3.0, n_seg)     # depth
     t[6] = a * a * rng.random(n_seg)            # distortion
-    return torch.from_numpy(t).cuda()
+    return xl.as_tuples(torch.from_numpy(t).cuda())
 
 
 def region_layout(n_rays, K, present, order_seed):
@@ -146,7 +146,7 @@ def test_fallback_cases():
     a, b = roff[2], roff[3]
     perm[a:b] = a + rng.permutation(b - a)
     ids_p = perm[ids]
-    seg_p = torch.empty_like(seg_out)
+    seg_p = xl.tuple_buffer(n_seg, seg_out.device)
     seg_p[:, dev(perm)] = seg_out
     ref = both(seg_out, dev(ro), dev(ids), dev(roff), grad, False)
     got = both(seg_p, dev(ro), dev(ids_p), dev(roff), grad, False)
