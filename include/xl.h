@@ -123,7 +123,7 @@ int xl_render_segments_fwd(const xl_samples* s, const int64_t* seg_offsets, int6
  * arguments, kernels and results as xl_render_segments_fwd, except that the
  * tile records go to a static device array of XL_STATIC_SCRATCH_BYTES per GPU,
  * held by the library until the process ends.  Hence:
- *   - at most 162,070,528 samples per call (xl_segments_workspace_bytes(n)
+ *   - at most 168,427,520 samples per call (xl_segments_workspace_bytes(n)
  *     <= XL_STATIC_SCRATCH_BYTES); larger calls fail with XL_EINVAL before
  *     anything is launched;
  *   - every call on one GPU shares that array: calls that overlap on one GPU

@@ -63,18 +63,45 @@ __device__ __forceinline__ void write_tuple(float* __restrict__ out, int64_t s, 
 // s_lo) of the segment whose last sample is base + p, or -1.  Empty segments
 // owned by this tile get the identity tuple when WRITE_EMPTY.
 constexpr int kStagedSegs = 64;  // segment gradients staged in LDS per tile (backward)
+constexpr int kMissing = -2;     // end-table entry of a sample past the array
+
+// Lane samples of tile t that exist (kRun except in the ragged last tile).
+__device__ __forceinline__ int lane_count(int64_t n, int64_t t, int lane) {
+  const int64_t rem = n - (t * kTile + static_cast<int64_t>(lane) * kRun);
+  return rem <= 0 ? 0 : (rem >= kRun ? kRun : static_cast<int>(rem));
+}
+
+// The tile's end table starts as -1 (no end) for every sample, and as
+// kMissing for the samples past the array in the ragged last tile.
+__device__ __forceinline__ void init_ends(int* endloc, int64_t n, int64_t t, int lane) {
+  const bool ragged = (t + 1) * kTile > n;  // uniform
+#pragma unroll
+  for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
+  if (ragged) {
+#pragma unroll
+    for (int j = 0; j < kRun; ++j)
+      if (t * kTile + lane + kWave * j >= n) endloc[lane + kWave * j] = kMissing;
+  }
+}
+
+// The lane's samples of tile t into registers: vector loads, or element
+// loads for the ragged last tile.
+template <int DT>
+__device__ __forceinline__ void load_lane(RawRun<DT>& raw, const SamplesDev& s, int64_t t, int lane) {
+  const int64_t i = t * kTile + static_cast<int64_t>(lane) * kRun;
+  if ((t + 1) * kTile <= s.n) raw.load(s.sigma, s.rgb, s.t0, s.t1, i);
+  else raw.load_part(s.sigma, s.rgb, s.t0, s.t1, i, lane_count(s.n, t, lane));
+}
 
 template <bool WRITE_EMPTY>
 __device__ __forceinline__ int64_t stage_ends(const int64_t* __restrict__ off, int64_t n_seg,
                                            int64_t n, int64_t t, int64_t n_tiles, int64_t s_lo,
                                            int lane, int* __restrict__ endloc,
-                                           int64_t* __restrict__ tailseg,
                                            float* __restrict__ seg_out,
                                            const float* __restrict__ gseg = nullptr,
                                            float* __restrict__ gl = nullptr) {
   const int64_t base = t * kTile;
   const int64_t tile_end = base + kTile < n ? base + kTile : n;
-  const int64_t last = tile_end - 1;
   const bool last_tile = (t == n_tiles - 1);
   for (int64_t j0 = 0;; j0 += kWave) {
     const int64_t sg = s_lo + j0 + lane;
@@ -99,7 +126,6 @@ __device__ __forceinline__ int64_t stage_ends(const int64_t* __restrict__ off, i
               gl[6 * kStagedSegs + loc] = 2.f * g.v[6];  // the sweep uses 2 g_L
             }
           }
-          if (a <= last && last <= e) *tailseg = sg;
         }
       }
     }
@@ -112,56 +138,44 @@ __device__ __forceinline__ int64_t stage_ends(const int64_t* __restrict__ off, i
 }
 
 // Per-lane view of one tile: the lane's kRun samples and the segment ends
-// among them.  FULL = every sample of the tile exists (all tiles but a ragged
-// last one); otherwise missing samples act as one-sample segments of their own
-// that are never written.
-template <int DT, bool FULL>
+// among them.  In the ragged last tile the samples past the array are zeros
+// whose end-table entry is kMissing: each acts as a one-sample segment of its
+// own that is never written.
+// RAGGED: the tile may be the ragged last one, whose missing samples have
+// kMissing entries (with RAGGED = false only ids and -1 occur, and the test
+// for an end is the cheaper sign test).
+template <int DT, bool RAGGED = true>
 struct LaneRun {
   Smp x[kRun];
-  int ends[kRun];   // local id of the segment ending at sample j, or -1
+  int ends[kRun];   // local id of the segment ending at sample j, -1, or kMissing
   bool endf[kRun];  // sample j ends a segment (or does not exist)
   bool h0;          // sample 0 starts a segment
-  int cnt;          // samples that exist (kRun when FULL)
-  int64_t i0;       // index of sample 0
 
-  // raw: the lane's samples, already loaded (FULL tiles only).
-  __device__ __forceinline__ void load(const SamplesDev& s, const int* endloc, int lane,
-                                       bool start_head, int64_t base, const RawRun<DT>* raw) {
-    i0 = base + static_cast<int64_t>(lane) * kRun;
-    if (FULL) {
-      cnt = kRun;
-    } else {
-      const int64_t rem = s.n - i0;
-      cnt = rem <= 0 ? 0 : (rem >= kRun ? kRun : static_cast<int>(rem));
-    }
+  // raw: the lane's samples, already loaded.
+  __device__ __forceinline__ void load(const int* endloc, int lane, bool start_head,
+                                       const RawRun<DT>* raw) {
 #pragma unroll
     for (int j = 0; j < kRun; ++j) ends[j] = endloc[lane * kRun + j];
-    h0 = lane == 0 ? start_head : (endloc[lane * kRun - 1] >= 0);
-    if (!FULL && cnt == 0) h0 = true;
+    h0 = lane == 0 ? start_head : (RAGGED ? endloc[lane * kRun - 1] != -1 : endloc[lane * kRun - 1] >= 0);
     float sg[kRun], c[3 * kRun], a[kRun], b[kRun];
-    if constexpr (FULL) {
-      raw->decode(sg, c, a, b);
-    } else {
-      // Missing samples are zeros (finite, as the scans' masked joins need).
-      load_run<DT>(s.sigma, s.rgb, s.t0, s.t1, i0, cnt, sg, c, a, b);
-    }
+    raw->decode(sg, c, a, b);
 #pragma unroll
     for (int j = 0; j < kRun; ++j) {
       x[j] = make_sample(sg[j], c[3 * j], c[3 * j + 1], c[3 * j + 2], a[j], b[j]);
-      endf[j] = (ends[j] >= 0) || (!FULL && j >= cnt);
+      endf[j] = RAGGED ? ends[j] != -1 : ends[j] >= 0;
     }
   }
   __device__ __forceinline__ bool head(int j) const { return j == 0 ? h0 : endf[j - 1]; }
 };
 
-template <int DT, bool FULL>
+template <int DT>
 __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int64_t t,
                                          int64_t s_lo, int64_t n_win, bool start_head, int lane,
-                                         int* endloc, int64_t tailseg, float* park,
+                                         int* endloc, float* park,
                                          float* __restrict__ seg_out, const TileRecs& recs,
                                          const RawRun<DT>* raw) {
-  LaneRun<DT, FULL> R;
-  R.load(s, endloc, lane, start_head, t * kTile, raw);
+  LaneRun<DT> R;
+  R.load(endloc, lane, start_head, raw);
 
   // The segment ends are in registers now; their LDS space stages the tuples of
   // segments that end in this tile as kTupStride-word records (slot = local
@@ -252,18 +266,15 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
     const int flags = (start_head ? kStartHead : 0) | (end_mask ? kHasEnd : 0) |
                       (head_mask ? kHasHead : 0) | (have ? kTailOpen : 0);
     recs.flags[t] = flags;
-    recs.tail_seg[t] = tailseg;
     if (have) recs.put(recs.tail, t, inc);
     if (!start_head && !end_mask) recs.put(recs.head, t, inc);
   }
 }
 
-// FULL instances process tiles [t_first, t_first + gridDim.x * kWavesPerBlock)
-// that are complete; the ragged last tile (if any) is a separate launch with
-// FULL = false, so the common instance carries no tail handling (and no
-// register cost for it).
-template <int DT, bool FULL>
-__global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
+// Tiles [t_first, t_end), one wave each; the ragged last tile (if any) loads
+// its samples element by element.
+template <int DT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(DT == kF32 ? 6 : 8))) void seg_fwd_kernel(SamplesDev s,
                                                          const int64_t* __restrict__ off,
                                                          int64_t n_seg, int64_t n_tiles,
                                                          int64_t t_first, int64_t t_end,
@@ -271,7 +282,6 @@ __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
                                                          TileRecs recs) {
   __shared__ __align__(16) int endloc_all[kWavesPerBlock][kTile];
   __shared__ float park_all[kWavesPerBlock][kRangeFields * kWave];
-  __shared__ int64_t tailseg_all[kWavesPerBlock];
   // wave index made provably uniform, so per-tile loads go through the scalar unit
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
   const int lane = threadIdx.x % kWave;
@@ -279,22 +289,20 @@ __global__ __launch_bounds__(kBlock) void seg_fwd_kernel(SamplesDev s,
   const bool active = t < t_end;
   // Issue the sample loads first: their latency overlaps the setup below.
   RawRun<DT> raw;
-  if (FULL && active) raw.load(s.sigma, s.rgb, s.t0, s.t1, t * kTile + static_cast<int64_t>(lane) * kRun);
+  if (active) load_lane(raw, s, t, lane);
   int* endloc = endloc_all[wave];
-#pragma unroll
-  for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
-  if (lane == 0) tailseg_all[wave] = -1;
+  init_ends(endloc, s.n, t, lane);
   __syncthreads();
   int64_t s_lo = 0, n_win = 0;
   bool start_head = false;
   if (active) {
     s_lo = recs.first_seg[t];
-    n_win = stage_ends<true>(off, n_seg, s.n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], seg_out);
+    n_win = stage_ends<true>(off, n_seg, s.n, t, n_tiles, s_lo, lane, endloc, seg_out);
     start_head = (off[s_lo] == t * kTile);
   }
   __syncthreads();
   if (!active) return;
-  fwd_tile<DT, FULL>(s, n_seg, t, s_lo, n_win, start_head, lane, endloc, tailseg_all[wave], park_all[wave],
+  fwd_tile<DT>(s, n_seg, t, s_lo, n_win, start_head, lane, endloc, park_all[wave],
                      seg_out, recs, &raw);
 }
 
@@ -425,7 +433,7 @@ __device__ __forceinline__ void reverse_step(const Smp& q, float PTj, float PZj,
   mf = q.m;
 }
 
-template <int DT, bool FULL>
+template <int DT, bool RAGGED>
 __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int64_t t,
                                          int flags, int64_t ts,
                                          int64_t s_lo, int lane, const int* endloc,
@@ -458,8 +466,8 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
     }
   };
   if (kEager) load_carries();
-  LaneRun<DT, FULL> R;
-  R.load(s, endloc, lane, start_head, t * kTile, raw);
+  LaneRun<DT, RAGGED> R;
+  R.load(endloc, lane, start_head, raw);
 
   // Pass 1: serial fold.  Records, for every sample, the transmittance and
   // sum_{k<j} w_k (m_j - m_k) in front of it, relative to the start of the
@@ -594,9 +602,8 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
     SA = Tq * sc.A; SF = Tq * sc.F; SL = Tq * Tq * sc.L; mf = sc.m0;
     TN = Tq * exp_neg(sc.tau);
   }
-  if constexpr (FULL) {
-    // Full tile: the lane's samples stay in registers from pass 1 (no
-    // re-read).  Each gradient goes to the LDS image of the tile's gradient
+  {
+    // The lane's samples stay in registers from pass 1 (no re-read).  Each gradient goes to the LDS image of the tile's gradient
     // block (dsigma, then drgb, as laid out in memory) as soon as it is
     // complete; the image is then written with full, contiguous 16-byte
     // stores (stores straight from the lanes, each covering a few bytes of
@@ -606,7 +613,7 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
     for (int j = kRun - 1; j >= 0; --j) {
       const Smp& q = R.x[j];
       const int endj = endloc[lane * kRun + j];  // re-read: frees registers across the scans
-      reverse_step<kEager>(q, PT[j], PZ[j], endj >= 0, endj, s_lo, n_seg, gl, gseg, g, SG, SA, SF,
+      reverse_step<kEager>(q, PT[j], PZ[j], RAGGED ? endj != -1 : endj >= 0, endj, s_lo, n_seg, gl, gseg, g, SG, SA, SF,
                    SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
       if (DT == kF32) {
         float* img = park;  // [kTile] dsigma, then [kTile][3] drgb
@@ -626,8 +633,19 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
         }
       }
     }
+    wave_lds_fence();
+    if (RAGGED) {
+      // Ragged last tile: element stores of the samples that exist.
+      const int m = static_cast<int>(s.n - t * kTile);
+      using E = std::conditional_t<DT == kF32, float, uint16_t>;
+      const E* im = reinterpret_cast<const E*>(park);
+      E* gs = static_cast<E*>(gsig_p) + t * kTile;
+      E* gc = static_cast<E*>(grgb_p) + 3 * t * kTile;
+      for (int k = lane; k < m; k += kWave) gs[k] = im[k];
+      for (int k = lane; k < 3 * m; k += kWave) gc[k] = im[kTile + k];
+      return;
+    }
     if (DT == kF32) {
-      wave_lds_fence();
       const uint4* img = reinterpret_cast<const uint4*>(park);
       uint4* gs = reinterpret_cast<uint4*>(static_cast<float*>(gsig_p) + t * kTile);
       uint4* gc = reinterpret_cast<uint4*>(static_cast<float*>(grgb_p) + 3 * t * kTile);
@@ -636,7 +654,6 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
 #pragma unroll
       for (int q = 0; q < 6; ++q) gc[q * kWave + lane] = img[2 * kWave + q * kWave + lane];
     } else {
-      wave_lds_fence();
       const uint4* img = reinterpret_cast<const uint4*>(park);
       uint4* gs = reinterpret_cast<uint4*>(static_cast<uint16_t*>(gsig_p) + t * kTile);
       uint4* gc = reinterpret_cast<uint4*>(static_cast<uint16_t*>(grgb_p) + 3 * t * kTile);
@@ -646,66 +663,10 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
 #pragma unroll
       for (int q = 0; q < 3; ++q) gc[q * kWave + lane] = img[kSigVec + q * kWave + lane];
     }
-    return;
-  }
-  float dsg[kRun], dc[3 * kRun];
-#pragma unroll
-  for (int j = kRun - 1; j >= 0; --j) {
-    reverse_step<false>(R.x[j], PT[j], PZ[j], R.endf[j], R.ends[j], s_lo, n_seg, gl, gseg, g, SG, SA, SF,
-                 SL, mf, TN, dsg[j], dc[3 * j], dc[3 * j + 1], dc[3 * j + 2]);
-  }
-
-  const int64_t i0 = R.i0;
-  if (FULL || R.cnt == kRun) {
-    if (DT == kF32) {
-      float4* GS = reinterpret_cast<float4*>(static_cast<float*>(gsig_p) + i0);
-      float4* GC = reinterpret_cast<float4*>(static_cast<float*>(grgb_p) + 3 * i0);
-#pragma unroll
-      for (int q = 0; q < kRun / 4; ++q)
-        GS[q] = make_float4(dsg[4 * q], dsg[4 * q + 1], dsg[4 * q + 2], dsg[4 * q + 3]);
-#pragma unroll
-      for (int q = 0; q < 3 * kRun / 4; ++q)
-        GC[q] = make_float4(dc[4 * q], dc[4 * q + 1], dc[4 * q + 2], dc[4 * q + 3]);
-    } else {
-      uint4* GS = reinterpret_cast<uint4*>(static_cast<uint16_t*>(gsig_p) + i0);
-      uint4* GC = reinterpret_cast<uint4*>(static_cast<uint16_t*>(grgb_p) + 3 * i0);
-#pragma unroll
-      for (int q = 0; q < kRun / 8; ++q) {
-        uint32_t w[4];
-#pragma unroll
-        for (int h = 0; h < 4; ++h) w[h] = pack2<sig_dt(DT)>(dsg[8 * q + 2 * h], dsg[8 * q + 2 * h + 1]);
-        GS[q] = make_uint4(w[0], w[1], w[2], w[3]);
-      }
-#pragma unroll
-      for (int q = 0; q < 3 * kRun / 8; ++q) {
-        uint32_t w[4];
-#pragma unroll
-        for (int h = 0; h < 4; ++h) w[h] = pack2<rgb_dt(DT)>(dc[8 * q + 2 * h], dc[8 * q + 2 * h + 1]);
-        GC[q] = make_uint4(w[0], w[1], w[2], w[3]);
-      }
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < kRun; ++j) {
-      if (j < R.cnt) {
-        const int64_t i = i0 + j;
-        if (DT == kF32) {
-          static_cast<float*>(gsig_p)[i] = dsg[j];
-          float* GC = static_cast<float*>(grgb_p);
-          GC[3 * i] = dc[3 * j]; GC[3 * i + 1] = dc[3 * j + 1]; GC[3 * i + 2] = dc[3 * j + 2];
-        } else {
-          static_cast<uint16_t*>(gsig_p)[i] = from_f32<sig_dt(DT)>(dsg[j]);
-          uint16_t* GC = static_cast<uint16_t*>(grgb_p);
-          GC[3 * i] = from_f32<rgb_dt(DT)>(dc[3 * j]);
-          GC[3 * i + 1] = from_f32<rgb_dt(DT)>(dc[3 * j + 1]);
-          GC[3 * i + 2] = from_f32<rgb_dt(DT)>(dc[3 * j + 2]);
-        }
-      }
-    }
   }
 }
 
-template <int DT, bool FULL>
+template <int DT, bool RAGGED>
 __device__ __forceinline__ void seg_bwd_body(
     const SamplesDev& s, const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
     int64_t t_first, int64_t t_end, const TileRecs& recs,
@@ -716,68 +677,70 @@ __device__ __forceinline__ void seg_bwd_body(
   // gradients (8 or 16 bytes per sample).
   constexpr int kParkWords = DT == kF32 ? 4 * kTile : 2 * kTile;
   __shared__ __align__(16) float park_all[kWavesPerBlock][kParkWords];
-  __shared__ int64_t tailseg_all[kWavesPerBlock];
   // wave index made provably uniform, so per-tile loads go through the scalar unit
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
   const int lane = threadIdx.x % kWave;
   const int64_t t = t_first + static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wave;
   const bool active = t < t_end;
   RawRun<DT> raw;
-  if (FULL && active) raw.load(s.sigma, s.rgb, s.t0, s.t1, t * kTile + static_cast<int64_t>(lane) * kRun);
+  if (active) {
+    if (RAGGED) load_lane(raw, s, t, lane);
+    else raw.load(s.sigma, s.rgb, s.t0, s.t1, t * kTile + static_cast<int64_t>(lane) * kRun);
+  }
   // (requested here so that their latency overlaps the staging below)
   const int flags = active ? recs.flags[t] : 0;
-  const int64_t ts = active ? recs.tail_seg[t] : -1;
+  // The segment leaving the tile through its last sample, if that segment is
+  // open (kTailOpen): the one holding the next tile's first sample.
+  const int64_t ts = (active && t + 1 < n_tiles) ? recs.first_seg[t + 1] : -1;
   int* endloc = endloc_all[wave];
   float* gl = gl_all[wave];
+  if (RAGGED) {
+    init_ends(endloc, s.n, t, lane);
+  } else {
 #pragma unroll
-  for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
-  if (lane == 0) tailseg_all[wave] = -1;
+    for (int j = 0; j < kRun; ++j) endloc[lane + kWave * j] = -1;
+  }
   __syncthreads();
   int64_t s_lo = 0;
   if (active) {
     s_lo = recs.first_seg[t];
-    stage_ends<false>(off, n_seg, s.n, t, n_tiles, s_lo, lane, endloc, &tailseg_all[wave], nullptr,
-                      gseg, gl);
+    stage_ends<false>(off, n_seg, s.n, t, n_tiles, s_lo, lane, endloc, nullptr, gseg, gl);
   }
   __syncthreads();
   if (!active) return;
-  bwd_tile<DT, FULL>(s, n_seg, t, flags, ts, s_lo, lane, endloc, gl, park_all[wave], recs, gseg, gsig_p, grgb_p,
+  bwd_tile<DT, RAGGED>(s, n_seg, t, flags, ts, s_lo, lane, endloc, gl, park_all[wave], recs, gseg, gsig_p, grgb_p,
                      &raw);
 }
 
 // Full tiles, held to 128 registers so that four waves share each SIMD; the
-// ragged last tile has its own unconstrained instance.
+// ragged last tile (element loads and stores) is a launch of its own, so the
+// common instance carries none of its code.
 template <int DT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void seg_bwd_kernel(
     SamplesDev s, const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
     int64_t t_first, int64_t t_end, TileRecs recs,
     const float* __restrict__ gseg, void* __restrict__ gsig_p, void* __restrict__ grgb_p) {
-  seg_bwd_body<DT, true>(s, off, n_seg, n_tiles, t_first, t_end, recs, gseg, gsig_p, grgb_p);
+  seg_bwd_body<DT, false>(s, off, n_seg, n_tiles, t_first, t_end, recs, gseg, gsig_p, grgb_p);
 }
 template <int DT>
 __global__ __launch_bounds__(kBlock) void seg_bwd_tail_kernel(
     SamplesDev s, const int64_t* __restrict__ off, int64_t n_seg, int64_t n_tiles,
     int64_t t_first, int64_t t_end, TileRecs recs,
     const float* __restrict__ gseg, void* __restrict__ gsig_p, void* __restrict__ grgb_p) {
-  seg_bwd_body<DT, false>(s, off, n_seg, n_tiles, t_first, t_end, recs, gseg, gsig_p, grgb_p);
+  seg_bwd_body<DT, true>(s, off, n_seg, n_tiles, t_first, t_end, recs, gseg, gsig_p, grgb_p);
 }
 
 static inline unsigned grid_for(int64_t count, int block) {
   return static_cast<unsigned>((count + block - 1) / block);
 }
 
-// Launches FULL tiles [0, n_full) and the ragged tile n_full (if any).
+// All tiles in one launch; the ragged last tile (if any) loads its samples
+// element by element.
 template <int DT>
 static void launch_fwd_dt(const SamplesDev& s, const int64_t* off, int64_t n_seg, int64_t nt,
                           float* seg_out, const TileRecs& recs, hipStream_t st) {
-  const int64_t n_full = s.n / kTile;
-  if (n_full > 0)
-    hipLaunchKernelGGL((seg_fwd_kernel<DT, true>), dim3(grid_for(n_full, kWavesPerBlock)),
-                       dim3(kBlock), 0, st, s, off, n_seg, nt, static_cast<int64_t>(0), n_full,
-                       seg_out, recs);
-  if (n_full < nt)
-    hipLaunchKernelGGL((seg_fwd_kernel<DT, false>), dim3(1), dim3(kBlock), 0, st, s, off, n_seg, nt,
-                       n_full, nt, seg_out, recs);
+  hipLaunchKernelGGL((seg_fwd_kernel<DT>), dim3(grid_for(nt, kWavesPerBlock)), dim3(kBlock), 0,
+                     st, s, off, n_seg, nt, static_cast<int64_t>(0), nt, seg_out, recs);
 }
 
 template <int DT>
@@ -786,9 +749,8 @@ static void launch_bwd_dt(const SamplesDev& s, const int64_t* off, int64_t n_seg
                           hipStream_t st) {
   const int64_t n_full = s.n / kTile;
   if (n_full > 0)
-    hipLaunchKernelGGL((seg_bwd_kernel<DT>), dim3(grid_for(n_full, kWavesPerBlock)),
-                       dim3(kBlock), 0, st, s, off, n_seg, nt, static_cast<int64_t>(0), n_full, recs,
-                       gseg, gs, gc);
+    hipLaunchKernelGGL((seg_bwd_kernel<DT>), dim3(grid_for(n_full, kWavesPerBlock)), dim3(kBlock), 0,
+                       st, s, off, n_seg, nt, static_cast<int64_t>(0), n_full, recs, gseg, gs, gc);
   if (n_full < nt)
     hipLaunchKernelGGL((seg_bwd_tail_kernel<DT>), dim3(1), dim3(kBlock), 0, st, s, off, n_seg, nt,
                        n_full, nt, recs, gseg, gs, gc);

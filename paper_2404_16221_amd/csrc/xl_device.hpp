@@ -250,87 +250,6 @@ __device__ __forceinline__ uint32_t pack2(float a, float b) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
 }
 
-// Load kRun consecutive samples starting at index i (i % kRun == 0) into
-// registers.  `full` means all kRun samples exist; otherwise only `cnt` are
-// loaded and the rest are zero.
-template <int DT>
-__device__ __forceinline__ void load_run(const void* __restrict__ sigma_p,
-                                         const void* __restrict__ rgb_p,
-                                         const float* __restrict__ t0_p,
-                                         const float* __restrict__ t1_p, int64_t i, int cnt,
-                                         float (&sg)[kRun], float (&c)[3 * kRun],
-                                         float (&a)[kRun], float (&b)[kRun]) {
-  if (cnt == kRun) {
-    const float4* T0 = reinterpret_cast<const float4*>(t0_p + i);
-    const float4* T1 = reinterpret_cast<const float4*>(t1_p + i);
-#pragma unroll
-    for (int q = 0; q < kRun / 4; ++q) {
-      const float4 u = T0[q], v = T1[q];
-      a[4 * q] = u.x; a[4 * q + 1] = u.y; a[4 * q + 2] = u.z; a[4 * q + 3] = u.w;
-      b[4 * q] = v.x; b[4 * q + 1] = v.y; b[4 * q + 2] = v.z; b[4 * q + 3] = v.w;
-    }
-    if (DT == kF32) {
-      const float4* S = reinterpret_cast<const float4*>(static_cast<const float*>(sigma_p) + i);
-      const float4* C = reinterpret_cast<const float4*>(static_cast<const float*>(rgb_p) + 3 * i);
-#pragma unroll
-      for (int q = 0; q < kRun / 4; ++q) {
-        const float4 u = S[q];
-        sg[4 * q] = u.x; sg[4 * q + 1] = u.y; sg[4 * q + 2] = u.z; sg[4 * q + 3] = u.w;
-      }
-#pragma unroll
-      for (int q = 0; q < 3 * kRun / 4; ++q) {
-        const float4 u = C[q];
-        c[4 * q] = u.x; c[4 * q + 1] = u.y; c[4 * q + 2] = u.z; c[4 * q + 3] = u.w;
-      }
-    } else {
-      const uint4* S = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(sigma_p) + i);
-      const uint4* C = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(rgb_p) + 3 * i);
-#pragma unroll
-      for (int q = 0; q < kRun / 8; ++q) {
-        const uint4 u = S[q];
-        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          sg[8 * q + 2 * h] = to_f32<sig_dt(DT)>(static_cast<uint16_t>(w[h] & 0xffffu));
-          sg[8 * q + 2 * h + 1] = to_f32<sig_dt(DT)>(static_cast<uint16_t>(w[h] >> 16));
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 3 * kRun / 8; ++q) {
-        const uint4 u = C[q];
-        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          c[8 * q + 2 * h] = to_f32<rgb_dt(DT)>(static_cast<uint16_t>(w[h] & 0xffffu));
-          c[8 * q + 2 * h + 1] = to_f32<rgb_dt(DT)>(static_cast<uint16_t>(w[h] >> 16));
-        }
-      }
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < kRun; ++j) {
-      const bool ok = j < cnt;
-      a[j] = ok ? t0_p[i + j] : 0.f;
-      b[j] = ok ? t1_p[i + j] : 0.f;
-      if (DT == kF32) {
-        const float* S = static_cast<const float*>(sigma_p);
-        const float* C = static_cast<const float*>(rgb_p);
-        sg[j] = ok ? S[i + j] : 0.f;
-        c[3 * j] = ok ? C[3 * (i + j)] : 0.f;
-        c[3 * j + 1] = ok ? C[3 * (i + j) + 1] : 0.f;
-        c[3 * j + 2] = ok ? C[3 * (i + j) + 2] : 0.f;
-      } else {
-        const uint16_t* S = static_cast<const uint16_t*>(sigma_p);
-        const uint16_t* C = static_cast<const uint16_t*>(rgb_p);
-        sg[j] = ok ? to_f32<sig_dt(DT)>(S[i + j]) : 0.f;
-        c[3 * j] = ok ? to_f32<rgb_dt(DT)>(C[3 * (i + j)]) : 0.f;
-        c[3 * j + 1] = ok ? to_f32<rgb_dt(DT)>(C[3 * (i + j) + 1]) : 0.f;
-        c[3 * j + 2] = ok ? to_f32<rgb_dt(DT)>(C[3 * (i + j) + 2]) : 0.f;
-      }
-    }
-  }
-}
-
 // The raw storage of kRun consecutive samples (i % kRun == 0, all present),
 // loaded as 16-byte vectors and decoded later: a tile issues these loads
 // before its setup so their latency overlaps it.
@@ -356,6 +275,50 @@ struct RawRun {
     for (int q = 0; q < kRun / 4; ++q) {
       t0[q] = reinterpret_cast<const float4*>(t0_p + i)[q];
       t1[q] = reinterpret_cast<const float4*>(t1_p + i)[q];
+    }
+  }
+
+  // The first cnt (0 <= cnt <= kRun) of the lane's samples by element loads,
+  // zeros for the rest: for the ragged last tile, whose vector loads would
+  // read past the arrays.  A zero sample is finite (as the scans' masked joins
+  // need) and adds nothing.
+  __device__ __forceinline__ void load_part(const void* __restrict__ sigma_p,
+                                            const void* __restrict__ rgb_p,
+                                            const float* __restrict__ t0_p,
+                                            const float* __restrict__ t1_p, int64_t i, int cnt) {
+    uint32_t sw[4 * kSigmaVec], cw[4 * kRgbVec];
+    if constexpr (DT == kF32) {
+      const uint32_t* S = static_cast<const uint32_t*>(sigma_p) + i;
+      const uint32_t* C = static_cast<const uint32_t*>(rgb_p) + 3 * i;
+#pragma unroll
+      for (int k = 0; k < kRun; ++k) sw[k] = k < cnt ? S[k] : 0u;
+#pragma unroll
+      for (int k = 0; k < 3 * kRun; ++k) cw[k] = k < 3 * cnt ? C[k] : 0u;
+    } else {
+      const uint16_t* S = static_cast<const uint16_t*>(sigma_p) + i;
+      const uint16_t* C = static_cast<const uint16_t*>(rgb_p) + 3 * i;
+#pragma unroll
+      for (int k = 0; k < kRun / 2; ++k)
+        sw[k] = (2 * k < cnt ? S[2 * k] : 0u) | (2 * k + 1 < cnt ? uint32_t(S[2 * k + 1]) << 16 : 0u);
+#pragma unroll
+      for (int k = 0; k < 3 * kRun / 2; ++k)
+        cw[k] = (2 * k < 3 * cnt ? C[2 * k] : 0u) |
+                (2 * k + 1 < 3 * cnt ? uint32_t(C[2 * k + 1]) << 16 : 0u);
+    }
+#pragma unroll
+    for (int q = 0; q < kSigmaVec; ++q) sg[q] = make_uint4(sw[4 * q], sw[4 * q + 1], sw[4 * q + 2], sw[4 * q + 3]);
+#pragma unroll
+    for (int q = 0; q < kRgbVec; ++q) rgb[q] = make_uint4(cw[4 * q], cw[4 * q + 1], cw[4 * q + 2], cw[4 * q + 3]);
+    float a[kRun], b[kRun];
+#pragma unroll
+    for (int k = 0; k < kRun; ++k) {
+      a[k] = k < cnt ? t0_p[i + k] : 0.f;
+      b[k] = k < cnt ? t1_p[i + k] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < kRun / 4; ++q) {
+      t0[q] = make_float4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
+      t1[q] = make_float4(b[4 * q], b[4 * q + 1], b[4 * q + 2], b[4 * q + 3]);
     }
   }
 
@@ -606,7 +569,7 @@ __device__ __forceinline__ Range unpark_range(const float* __restrict__ lds, int
 // 256-byte aligned.
 constexpr int64_t kRecGroup = 64;
 constexpr int kPartVecs = 3;  // (tau, r, g, b), (A, F, B, L), (m0, m1, tlo, 0)
-constexpr size_t kRecBytesPerTile = 8 + 8 + 4 + 4 * 16 * kPartVecs;
+constexpr size_t kRecBytesPerTile = 8 + 4 + 4 * 16 * kPartVecs;
 
 __host__ __device__ inline int64_t rec_stride(int64_t n_tiles) {
   const int64_t nt = n_tiles > 0 ? n_tiles : 1;
@@ -616,7 +579,6 @@ __host__ __device__ inline int64_t rec_stride(int64_t n_tiles) {
 struct TileRecs {
   int64_t* first_seg;  // segment containing the tile's first sample (or the
                        // first segment starting at it, empty ones included)
-  int64_t* tail_seg;   // segment containing the tile's last sample
   int32_t* flags;      // kStartHead | kHasEnd | kHasHead | kTailOpen
   float4* head;  // [stride][kPartVecs] first sample .. first segment end (whole tile if none)
   float4* tail;  // last segment head .. last sample
@@ -629,7 +591,6 @@ struct TileRecs {
     r.stride = rec_stride(n_tiles);
     char* p = static_cast<char*>(ws);
     r.first_seg = reinterpret_cast<int64_t*>(p); p += 8 * r.stride;
-    r.tail_seg = reinterpret_cast<int64_t*>(p); p += 8 * r.stride;
     r.flags = reinterpret_cast<int32_t*>(p); p += 4 * r.stride;
     const int64_t rb = 16 * kPartVecs * r.stride;
     r.head = reinterpret_cast<float4*>(p); p += rb;

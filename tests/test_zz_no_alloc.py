@@ -9,7 +9,7 @@ import torch
 from paper_2404_16221_amd import _lib as xl
 from paper_2404_16221_amd import synth
 
-MAX_SAMPLES = 162_070_528  # largest n whose tile records fit XL_STATIC_SCRATCH_BYTES
+MAX_SAMPLES = 168_427_520  # largest n whose tile records fit XL_STATIC_SCRATCH_BYTES
 
 
 def test_static_limit_and_rejection_on_the_host():
