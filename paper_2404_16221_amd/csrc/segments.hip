@@ -335,7 +335,8 @@ __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restri
     for (int64_t u = t + 1; u < n_tiles; ++u) {
       const int fu = recs.flags[u];
       if (!(fu & kStartHead)) {
-        recs.put(recs.pre, u, acc);
+        // (the tile right after the start reads the start's tail itself)
+        if (u > t + 1) recs.put(recs.pre, u, acc);
         if (fu & kHasEnd) {
           const int64_t sgi = recs.first_seg[u];
           if (sgi >= 0 && sgi < n_seg) write_tuple(seg_out, sgi, combine(acc, recs.get(recs.head, u)));
@@ -367,7 +368,8 @@ __global__ void seg_fixup_kernel(int64_t n_tiles, int64_t n_seg, float* __restri
     }
     for (int64_t u = e - 1; u >= 0; --u) {
       const int fu = recs.flags[u];
-      if (have && (fu & kTailOpen)) recs.put(recs.suf, u, acc);
+      // (the tile right before the end reads the end's head itself)
+      if (have && (fu & kTailOpen) && u < e - 1) recs.put(recs.suf, u, acc);
       if (fu & kHasEnd) break;
       const Part part = recs.get(recs.head, u);
       acc = have ? combine(part, acc) : part;
@@ -435,7 +437,7 @@ __device__ __forceinline__ void reverse_step(const Smp& q, float PTj, float PZj,
 
 template <int DT, bool RAGGED>
 __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int64_t t,
-                                         int flags, int64_t ts,
+                                         int flags, int flags_prev, int flags_next, int64_t ts,
                                          int64_t s_lo, int lane, const int* endloc,
                                          const float* __restrict__ gl, float* park,
                                          const TileRecs& recs,
@@ -443,20 +445,28 @@ __device__ __forceinline__ void bwd_tile(const SamplesDev& s, int64_t n_seg, int
                                          void* __restrict__ grgb_p, const RawRun<DT>* raw) {
   const bool start_head = (flags & kStartHead) != 0;
   const bool tail_open = (flags & kTailOpen) != 0;
-  // The 16-bit forms are bound by instruction issue and latency; the FP32 form
-  // moves half again as many bytes and runs three waves per SIMD (its 8 KB
-  // gradient image fills the LDS).  Only the former request the tile carries
-  // before the lane work and branch around rare restarts (measured: each
-  // helps them by a few percent and slows the FP32 form).
+  // Only the 16-bit forms request the tile carries before the lane work and
+  // branch around rare restarts (measured: each helps them by a few percent
+  // and slows the FP32 form, which runs three waves per SIMD: its 8 KB
+  // gradient image fills the LDS).
   constexpr bool kEager = DT != kF32;
   // Tile-uniform carries: the prefix into the tile, the suffix out of it and
   // the gradient of the segment that leaves it (g_L doubled, as in the sweep).
   Part pre_t, suf_t;
   float gt[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  // A segment that crosses only the boundary before the tile has, as prefix,
+  // the previous tile's tail record (the fixup writes prefixes only deeper
+  // into longer chains); likewise the suffix of one that ends in the next
+  // tile is that tile's head record.
   auto load_carries = [&]() {
-    if (!start_head) pre_t = recs.get(recs.pre, t);
+    // (the common case is requested first, without waiting for the flags)
+    if (!start_head) {
+      pre_t = recs.get(recs.tail, t - 1);
+      if (!(flags_prev & kHasHead)) pre_t = recs.get(recs.pre, t);
+    }
     if (tail_open) {
-      suf_t = recs.get(recs.suf, t);
+      suf_t = recs.get(recs.head, t + 1);
+      if (!(flags_next & kHasEnd)) suf_t = recs.get(recs.suf, t);
       if (ts >= 0 && ts < n_seg) {
         const Tup7 t = load_tup7(gseg, ts);
 #pragma unroll
@@ -689,6 +699,8 @@ __device__ __forceinline__ void seg_bwd_body(
   }
   // (requested here so that their latency overlaps the staging below)
   const int flags = active ? recs.flags[t] : 0;
+  const int flags_prev = (active && t > 0) ? recs.flags[t - 1] : 0;
+  const int flags_next = (active && t + 1 < n_tiles) ? recs.flags[t + 1] : 0;
   // The segment leaving the tile through its last sample, if that segment is
   // open (kTailOpen): the one holding the next tile's first sample.
   const int64_t ts = (active && t + 1 < n_tiles) ? recs.first_seg[t + 1] : -1;
@@ -708,7 +720,7 @@ __device__ __forceinline__ void seg_bwd_body(
   }
   __syncthreads();
   if (!active) return;
-  bwd_tile<DT, RAGGED>(s, n_seg, t, flags, ts, s_lo, lane, endloc, gl, park_all[wave], recs, gseg, gsig_p, grgb_p,
+  bwd_tile<DT, RAGGED>(s, n_seg, t, flags, flags_prev, flags_next, ts, s_lo, lane, endloc, gl, park_all[wave], recs, gseg, gsig_p, grgb_p,
                      &raw);
 }
 
