@@ -186,11 +186,15 @@ def _tup(t: torch.Tensor, name: str) -> int:
         raise ValueError(f"{name} must be a float32 CUDA tensor")
     if t.dim() != 2 or t.shape[0] != TUPLE:
         raise ValueError(f"{name} must be [7, n_seg] (see tuple_buffer)")
-    if t.shape[1] == 0:
+    n = t.shape[1]
+    if n == 0:
         return 0
-    if t.stride(0) != 1 or (t.shape[1] > 1 and t.stride(1) != TUPLE_STRIDE):
+    records = t.untyped_storage().nbytes() - t.storage_offset() * 4
+    if (t.stride(0) != 1 or (n > 1 and t.stride(1) != TUPLE_STRIDE)
+            or records < 4 * TUPLE_STRIDE * n or t.data_ptr() % 16):
         raise ValueError(f"{name} must be tuple records: a [7, n_seg] view with strides "
-                         f"(1, {TUPLE_STRIDE}) from tuple_buffer or as_tuples")
+                         f"(1, {TUPLE_STRIDE}) over 16-byte-aligned storage, from tuple_buffer "
+                         "or as_tuples")
     return t.data_ptr()
 
 

@@ -168,3 +168,19 @@ def test_fallback_cases():
     z = both(e, dev(np.zeros(1, np.int64)), dev(np.zeros(0, np.int64)), dev(np.zeros(2, np.int64)),
              torch.zeros((7, 0), device="cuda"), False)
     assert z[1][0].shape == (7, 0)
+
+
+def test_tuple_arrays_must_be_records():
+    """A plain [7, n] tensor is not the records layout: refused before any launch."""
+    for n in (3, 1):
+        ro = dev(np.array([0, n], np.int64))
+        ids = dev(np.arange(n, dtype=np.int64))
+        plain = torch.zeros((7, n), device="cuda")
+        with pytest.raises(ValueError, match="tuple records"):
+            xl.xl_merge_fwd(plain, ro, ids)
+    ro = dev(np.array([0, 2, 3], np.int64))
+    ids = dev(np.array([0, 1, 2], np.int64))
+    rec = xl.tuple_buffer(3, "cuda", zero=True)
+    out = xl.xl_merge_fwd(rec, ro, ids)
+    torch.cuda.synchronize()
+    assert torch.equal(out[0].cpu(), torch.ones(2))  # identity tuples: T = 1
