@@ -233,8 +233,10 @@ def test_edge_cases_forward_backward(shuffle):
     _check_backward(b, d, rays, gseg, gs, gc, grad_ray, "edge")
 
 
-@pytest.mark.parametrize("n_samples", [1, 7, 511, 512, 513, 1023, 1024, 1025, 1100, 2100])
+@pytest.mark.parametrize("n_samples", [1, 7, 509, 511, 512, 513, 1021, 1023, 1024, 1025, 1100, 2100])
 def test_tiny_and_ragged_sizes(n_samples):
+    """n_samples on the first ray plus 3 on the second: 509 and 1021 give whole
+    tiles only (512, 1024 samples), the others a ragged last tile."""
     rng = np.random.default_rng(n_samples)
     # one long ray cut into segments of random length
     cuts = np.sort(rng.choice(np.arange(1, n_samples), size=min(5, n_samples - 1), replace=False)) \
