@@ -768,15 +768,16 @@ def main():
         forms["k64"] = make("k64-bf16sigma-f16rgb-fp64merge", w64, xl.BF16_F16, 64, fp64=True,
                             grad=g64)
     # The first ~25 ms of sustained load run up to 25 % slower (the GPU's
-    # power and clock settle); steady state is what a training run sees, so
-    # the GPU is held busy for half a second before the first timed form.
-    first = next(iter(forms.values()))
-    t_end = time.perf_counter() + 0.5
-    while time.perf_counter() < t_end:
-        for _ in range(10):
-            first.step()
-        torch.cuda.synchronize()
+    # power and clock settle, also after the pauses between forms, where the
+    # host copies results for the error check); steady state is what a
+    # training run sees, so the GPU is held busy with each form's own steps
+    # for half a second before that form is timed.
     for key, f in forms.items():
+        t_end = time.perf_counter() + 0.5
+        while time.perf_counter() < t_end:
+            for _ in range(10):
+                f.step()
+            torch.cuda.synchronize()
         ms, kms, wall = time_form(f, args.steps, args.warmup)
         results[key] = dict(name=f.name, ms_per_step=ms, samples_per_s=f.n / (ms * 1e-3),
                             step_gbs=f.bytes_step() / (ms * 1e-3) / 1e9,
