@@ -14,8 +14,10 @@
 //      the merge operator, see xl_device.hpp);
 //   3. a segmented wave scan carries the open range across lanes;
 //   4. segments that cross a tile boundary are completed by a small fixup
-//      kernel from per-tile head/tail ranges, which also leaves the carries
-//      the backward pass needs (prefix into and suffix out of each tile).
+//      kernel from per-tile head/tail ranges; the backward takes a tile's
+//      carries (prefix into and suffix out of it) from the neighbouring
+//      tile's tail/head range when the segment crosses one boundary, and from
+//      the fixup's carry records inside longer chains.
 // The backward recomputes transmittance with the same forward scan, takes the
 // suffix with a reverse scan, and applies the exact per-sample Jacobian of the
 // merge operator, so nothing per sample is stored between the passes.
@@ -272,7 +274,9 @@ __device__ __forceinline__ void fwd_tile(const SamplesDev& s, int64_t n_seg, int
 }
 
 // Tiles [t_first, t_end), one wave each; the ragged last tile (if any) loads
-// its samples element by element.
+// its samples element by element.  The 16-bit forms are held to 64 registers
+// (eight waves per SIMD; the ragged tile's code would otherwise push BF16 to
+// 65), FP32 to six waves.
 template <int DT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(DT == kF32 ? 6 : 8))) void seg_fwd_kernel(SamplesDev s,
                                                          const int64_t* __restrict__ off,
