@@ -212,6 +212,13 @@ __device__ __forceinline__ void append(Range& r, float& Tr, const Smp& s) {
 
 // Orders the calling wave's LDS accesses for the compiler; the hardware
 // already performs one wave's LDS operations in order.
+// A 16-byte store marked non-temporal (streaming: written once, not re-read
+// by this kernel).
+__device__ __forceinline__ void store_stream(uint4* p, uint4 v) {
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<u32x4*>(p));
+}
+
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
