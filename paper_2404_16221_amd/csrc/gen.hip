@@ -15,7 +15,8 @@
 //                block counts -> stable region-major slots)
 //   gen_rank     packed index of every segment (stable counting sort by box)
 //   scan         packed segment lengths -> seg_offsets
-//   gen_fill     one lane per ray: regenerate samples into their packed slots
+//   gen_fill     one lane per 64-sample chunk of a ray: regenerate its samples
+//                into their packed slots
 #include <cstdio>
 
 #include "../../include/xl.h"
@@ -227,9 +228,9 @@ struct GenWs {
   int32_t* chunk_ray; // [R * chunks] ray of each compact chunk
 };
 
-__global__ void gen_struct_kernel(GenDev g, GenWs w) {
-  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= g.n_rays) return;
+// Structure of one ray: its position scale and start, the position at every
+// chunk start, and its segments (runs of samples in one box).
+__device__ __forceinline__ void struct_ray(const GenDev& g, const GenWs& w, int64_t r) {
   const RayState s = ray_state(g, r);
   double tot = 0.0;
   for (int i = 0; i < s.count; ++i) tot = d_add(tot, width_of(g, s.key, i));
@@ -239,7 +240,11 @@ __global__ void gen_struct_kernel(GenDev g, GenWs w) {
   w.scale[r] = scale;
   w.s0[r] = s0;
   const int M = g.max_segs;
-  int k = -1, cur = -1;
+  // The open segment's length stays in a register and is stored when the
+  // segment closes: a read-modify-write of memory per sample would put a
+  // memory round trip on this serial loop.  Past max_segs the last segment
+  // takes the remaining samples (and err is raised).
+  int k = -1, cur = -1, len = 0;
   double run = s0;
   for (int i = 0; i < s.count; ++i) {
     if (i % kChunk == 0) w.chunk_run[r * g.chunks + i / kChunk] = run;
@@ -248,19 +253,64 @@ __global__ void gen_struct_kernel(GenDev g, GenWs w) {
     const int b = box_of(g, s, static_cast<float>(t0), static_cast<float>(run));
     if (b != cur) {
       if (k + 1 < M) {
+        if (k >= 0) w.seg_len[r * M + k] = len;
         ++k;
         w.seg_box[r * M + k] = b;
-        w.seg_len[r * M + k] = 0;
+        len = 0;
       } else {
         w.err[0] = 1;
       }
       cur = b;
     }
-    w.seg_len[r * M + k] += 1;
+    ++len;
   }
+  if (k >= 0) w.seg_len[r * M + k] = len;
   w.nseg[r] = k + 1;
   w.nseg64[r] = k + 1;
   w.nchunk[r] = (s.count + kChunk - 1) / kChunk;
+}
+
+// One lane per ray.  The lanes of a wave loop as long as their longest ray,
+// so each block first ranks its kStructRays rays by sample count; a lane then
+// takes the rays of rank tid and tid + kStructBlock, and each wave's loops
+// run over rays of similar length.  (Blocks stay at two waves: wider ones
+// are starved of slots next to another stream's kernels of two-wave blocks.)
+constexpr int kStructBlock = 128;
+constexpr int kStructRays = 2 * kStructBlock;
+
+__global__ __launch_bounds__(kStructBlock) void gen_struct_kernel(GenDev g, GenWs w) {
+  __shared__ int cnt[kStructRays];
+  __shared__ int perm[kStructRays];
+  const int tid = threadIdx.x;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kStructRays;
+  const uint64_t span = static_cast<uint64_t>(g.n_max - g.n_min + 1);
+  int mine[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t r = r0 + tid + h * kStructBlock;
+    mine[h] = 0x7fffffff;  // past the last ray: ranked last
+    if (r < g.n_rays) {
+      const uint64_t key = mix64(g.seedkey + static_cast<uint64_t>(g.ray0 + r) * kGamma);
+      mine[h] = g.n_min + static_cast<int32_t>(((draw(key, 3) >> 32) * span) >> 32);
+    }
+    cnt[tid + h * kStructBlock] = mine[h];
+  }
+  __syncthreads();
+  int rank[2] = {0, 0};
+  for (int j = 0; j < kStructRays; ++j) {
+    const int c = cnt[j];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      rank[h] += (c < mine[h] || (c == mine[h] && j < tid + h * kStructBlock)) ? 1 : 0;
+  }
+  perm[rank[0]] = tid;
+  perm[rank[1]] = tid + kStructBlock;
+  __syncthreads();
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    const int64_t r = r0 + perm[tid + h * kStructBlock];
+    if (r < g.n_rays) struct_ray(g, w, r);
+  }
 }
 
 // Ray of every compact chunk (the chunks of all rays, ray after ray).
@@ -409,48 +459,60 @@ __global__ void gen_fill_kernel(GenDev g, GenWs w, void* __restrict__ sigma, voi
     first += w.seg_len[r * M + k];
     ++k;
   }
+  // One loop over the aligned groups of packed slots of every segment the
+  // chunk touches (the segment changes inside the loop): lanes whose chunks
+  // cross segment boundaries at different samples then take as many passes
+  // as their own groups, not the sum over segments of the longest lane's.
   int i = i_begin;
-  for (; k < ns && i < i_end; ++k) {
-    const int len = w.seg_len[r * M + k];
-    const int64_t base_slot = w.seg_off[w.seg_pid[r * M + k]];
-    const int64_t d0 = base_slot + (i - first);                       // first slot to write
-    const int64_t d1 = base_slot + ((i_end < first + len ? i_end : first + len) - first);
-    first += len;
-    for (int64_t g0 = d0 & ~static_cast<int64_t>(kGroup - 1); g0 < d1; g0 += kGroup) {
-      float sg[kGroup], cl[3 * kGroup], a[kGroup], b[kGroup];
+  int len = w.seg_len[r * M + k];
+  int64_t d0 = w.seg_off[w.seg_pid[r * M + k]] + (i - first);  // first slot to write
+  int64_t d1 = d0 + ((i_end < first + len ? i_end : first + len) - i);
+  int64_t g0 = d0 & ~static_cast<int64_t>(kGroup - 1);
+  while (i < i_end) {
+    float sg[kGroup], cl[3 * kGroup], a[kGroup], b[kGroup];
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) {
+      sg[q] = 0.f; cl[3 * q] = cl[3 * q + 1] = cl[3 * q + 2] = 0.f; a[q] = b[q] = 0.f;
+      const int64_t p = g0 + q;
+      if (p < d0 || p >= d1) continue;
+      const double t0 = run;
+      run = d_add(run, d_mul(width_of(g, key, i), scale));
+      const uint64_t base = kRaySlots + static_cast<uint64_t>(kSampleStride) * i;
+      const uint64_t v1 = draw(key, base), v2 = draw(key, base + 1);
+      // 20- and 16-bit fields are exact in float32, so they are formed there
+      // (the same values as the float64 field() rounded to float32)
+      const float u1 = f_mul(static_cast<float>(static_cast<uint32_t>((v1 >> 20) & 0xFFFFFu) + 1u), 0x1p-20f);
+      const float u2 = f_mul(static_cast<float>(static_cast<uint32_t>(v1 & 0xFFFFFu)), 0x1p-20f);
+      const float z = f_mul(f_sqrt(f_mul(-2.f, log_f32(u1))), cos2pi_f32(u2));
+      const float v = exp_f32(f_add(g.mu, f_mul(g.sg, z)));
+      sg[q] = field(v2, 48, 16) < g.zero_frac ? 0.f : v;
+      cl[3 * q] = f_mul(static_cast<float>(static_cast<uint32_t>((v2 >> 32) & 0xFFFFu)), 0x1p-16f);
+      cl[3 * q + 1] = f_mul(static_cast<float>(static_cast<uint32_t>((v2 >> 16) & 0xFFFFu)), 0x1p-16f);
+      cl[3 * q + 2] = f_mul(static_cast<float>(static_cast<uint32_t>(v2 & 0xFFFFu)), 0x1p-16f);
+      a[q] = static_cast<float>(t0);
+      b[q] = static_cast<float>(run);
+      ++i;
+    }
+    if (g0 >= d0 && g0 + kGroup <= d1) {
+      store_group<DT>(sigma, rgb, t_start, t_end, g0, sg, cl, a, b);
+    } else {
 #pragma unroll
       for (int q = 0; q < kGroup; ++q) {
-        sg[q] = 0.f; cl[3 * q] = cl[3 * q + 1] = cl[3 * q + 2] = 0.f; a[q] = b[q] = 0.f;
         const int64_t p = g0 + q;
         if (p < d0 || p >= d1) continue;
-        const double t0 = run;
-        run = d_add(run, d_mul(width_of(g, key, i), scale));
-        const uint64_t base = kRaySlots + static_cast<uint64_t>(kSampleStride) * i;
-        const uint64_t v1 = draw(key, base), v2 = draw(key, base + 1);
-        const float u1 = static_cast<float>(field(v1, 20, 20) + 0x1p-20);
-        const float u2 = static_cast<float>(field(v1, 0, 20));
-        const float z = f_mul(f_sqrt(f_mul(-2.f, log_f32(u1))), cos2pi_f32(u2));
-        const float v = exp_f32(f_add(g.mu, f_mul(g.sg, z)));
-        sg[q] = field(v2, 48, 16) < g.zero_frac ? 0.f : v;
-        cl[3 * q] = static_cast<float>(field(v2, 32, 16));
-        cl[3 * q + 1] = static_cast<float>(field(v2, 16, 16));
-        cl[3 * q + 2] = static_cast<float>(field(v2, 0, 16));
-        a[q] = static_cast<float>(t0);
-        b[q] = static_cast<float>(run);
-        ++i;
+        put_sample<DT>(sigma, rgb, p, sg[q], cl[3 * q], cl[3 * q + 1], cl[3 * q + 2]);
+        t_start[p] = a[q];
+        t_end[p] = b[q];
       }
-      if (g0 >= d0 && g0 + kGroup <= d1) {
-        store_group<DT>(sigma, rgb, t_start, t_end, g0, sg, cl, a, b);
-      } else {
-#pragma unroll
-        for (int q = 0; q < kGroup; ++q) {
-          const int64_t p = g0 + q;
-          if (p < d0 || p >= d1) continue;
-          put_sample<DT>(sigma, rgb, p, sg[q], cl[3 * q], cl[3 * q + 1], cl[3 * q + 2]);
-          t_start[p] = a[q];
-          t_end[p] = b[q];
-        }
-      }
+    }
+    g0 += kGroup;
+    if (g0 >= d1 && i < i_end) {  // this segment's part of the chunk is written: the next one
+      first += len;
+      ++k;
+      len = w.seg_len[r * M + k];
+      d0 = w.seg_off[w.seg_pid[r * M + k]];
+      d1 = d0 + ((i_end < first + len ? i_end : first + len) - i);
+      g0 = d0 & ~static_cast<int64_t>(kGroup - 1);
     }
   }
 }
@@ -652,7 +714,7 @@ hipError_t gen_plan(const xl_gen_params* p, void* ws, hipStream_t st, int64_t* n
   if (e != hipSuccess) return e;
   const bool any = L.R > 0;  // (an empty grid is not a valid launch)
   if (any) {
-    hipLaunchKernelGGL(gen_struct_kernel, dim3(blocks(L.R, 128)), dim3(128), 0, st, g, w);
+    hipLaunchKernelGGL(gen_struct_kernel, dim3(blocks(L.R, kStructRays)), dim3(kStructBlock), 0, st, g, w);
     hipLaunchKernelGGL(block_hist_kernel, dim3(static_cast<unsigned>(L.nblk)), dim3(kRayBlock), 0, st,
                        g, w, L.nblk, static_cast<int>(L.K));
   }
