@@ -464,12 +464,14 @@ int xl_render_breakable_bwd(const xl_breakable* b, const int64_t* seg_offsets, i
  * evaluation), rendered with xl_render_segments_fwd + xl_merge_fwd and kept
  * until released.  Up to max_slots requests run at once, each on its own HIP
  * stream.  The server allocates hbm_budget_bytes of device memory once, at
- * creation, and carves every request's buffers out of it.  Requests are
- * admitted in arrival order, one at a time, when a slot is free: generation
- * planning fixes the exact footprint, and the request waits until that much
- * memory is free next to the requests in flight and the results not yet
- * released.  A request whose footprint exceeds the whole budget fails at once
- * with XL_ENOMEM.  Results hold their memory until xl_serve_release: a client
+ * creation, and carves every request's buffers out of it.  Slots take
+ * requests in arrival order; a slot plans its request's generation (which
+ * fixes the exact footprint), then admissions run one at a time: the request
+ * waits until that much memory is free next to the requests in flight and
+ * the results not yet released.  A request whose footprint exceeds the whole
+ * budget fails at once with XL_ENOMEM.  Each slot also holds the generator's
+ * plan workspace (about 470 bytes per ray of its largest request so far),
+ * allocated outside the budget when a larger request first arrives.  Results hold their memory until xl_serve_release: a client
  * that keeps results while it waits for later requests must leave room for
  * them.  A request's result does not depend on the others.  All functions
  * are thread-safe.

@@ -14,20 +14,23 @@
 //     server starts and carved per request (arena.hpp): no driver allocation
 //     or free happens per request, so the workers never serialise on the
 //     allocator.
-//   * max_slots worker threads, each owning one HIP stream (default priority),
-//     take requests in arrival order.  Admission is one request at a time: the
-//     admitting worker reserves the request's head (result, generator
-//     workspace, ray offsets), runs the generator's plan phase on its own
-//     stream, which fixes the exact footprint (samples, segment arrays,
-//     tuples, tile records), and reserves that body, waiting for memory that
-//     running requests or released results give back.  A request whose
-//     footprint exceeds the whole budget fails at once with XL_ENOMEM.  The
-//     worker then launches generation, segment composite and merge.  Requests
-//     therefore join while others are on the GPU as soon as a slot and memory
-//     free up, and the kernels of different requests overlap on the device.
-//     Only the admitting worker waits for memory, and it holds nothing but its
-//     head while it does, so workers never wait on each other's partial
-//     reservations.
+//   * max_slots worker threads, each owning one HIP stream (default priority)
+//     and a generator workspace, take requests in arrival order.  A worker
+//     runs the generator's plan phase on its own stream, with no lock held,
+//     which fixes the exact footprint (result, ray offsets, samples, segment
+//     arrays, tuples, tile records).  Admission is then one request at a
+//     time: the admitting worker reserves that footprint in one piece,
+//     waiting for memory that running requests or released results give
+//     back; it holds no other reservation while it waits, so workers never
+//     wait on each other's partial reservations.  A request whose footprint
+//     exceeds the whole budget fails at once with XL_ENOMEM.  The worker then
+//     launches generation, segment composite and merge.  Requests therefore
+//     join while others are on the GPU as soon as a slot frees up, the plans
+//     of different slots run side by side (a plan waits for its own counts
+//     to come back to the host), and the kernels of different requests
+//     overlap on the device.  The generator workspace lives outside the
+//     budget: it is allocated when a slot first takes a request larger than
+//     any before (about 470 bytes per ray at 8 segments per ray).
 //   * Each request has its own buffers and runs the same kernels, so its result
 //     does not depend on what else is in flight (bit for bit).
 //   * xl_serve_poll waits for a ticket (bounded by a timeout) and reports the
@@ -120,7 +123,7 @@ static void release_block(Server* s, size_t off, size_t bytes) {
 }
 
 static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int64_t* pinned,
-                    const std::shared_ptr<Job>& j) {
+                    void** ws, size_t* ws_cap, const std::shared_ptr<Job>& j) {
   const xl_request& q = j->req;
   if (q.inject_fault) {
     finish(s, j, XL_EFAULT, "fault injected by the request");
@@ -142,23 +145,68 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int
   const int dtype = s->cfg.dtype;
   const size_t es = dtype == XL_F32 ? 4 : 2;
 
-  // Block layout: [result | generator workspace | ray offsets | samples, segment
-  // arrays, region offsets, tuples, tile records].
+  // Block layout: [result | ray offsets | samples, segment arrays, region
+  // offsets, tuples, tile records].  The generator's workspace (its plan,
+  // read again by the fill) belongs to the slot, outside the budget.
   const int n_regions = p.grid[0] * p.grid[1] * p.grid[2];
   const size_t b_out = round256(4 * 7 * p.n_rays), b_ro = round256(8 * (p.n_rays + 1));
-  const size_t ws_b = round256(gen_workspace_bytes(&p));
-  const size_t head = b_out + ws_b + b_ro;
+  const size_t head = b_out + b_ro;
   auto body = [&](int64_t n, int64_t n_seg) -> size_t {
     return round256(n * es) + round256(3 * n * es) + 2 * round256(4 * n) + round256(8 * (n_seg + 1)) +
            round256(8 * n_seg) + round256(8 * (n_regions + 1)) + round256(4 * XL_TUPLE_STRIDE * n_seg) +
            round256(xl_segments_workspace_bytes(n));
   };
   char m[200];
-  if (head > s->arena.size()) {
-    std::snprintf(m, sizeof(m), "request needs more than %llu bytes, budget is %llu",
-                  static_cast<unsigned long long>(head),
+  auto over_budget = [&](size_t need) {
+    std::snprintf(m, sizeof(m), "request needs %s%llu bytes, budget is %llu",
+                  need == head ? "more than " : "", static_cast<unsigned long long>(need),
                   static_cast<unsigned long long>(s->arena.size()));
     finish(s, j, XL_ENOMEM, m);
+  };
+  // At least n_min samples and one segment per ray: fail before planning a
+  // request that cannot fit whatever its plan gives.
+  if (head > s->arena.size()) {
+    over_budget(head);
+    return;
+  }
+  const int64_t n_lo = p.n_rays * static_cast<int64_t>(p.n_min > 0 ? p.n_min : 0);
+  if (head + body(n_lo, p.n_min > 0 ? p.n_rays : 0) > s->arena.size()) {
+    over_budget(head + body(n_lo, p.n_min > 0 ? p.n_rays : 0));
+    return;
+  }
+  // The slot's workspace grows to the largest request it has taken (its
+  // previous request has completed: run_job synchronises before it returns).
+  const size_t ws_need = gen_workspace_bytes(&p);
+  if (ws_need > *ws_cap) {
+    if (*ws) (void)hipFree(*ws);
+    *ws = nullptr;
+    *ws_cap = 0;
+    if (hipMalloc(ws, ws_need) != hipSuccess) {
+      *ws = nullptr;
+      std::snprintf(m, sizeof(m), "generator workspace of %llu bytes could not be allocated",
+                    static_cast<unsigned long long>(ws_need));
+      finish(s, j, XL_ENOMEM, m);
+      return;
+    }
+    *ws_cap = ws_need;
+  }
+
+  // The plan runs before admission and without any lock, so the plans of
+  // requests taken by different slots overlap each other and running work.
+  int64_t n = 0, n_seg = 0;
+  int overflow = 0;
+  if (gen_plan(&p, *ws, st, &n, &n_seg, &overflow, pinned) != hipSuccess || overflow) {
+    (void)hipStreamSynchronize(st);  // cleanup on a path that already reports failure
+    finish(s, j, XL_EHIP, "generator plan failed");
+    return;
+  }
+  j->n_samples = n;
+  j->n_seg = n_seg;
+  const size_t fp = head + body(n, n_seg);
+  j->footprint = fp;
+  j->result_bytes = b_out;
+  if (fp > s->arena.size()) {
+    over_budget(fp);
     return;
   }
   // Waits (under the server mutex) until `bytes` can be carved out or the
@@ -169,50 +217,20 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int
     s->cv_budget.wait(lk, [&] { return s->stop || (got = s->arena.alloc(bytes, at)); });
     return got;
   };
-  std::unique_lock<std::mutex> admission(s->admit_mu);
-  size_t off = 0, off_b = 0;
-  if (!reserve(head, &off)) {
-    admission.unlock();
-    finish(s, j, XL_EAGAIN, "server stopped before the request was admitted");
-    return;
+  // One reservation per request, one admission at a time: the admitting
+  // worker holds nothing while it waits, and the others wait for it.
+  size_t off = 0;
+  {
+    std::lock_guard<std::mutex> admission(s->admit_mu);
+    if (!reserve(fp, &off)) {
+      finish(s, j, XL_EAGAIN, "server stopped before the request was admitted");
+      return;
+    }
   }
   char* blk = s->base + off;
   float* out = reinterpret_cast<float*>(blk);
-  void* ws = blk + b_out;
-  int64_t* ro = reinterpret_cast<int64_t*>(blk + b_out + ws_b);
-
-  int64_t n = 0, n_seg = 0;
-  int overflow = 0;
-  if (gen_plan(&p, ws, st, &n, &n_seg, &overflow, pinned) != hipSuccess || overflow) {
-    (void)hipStreamSynchronize(st);  // cleanup on a path that already reports failure
-    admission.unlock();
-    release_block(s, off, head);
-    finish(s, j, XL_EHIP, "generator plan failed");
-    return;
-  }
-  j->n_samples = n;
-  j->n_seg = n_seg;
-  const size_t bb = body(n, n_seg);
-  const size_t fp = head + bb;
-  j->footprint = fp;
-  j->result_bytes = b_out;
-  if (fp > s->arena.size()) {
-    admission.unlock();
-    release_block(s, off, head);
-    std::snprintf(m, sizeof(m), "request needs %llu bytes, budget is %llu",
-                  static_cast<unsigned long long>(fp),
-                  static_cast<unsigned long long>(s->arena.size()));
-    finish(s, j, XL_ENOMEM, m);
-    return;
-  }
-  if (!reserve(bb, &off_b)) {
-    admission.unlock();
-    release_block(s, off, head);
-    finish(s, j, XL_EAGAIN, "server stopped before the request was admitted");
-    return;
-  }
-  admission.unlock();
-  char* c = s->base + off_b;
+  int64_t* ro = reinterpret_cast<int64_t*>(blk + b_out);
+  char* c = blk + head;
 
   void* sigma = c; c += round256(n * es);
   void* rgb = c; c += round256(3 * n * es);
@@ -225,7 +243,7 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int
   void* recs = c;  // per-tile records of the segment composite
 
   hipError_t e = hipEventRecord(e0, st);
-  if (e == hipSuccess) e = gen_fill(&p, dtype, ws, n_seg, sigma, rgb, t0, t1, so, ro, ids, roff, st);
+  if (e == hipSuccess) e = gen_fill(&p, dtype, *ws, n_seg, sigma, rgb, t0, t1, so, ro, ids, roff, st);
   SamplesDev sd{dtype, sigma, rgb, t0, t1, n};
   if (e == hipSuccess) e = launch_segments_fwd(sd, so, n_seg, seg_out, recs, st);
   if (e == hipSuccess)
@@ -244,13 +262,12 @@ static void run_job(Server* s, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int
       j->device_end_ms = b;
     }
   }
-  release_block(s, off_b, bb);
   if (e != hipSuccess || es2 != hipSuccess) {
-    release_block(s, off, head);
+    release_block(s, off, fp);
     finish(s, j, XL_EHIP, hipGetErrorString(e != hipSuccess ? e : es2));
     return;
   }
-  release_block(s, off + b_out, head - b_out);  // the result stays until released
+  release_block(s, off + b_out, fp - b_out);  // the result stays until released
   j->ray_out = out;
   j->arena_off = off;
   finish(s, j, XL_OK, nullptr);
@@ -265,6 +282,8 @@ static void worker(Server* s) {
   hipStream_t st = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int64_t* pinned = nullptr;  // the plan phase's readback values
+  void* ws = nullptr;         // the generator's workspace, grown on demand
+  size_t ws_cap = 0;
   // A slot whose stream, events or buffer cannot be made fails every request it takes.
   const bool ready = hipSetDevice(s->cfg.device) == hipSuccess &&
                      hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
@@ -284,11 +303,12 @@ static void worker(Server* s) {
     if (stopping(s))
       finish(s, j, XL_EAGAIN, "server destroyed before the request started");
     else if (ready)
-      run_job(s, st, e0, e1, pinned, j);
+      run_job(s, st, e0, e1, pinned, &ws, &ws_cap, j);
     else
       finish(s, j, XL_EHIP, "serving slot has no stream or events");
   }
   if (pinned) (void)hipHostFree(pinned);
+  if (ws) (void)hipFree(ws);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (st) (void)hipStreamDestroy(st);
