@@ -65,6 +65,36 @@ def test_result_is_the_same_alone_and_in_a_mix():
             srv.release(t)
 
 
+def test_slot_workspace_grows_and_results_stay_the_same():
+    """One slot takes a small view, a larger one (its generator workspace,
+    held outside the budget, grows), then the small one again: each result
+    equals the same request served alone by a fresh server, bit for bit."""
+    sizes = {"small": (64, 48), "large": (320, 240)}
+    reqs = {k: request(w, h, seed=21 + i, **SCENE) for i, (k, (w, h)) in enumerate(sizes.items())}
+
+    def alone(k):
+        with Server(max_slots=1, dtype=torch.float16) as srv:
+            t = srv.submit(reqs[k])
+            assert srv.poll(t, timeout_us=60_000_000)["rc"] == 0
+            out = srv.result(t, sizes[k][0] * sizes[k][1])
+            torch.cuda.synchronize()
+            srv.release(t)
+        return out
+
+    ref = {k: alone(k) for k in sizes}
+    order = ["small", "large", "small"]
+    with Server(max_slots=1, dtype=torch.float16) as srv:
+        ts = [srv.submit(reqs[k]) for k in order]
+        res = wait_all(srv, ts)
+        assert all(v["rc"] == 0 for v in res.values()), res
+        for k, t in zip(order, ts):
+            out = srv.result(t, sizes[k][0] * sizes[k][1])
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref[k]), k
+            srv.release(t)
+        assert srv.stats()["budget_used_bytes"] == 0
+
+
 def test_queue_full_returns_eagain_and_accepted_requests_finish():
     with Server(max_slots=1, max_queue=2, dtype=torch.float16) as srv:
         tickets, rejected = [], 0
