@@ -140,6 +140,23 @@ __device__ float2 ray_span(const PackDev& p, int64_t r, const Box& bx) {
 }
 
 // Samples [first, first + count) of the ray (s0, n) that meet [tin, tout).
+// Probe of a search over [a, c) (c > a) for a key at `key`, with v_lo and
+// v_hi bounds of the keys at a and at c - 1: the interpolated position for
+// the first kInterp probes (positions along a ray are close to evenly
+// spread), the midpoint after that.  Always inside [a, c - 1], so every
+// probe shrinks the range and the search ends within kInterp + log2(n) + 1.
+constexpr int kInterp = 6;
+__device__ __forceinline__ int64_t probe(int64_t a, int64_t c, float v_lo, float v_hi, float key, int it) {
+  if (it < kInterp) {
+    float g = (key - v_lo) / (v_hi - v_lo) * static_cast<float>(c - a);
+    if (!(g >= 0.f)) g = 0.f;  // also NaN (equal bounds)
+    const float top = static_cast<float>(c - a - 1);
+    if (g > top) g = top;
+    return a + static_cast<int64_t>(g);
+  }
+  return (a + c) >> 1;
+}
+
 __device__ void run_of(const PackDev& p, float tin, float tout, int64_t s0, int64_t n,
                        int64_t& first, int64_t& count) {
   first = 0;
@@ -148,20 +165,34 @@ __device__ void run_of(const PackDev& p, float tin, float tout, int64_t s0, int6
   // first sample reaching into the box: it ends after t_in, or has zero
   // length at t_in
   int64_t a = 0, c = n;
-  while (a < c) {
-    const int64_t m = (a + c) >> 1;
+  float v_lo = p.t0[s0], v_hi = p.t1[s0 + n - 1];
+  for (int it = 0; a < c; ++it) {
+    const int64_t m = probe(a, c, v_lo, v_hi, tin, it);
     const float e = p.t1[s0 + m];
     const bool in = e > tin || (e == tin && p.t0[s0 + m] == tin);
-    if (in) c = m;
-    else a = m + 1;
+    if (in) {
+      c = m;
+      v_hi = e;
+    } else {
+      a = m + 1;
+      v_lo = e;
+    }
   }
   first = a;
   // first sample starting at or after t_out
   c = n;
-  while (a < c) {
-    const int64_t m = (a + c) >> 1;
-    if (p.t0[s0 + m] >= tout) c = m;
-    else a = m + 1;
+  v_lo = tin;
+  v_hi = p.t1[s0 + n - 1];
+  for (int it = 0; a < c; ++it) {
+    const int64_t m = probe(a, c, v_lo, v_hi, tout, it);
+    const float s = p.t0[s0 + m];
+    if (s >= tout) {
+      c = m;
+      v_hi = s;
+    } else {
+      a = m + 1;
+      v_lo = s;
+    }
   }
   count = a - first;
 }
