@@ -394,13 +394,15 @@ def _tree(axis, plane, device):
 
 
 def xl_pack(origins, dirs, t_start, t_end, ray_offsets, axis, plane, levels: int,
-            with_src: bool = True) -> dict:
+            with_src: bool = True, reuse: Optional[dict] = None) -> dict:
     """Cut, tag and pack ray-major samples region-major (xl_pack_plan + xl_pack_fill).
 
     origins, dirs: device float32 [R, 3]; t_start, t_end: device float32 [n];
     ray_offsets: device int64 [R + 1]; axis, plane: the partition tree (host or
     device).  Returns device tensors t_start, t_end, src (or None),
-    seg_offsets, ray_offsets, seg_ids, seg_box, region_offsets."""
+    seg_offsets, ray_offsets, seg_ids, seg_box, region_offsets, and the
+    workspace.  reuse: the result of an earlier call whose tensors (workspace
+    included) are written again where their shapes fit, instead of allocating."""
     dev = origins.device
     R = origins.shape[0]
     if origins.shape != (R, 3) or dirs.shape != (R, 3) or ray_offsets.shape != (R + 1,):
@@ -414,20 +416,29 @@ def xl_pack(origins, dirs, t_start, t_end, ray_offsets, axis, plane, levels: int
                   _dev(t_start, "t_start", torch.float32), _dev(t_end, "t_end", torch.float32),
                   _dev(ray_offsets, "ray_offsets", torch.int64), R)
     L = lib()
+    old = reuse or {}
+
+    def buf(key, shape, dtype):
+        t = old.get(key)
+        if t is not None and tuple(t.shape) == shape and t.dtype == dtype and t.device == dev:
+            return t
+        return torch.empty(shape, dtype=dtype, device=dev)
+
     wsb = L.xl_pack_workspace_bytes(R, levels)
-    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    ws = buf("workspace", (max(wsb, 1),), torch.uint8)
     npc, nseg = _i64(0), _i64(0)
     _check(L.xl_pack_plan(ctypes.byref(rays), a.data_ptr(), p.data_ptr(), levels, ws.data_ptr(), wsb,
                           ctypes.byref(npc), ctypes.byref(nseg), _stream()))
     n, n_seg = npc.value, nseg.value
-    out = dict(t_start=torch.empty(n, dtype=torch.float32, device=dev),
-               t_end=torch.empty(n, dtype=torch.float32, device=dev),
-               src=torch.empty(n, dtype=torch.int64, device=dev) if with_src else None,
-               seg_offsets=torch.empty(n_seg + 1, dtype=torch.int64, device=dev),
-               ray_offsets=torch.empty(R + 1, dtype=torch.int64, device=dev),
-               seg_ids=torch.empty(n_seg, dtype=torch.int64, device=dev),
-               seg_box=torch.empty(n_seg, dtype=torch.int32, device=dev),
-               region_offsets=torch.empty((1 << levels) + 1, dtype=torch.int64, device=dev))
+    out = dict(t_start=buf("t_start", (n,), torch.float32),
+               t_end=buf("t_end", (n,), torch.float32),
+               src=buf("src", (n,), torch.int64) if with_src else None,
+               seg_offsets=buf("seg_offsets", (n_seg + 1,), torch.int64),
+               ray_offsets=buf("ray_offsets", (R + 1,), torch.int64),
+               seg_ids=buf("seg_ids", (n_seg,), torch.int64),
+               seg_box=buf("seg_box", (n_seg,), torch.int32),
+               region_offsets=buf("region_offsets", ((1 << levels) + 1,), torch.int64),
+               workspace=ws)
     _check(L.xl_pack_fill(ctypes.byref(rays), a.data_ptr(), p.data_ptr(), levels, ws.data_ptr(), wsb,
                           n_seg, _dev(out["t_start"], "t_start"), _dev(out["t_end"], "t_end"),
                           _dev(out["src"], "src") if with_src else None,

@@ -54,6 +54,32 @@ def test_random_rays_bit_exact(levels):
         assert got["src"].shape[0] > ts.shape[0]  # samples were cut
 
 
+def test_reused_buffers_give_the_same_pack():
+    """A pack written into the outputs and workspace of an earlier one (the
+    bench's repeated packs) equals a fresh pack; so does one without src."""
+    o, d, ts, te, ro = synth.random_rays(7, 300, 70)
+    axis, plane = tree_for(6, 3)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    args = (T(o), T(d), T(ts), T(te), T(ro), axis, plane, 6)
+    fresh = {k: v.clone() for k, v in xl.xl_pack(*args).items() if v is not None}
+    first = xl.xl_pack(*args)
+    for k in ("t_start", "t_end", "src", "seg_ids"):
+        first[k].fill_(-1)  # stale contents must be overwritten
+    again = xl.xl_pack(*args, reuse=first)
+    torch.cuda.synchronize()
+    assert again["t_start"].data_ptr() == first["t_start"].data_ptr()
+    for k in KEYS + ("region_offsets",):
+        assert torch.equal(again[k], fresh[k]), k
+    for k in ("t_start", "t_end", "seg_ids"):
+        again[k].fill_(-1)
+    nosrc = xl.xl_pack(*args, with_src=False, reuse=again)
+    torch.cuda.synchronize()
+    assert nosrc["src"] is None
+    for k in KEYS + ("region_offsets",):
+        if k != "src":
+            assert torch.equal(nosrc[k], fresh[k]), k
+
+
 def test_edge_cases_bit_exact():
     axis, plane = tree_for(3, 9)
     # no rays
